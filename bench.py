@@ -1,0 +1,212 @@
+"""Benchmark of the TaylorGrid SDF-fitting hot path on one MI355X.
+
+Workload (the paper's 3D SDF fitting task, Sec. 3.2, at the 128^3 resolution of Table 1/2):
+128^3 vertices on [-1,1]^3, order K=2 (10 FP32 coefficients per vertex), 2^20 queries per
+step (half uniform in the box, half jittered points on a seeded union of 8 spheres and a
+torus), L1 reconstruction + 0.1 * eikonal, Adam lr 1e-2.  One step = bucketing sort +
+forward (f, grad f) + loss + adjoint scatter + fused Adam over every coefficient.  Query
+batches are generated on the host before timing and are resident in HBM.
+
+Prints one JSON line.  --gpus must be 1 (the path runs on one GPU; see the design doc for how it
+would shard).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "queries/s fwd+bwd at 128^3 K=2 (and % HBM peak); served query p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+RES = 128
+ORDER = 2
+NQ = 1 << 20
+EIK = 0.1
+LR = 1e-2
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def unique_vertices(q, res, lo=-1.0, hi=1.0):
+    h = (hi - lo) / (res - 1)
+    c = np.minimum(np.floor((np.clip(q, lo, hi) - lo) / h).astype(np.int64), res - 2)
+    ids = []
+    for b in range(8):
+        v = c + np.array([(b >> a) & 1 for a in range(3)])
+        ids.append(v[:, 0] + res * (v[:, 1] + res * v[:, 2]))
+    return int(np.unique(np.concatenate(ids)).size)
+
+
+def algorithmic_bytes(nq, U, C, nvert):
+    fwd = nq * (12 + 16) + U * C * 4          # read q, write f and grad f; read touched coefficients
+    loss = nq * (4 + 12 + 4) + nq * (4 + 12)  # read f, grad f, d; write g_f, g_grad
+    bwd = nq * (12 + 16) + U * C * 4          # read q, g_f, g_grad; write touched gradients
+    adam = nvert * C * 4 * 7                  # read master, m, v, grad; write master, m, v
+    return {"sort": 0, "forward": fwd, "loss": loss, "backward": bwd, "adam": adam}
+
+
+def cpu_baseline(C64, q, d):
+    """The FP64 oracle on the same step: forward + loss + adjoint over the whole batch
+    (2^20 queries) and Adam over every coefficient, on the host cores."""
+    import oracle
+
+    geom = oracle.Geometry(3, (RES,) * 3, ORDER, (-1.0,) * 3, (1.0,) * 3)
+    t0 = time.perf_counter()
+    f, g = oracle.forward(geom, C64, q)
+    _, gf, gg = oracle.sdf_loss(f, g, d, EIK)
+    dC, _ = oracle.backward(geom, C64, q, gf, gg)
+    flat = C64.reshape(-1)
+    oracle.adam(flat, np.zeros_like(flat), np.zeros_like(flat), dC.reshape(-1), LR, step=1)
+    dt = time.perf_counter() - t0
+    return {"value": len(q) / dt, "unit": "queries/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"one full step: {len(q)} queries fwd+loss+bwd at {RES}^3 K={ORDER} + Adam over "
+                      f"{flat.size} coefficients, FP64, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--batches", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this path runs on one GPU only (no multi-GPU path is built); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2402_14415_amd import synth
+    from paper_2402_14415_amd.grid import TaylorGrid, sdf_loss
+
+    dev = torch.device("cuda", 0)
+    log("bench: generating inputs")
+    C64, _ = synth.normal_coeffs((RES, RES, RES, 10), std=0.05, seed=0)
+    scene = synth.Scene(0)
+    batches = []
+    for b in range(args.batches):
+        q, d = synth.scene_batch(scene, NQ, seed=0, step=b)
+        batches.append((q, d))
+    U = unique_vertices(batches[0][0], RES)
+
+    grid = TaylorGrid(3, (RES,) * 3, ORDER, (-1.0,) * 3, (1.0,) * 3,
+                      coeffs=torch.from_numpy(C64.astype(np.float32)), device=dev)
+    dev_batches = [(torch.tensor(q, dtype=torch.float32, device=dev), torch.tensor(d, dtype=torch.float32, device=dev))
+                   for q, d in batches]
+    ws = grid.workspace(NQ)
+    f = torch.empty(NQ, device=dev)
+    g = torch.empty((NQ, 3), device=dev)
+    gf = torch.empty(NQ, device=dev)
+    gg = torch.empty((NQ, 3), device=dev)
+    loss = torch.empty(3, dtype=torch.float64, device=dev)
+    gns = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def step(i, ev=None):
+        q, d = dev_batches[i % len(dev_batches)]
+        s = torch.cuda.current_stream(dev)
+        if ev is not None:
+            ev[0].record(s)
+        grid.sort(q, ws)
+        if ev is not None:
+            ev[1].record(s)
+        grid.forward(q, ws, out=(f, g))
+        if ev is not None:
+            ev[2].record(s)
+        sdf_loss(f, g, d, EIK, ws, g_f=gf, g_grad=gg, loss=loss)
+        if ev is not None:
+            ev[3].record(s)
+        grid.backward(q, ws, gf, gg)
+        if ev is not None:
+            ev[4].record(s)
+        grid.adam_step(ws, lr=LR, grad_norm_sq=gns)
+        if ev is not None:
+            ev[5].record(s)
+
+    log("bench: warmup")
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    first_loss = float(loss[0])
+
+    log("bench: timed region")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = NQ / (elapsed / args.steps)
+    log(f"bench: {ms_per_step:.3f} ms/step, {value:.3e} queries/s, loss {first_loss:.4f} -> {float(loss[0]):.4f}")
+
+    names = ["sort", "forward", "loss", "backward", "adam"]
+    C = 10
+    nvert = RES ** 3
+    alg = algorithmic_bytes(NQ, U, C, nvert)
+    per_call_us = {}
+    if not args.no_breakdown:
+        # Per-call durations from HIP events recorded on the stream the kernels run on.
+        reps = max(10, args.steps)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(reps)]
+        for i in range(reps):
+            step(i, evs[i])
+        torch.cuda.synchronize()
+        for k, nm in enumerate(names):
+            per_call_us[nm] = 1e3 * float(np.mean([e[k].elapsed_time(e[k + 1]) for e in evs]))
+        log("bench: per-call us " + json.dumps({k: round(v, 2) for k, v in per_call_us.items()}))
+
+    total_alg = sum(alg.values())
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sdf_fit_128^3_K2_fp32", "grid_vertices": f"{RES}^3", "order": ORDER,
+                   "queries_per_step": NQ, "loss": "L1 + 0.1*eikonal", "optimizer": "Adam lr=1e-2",
+                   "step": "sort + forward + loss + backward + adam", "unique_vertices": U},
+        "step_hbm": {"algorithmic_bytes": total_alg,
+                     "achieved_GBs": total_alg / (ms_per_step * 1e-3) / 1e9,
+                     "frac": total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+    }
+    if per_call_us:
+        dom = max(names, key=lambda k: per_call_us[k])
+        ach = alg[dom] / (per_call_us[dom] * 1e-6) / 1e9
+        out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS, "traffic": None}
+        fb_us = per_call_us["forward"] + per_call_us["backward"]
+        fb_bytes = alg["forward"] + alg["backward"]
+        out["fwd_bwd"] = {"queries_per_s": NQ / (fb_us * 1e-6), "us": fb_us,
+                          "achieved_GBs": fb_bytes / (fb_us * 1e-6) / 1e9,
+                          "frac": fb_bytes / (fb_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+        out["breakdown_us"] = per_call_us
+        out["kernels"] = {nm: {"us": per_call_us[nm], "algorithmic_bytes": alg[nm],
+                               "GBs": alg[nm] / (per_call_us[nm] * 1e-6) / 1e9} for nm in names}
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        q0, d0 = batches[0]
+        out["cpu_baseline"] = cpu_baseline(C64.astype(np.float32).astype(np.float64), q0, d0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

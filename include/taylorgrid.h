@@ -1,0 +1,196 @@
+/*
+ * taylorgrid.h -- C ABI of the MI355X (gfx950) TaylorGrid query path.
+ *
+ * TaylorGrid (arXiv 2402.14415, Sec. 3.1) represents a field f: R^n -> R (n = 2 or 3) by a
+ * dense grid whose vertices each store the low-order Taylor series of f at that vertex
+ * (value, gradient and, at order 2, the symmetric Hessian).  A query point is located in
+ * its cell (Eq. 2); each corner's Taylor polynomial (Eq. 1) is evaluated at the point's
+ * offset from that corner (Eq. 3); the corner values are blended with multilinear weights
+ * (Eq. 4).  The grid is optimised directly, with no network (Sec. 3.1, Sec. 4.1), which
+ * needs the adjoint of that map; the SDF task adds an L1 reconstruction term (Eq. 6) and
+ * an eikonal term (Eq. 8) that needs the field's spatial gradient.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Grid geometry: res[a] vertices on axis a span the closed box [lo[a], hi[a]]; vertex i
+ *    sits at lo + i*h, h = (hi - lo)/(res - 1).  Queries outside the box are clamped to it;
+ *    the spatial gradient is zero along a clamped axis.  The cell of a point is
+ *    floor((x - lo)/h) capped at res - 2 (a point on the high face uses the last cell).
+ *  Coefficient layout: [res_z][res_y][res_x][C] (x fastest; 2D: [res_y][res_x][C]), C =
+ *    tg_coeffs_per_vertex(dim, order) values per vertex holding the partial derivatives of
+ *    f at the vertex in graded-lexicographic order (3D order 2: f, fx, fy, fz, fxx, fxy,
+ *    fxz, fyy, fyz, fzz; 2D order 2: f, fx, fy, fxx, fxy, fyy), in world units.
+ *  Queries: q is [n][dim] FP32, row-major.  Outputs are in the caller's query order.
+ *  Memory: every pointer argument is DEVICE memory unless marked (host).  The library
+ *    never allocates, copies or frees device memory; buffers belong to the caller and must
+ *    outlive the calls that use them.  Workspaces are caller-allocated device buffers of at
+ *    least the size the matching *_workspace_bytes function returns; their content is
+ *    private to the library between the calls documented to share it.
+ *  Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every
+ *    call only enqueues work and returns; results are ready when the stream reaches them.
+ *  Errors: arguments are validated on the host before anything is enqueued; on failure
+ *    the call returns a non-zero tg_status and enqueues nothing (outputs untouched).  A
+ *    launch failure is reported as TG_ERR_DEVICE.  tg_last_error() returns a thread-local
+ *    description of the last failure.  No call aborts or throws.
+ *  Sizes: n = 0 is a no-op returning TG_OK.  n must be below 2^31.
+ *  Concurrency: calls on different grid handles may run concurrently.  Calls on one
+ *    handle must be serialised by the caller (the handle records the last sort).
+ */
+#ifndef TAYLORGRID_H
+#define TAYLORGRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TG_OK = 0,
+    TG_ERR_INVALID_ARG = 1, /* a NULL, out-of-range or inconsistent argument */
+    TG_ERR_UNSUPPORTED = 2, /* valid request this build does not implement */
+    TG_ERR_DEVICE = 3,      /* HIP reported an error on launch */
+    TG_ERR_CAPACITY = 4,    /* workspace too small or size beyond the supported maximum */
+    TG_ERR_STATE = 5        /* workspace does not hold the sort this call needs */
+} tg_status;
+
+typedef enum { TG_F32 = 0, TG_BF16 = 1, TG_F16 = 2 } tg_dtype;
+
+/* Grid geometry and storage type (host struct, copied by tg_create). */
+typedef struct {
+    int32_t dim;     /* 2 or 3 */
+    int32_t res[3];  /* vertices per axis, each in [2, 65536]; res[2] unused when dim == 2 */
+    int32_t order;   /* Taylor order K: 0, 1 or 2 */
+    float lo[3];     /* box corner; lo[2] unused when dim == 2 */
+    float hi[3];     /* hi[a] > lo[a], both finite */
+    int32_t storage; /* tg_dtype of `coeffs` */
+} tg_grid_desc;
+
+/* Device buffers of one grid, all with the coefficient layout above (host struct).
+ * A pointer may be NULL when no call that needs it is made. */
+typedef struct {
+    void* coeffs;  /* storage dtype; read by tg_forward, tg_query; rewritten by tg_adam_step
+                      when storage != TG_F32 (round-to-nearest-even copy of master) */
+    float* master; /* FP32 master coefficients updated by tg_adam_step; when storage ==
+                      TG_F32 it must equal `coeffs` */
+    float* grad;   /* FP32 gradient: written (or accumulated) by tg_backward, read by
+                      tg_adam_step */
+    float* adam_m; /* FP32 first moment */
+    float* adam_v; /* FP32 second moment */
+} tg_grid_buffers;
+
+typedef struct tg_grid tg_grid; /* opaque host-side handle: geometry + buffer pointers */
+
+/* Adam hyper-parameters (host struct).  step counts from 1. */
+typedef struct {
+    float lr, beta1, beta2, eps, weight_decay;
+    int64_t step;
+} tg_adam_params;
+
+/* One serving request (host struct): n query points against grid index `grid`. */
+typedef struct {
+    int32_t grid;    /* index into the grids array of tg_query */
+    int32_t pad_;
+    int64_t n;       /* number of points, >= 0 */
+    const float* q;  /* [n][dim] */
+    float* sdf;      /* [n] field value */
+    float* normal;   /* [n][dim] unit gradient (zero where the gradient vanishes); NULL = skip */
+} tg_request;
+
+/* Flags. */
+#define TG_BWD_ACCUMULATE 1  /* tg_backward: grad += contribution (default: grad = contribution) */
+#define TG_ADAM_ZERO_GRAD 1  /* tg_adam_step: zero grad after reading it */
+
+/* binom(dim + order, order), or -1 when dim is not 2/3 or order is not 0..2. */
+int32_t tg_coeffs_per_vertex(int32_t dim, int32_t order);
+
+/* Create a handle (host only; nothing is enqueued).  The descriptor is copied; buffers may
+ * be NULL and set later with tg_set_buffers.  *out receives the handle on success. */
+tg_status tg_create(const tg_grid_desc* desc, const tg_grid_buffers* bufs, tg_grid** out);
+
+/* Replace the buffer pointers of a handle (host only). */
+tg_status tg_set_buffers(tg_grid* grid, const tg_grid_buffers* bufs);
+
+/* Free a handle (host only).  NULL is accepted. */
+tg_status tg_destroy(tg_grid* grid);
+
+/* Device workspace bytes that tg_sort_queries, tg_forward and tg_backward need for n
+ * queries on this grid (the sort, sized for the worst case), plus the reduction scratch
+ * that tg_sdf_loss and tg_adam_step use.  0 on an invalid handle or n. */
+size_t tg_workspace_bytes(const tg_grid* grid, int64_t n);
+
+/* Bytes of reduction scratch that tg_sdf_loss and tg_adam_step need (a constant). */
+size_t tg_reduce_workspace_bytes(void);
+
+/* Bucket the queries by brick of cells (an implementation step that makes the grid
+ * gathers of tg_forward and the adjoint scatter of tg_backward local; it has no
+ * counterpart in the paper).  Writes the sort into `ws`, and records (q, n, ws) in the
+ * handle: tg_forward and tg_backward on the same (q, n, ws) reuse it.  The queries must
+ * not change between this call and the calls that reuse the sort. */
+tg_status tg_sort_queries(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* Field value and spatial gradient at each query (Sec. 3.1, Eq. 2-4):
+ *   f[i] = sum over the 2^dim corners b of the cell of w_b(x) T_b(x - v_b),
+ *   grad_f[i][a] = df/dx_a (0 on a clamped axis).
+ * Requires the sort of (q, n) in ws (TG_ERR_STATE otherwise).  grad_f may be NULL. */
+tg_status tg_forward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes,
+                     float* f, float* grad_f, void* stream);
+
+/* SDF objective (Sec. 3.2, Eq. 6 unweighted, plus the eikonal term of Eq. 8):
+ *   L = mean_i |f_i - d_i| + eik_weight * mean_i (|grad_f_i| - 1)^2,
+ * written as loss[0] = L, loss[1] = L1 mean, loss[2] = eikonal mean, in FP64 (device).
+ * Writes the upstream gradients g_f[i] = dL/df_i and, if grad_f != NULL,
+ * g_grad[i][a] = dL/d(grad_f_i)_a.  grad_f == NULL drops the eikonal term (g_grad unused).
+ * ws must hold tg_reduce_workspace_bytes(). */
+tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_f, const float* d,
+                      float eik_weight, float* g_f, float* g_grad, double* loss, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Adjoint of tg_forward (the exact transpose of the map C -> (f, grad f), which is linear
+ * in the coefficients; the paper prints no formula).  For upstream gradients g_f [n] and
+ * g_grad [n][dim] (either may be NULL = zero) it writes, for every vertex of the grid,
+ *   grad[v][alpha] (=, or += with TG_BWD_ACCUMULATE) sum over queries of
+ *     g_f w_b m_alpha(d_b) + sum_a g_grad_a (dw_b/dx_a m_alpha(d_b) + w_b dm_alpha/dd_a(d_b)),
+ * with m_alpha(d) = d^alpha / alpha! the Taylor monomials of Eq. 1.  Vertices no query
+ * touches are written 0 (or left unchanged when accumulating).  If dq != NULL it also
+ * writes dq[i][a] = g_f df/dx_a + sum_c g_grad_c d2f/dx_a dx_c (0 on a clamped axis).
+ * Requires the sort of (q, n) in ws; needs bufs.grad (and bufs.coeffs when dq != NULL).
+ * The result does not depend on the order of the queries up to FP32 rounding of the sums. */
+tg_status tg_backward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes,
+                      const float* g_f, const float* g_grad, float* dq, int32_t flags,
+                      void* stream);
+
+/* One Adam step over every coefficient (the paper trains the grid with a fixed learning
+ * rate and names no optimizer; this is Adam with bias correction, eps added to the
+ * corrected root, and weight decay added to the gradient):
+ *   g' = grad + wd*master; m = b1 m + (1-b1) g'; v = b2 v + (1-b2) g'^2;
+ *   master -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+ * then, when storage != TG_F32, coeffs = round_to_nearest_even(master) (FP16 saturates to
+ * +-65504).  If grad_norm_sq != NULL (device double) it receives sum(grad^2) in FP64.
+ * TG_ADAM_ZERO_GRAD zeroes grad afterwards.  ws must hold tg_reduce_workspace_bytes(). */
+tg_status tg_adam_step(tg_grid* grid, const tg_adam_params* params, double* grad_norm_sq,
+                       void* ws, size_t ws_bytes, int32_t flags, void* stream);
+
+/* Serving: field value and unit normal for a batch of requests against several resident
+ * grids, in one launch per group of up to TG_QUERY_MAX_REQS requests referencing up to
+ * TG_QUERY_MAX_GRIDS distinct grids (larger batches are split into several launches).
+ * grids (host array of handles) and reqs (host array) are read during the call only; no
+ * workspace or sort is needed.  The arithmetic per query is the same as tg_forward's, so a
+ * request's result does not depend on which other requests share the launch. */
+#define TG_QUERY_MAX_REQS 32
+#define TG_QUERY_MAX_GRIDS 16
+tg_status tg_query(const tg_grid* const* grids, int32_t n_grids, const tg_request* reqs,
+                   int32_t n_reqs, void* stream);
+
+/* Static description of a status code; never NULL. */
+const char* tg_status_string(tg_status status);
+
+/* Thread-local description of the last failing call on this thread ("" if none). */
+const char* tg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TAYLORGRID_H */

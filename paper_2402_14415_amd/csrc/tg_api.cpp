@@ -1,0 +1,363 @@
+// C ABI of the TaylorGrid library: host-side validation, workspace layout and dispatch.
+// Every argument is checked before anything is enqueued; see include/taylorgrid.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "tg_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tg_status fail(tg_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+tg_status fail(tg_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+tg_status ok()
+{
+    return TG_OK;
+}
+
+tg_status device_status(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return ok();
+    return fail(TG_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a)
+{
+    return (reinterpret_cast<uintptr_t>(p) % a) == 0;
+}
+
+size_t align_up(size_t x, size_t a)
+{
+    return (x + a - 1) / a * a;
+}
+
+tg_status check_buffers(const tg_grid_desc& d, const tg_grid_buffers& b)
+{
+    const void* ptrs[5] = {b.coeffs, b.master, b.grad, b.adam_m, b.adam_v};
+    for (int k = 0; k < 5; ++k)
+        if (ptrs[k] && !aligned(ptrs[k], 16))
+            return fail(TG_ERR_INVALID_ARG, "grid buffer %d is not 16-byte aligned", k);
+    if (d.storage == TG_F32 && b.coeffs && b.master && b.coeffs != b.master)
+        return fail(TG_ERR_INVALID_ARG, "with FP32 storage, coeffs and master must be the same buffer");
+    if (d.storage != TG_F32 && b.coeffs && b.master && b.coeffs == static_cast<const void*>(b.master))
+        return fail(TG_ERR_INVALID_ARG, "with 16-bit storage, coeffs and master must be different buffers");
+    return ok();
+}
+
+}  // namespace
+
+namespace tg {
+
+WsLayout ws_layout(const tg_grid* g, int64_t n)
+{
+    WsLayout L;
+    const int dim = g->desc.dim;
+    L.nkeys = 2 * g->nbricks;
+    L.nkeys_pad = (L.nkeys / kScanTile + 1) * kScanTile;
+    L.ntiles = L.nkeys_pad / kScanTile;
+    L.lds_path = L.nkeys <= kMaxLdsKeys;
+    L.sort_blocks = 0;
+    L.sort_slice = 0;
+    if (L.lds_path) {
+        int64_t nb = (n + 4095) / 4096;
+        nb = nb < 1 ? 1 : (nb > kMaxSortBlocks ? kMaxSortBlocks : nb);
+        L.sort_blocks = nb;
+        L.sort_slice = (n + nb - 1) / nb;
+    }
+    size_t off = 0;
+    L.reduce_off = off;
+    off = align_up(off + kReduceBytes, 256);
+    L.counts_off = off;
+    off = align_up(off + (size_t)L.nkeys_pad * 4, 256);
+    L.offs_off = off;
+    off = align_up(off + (size_t)L.nkeys_pad * 4, 256);
+    L.tiles_off = off;
+    off = align_up(off + (size_t)L.ntiles * 4, 256);
+    L.scratch_off = off;
+    off = align_up(off + (size_t)L.sort_blocks * (size_t)L.nkeys * 4, 256);
+    L.rec_off = off;
+    off = align_up(off + (size_t)n * ((size_t)1 << dim) * 16, 256);
+    L.total = off;
+    return L;
+}
+
+}  // namespace tg
+
+extern "C" {
+
+int32_t tg_coeffs_per_vertex(int32_t dim, int32_t order)
+{
+    if ((dim != 2 && dim != 3) || order < 0 || order > 2) return -1;
+    int64_t num = 1, den = 1;
+    for (int i = 1; i <= order; ++i) {
+        num *= dim + i;
+        den *= i;
+    }
+    return (int32_t)(num / den);
+}
+
+tg_status tg_create(const tg_grid_desc* desc, const tg_grid_buffers* bufs, tg_grid** out)
+{
+    if (!desc || !out) return fail(TG_ERR_INVALID_ARG, "tg_create: desc and out must not be NULL");
+    const tg_grid_desc d = *desc;
+    if (d.dim != 2 && d.dim != 3) return fail(TG_ERR_INVALID_ARG, "tg_create: dim must be 2 or 3 (got %d)", d.dim);
+    if (d.order < 0 || d.order > 2) return fail(TG_ERR_INVALID_ARG, "tg_create: order must be 0, 1 or 2 (got %d)", d.order);
+    if (d.storage != TG_F32 && d.storage != TG_BF16 && d.storage != TG_F16)
+        return fail(TG_ERR_INVALID_ARG, "tg_create: unknown storage type %d", d.storage);
+    int64_t nvert = 1;
+    for (int a = 0; a < d.dim; ++a) {
+        if (d.res[a] < 2 || d.res[a] > 65536)
+            return fail(TG_ERR_INVALID_ARG, "tg_create: res[%d] = %d outside [2, 65536]", a, d.res[a]);
+        if (!std::isfinite(d.lo[a]) || !std::isfinite(d.hi[a]) || !(d.hi[a] > d.lo[a]))
+            return fail(TG_ERR_INVALID_ARG, "tg_create: need finite lo[%d] < hi[%d]", a, a);
+        nvert *= d.res[a];
+    }
+    const int32_t C = tg_coeffs_per_vertex(d.dim, d.order);
+    if (nvert * C > ((int64_t)1 << 40)) return fail(TG_ERR_CAPACITY, "tg_create: grid too large");
+    tg_grid_buffers b;
+    memset(&b, 0, sizeof(b));
+    if (bufs) b = *bufs;
+    const tg_status bs = check_buffers(d, b);
+    if (bs != TG_OK) return bs;
+
+    tg_grid* g = new (std::nothrow) tg_grid;
+    if (!g) return fail(TG_ERR_CAPACITY, "tg_create: out of host memory");
+    memset(g, 0, sizeof(*g));
+    g->desc = d;
+    g->bufs = b;
+    g->C = C;
+    g->nvert = nvert;
+    constexpr int B3 = tg::BrickEdge<3>::value, B2 = tg::BrickEdge<2>::value;
+    const int B = d.dim == 3 ? B3 : B2;
+    int64_t nb = 1;
+    int64_t stride = 1;
+    for (int a = 0; a < 3; ++a) {
+        tg::Geom& G = g->geom;
+        if (a < d.dim) {
+            G.res[a] = d.res[a];
+            G.nvb[a] = (d.res[a] + B - 1) / B;
+            G.lo[a] = d.lo[a];
+            G.hi[a] = d.hi[a];
+            const double h = ((double)d.hi[a] - (double)d.lo[a]) / (double)(d.res[a] - 1);
+            G.h[a] = (float)h;
+            G.inv_h[a] = (float)(1.0 / h);
+            G.lo_d[a] = (double)d.lo[a];
+            G.inv_h_d[a] = 1.0 / h;
+            G.stride[a] = stride;
+            stride *= d.res[a];
+            nb *= G.nvb[a];
+        } else {
+            G.res[a] = 1;
+            G.nvb[a] = 1;
+            G.lo[a] = 0.0f;
+            G.hi[a] = 1.0f;
+            G.h[a] = 1.0f;
+            G.inv_h[a] = 1.0f;
+            G.lo_d[a] = 0.0;
+            G.inv_h_d[a] = 1.0;
+            G.stride[a] = stride;
+        }
+    }
+    g->nbricks = nb;
+    *out = g;
+    return ok();
+}
+
+tg_status tg_set_buffers(tg_grid* grid, const tg_grid_buffers* bufs)
+{
+    if (!grid || !bufs) return fail(TG_ERR_INVALID_ARG, "tg_set_buffers: NULL argument");
+    const tg_status bs = check_buffers(grid->desc, *bufs);
+    if (bs != TG_OK) return bs;
+    grid->bufs = *bufs;
+    return ok();
+}
+
+tg_status tg_destroy(tg_grid* grid)
+{
+    delete grid;
+    return ok();
+}
+
+size_t tg_reduce_workspace_bytes(void)
+{
+    return tg::kReduceBytes;
+}
+
+size_t tg_workspace_bytes(const tg_grid* grid, int64_t n)
+{
+    if (!grid || n < 0 || n > tg::kMaxQueries) return 0;
+    return tg::ws_layout(grid, n).total;
+}
+
+static tg_status check_queries(const char* fn, const tg_grid* grid, const float* q, int64_t n, const void* ws,
+                               size_t ws_bytes, tg::WsLayout* L)
+{
+    if (!grid) return fail(TG_ERR_INVALID_ARG, "%s: grid is NULL", fn);
+    if (n < 0) return fail(TG_ERR_INVALID_ARG, "%s: n = %lld is negative", fn, (long long)n);
+    if (n > tg::kMaxQueries) return fail(TG_ERR_CAPACITY, "%s: n = %lld exceeds %lld", fn, (long long)n, (long long)tg::kMaxQueries);
+    if (n > 0 && !q) return fail(TG_ERR_INVALID_ARG, "%s: q is NULL", fn);
+    if (!ws) return fail(TG_ERR_INVALID_ARG, "%s: workspace is NULL", fn);
+    if (!aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "%s: workspace must be 256-byte aligned", fn);
+    *L = tg::ws_layout(grid, n);
+    if (L->ntiles > tg::kMaxScanTiles) return fail(TG_ERR_UNSUPPORTED, "%s: grid has too many bricks to sort", fn);
+    if (ws_bytes < L->total)
+        return fail(TG_ERR_CAPACITY, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, L->total);
+    return ok();
+}
+
+static tg_status check_sorted(const char* fn, const tg_grid* grid, const float* q, int64_t n, const void* ws)
+{
+    if (!grid->sort_valid || grid->sort_q != q || grid->sort_n != n || grid->sort_ws != ws)
+        return fail(TG_ERR_STATE, "%s: workspace does not hold the sort of these queries (call tg_sort_queries first)", fn);
+    return ok();
+}
+
+tg_status tg_sort_queries(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes, void* stream)
+{
+    tg::WsLayout L;
+    tg_status st = check_queries("tg_sort_queries", grid, q, n, ws, ws_bytes, &L);
+    if (st != TG_OK) return st;
+    (void)hipGetLastError();
+    grid->sort_valid = false;
+    const hipError_t e = tg::launch_sort(grid, q, n, static_cast<char*>(ws), L, static_cast<hipStream_t>(stream));
+    st = device_status(e, "tg_sort_queries");
+    if (st == TG_OK) {
+        grid->sort_q = q;
+        grid->sort_n = n;
+        grid->sort_ws = ws;
+        grid->sort_valid = true;
+    }
+    return st;
+}
+
+tg_status tg_forward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes, float* f, float* grad_f,
+                     void* stream)
+{
+    tg::WsLayout L;
+    tg_status st = check_queries("tg_forward", grid, q, n, ws, ws_bytes, &L);
+    if (st != TG_OK) return st;
+    if (n > 0 && !f) return fail(TG_ERR_INVALID_ARG, "tg_forward: f is NULL");
+    if (!grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_forward: grid has no coeffs buffer");
+    st = check_sorted("tg_forward", grid, q, n, ws);
+    if (st != TG_OK) return st;
+    if (n == 0) return ok();
+    (void)hipGetLastError();
+    return device_status(tg::launch_forward(grid, n, static_cast<const char*>(ws), L, f, grad_f,
+                                            static_cast<hipStream_t>(stream)),
+                         "tg_forward");
+}
+
+tg_status tg_backward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes, const float* g_f,
+                      const float* g_grad, float* dq, int32_t flags, void* stream)
+{
+    tg::WsLayout L;
+    tg_status st = check_queries("tg_backward", grid, q, n, ws, ws_bytes, &L);
+    if (st != TG_OK) return st;
+    if (flags & ~TG_BWD_ACCUMULATE) return fail(TG_ERR_INVALID_ARG, "tg_backward: unknown flags 0x%x", flags);
+    if (!grid->bufs.grad) return fail(TG_ERR_INVALID_ARG, "tg_backward: grid has no grad buffer");
+    if (dq && !grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_backward: dq needs the coeffs buffer");
+    st = check_sorted("tg_backward", grid, q, n, ws);
+    if (st != TG_OK) return st;
+    const bool acc = (flags & TG_BWD_ACCUMULATE) != 0;
+    if (n == 0 && acc) return ok();
+    (void)hipGetLastError();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const char* w = static_cast<const char*>(ws);
+    hipError_t e = tg::launch_backward(grid, n, w, L, g_f, g_grad, acc, s);
+    if (e == hipSuccess && dq && n > 0) e = tg::launch_dq(grid, n, w, L, g_f, g_grad, dq, s);
+    return device_status(e, "tg_backward");
+}
+
+tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_f, const float* d, float eik_weight,
+                      float* g_f, float* g_grad, double* loss, void* ws, size_t ws_bytes, void* stream)
+{
+    if (dim != 2 && dim != 3) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: dim must be 2 or 3");
+    if (n < 0) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: n is negative");
+    if (n > 0 && (!f || !d || !g_f)) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: f, d and g_f must not be NULL");
+    if (n > 0 && grad_f && !g_grad) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: g_grad is NULL but grad_f is given");
+    if (!loss) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: loss is NULL");
+    if (!std::isfinite(eik_weight)) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: eik_weight is not finite");
+    if (!ws || !aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: workspace NULL or not 256-byte aligned");
+    if (ws_bytes < tg::kReduceBytes) return fail(TG_ERR_CAPACITY, "tg_sdf_loss: workspace smaller than %zu bytes", tg::kReduceBytes);
+    (void)hipGetLastError();
+    return device_status(tg::launch_sdf_loss(dim, n, f, grad_f, d, eik_weight, g_f, g_grad, loss,
+                                             static_cast<double*>(ws), static_cast<hipStream_t>(stream)),
+                         "tg_sdf_loss");
+}
+
+tg_status tg_adam_step(tg_grid* grid, const tg_adam_params* p, double* grad_norm_sq, void* ws, size_t ws_bytes,
+                       int32_t flags, void* stream)
+{
+    if (!grid || !p) return fail(TG_ERR_INVALID_ARG, "tg_adam_step: grid and params must not be NULL");
+    if (flags & ~TG_ADAM_ZERO_GRAD) return fail(TG_ERR_INVALID_ARG, "tg_adam_step: unknown flags 0x%x", flags);
+    const tg_grid_buffers& b = grid->bufs;
+    if (!b.master || !b.grad || !b.adam_m || !b.adam_v)
+        return fail(TG_ERR_INVALID_ARG, "tg_adam_step: master, grad, adam_m and adam_v are required");
+    if (grid->desc.storage != TG_F32 && !b.coeffs)
+        return fail(TG_ERR_INVALID_ARG, "tg_adam_step: 16-bit storage needs the coeffs buffer");
+    if (p->step < 1) return fail(TG_ERR_INVALID_ARG, "tg_adam_step: step must be >= 1");
+    if (!std::isfinite(p->lr) || !(p->beta1 >= 0.0f && p->beta1 < 1.0f) || !(p->beta2 >= 0.0f && p->beta2 < 1.0f) ||
+        !(p->eps >= 0.0f) || !std::isfinite(p->weight_decay))
+        return fail(TG_ERR_INVALID_ARG, "tg_adam_step: hyper-parameters out of range");
+    if (!ws || !aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "tg_adam_step: workspace NULL or not 256-byte aligned");
+    if (ws_bytes < tg::kReduceBytes) return fail(TG_ERR_CAPACITY, "tg_adam_step: workspace smaller than %zu bytes", tg::kReduceBytes);
+    (void)hipGetLastError();
+    return device_status(tg::launch_adam(grid, *p, grad_norm_sq, static_cast<double*>(ws), (flags & TG_ADAM_ZERO_GRAD) != 0,
+                                         static_cast<hipStream_t>(stream)),
+                         "tg_adam_step");
+}
+
+tg_status tg_query(const tg_grid* const* grids, int32_t n_grids, const tg_request* reqs, int32_t n_reqs, void* stream)
+{
+    if (n_reqs < 0) return fail(TG_ERR_INVALID_ARG, "tg_query: n_reqs is negative");
+    if (n_reqs == 0) return ok();
+    if (!grids || n_grids < 1 || !reqs) return fail(TG_ERR_INVALID_ARG, "tg_query: grids and reqs must not be NULL");
+    for (int32_t k = 0; k < n_grids; ++k)
+        if (!grids[k] || !grids[k]->bufs.coeffs)
+            return fail(TG_ERR_INVALID_ARG, "tg_query: grid %d is NULL or has no coeffs", k);
+    for (int32_t i = 0; i < n_reqs; ++i) {
+        const tg_request& r = reqs[i];
+        if (r.grid < 0 || r.grid >= n_grids) return fail(TG_ERR_INVALID_ARG, "tg_query: request %d names grid %d", i, r.grid);
+        if (r.n < 0 || r.n > 0x7fffffffLL) return fail(TG_ERR_INVALID_ARG, "tg_query: request %d has n = %lld", i, (long long)r.n);
+        if (r.n > 0 && (!r.q || !r.sdf)) return fail(TG_ERR_INVALID_ARG, "tg_query: request %d has a NULL q or sdf", i);
+    }
+    (void)hipGetLastError();
+    return device_status(tg::launch_query(grids, n_grids, reqs, n_reqs, static_cast<hipStream_t>(stream)), "tg_query");
+}
+
+const char* tg_status_string(tg_status status)
+{
+    switch (status) {
+    case TG_OK: return "ok";
+    case TG_ERR_INVALID_ARG: return "invalid argument";
+    case TG_ERR_UNSUPPORTED: return "unsupported";
+    case TG_ERR_DEVICE: return "device error";
+    case TG_ERR_CAPACITY: return "capacity exceeded";
+    case TG_ERR_STATE: return "workspace state mismatch";
+    }
+    return "unknown status";
+}
+
+const char* tg_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,318 @@
+// Device-side building blocks of the TaylorGrid query path for gfx950.
+//
+// The field of a TaylorGrid (arXiv 2402.14415, Sec. 3.1) at a point x is
+//   f(x) = sum over the 2^dim corners b of x's cell of  w_b(x) * T_b(x - v_b)      (Eq. 2-4)
+// where T_b is vertex v_b's stored Taylor polynomial (Eq. 1) and w_b the multilinear weight.
+// This header holds the pieces every kernel shares: the geometry passed to kernels, the
+// cell location, coefficient loads in the three storage types, and the per-corner Taylor
+// polynomial with its gradient.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace tg {
+
+// Cells per brick edge.  A brick is the unit of query bucketing, of LDS staging in the
+// forward, and of gradient ownership in the backward.
+template <int DIM> struct BrickEdge;
+template <> struct BrickEdge<3> { static constexpr int value = 8; };
+template <> struct BrickEdge<2> { static constexpr int value = 16; };
+
+// Coefficients per vertex: binom(DIM + K, K).
+template <int DIM, int K> struct NumCoeffs {
+    static constexpr int value = DIM == 3 ? (K == 0 ? 1 : K == 1 ? 4 : 10) : (K == 0 ? 1 : K == 1 ? 3 : 6);
+};
+
+enum StorageKind { ST_F32 = 0, ST_BF16 = 1, ST_F16 = 2 };
+
+// Geometry passed by value to every kernel.
+struct Geom {
+    int32_t res[3];     // vertices per axis
+    int32_t nvb[3];     // vertex bricks per axis = ceil(res / B)
+    float lo[3], hi[3];
+    float h[3];         // vertex spacing
+    float inv_h[3];
+    double lo_d[3];     // FP64 copies for the cell location
+    double inv_h_d[3];
+    int64_t stride[3];  // vertex strides (x fastest)
+};
+
+// Cell location of one query on one axis (Eq. 2).  The cell index is computed in FP64 so
+// that it agrees with an FP64 reference except for points within one FP64 rounding of a
+// face; every kernel calls this same function so the sort, the forward and the backward
+// always agree on a query's cell.
+struct AxisLoc {
+    int32_t cell;  // in [0, res - 2]
+    float t;       // local coordinate in [0, 1]
+    bool clamped;  // the query lay outside [lo, hi] on this axis
+};
+
+__device__ __forceinline__ AxisLoc locate_axis(float q, float lo, float hi, double lo_d,
+                                               double inv_h_d, int32_t res)
+{
+    AxisLoc L;
+    L.clamped = (q < lo) || (q > hi);
+    const float x = fminf(fmaxf(q, lo), hi);  // a NaN query lands on lo
+    const double s = __dmul_rn(__dsub_rn((double)x, lo_d), inv_h_d);
+    double fl = floor(s);
+    int32_t c = (int32_t)fl;
+    c = c < 0 ? 0 : c;
+    c = c > res - 2 ? res - 2 : c;
+    L.cell = c;
+    L.t = (float)__dsub_rn(s, (double)c);
+    return L;
+}
+
+template <int DIM>
+__device__ __forceinline__ void locate(const Geom& g, const float* q, AxisLoc* L)
+{
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) L[a] = locate_axis(q[a], g.lo[a], g.hi[a], g.lo_d[a], g.inv_h_d[a], g.res[a]);
+}
+
+// ------------------------------------------------------------------ storage conversions
+__device__ __forceinline__ float bf16_bits_to_float(uint32_t bits16)
+{
+    return __uint_as_float(bits16 << 16);
+}
+
+__device__ __forceinline__ uint16_t float_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float f16_bits_to_float(uint32_t bits16)
+{
+    return __half2float(__ushort_as_half((unsigned short)bits16));
+}
+
+__device__ __forceinline__ uint16_t float_to_f16_rne_sat(float f)
+{
+    // saturate finite values to the largest FP16 magnitude instead of overflowing to inf
+    if (f == f) f = fminf(fmaxf(f, -65504.0f), 65504.0f);
+    return (uint16_t)__half_as_ushort(__float2half_rn(f));
+}
+
+template <int ST> __device__ __forceinline__ float load_scalar(const void* base, int64_t i)
+{
+    if constexpr (ST == ST_F32) {
+        return static_cast<const float*>(base)[i];
+    } else if constexpr (ST == ST_BF16) {
+        return bf16_bits_to_float(static_cast<const uint16_t*>(base)[i]);
+    } else {
+        return f16_bits_to_float(static_cast<const uint16_t*>(base)[i]);
+    }
+}
+
+// Two consecutive coefficients starting at an even index i (8-byte aligned in FP32).
+template <int ST> __device__ __forceinline__ float2 load_pair(const void* base, int64_t i)
+{
+    if constexpr (ST == ST_F32) {
+        return *reinterpret_cast<const float2*>(static_cast<const float*>(base) + i);
+    } else {
+        const uint32_t v = *reinterpret_cast<const uint32_t*>(static_cast<const uint16_t*>(base) + i);
+        if constexpr (ST == ST_BF16) return make_float2(bf16_bits_to_float(v & 0xffffu), bf16_bits_to_float(v >> 16));
+        else return make_float2(f16_bits_to_float(v & 0xffffu), f16_bits_to_float(v >> 16));
+    }
+}
+
+// Load the C coefficients of one vertex from global memory (direct gather).
+template <int ST, int C>
+__device__ __forceinline__ void load_vertex(const void* base, int64_t vertex, float* out)
+{
+    const int64_t e0 = vertex * C;
+    if constexpr (ST == ST_F32) {
+        const float* p = static_cast<const float*>(base) + e0;
+        if constexpr (C % 2 == 0) {
+            // 8-byte aligned because C is even
+#pragma unroll
+            for (int k = 0; k < C; k += 2) {
+                float2 v = *reinterpret_cast<const float2*>(p + k);
+                out[k] = v.x;
+                out[k + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < C; ++k) out[k] = p[k];
+        }
+    } else {
+        const uint16_t* p = static_cast<const uint16_t*>(base) + e0;
+        if constexpr (C % 2 == 0) {
+#pragma unroll
+            for (int k = 0; k < C; k += 2) {
+                uint32_t v = *reinterpret_cast<const uint32_t*>(p + k);
+                if constexpr (ST == ST_BF16) {
+                    out[k] = bf16_bits_to_float(v & 0xffffu);
+                    out[k + 1] = bf16_bits_to_float(v >> 16);
+                } else {
+                    out[k] = f16_bits_to_float(v & 0xffffu);
+                    out[k + 1] = f16_bits_to_float(v >> 16);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < C; ++k) out[k] = load_scalar<ST>(base, e0 + k);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ Taylor polynomial
+// Value and gradient (in x) of sum_alpha c_alpha d^alpha / alpha!  at world offset d = x - v
+// (Eq. 1 truncated at order K, with the 1/2! of the quadratic terms; coefficients in
+// graded-lex order).
+template <int DIM, int K>
+__device__ __forceinline__ void taylor_eval(const float* c, const float* d, float& T, float* dT)
+{
+    if constexpr (K == 0) {
+        T = c[0];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) dT[a] = 0.0f;
+    } else if constexpr (K == 1) {
+        T = c[0];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            T = fmaf(c[1 + a], d[a], T);
+            dT[a] = c[1 + a];
+        }
+    } else if constexpr (DIM == 3) {
+        // c: f, gx, gy, gz, hxx, hxy, hxz, hyy, hyz, hzz
+        const float Hx = fmaf(c[4], d[0], fmaf(c[5], d[1], c[6] * d[2]));
+        const float Hy = fmaf(c[5], d[0], fmaf(c[7], d[1], c[8] * d[2]));
+        const float Hz = fmaf(c[6], d[0], fmaf(c[8], d[1], c[9] * d[2]));
+        dT[0] = c[1] + Hx;
+        dT[1] = c[2] + Hy;
+        dT[2] = c[3] + Hz;
+        // T = f + d.(g + H d / 2)
+        T = fmaf(d[0], fmaf(0.5f, Hx, c[1]), fmaf(d[1], fmaf(0.5f, Hy, c[2]), fmaf(d[2], fmaf(0.5f, Hz, c[3]), c[0])));
+    } else {
+        // c: f, gx, gy, hxx, hxy, hyy
+        const float Hx = fmaf(c[3], d[0], c[4] * d[1]);
+        const float Hy = fmaf(c[4], d[0], c[5] * d[1]);
+        dT[0] = c[1] + Hx;
+        dT[1] = c[2] + Hy;
+        T = fmaf(d[0], fmaf(0.5f, Hx, c[1]), fmaf(d[1], fmaf(0.5f, Hy, c[2]), c[0]));
+    }
+}
+
+// Second derivatives of one corner polynomial: the stored Hessian at order 2, else 0.
+// Returned in the order xx, xy, xz, yy, yz, zz (3D) or xx, xy, yy (2D).
+template <int DIM, int K>
+__device__ __forceinline__ void taylor_hess(const float* c, float* H)
+{
+    constexpr int NH = DIM == 3 ? 6 : 3;
+#pragma unroll
+    for (int k = 0; k < NH; ++k) H[k] = (K == 2) ? c[1 + DIM + k] : 0.0f;
+}
+
+// Per-axis interpolation factors of a located query: W[a][b] is the weight factor of the
+// corner with bit b on axis a (1 - t or t), Dw[a][b] its derivative in x, Dd[a][b] the
+// world offset x - v on that axis.
+template <int DIM> struct AxisFactors {
+    float W[DIM][2];
+    float Dw[DIM][2];
+    float Dd[DIM][2];
+};
+
+template <int DIM>
+__device__ __forceinline__ AxisFactors<DIM> axis_factors(const Geom& g, const AxisLoc* L)
+{
+    AxisFactors<DIM> F;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const float t = L[a].t;
+        F.W[a][0] = 1.0f - t;
+        F.W[a][1] = t;
+        F.Dw[a][0] = -g.inv_h[a];
+        F.Dw[a][1] = g.inv_h[a];
+        F.Dd[a][0] = t * g.h[a];
+        F.Dd[a][1] = (t - 1.0f) * g.h[a];
+    }
+    return F;
+}
+
+// Weight of corner b and its gradient.
+template <int DIM>
+__device__ __forceinline__ void corner_weight(const AxisFactors<DIM>& F, int b, float& w, float* dw)
+{
+    if constexpr (DIM == 3) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+        const float wyz = F.W[1][by] * F.W[2][bz];
+        w = F.W[0][bx] * wyz;
+        dw[0] = F.Dw[0][bx] * wyz;
+        dw[1] = F.W[0][bx] * F.Dw[1][by] * F.W[2][bz];
+        dw[2] = F.W[0][bx] * F.W[1][by] * F.Dw[2][bz];
+    } else {
+        const int bx = b & 1, by = (b >> 1) & 1;
+        w = F.W[0][bx] * F.W[1][by];
+        dw[0] = F.Dw[0][bx] * F.W[1][by];
+        dw[1] = F.W[0][bx] * F.Dw[1][by];
+    }
+}
+
+// Mixed second derivatives of corner b's weight: xy, xz, yz (3D) or xy (2D); the pure
+// second derivatives of a multilinear weight vanish.
+template <int DIM>
+__device__ __forceinline__ void corner_weight_d2(const AxisFactors<DIM>& F, int b, float* d2w)
+{
+    if constexpr (DIM == 3) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+        d2w[0] = F.Dw[0][bx] * F.Dw[1][by] * F.W[2][bz];
+        d2w[1] = F.Dw[0][bx] * F.W[1][by] * F.Dw[2][bz];
+        d2w[2] = F.W[0][bx] * F.Dw[1][by] * F.Dw[2][bz];
+    } else {
+        const int bx = b & 1, by = (b >> 1) & 1;
+        d2w[0] = F.Dw[0][bx] * F.Dw[1][by];
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ void corner_offset(const AxisFactors<DIM>& F, int b, float* d)
+{
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) d[a] = F.Dd[a][(b >> a) & 1];
+}
+
+// Adjoint of one corner: the contribution of a query to vertex v_b's coefficient alpha,
+//   m_alpha(d) * s + sum_a u_a dm_alpha/dd_a(d),  s = gf w + gg.dw,  u = w gg,
+// m_alpha(d) = d^alpha / alpha!.  Written into out[C].
+template <int DIM, int K>
+__device__ __forceinline__ void corner_adjoint(const float* d, float s, const float* u, float* out)
+{
+    out[0] = s;
+    if constexpr (K >= 1) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) out[1 + a] = fmaf(s, d[a], u[a]);
+    }
+    if constexpr (K == 2) {
+        if constexpr (DIM == 3) {
+            const float hx = 0.5f * d[0], hy = 0.5f * d[1], hz = 0.5f * d[2];
+            out[4] = fmaf(s * hx, d[0], u[0] * d[0]);                       // xx: d^2/2, grad (d, 0, 0)
+            out[5] = fmaf(s * d[0], d[1], fmaf(u[0], d[1], u[1] * d[0]));   // xy
+            out[6] = fmaf(s * d[0], d[2], fmaf(u[0], d[2], u[2] * d[0]));   // xz
+            out[7] = fmaf(s * hy, d[1], u[1] * d[1]);                       // yy
+            out[8] = fmaf(s * d[1], d[2], fmaf(u[1], d[2], u[2] * d[1]));   // yz
+            out[9] = fmaf(s * hz, d[2], u[2] * d[2]);                       // zz
+        } else {
+            const float hx = 0.5f * d[0], hy = 0.5f * d[1];
+            out[3] = fmaf(s * hx, d[0], u[0] * d[0]);                       // xx
+            out[4] = fmaf(s * d[0], d[1], fmaf(u[0], d[1], u[1] * d[0]));   // xy
+            out[5] = fmaf(s * hy, d[1], u[1] * d[1]);                       // yy
+        }
+    }
+}
+
+// Linear brick index (x fastest) of brick coordinates.
+template <int DIM>
+__device__ __forceinline__ int32_t brick_linear(const Geom& g, const int32_t* bc)
+{
+    if constexpr (DIM == 3) return (bc[2] * g.nvb[1] + bc[1]) * g.nvb[0] + bc[0];
+    else return bc[1] * g.nvb[0] + bc[0];
+}
+
+}  // namespace tg

@@ -1,0 +1,245 @@
+// TaylorGrid forward (value and spatial gradient) and the query adjoint dq, per brick.
+//
+// One workgroup per brick of B^dim cells.  It stages the (B+1)^dim vertex coefficient
+// blocks that the brick's cells touch into LDS as FP32 (converting BF16/FP16 storage on
+// the way), with coalesced row loads, then evaluates every query bucketed to the brick
+// (its primary records) reading corners from LDS:
+//   f = sum_b w_b T_b(d_b),  grad f = sum_b (grad w_b T_b + w_b grad T_b)      (Sec. 3.1, Eq. 2-4)
+// Results are written in the caller's query order.  The dq mode evaluates the field's
+// Hessian as well and writes dq = g_f grad f + Hess f . g_grad.
+#include "tg_internal.hpp"
+
+namespace tg {
+
+enum { MODE_FWD = 0, MODE_DQ = 1 };
+
+template <int C> struct LdsPad { static constexpr int value = C == 1 ? 1 : (C <= 4 ? 4 : (C <= 8 ? 8 : 12)); };
+
+template <int DIM> __device__ __forceinline__ void brick_coords(const Geom& g, int32_t brick, int32_t* bc)
+{
+    bc[0] = brick % g.nvb[0];
+    if constexpr (DIM == 3) {
+        const int32_t r = brick / g.nvb[0];
+        bc[1] = r % g.nvb[1];
+        bc[2] = r / g.nvb[1];
+    } else {
+        bc[1] = brick / g.nvb[0];
+    }
+}
+
+template <int CP>
+__device__ __forceinline__ void lds_vertex(const float* lds, int lv, float* c)
+{
+    if constexpr (CP == 1) {
+        c[0] = lds[lv];
+    } else {
+        const float4* p = reinterpret_cast<const float4*>(lds + lv * CP);
+#pragma unroll
+        for (int k = 0; k < CP / 4; ++k) {
+            const float4 v = p[k];
+            c[4 * k + 0] = v.x;
+            c[4 * k + 1] = v.y;
+            c[4 * k + 2] = v.z;
+            c[4 * k + 3] = v.w;
+        }
+    }
+}
+
+// Hessian entry index of (a, c) in the packed order xx, xy, xz, yy, yz, zz / xx, xy, yy.
+template <int DIM> __host__ __device__ constexpr int hidx(int a, int c)
+{
+    return DIM == 3 ? (a > c ? hidx<DIM>(c, a) : (a == 0 ? c : (a == 1 ? 2 + c : 5)))
+                    : (a > c ? hidx<DIM>(c, a) : (a == 0 ? c : 2));
+}
+
+template <int DIM, int K, int ST, int MODE>
+__global__ __launch_bounds__(kThreads) void k_forward(Geom g, int64_t nbricks, const void* __restrict__ coeffs,
+                                                     const float4* __restrict__ rec,
+                                                     const int32_t* __restrict__ offs,
+                                                     float* __restrict__ f_out, float* __restrict__ grad_out,
+                                                     const float* __restrict__ gf, const float* __restrict__ gg,
+                                                     float* __restrict__ dq_out)
+{
+    constexpr int B = BrickEdge<DIM>::value;
+    constexpr int C = NumCoeffs<DIM, K>::value;
+    constexpr int CP = LdsPad<C>::value;
+    constexpr int NV1 = B + 1;
+    constexpr int NROWS = DIM == 3 ? NV1 * NV1 : NV1;
+    constexpr int ROWLEN = NV1 * C;
+    constexpr int NH = DIM == 3 ? 6 : 3;
+    __shared__ __align__(16) float lds[NROWS * NV1 * CP];
+
+    // Each XCD (blocks are dealt round-robin to the 8 XCDs) gets a contiguous range of
+    // bricks, so the vertex layers neighbouring bricks share stay in one L2.
+    const int32_t per = (int32_t)((nbricks + 7) / 8);
+    const int32_t brick = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
+    if (brick >= nbricks) return;
+    const int32_t beg = offs[2 * brick];
+    const int32_t end = offs[2 * brick + 1];
+    if (beg == end) return;
+
+    int32_t bc[3];
+    brick_coords<DIM>(g, brick, bc);
+    int32_t v0[3], nv[3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        v0[a] = bc[a] * B;
+        nv[a] = min(B, g.res[a] - 1 - v0[a]) + 1;  // >= 2 for a brick that has queries
+    }
+
+    // Stage the brick's vertices: rows of NV1 vertices along x are contiguous in HBM.  With
+    // an even coefficient count a pair of coefficients never straddles two vertices, so
+    // rows are copied two coefficients per load.
+    if constexpr (C % 2 == 0) {
+        constexpr int RP = ROWLEN / 2;
+        for (int e = threadIdx.x; e < NROWS * RP; e += kThreads) {
+            const int row = e / RP;
+            const int rem = 2 * (e - row * RP);
+            const int vx = rem / C;
+            const int cc = rem - vx * C;
+            const int ry = DIM == 3 ? row % NV1 : row;
+            const int rz = DIM == 3 ? row / NV1 : 0;
+            bool ok = vx < nv[0] && ry < nv[1];
+            if constexpr (DIM == 3) ok = ok && rz < nv[2];
+            if (ok) {
+                int64_t vert = (int64_t)(v0[0] + vx) + (int64_t)(v0[1] + ry) * g.stride[1];
+                if constexpr (DIM == 3) vert += (int64_t)(v0[2] + rz) * g.stride[2];
+                *reinterpret_cast<float2*>(&lds[(row * NV1 + vx) * CP + cc]) = load_pair<ST>(coeffs, vert * C + cc);
+            }
+        }
+    } else {
+        for (int e = threadIdx.x; e < NROWS * ROWLEN; e += kThreads) {
+            const int row = e / ROWLEN;
+            const int rem = e - row * ROWLEN;
+            const int vx = rem / C;
+            const int cc = rem - vx * C;
+            const int ry = DIM == 3 ? row % NV1 : row;
+            const int rz = DIM == 3 ? row / NV1 : 0;
+            bool ok = vx < nv[0] && ry < nv[1];
+            if constexpr (DIM == 3) ok = ok && rz < nv[2];
+            if (ok) {
+                int64_t vert = (int64_t)(v0[0] + vx) + (int64_t)(v0[1] + ry) * g.stride[1];
+                if constexpr (DIM == 3) vert += (int64_t)(v0[2] + rz) * g.stride[2];
+                lds[(row * NV1 + vx) * CP + cc] = load_scalar<ST>(coeffs, vert * C + cc);
+            }
+        }
+    }
+    __syncthreads();
+
+    for (int32_t j = beg + threadIdx.x; j < end; j += kThreads) {
+        const float4 r = rec[j];
+        const float q[3] = {r.x, r.y, r.z};
+        const int32_t idx = __float_as_int(r.w);
+        AxisLoc L[DIM];
+        locate<DIM>(g, q, L);
+        int lc[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) lc[a] = min(max(L[a].cell - v0[a], 0), nv[a] - 2);
+        const AxisFactors<DIM> F = axis_factors<DIM>(g, L);
+
+        float f = 0.0f;
+        float gr[DIM];
+        float hf[NH];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) gr[a] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < NH; ++k) hf[k] = 0.0f;
+
+#pragma unroll
+        for (int b = 0; b < (1 << DIM); ++b) {
+            int lv = lc[0] + (b & 1) + NV1 * (lc[1] + ((b >> 1) & 1));
+            if constexpr (DIM == 3) lv += NV1 * NV1 * (lc[2] + ((b >> 2) & 1));
+            float c[CP];
+            lds_vertex<CP>(lds, lv, c);
+            float d[DIM];
+            corner_offset<DIM>(F, b, d);
+            float T, dT[DIM];
+            taylor_eval<DIM, K>(c, d, T, dT);
+            float w, dw[DIM];
+            corner_weight<DIM>(F, b, w, dw);
+            f = fmaf(w, T, f);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) gr[a] = fmaf(dw[a], T, fmaf(w, dT[a], gr[a]));
+            if constexpr (MODE == MODE_DQ) {
+                float H[NH];
+                taylor_hess<DIM, K>(c, H);
+                float d2w[DIM == 3 ? 3 : 1];
+                corner_weight_d2<DIM>(F, b, d2w);
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+                    for (int cc = a; cc < DIM; ++cc) {
+                        const int k = hidx<DIM>(a, cc);
+                        float v = fmaf(w, H[k], fmaf(dw[a], dT[cc], dw[cc] * dT[a]));
+                        if (a != cc) {
+                            const int m = DIM == 3 ? (a == 0 ? cc - 1 : 2) : 0;  // xy, xz, yz
+                            v = fmaf(d2w[m], T, v);
+                        }
+                        hf[k] += v;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+            if (L[a].clamped) gr[a] = 0.0f;
+
+        if constexpr (MODE == MODE_FWD) {
+            f_out[idx] = f;
+            if (grad_out) {
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) grad_out[(int64_t)idx * DIM + a] = gr[a];
+            }
+        } else {
+            const float sf = gf ? gf[idx] : 0.0f;
+            float sg[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) sg[a] = (gg && !L[a].clamped) ? gg[(int64_t)idx * DIM + a] : 0.0f;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                float v = sf * gr[a];
+#pragma unroll
+                for (int cc = 0; cc < DIM; ++cc) v = fmaf(sg[cc], hf[hidx<DIM>(a, cc)], v);
+                dq_out[(int64_t)idx * DIM + a] = L[a].clamped ? 0.0f : v;
+            }
+        }
+    }
+}
+
+template <int MODE>
+static hipError_t dispatch(const tg_grid* g, const char* ws, const WsLayout& L, float* f, float* grad_f,
+                           const float* gf, const float* gg, float* dq, hipStream_t s)
+{
+    const float4* rec = reinterpret_cast<const float4*>(ws + L.rec_off);
+    const int32_t* offs = reinterpret_cast<const int32_t*>(ws + L.offs_off);
+    const dim3 grid((unsigned)(8 * ((g->nbricks + 7) / 8))), block(kThreads);
+    const void* cf = g->bufs.coeffs;
+    const int dim = g->desc.dim, K = g->desc.order, st = g->desc.storage;
+#define TG_FWD_CASE(D, KK, ST)                                                                          \
+    if (dim == D && K == KK && st == ST) {                                                              \
+        hipLaunchKernelGGL((k_forward<D, KK, ST, MODE>), grid, block, 0, s, g->geom, g->nbricks, cf, rec, offs, f, \
+                           grad_f, gf, gg, dq);                                                         \
+        return hipGetLastError();                                                                       \
+    }
+#define TG_FWD_ST(D, KK) TG_FWD_CASE(D, KK, ST_F32) TG_FWD_CASE(D, KK, ST_BF16) TG_FWD_CASE(D, KK, ST_F16)
+    TG_FWD_ST(3, 2) TG_FWD_ST(3, 1) TG_FWD_ST(3, 0) TG_FWD_ST(2, 2) TG_FWD_ST(2, 1) TG_FWD_ST(2, 0)
+#undef TG_FWD_ST
+#undef TG_FWD_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_forward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, float* f,
+                          float* grad_f, hipStream_t s)
+{
+    (void)n;
+    return dispatch<MODE_FWD>(g, ws, L, f, grad_f, nullptr, nullptr, nullptr, s);
+}
+
+hipError_t launch_dq(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
+                     const float* g_grad, float* dq, hipStream_t s)
+{
+    (void)n;
+    return dispatch<MODE_DQ>(g, ws, L, nullptr, nullptr, g_f, g_grad, dq, s);
+}
+
+}  // namespace tg

@@ -1,0 +1,74 @@
+// Host-side internals shared by the C-ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "taylorgrid.h"
+#include "tg_device.hpp"
+
+struct tg_grid {
+    tg_grid_desc desc;
+    tg_grid_buffers bufs;
+    tg::Geom geom;
+    int32_t C;          // coefficients per vertex
+    int64_t nvert;      // vertices
+    int64_t nbricks;    // vertex bricks (launch size of the forward and backward)
+    // last sort written by tg_sort_queries on this handle
+    const float* sort_q;
+    int64_t sort_n;
+    const void* sort_ws;
+    bool sort_valid;
+};
+
+namespace tg {
+
+constexpr int kThreads = 256;
+constexpr int kSortThreads = 1024;       // threads per block of the LDS-histogram sort
+constexpr int32_t kMaxLdsKeys = 16384;   // keys whose LDS histogram fits 64 KB
+constexpr int kMaxSortBlocks = 128;
+constexpr int kMaxReduceBlocks = 2048;  // FP64 partials: 4 per block
+constexpr size_t kReduceBytes = (size_t)kMaxReduceBlocks * 4 * sizeof(double);
+constexpr int kScanTile = 4096;          // keys per scan tile (256 threads x 16)
+constexpr int64_t kMaxScanTiles = 4096;  // one workgroup scans the tile totals
+constexpr int64_t kMaxQueries = (int64_t)1 << 28;  // sort entries stay below 2^31
+
+// Workspace layout of one grid for n queries.  Offsets are from the workspace base and
+// 256-byte aligned.
+struct WsLayout {
+    size_t reduce_off;   // FP64 reduction partials (tg_sdf_loss, tg_adam_step)
+    size_t counts_off;   // int32 [nkeys_pad]: per-key totals, or counts then cursors (atomic path)
+    size_t offs_off;     // int32 [nkeys_pad]: exclusive bucket offsets (+ total at [nkeys])
+    size_t tiles_off;    // int32 [ntiles]: scan tile totals, or the block-arrival counter
+    size_t scratch_off;  // int32 [sort_blocks x nkeys]: per-block key counts, then offsets
+    size_t rec_off;      // float4 [n * 2^dim]: sorted query records (x, y, z, index bits)
+    size_t total;
+    int64_t nkeys;       // 2 * nbricks (primary / secondary bucket of every vertex brick)
+    int64_t nkeys_pad;   // multiple of kScanTile, > nkeys
+    int64_t ntiles;
+    bool lds_path;       // sort with LDS histograms (else global atomic counters)
+    int64_t sort_blocks; // blocks of the LDS-histogram sort
+    int64_t sort_slice;  // queries per sort block
+};
+
+WsLayout ws_layout(const tg_grid* g, int64_t n);
+
+// Kernel launchers (return the launch status).
+hipError_t launch_sort(const tg_grid* g, const float* q, int64_t n, char* ws, const WsLayout& L,
+                       hipStream_t s);
+hipError_t launch_forward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, float* f,
+                          float* grad_f, hipStream_t s);
+hipError_t launch_dq(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
+                     const float* g_grad, float* dq, hipStream_t s);
+hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L,
+                           const float* g_f, const float* g_grad, bool accumulate, hipStream_t s);
+hipError_t launch_sdf_loss(int dim, int64_t n, const float* f, const float* grad_f, const float* d,
+                           float eik_weight, float* g_f, float* g_grad, double* loss, double* partials,
+                           hipStream_t s);
+hipError_t launch_adam(const tg_grid* g, const tg_adam_params& p, double* grad_norm_sq, double* partials,
+                       bool zero_grad, hipStream_t s);
+hipError_t launch_query(const tg_grid* const* grids, int32_t n_grids, const tg_request* reqs, int32_t n_reqs,
+                        hipStream_t s);
+
+}  // namespace tg

@@ -1,0 +1,229 @@
+// SDF objective (upstream gradients + FP64 loss) and the fused Adam step.
+//
+// Both are streaming kernels: grid-stride over their elements, FP64 per-block partial sums
+// written to the reduction scratch, then a one-block kernel that adds the partials in a
+// fixed order (deterministic FP64 result on the device).
+#include "tg_internal.hpp"
+
+namespace tg {
+
+// Sum of one double across the block (256 threads); valid in thread 0.
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double part[kThreads / 64];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) part[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kThreads / 64; ++w) r += part[w];
+    return r;
+}
+
+static inline unsigned reduce_blocks(int64_t n, int per_thread)
+{
+    int64_t b = (n + (int64_t)kThreads * per_thread - 1) / ((int64_t)kThreads * per_thread);
+    if (b < 1) b = 1;
+    if (b > kMaxReduceBlocks) b = kMaxReduceBlocks;
+    return (unsigned)b;
+}
+
+// ------------------------------------------------------------------ SDF loss (Eq. 6, Eq. 8)
+template <int DIM, bool EIK>
+__global__ __launch_bounds__(kThreads) void k_sdf_loss(int64_t n, const float* __restrict__ f,
+                                                      const float* __restrict__ grad, const float* __restrict__ d,
+                                                      float w_eik, float inv_n, float* __restrict__ gf,
+                                                      float* __restrict__ gg, double* __restrict__ partials)
+{
+    double acc_r = 0.0, acc_e = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const float r = f[i] - d[i];
+        acc_r += (double)fabsf(r);
+        gf[i] = r > 0.0f ? inv_n : (r < 0.0f ? -inv_n : 0.0f);
+        if constexpr (EIK) {
+            float g[DIM];
+            float n2 = 0.0f;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                g[a] = grad[i * DIM + a];
+                n2 = fmaf(g[a], g[a], n2);
+            }
+            const float nrm = sqrtf(n2);
+            const float e = nrm - 1.0f;
+            acc_e += (double)e * (double)e;
+            const float k = nrm > 0.0f ? 2.0f * w_eik * e / nrm * inv_n : 0.0f;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) gg[i * DIM + a] = k * g[a];
+        }
+    }
+    const double sr = block_sum(acc_r);
+    const double se = block_sum(acc_e);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x + 0] = sr;
+        partials[2 * blockIdx.x + 1] = se;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_loss_finish(const double* __restrict__ partials, int nblocks,
+                                                         double inv_n, double w_eik, double* __restrict__ loss)
+{
+    double sr = 0.0, se = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kThreads) {
+        sr += partials[2 * b];
+        se += partials[2 * b + 1];
+    }
+    sr = block_sum(sr);
+    se = block_sum(se);
+    if (threadIdx.x == 0) {
+        loss[1] = sr * inv_n;
+        loss[2] = se * inv_n;
+        loss[0] = loss[1] + w_eik * loss[2];
+    }
+}
+
+hipError_t launch_sdf_loss(int dim, int64_t n, const float* f, const float* grad_f, const float* d, float eik_weight,
+                           float* g_f, float* g_grad, double* loss, double* partials, hipStream_t s)
+{
+    const unsigned nb = reduce_blocks(n, 4);
+    const float inv_n = n > 0 ? (float)(1.0 / (double)n) : 0.0f;
+    const dim3 grid(nb), block(kThreads);
+    if (grad_f) {
+        if (dim == 3)
+            hipLaunchKernelGGL((k_sdf_loss<3, true>), grid, block, 0, s, n, f, grad_f, d, eik_weight, inv_n, g_f, g_grad, partials);
+        else
+            hipLaunchKernelGGL((k_sdf_loss<2, true>), grid, block, 0, s, n, f, grad_f, d, eik_weight, inv_n, g_f, g_grad, partials);
+    } else {
+        hipLaunchKernelGGL((k_sdf_loss<3, false>), grid, block, 0, s, n, f, grad_f, d, eik_weight, inv_n, g_f, g_grad, partials);
+    }
+    const double w = grad_f ? (double)eik_weight : 0.0;
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), block, 0, s, partials, (int)nb, n > 0 ? 1.0 / (double)n : 0.0, w, loss);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Adam
+struct AdamArgs {
+    float lr_over_bc1;       // lr / (1 - beta1^t)
+    float inv_sqrt_bc2;      // 1 / sqrt(1 - beta2^t)
+    float beta1, beta2, one_minus_beta1, one_minus_beta2, eps, wd;
+};
+
+__device__ __forceinline__ float adam_elem(const AdamArgs& A, float g, float& th, float& m, float& v)
+{
+    const float gp = fmaf(A.wd, th, g);
+    m = fmaf(A.beta1, m, A.one_minus_beta1 * gp);
+    v = fmaf(A.beta2, v, A.one_minus_beta2 * gp * gp);
+    const float denom = fmaf(sqrtf(v), A.inv_sqrt_bc2, A.eps);
+    th = th - A.lr_over_bc1 * (m / denom);
+    return th;
+}
+
+template <int ST>
+__device__ __forceinline__ void store_copy(void* coeffs, int64_t i, float v)
+{
+    if constexpr (ST == ST_BF16) static_cast<uint16_t*>(coeffs)[i] = float_to_bf16_rne(v);
+    else if constexpr (ST == ST_F16) static_cast<uint16_t*>(coeffs)[i] = float_to_f16_rne_sat(v);
+}
+
+// Vectorised by 4 over the first n4*4 elements; the scalar tail is handled by block 0.
+template <int ST>
+__global__ __launch_bounds__(kThreads) void k_adam(int64_t n, AdamArgs A, float* __restrict__ master,
+                                                  float* __restrict__ mom1, float* __restrict__ mom2,
+                                                  float* __restrict__ grad, void* __restrict__ coeffs,
+                                                  int zero_grad, double* __restrict__ partials)
+{
+    double ss = 0.0;
+    const int64_t n4 = n / 4;
+    float4* th4 = reinterpret_cast<float4*>(master);
+    float4* m4 = reinterpret_cast<float4*>(mom1);
+    float4* v4 = reinterpret_cast<float4*>(mom2);
+    float4* g4 = reinterpret_cast<float4*>(grad);
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n4; i += (int64_t)gridDim.x * kThreads) {
+        float4 t = th4[i], m = m4[i], v = v4[i];
+        const float4 g = g4[i];
+        ss += (double)g.x * g.x + (double)g.y * g.y + (double)g.z * g.z + (double)g.w * g.w;
+        adam_elem(A, g.x, t.x, m.x, v.x);
+        adam_elem(A, g.y, t.y, m.y, v.y);
+        adam_elem(A, g.z, t.z, m.z, v.z);
+        adam_elem(A, g.w, t.w, m.w, v.w);
+        th4[i] = t;
+        m4[i] = m;
+        v4[i] = v;
+        if (zero_grad) g4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if constexpr (ST != ST_F32) {
+            if constexpr (ST == ST_BF16) {
+                const uint2 packed = make_uint2((uint32_t)float_to_bf16_rne(t.x) | ((uint32_t)float_to_bf16_rne(t.y) << 16),
+                                                (uint32_t)float_to_bf16_rne(t.z) | ((uint32_t)float_to_bf16_rne(t.w) << 16));
+                reinterpret_cast<uint2*>(coeffs)[i] = packed;
+            } else {
+                const uint2 packed = make_uint2((uint32_t)float_to_f16_rne_sat(t.x) | ((uint32_t)float_to_f16_rne_sat(t.y) << 16),
+                                                (uint32_t)float_to_f16_rne_sat(t.z) | ((uint32_t)float_to_f16_rne_sat(t.w) << 16));
+                reinterpret_cast<uint2*>(coeffs)[i] = packed;
+            }
+        }
+    }
+    if (blockIdx.x == 0) {
+        for (int64_t i = n4 * 4 + threadIdx.x; i < n; i += kThreads) {
+            float t = master[i], m = mom1[i], v = mom2[i];
+            const float g = grad[i];
+            ss += (double)g * g;
+            adam_elem(A, g, t, m, v);
+            master[i] = t;
+            mom1[i] = m;
+            mom2[i] = v;
+            if (zero_grad) grad[i] = 0.0f;
+            store_copy<ST>(coeffs, i, t);
+        }
+    }
+    const double tot = block_sum(ss);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sum_finish(const double* __restrict__ partials, int nblocks,
+                                                        double* __restrict__ out)
+{
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kThreads) s += partials[b];
+    s = block_sum(s);
+    if (threadIdx.x == 0) *out = s;
+}
+
+hipError_t launch_adam(const tg_grid* g, const tg_adam_params& p, double* grad_norm_sq, double* partials,
+                       bool zero_grad, hipStream_t s)
+{
+    const int64_t n = g->nvert * g->C;
+    const double bc1 = 1.0 - pow((double)p.beta1, (double)p.step);
+    const double bc2 = 1.0 - pow((double)p.beta2, (double)p.step);
+    AdamArgs A;
+    A.lr_over_bc1 = (float)((double)p.lr / bc1);
+    A.inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
+    A.beta1 = p.beta1;
+    A.beta2 = p.beta2;
+    A.one_minus_beta1 = (float)(1.0 - (double)p.beta1);
+    A.one_minus_beta2 = (float)(1.0 - (double)p.beta2);
+    A.eps = p.eps;
+    A.wd = p.weight_decay;
+    const unsigned nb = reduce_blocks(n / 4 + 1, 8);
+    const dim3 grid(nb), block(kThreads);
+    const int zg = zero_grad ? 1 : 0;
+    switch (g->desc.storage) {
+    case ST_F32:
+        hipLaunchKernelGGL(k_adam<ST_F32>, grid, block, 0, s, n, A, g->bufs.master, g->bufs.adam_m, g->bufs.adam_v,
+                           g->bufs.grad, g->bufs.coeffs, zg, partials);
+        break;
+    case ST_BF16:
+        hipLaunchKernelGGL(k_adam<ST_BF16>, grid, block, 0, s, n, A, g->bufs.master, g->bufs.adam_m, g->bufs.adam_v,
+                           g->bufs.grad, g->bufs.coeffs, zg, partials);
+        break;
+    default:
+        hipLaunchKernelGGL(k_adam<ST_F16>, grid, block, 0, s, n, A, g->bufs.master, g->bufs.adam_m, g->bufs.adam_v,
+                           g->bufs.grad, g->bufs.coeffs, zg, partials);
+        break;
+    }
+    if (grad_norm_sq) hipLaunchKernelGGL(k_sum_finish, dim3(1), block, 0, s, partials, (int)nb, grad_norm_sq);
+    return hipGetLastError();
+}
+
+}  // namespace tg

@@ -1,0 +1,232 @@
+"""Python surface of the TaylorGrid library: a grid that owns its device tensors.
+
+Every call marshals torch tensors into the C ABI (include/taylorgrid.h) and enqueues the
+HIP kernels on torch's current stream; no arithmetic of the method runs in Python.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+_STORAGE = {"f32": (_lib.TG_F32, torch.float32), "bf16": (_lib.TG_BF16, torch.bfloat16),
+            "f16": (_lib.TG_F16, torch.float16)}
+
+
+def coeffs_per_vertex(dim: int, order: int) -> int:
+    c = _lib.lib().tg_coeffs_per_vertex(dim, order)
+    if c < 0:
+        raise ValueError(f"unsupported dim={dim} order={order}")
+    return int(c)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_tensor(name, t, dtype, device, numel=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+class TaylorGrid:
+    """A dense TaylorGrid (arXiv 2402.14415, Sec. 3.1) with its optimiser state on one GPU.
+
+    Tensors (all [res_z, res_y, res_x, C] or [res_y, res_x, C]):
+      master  FP32 coefficients (the optimised parameters)
+      coeffs  storage copy read by the kernels (== master for f32 storage)
+      grad    FP32 gradient written by ``backward``
+      adam_m, adam_v  FP32 Adam moments
+    """
+
+    def __init__(self, dim, res, order, lo, hi, storage="f32", device="cuda", coeffs=None, optimizer=True):
+        self.dim = int(dim)
+        res = [int(r) for r in (res if hasattr(res, "__len__") else [res] * self.dim)]
+        self.res = tuple(res[: self.dim])
+        self.order = int(order)
+        lo = [float(v) for v in (lo if hasattr(lo, "__len__") else [lo] * self.dim)]
+        hi = [float(v) for v in (hi if hasattr(hi, "__len__") else [hi] * self.dim)]
+        self.lo = tuple(lo[: self.dim])
+        self.hi = tuple(hi[: self.dim])
+        self.storage = storage
+        st, sdt = _STORAGE[storage]
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.C = coeffs_per_vertex(self.dim, self.order)
+        self.shape = tuple(reversed(self.res)) + (self.C,)
+
+        if coeffs is not None:
+            master = torch.as_tensor(coeffs).to(device=self.device, dtype=torch.float32).reshape(self.shape).contiguous()
+        else:
+            master = torch.zeros(self.shape, dtype=torch.float32, device=self.device)
+        self.master = master
+        self.coeffs = master if storage == "f32" else master.to(sdt)
+        self.grad = torch.zeros_like(master)
+        if optimizer:
+            self.adam_m = torch.zeros_like(master)
+            self.adam_v = torch.zeros_like(master)
+        else:
+            self.adam_m = self.adam_v = None
+        self.step_count = 0
+
+        desc = _lib.GridDesc()
+        desc.dim = self.dim
+        desc.order = self.order
+        desc.storage = st
+        for a in range(3):
+            desc.res[a] = self.res[a] if a < self.dim else 1
+            desc.lo[a] = self.lo[a] if a < self.dim else 0.0
+            desc.hi[a] = self.hi[a] if a < self.dim else 1.0
+        self._desc = desc
+        handle = ctypes.c_void_p()
+        _lib.call("tg_create", ctypes.byref(desc), ctypes.byref(self._buffers()), ctypes.byref(handle))
+        self._h = handle
+        self._sorted = None  # (q tensor, ws tensor) of the last sort
+
+    # ------------------------------------------------------------------ plumbing
+    def _buffers(self, grad=None):
+        b = _lib.GridBuffers()
+        b.coeffs = self.coeffs.data_ptr()
+        b.master = self.master.data_ptr()
+        b.grad = (self.grad if grad is None else grad).data_ptr()
+        b.adam_m = self.adam_m.data_ptr() if self.adam_m is not None else None
+        b.adam_v = self.adam_v.data_ptr() if self.adam_v is not None else None
+        return b
+
+    def rebind(self, grad=None):
+        """Point the handle at the current tensors (after replacing one of them)."""
+        _lib.call("tg_set_buffers", self._h, ctypes.byref(self._buffers(grad)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib._lib is not None:
+            _lib.lib().tg_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sync_storage(self):
+        """Refresh the storage copy from the master (round to nearest even)."""
+        if self.storage != "f32":
+            self.coeffs.copy_(self.master.to(self.coeffs.dtype))
+
+    def workspace_bytes(self, n):
+        return int(_lib.lib().tg_workspace_bytes(self._h, int(n)))
+
+    def workspace(self, n):
+        """A device workspace for n queries (sort + reduction scratch)."""
+        return torch.empty(self.workspace_bytes(n), dtype=torch.uint8, device=self.device)
+
+    def _q(self, q):
+        _check_tensor("q", q, torch.float32, self.device)
+        if q.dim() != 2 or q.shape[1] != self.dim:
+            raise ValueError(f"q must be [n, {self.dim}]")
+        return q.shape[0]
+
+    # ------------------------------------------------------------------ hot path
+    def sort(self, q, ws):
+        n = self._q(q)
+        _lib.call("tg_sort_queries", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _stream(self.device))
+        self._sorted = (q, ws)
+
+    def ensure_sorted(self, q, ws):
+        if self._sorted is None or self._sorted[0] is not q or self._sorted[1] is not ws:
+            self.sort(q, ws)
+
+    def forward(self, q, ws, want_grad=True, out=None):
+        """f [n] and grad f [n, dim] (or None)."""
+        n = self._q(q)
+        if out is None:
+            f = torch.empty(n, dtype=torch.float32, device=self.device)
+            g = torch.empty((n, self.dim), dtype=torch.float32, device=self.device) if want_grad else None
+        else:
+            f, g = out
+        _lib.call("tg_forward", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _ptr(f), _ptr(g), _stream(self.device))
+        return f, g
+
+    def backward(self, q, ws, g_f=None, g_grad=None, want_dq=False, accumulate=False, grad_out=None, dq_out=None):
+        """Writes (or accumulates) dL/dC into ``grad`` (or ``grad_out``); returns dq or None."""
+        n = self._q(q)
+        if g_f is not None:
+            _check_tensor("g_f", g_f, torch.float32, self.device, n)
+        if g_grad is not None:
+            _check_tensor("g_grad", g_grad, torch.float32, self.device, n * self.dim)
+        dq = None
+        if want_dq:
+            dq = dq_out if dq_out is not None else torch.empty((n, self.dim), dtype=torch.float32, device=self.device)
+        flags = _lib.TG_BWD_ACCUMULATE if accumulate else 0
+        if grad_out is not None:
+            _check_tensor("grad_out", grad_out, torch.float32, self.device, self.master.numel())
+            self.rebind(grad=grad_out)
+        try:
+            _lib.call("tg_backward", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _ptr(g_f), _ptr(g_grad), _ptr(dq),
+                      flags, _stream(self.device))
+        finally:
+            if grad_out is not None:
+                self.rebind()
+        return dq
+
+    def adam_step(self, ws, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0, grad_norm_sq=None,
+                  zero_grad=False, step=None):
+        """One fused Adam step; grad_norm_sq (device float64 [1]) receives sum(grad^2)."""
+        if self.adam_m is None:
+            raise RuntimeError("grid was created without optimiser state")
+        self.step_count = self.step_count + 1 if step is None else int(step)
+        p = _lib.AdamParams(lr, betas[0], betas[1], eps, weight_decay, self.step_count)
+        if grad_norm_sq is not None:
+            _check_tensor("grad_norm_sq", grad_norm_sq, torch.float64, self.device)
+        flags = _lib.TG_ADAM_ZERO_GRAD if zero_grad else 0
+        _lib.call("tg_adam_step", self._h, ctypes.byref(p), _ptr(grad_norm_sq), _ptr(ws), ws.numel(), flags,
+                  _stream(self.device))
+
+
+def sdf_loss(f, grad_f, d, eik_weight, ws, g_f=None, g_grad=None, loss=None):
+    """L1 + eikonal SDF objective; returns (loss float64[3] on device, g_f, g_grad)."""
+    n = f.numel()
+    dev = f.device
+    dim = grad_f.shape[1] if grad_f is not None else 3
+    g_f = torch.empty(n, dtype=torch.float32, device=dev) if g_f is None else g_f
+    if grad_f is not None and g_grad is None:
+        g_grad = torch.empty((n, dim), dtype=torch.float32, device=dev)
+    loss = torch.empty(3, dtype=torch.float64, device=dev) if loss is None else loss
+    _check_tensor("f", f, torch.float32, dev)
+    _check_tensor("d", d, torch.float32, dev, n)
+    if grad_f is not None:
+        _check_tensor("grad_f", grad_f, torch.float32, dev, n * dim)
+    _lib.call("tg_sdf_loss", dim, n, _ptr(f), _ptr(grad_f), _ptr(d), float(eik_weight), _ptr(g_f),
+              _ptr(g_grad) if grad_f is not None else None, _ptr(loss), _ptr(ws), ws.numel(), _stream(dev))
+    return loss, g_f, g_grad
+
+
+def query(grids, requests, stream=None):
+    """Serve a batch: ``requests`` is a list of (grid index, q, sdf_out, normal_out or None)."""
+    if not requests:
+        return
+    dev = requests[0][1].device
+    hs = (ctypes.c_void_p * len(grids))(*[g.handle.value for g in grids])
+    reqs = (_lib.Request * len(requests))()
+    for i, (gi, q, sdf, normal) in enumerate(requests):
+        reqs[i].grid = gi
+        reqs[i].n = q.shape[0]
+        reqs[i].q = q.data_ptr() if q.numel() else None
+        reqs[i].sdf = sdf.data_ptr() if sdf.numel() else None
+        reqs[i].normal = normal.data_ptr() if (normal is not None and normal.numel()) else None
+    s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(dev)
+    _lib.call("tg_query", hs, len(grids), reqs, len(requests), s)

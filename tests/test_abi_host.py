@@ -1,0 +1,171 @@
+"""Host-side contract of the C ABI (no GPU needed: every call here fails validation before
+anything is enqueued, or is a pure host function)."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2402_14415_amd import _lib
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH), reason="libtaylorgrid.so not built")
+
+
+def L():
+    return _lib.lib()
+
+
+def _desc(dim=3, res=(16, 16, 16), order=2, lo=(-1, -1, -1), hi=(1, 1, 1), storage=0):
+    d = _lib.GridDesc()
+    d.dim = dim
+    d.order = order
+    d.storage = storage
+    for a in range(3):
+        d.res[a] = res[a] if a < len(res) else 1
+        d.lo[a] = lo[a] if a < len(lo) else 0
+        d.hi[a] = hi[a] if a < len(hi) else 1
+    return d
+
+
+def _create(desc, bufs=None):
+    h = ctypes.c_void_p()
+    st = L().tg_create(ctypes.byref(desc), ctypes.byref(bufs) if bufs else None, ctypes.byref(h))
+    return st, h
+
+
+def test_exports_every_declared_symbol():
+    names = _lib.declared_functions()
+    assert "tg_forward" in names and "tg_backward" in names and "tg_query" in names
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(_lib._SIGS), "binding and header disagree"
+
+
+def test_coeffs_per_vertex():
+    assert [L().tg_coeffs_per_vertex(3, k) for k in range(3)] == [1, 4, 10]
+    assert [L().tg_coeffs_per_vertex(2, k) for k in range(3)] == [1, 3, 6]
+    assert L().tg_coeffs_per_vertex(4, 1) == -1
+    assert L().tg_coeffs_per_vertex(3, 3) == -1
+
+
+def test_status_strings():
+    for s in range(6):
+        assert L().tg_status_string(s)
+    assert L().tg_status_string(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("field,value", [
+    ("dim", 4), ("order", 3), ("order", -1), ("storage", 7)])
+def test_create_rejects_bad_descriptor(field, value):
+    d = _desc()
+    setattr(d, field, value)
+    st, h = _create(d)
+    assert st == 1 and not h.value
+    assert L().tg_last_error()
+
+
+def test_create_rejects_bad_geometry():
+    d = _desc(res=(1, 16, 16))
+    assert _create(d)[0] == 1
+    d = _desc(lo=(0, 0, 0), hi=(0, 1, 1))
+    assert _create(d)[0] == 1
+    d = _desc(lo=(float("nan"), 0, 0))
+    assert _create(d)[0] == 1
+    assert L().tg_create(None, None, None) == 1
+
+
+def test_create_rejects_inconsistent_buffers():
+    b = _lib.GridBuffers()
+    b.coeffs = 0x1000
+    b.master = 0x2000
+    assert _create(_desc(storage=0), b)[0] == 1  # f32: coeffs must equal master
+    b.master = 0x1000
+    assert _create(_desc(storage=1), b)[0] == 1  # bf16: must differ
+    b.coeffs = 0x1004
+    assert _create(_desc(storage=1), b)[0] == 1  # misaligned
+
+
+def test_workspace_sizes_and_state_errors():
+    b = _lib.GridBuffers()
+    b.coeffs = b.master = 0x1000
+    st, h = _create(_desc(res=(128, 128, 128)), b)
+    assert st == 0
+    try:
+        n = 1 << 20
+        ws = L().tg_workspace_bytes(h, n)
+        # worst case: every query emits 8 bucket records of 16 bytes
+        assert ws >= n * 8 * 16 + L().tg_reduce_workspace_bytes()
+        assert L().tg_workspace_bytes(h, -1) == 0
+        assert L().tg_workspace_bytes(None, 10) == 0
+        fake = ctypes.c_void_p(0x100000)
+        # a workspace that is too small is refused before any launch
+        assert L().tg_sort_queries(h, fake, n, fake, ws - 1, None) == 4
+        # forward without a sort of these queries is refused
+        assert L().tg_forward(h, fake, n, fake, ws, fake, None, None) == 5
+        # backward without grad buffer is refused
+        assert L().tg_backward(h, fake, n, fake, ws, None, None, None, 0, None) == 1
+        # misaligned workspace, negative n, NULL q
+        assert L().tg_sort_queries(h, fake, n, ctypes.c_void_p(0x100010), ws, None) == 1
+        assert L().tg_sort_queries(h, fake, -5, fake, ws, None) == 1
+        assert L().tg_sort_queries(h, None, 10, fake, ws, None) == 1
+        assert L().tg_sort_queries(h, fake, 1 << 29, fake, 1 << 40, None) == 4
+        # adam needs all four buffers, and a valid step
+        p = _lib.AdamParams(1e-2, 0.9, 0.999, 1e-8, 0.0, 1)
+        assert L().tg_adam_step(h, ctypes.byref(p), None, fake, 1 << 20, 0, None) == 1
+        # unknown flags
+        assert L().tg_backward(h, fake, n, fake, ws, None, None, None, 4, None) == 1
+    finally:
+        assert L().tg_destroy(h) == 0
+
+
+def test_adam_parameter_validation():
+    b = _lib.GridBuffers()
+    b.coeffs = b.master = 0x1000
+    b.grad = 0x2000
+    b.adam_m = 0x3000
+    b.adam_v = 0x4000
+    st, h = _create(_desc(), b)
+    assert st == 0
+    try:
+        fake = ctypes.c_void_p(0x100000)
+        for p in [_lib.AdamParams(1e-2, 0.9, 0.999, 1e-8, 0.0, 0),
+                  _lib.AdamParams(float("nan"), 0.9, 0.999, 1e-8, 0.0, 1),
+                  _lib.AdamParams(1e-2, 1.0, 0.999, 1e-8, 0.0, 1),
+                  _lib.AdamParams(1e-2, 0.9, 0.999, -1.0, 0.0, 1)]:
+            assert L().tg_adam_step(h, ctypes.byref(p), None, fake, 1 << 20, 0, None) == 1
+        p = _lib.AdamParams(1e-2, 0.9, 0.999, 1e-8, 0.0, 1)
+        assert L().tg_adam_step(h, ctypes.byref(p), None, fake, 16, 0, None) == 4  # scratch too small
+        assert L().tg_adam_step(h, ctypes.byref(p), None, fake, 1 << 20, 8, None) == 1  # bad flag
+    finally:
+        L().tg_destroy(h)
+
+
+def test_loss_validation():
+    fake = ctypes.c_void_p(0x100000)
+    big = L().tg_reduce_workspace_bytes()
+    assert L().tg_sdf_loss(4, 10, fake, fake, fake, 0.1, fake, fake, fake, fake, big, None) == 1
+    assert L().tg_sdf_loss(3, 10, None, fake, fake, 0.1, fake, fake, fake, fake, big, None) == 1
+    assert L().tg_sdf_loss(3, 10, fake, fake, fake, 0.1, fake, None, fake, fake, big, None) == 1
+    assert L().tg_sdf_loss(3, 10, fake, fake, fake, float("inf"), fake, fake, fake, fake, big, None) == 1
+    assert L().tg_sdf_loss(3, 10, fake, fake, fake, 0.1, fake, fake, fake, fake, 8, None) == 4
+
+
+def test_query_validation():
+    b = _lib.GridBuffers()
+    b.coeffs = b.master = 0x1000
+    st, h = _create(_desc(), b)
+    assert st == 0
+    try:
+        hs = (ctypes.c_void_p * 1)(h.value)
+        r = (_lib.Request * 1)()
+        r[0].grid = 1
+        r[0].n = 10
+        r[0].q = r[0].sdf = 0x5000
+        assert L().tg_query(hs, 1, r, 1, None) == 1  # grid index out of range
+        r[0].grid = 0
+        r[0].q = None
+        assert L().tg_query(hs, 1, r, 1, None) == 1  # NULL q
+        assert L().tg_query(hs, 1, r, 0, None) == 0  # empty batch is a no-op
+        assert L().tg_query(hs, 1, r, -1, None) == 1
+    finally:
+        L().tg_destroy(h)
