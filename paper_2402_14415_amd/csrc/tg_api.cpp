@@ -92,6 +92,20 @@ WsLayout ws_layout(const tg_grid* g, int64_t n)
     off = align_up(off + (size_t)L.ntiles * 4, 256);
     L.scratch_off = off;
     off = align_up(off + (size_t)L.sort_blocks * (size_t)L.nkeys * 4, 256);
+    const int64_t fan = (int64_t)1 << dim;  // records per query, at most
+    const int B = dim == 3 ? BrickEdge<3>::value : BrickEdge<2>::value;
+    L.acc_floats = (dim == 3 ? (int64_t)B * B * B : (int64_t)B * B) * g->C;
+    L.max_fitems = g->nbricks + (n + kFwdChunk - 1) / kFwdChunk;
+    L.max_bitems = g->nbricks + (n * fan + kBwdItem - 1) / kBwdItem;
+    L.max_slots = L.max_bitems;  // a split item's slot is its item index
+    L.meta_off = off;
+    off = align_up(off + 64, 256);
+    L.fitems_off = off;
+    off = align_up(off + (size_t)L.max_fitems * 8, 256);
+    L.bitems_off = off;
+    off = align_up(off + (size_t)L.max_bitems * 16, 256);
+    L.parts_off = off;
+    off = align_up(off + (size_t)L.max_slots * (size_t)L.acc_floats * 4, 256);
     L.rec_off = off;
     off = align_up(off + (size_t)n * ((size_t)1 << dim) * 16, 256);
     L.total = off;

@@ -4,16 +4,15 @@
 // (g_f, g_grad) a query contributes to coefficient alpha of corner vertex v_b
 //   m_alpha(d_b) s_b + sum_a u_a dm_alpha/dd_a(d_b),   s_b = g_f w_b + g_grad . grad w_b,
 //   u = w_b g_grad,  m_alpha(d) = d^alpha / alpha!  (the Taylor monomials of Sec. 3.1, Eq. 1).
-// One workgroup owns a brick of B^dim vertices and accumulates, in LDS, the contributions
-// of every query whose cell touches one of its vertices (the primary and secondary buckets
-// of that vertex brick, see tg_sort.hip); the brick is then written to HBM once with
-// coalesced row stores.  No global atomics, and every vertex is written exactly once.
 //
-// LDS accumulation: LDS floating-point atomics are an order of magnitude slower than LDS
-// integer atomics on this GPU, so each vertex's accumulator is updated with a plain
-// vectorised read-add-write (float4) under a per-vertex claim taken with an integer LDS
-// compare-and-swap.  Two lanes only contend when their queries share a vertex, which is
-// rare in the bucket's arbitrary order; a lane that loses the claim retries.
+// Gather formulation: a workgroup owns a brick of B^dim vertices and one thread owns one
+// vertex, accumulating its C coefficients in registers.  The brick's records (the queries
+// whose cells touch its vertices: the primary and secondary buckets of the vertex brick,
+// see tg_sort.hip) are staged in LDS in chunks, counting-sorted by cell (LDS integer
+// atomics); each thread then walks the records of the 2^dim cells around its vertex, as
+// one flattened loop over (corner, record) so that a lane's trip count is its total record
+// count.  No floating-point atomics, no races, and every vertex is written exactly once.
+// Crowded bricks are split into several work items whose partial sums a merge kernel adds.
 #include "tg_internal.hpp"
 
 namespace tg {
@@ -30,50 +29,67 @@ template <int DIM> __device__ __forceinline__ void vbrick_coords(const Geom& g, 
     }
 }
 
-// Accumulator row stride: C rounded up to a multiple of 4 (one float4 per 4 coefficients).
-template <int C> struct AccPad { static constexpr int value = (C + 3) / 4 * 4; };
+template <int DIM> struct BwdShape {
+    static constexpr int B = BrickEdge<DIM>::value;
+    static constexpr int NOWN = DIM == 3 ? B * B * B : B * B;  // vertices = threads
+    static constexpr int NC1 = B + 1;                           // cells -1..B-1 per axis
+    static constexpr int NCELL = DIM == 3 ? NC1 * NC1 * NC1 : NC1 * NC1;
+    static constexpr int CHUNK = 1024;                          // records staged at a time
+};
 
-template <int C, int CP>
-__device__ __forceinline__ void add_row(float* row, const float* v)
+// Writes (or adds) one vertex's C coefficients.
+template <int C>
+__device__ __forceinline__ void store_vertex(float* __restrict__ dst, const float* v, int accumulate)
 {
-    float4* p = reinterpret_cast<float4*>(row);
+    if constexpr (C % 2 == 0) {
+        float2* o = reinterpret_cast<float2*>(dst);
 #pragma unroll
-    for (int k = 0; k < CP / 4; ++k) {
-        float4 a = p[k];
-        a.x += v[4 * k + 0];
-        if (4 * k + 1 < C) a.y += v[4 * k + 1];
-        if (4 * k + 2 < C) a.z += v[4 * k + 2];
-        if (4 * k + 3 < C) a.w += v[4 * k + 3];
-        p[k] = a;
+        for (int k = 0; k < C / 2; ++k) {
+            float2 x = make_float2(v[2 * k], v[2 * k + 1]);
+            if (accumulate) {
+                const float2 old = o[k];
+                x.x += old.x;
+                x.y += old.y;
+            }
+            o[k] = x;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < C; ++k) dst[k] = accumulate ? dst[k] + v[k] : v[k];
     }
 }
 
-// Blocks are visited in an order that gives each XCD (blocks are dealt round-robin to the
-// 8 XCDs) a contiguous range of bricks, so neighbouring bricks share an L2.
-__device__ __forceinline__ int32_t xcd_brick(int64_t nbricks)
-{
-    const int32_t per = (int32_t)((nbricks + 7) / 8);
-    return (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
-}
-
 template <int DIM, int K>
-__global__ __launch_bounds__(kThreads) void k_backward(Geom g, int64_t nbricks, const float4* __restrict__ rec,
-                                                      const int32_t* __restrict__ offs,
-                                                      const float* __restrict__ gf, const float* __restrict__ gg,
-                                                      float* __restrict__ grad, int accumulate)
+__global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const int4* __restrict__ items,
+                                                                 const int32_t* __restrict__ meta, int64_t max_items,
+                                                                 float* __restrict__ parts,
+                                                                 const float4* __restrict__ rec,
+                                                                 const int32_t* __restrict__ offs,
+                                                                 const float* __restrict__ gf,
+                                                                 const float* __restrict__ gg,
+                                                                 float* __restrict__ grad, int accumulate)
 {
-    constexpr int B = BrickEdge<DIM>::value;
+    using S = BwdShape<DIM>;
+    constexpr int B = S::B, NOWN = S::NOWN, NC1 = S::NC1, NCELL = S::NCELL, CHUNK = S::CHUNK;
     constexpr int C = NumCoeffs<DIM, K>::value;
-    constexpr int CP = AccPad<C>::value;
-    constexpr int NOWN = DIM == 3 ? B * B * B : B * B;
-    __shared__ __align__(16) float acc[NOWN * CP];
-    __shared__ uint32_t claim[NOWN];
+    constexpr int PER = CHUNK / NOWN;
+    __shared__ float4 ent[2 * CHUNK];  // cell-sorted (t, g_f) and (g_grad, -) per record
+    __shared__ uint32_t cstart[NCELL + 1];
+    __shared__ uint32_t ccount[NCELL];
+    __shared__ int32_t wsum[NOWN / 64];
 
-    const int32_t brick = xcd_brick(nbricks);
-    if (brick >= nbricks) return;
-    const int32_t beg = offs[2 * brick];
-    const int32_t end = offs[2 * brick + 2];
-    if (accumulate && beg == end) return;
+    // Split bricks' items come first (longest first), whole bricks from the array's end.
+    const int32_t nsplit = meta[META_BSPLIT], nwhole = meta[META_BWHOLE];
+    const int32_t bid = blockIdx.x;
+    int32_t item;
+    if (bid < nsplit) item = bid;
+    else if (bid < nsplit + nwhole) item = (int32_t)(max_items - 1 - (bid - nsplit));
+    else return;
+    const int4 wi = items[item];
+    const int32_t brick = wi.x, chunk = wi.y, nchunk = wi.z;
+    const int32_t beg = offs[2 * brick] + chunk * kBwdItem;
+    const int32_t end = min(offs[2 * brick + 2], beg + kBwdItem);
+    if (accumulate && nchunk == 1 && beg >= end) return;
 
     int32_t bc[3];
     vbrick_coords<DIM>(g, brick, bc);
@@ -83,97 +99,205 @@ __global__ __launch_bounds__(kThreads) void k_backward(Geom g, int64_t nbricks, 
         base[a] = bc[a] * B;
         nown[a] = min(B, g.res[a] - base[a]);
     }
-
-    for (int e = threadIdx.x; e < NOWN * CP / 4; e += kThreads)
-        reinterpret_cast<float4*>(acc)[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    for (int e = threadIdx.x; e < NOWN; e += kThreads) claim[e] = 0u;
-    __syncthreads();
-
-    for (int32_t j = beg + threadIdx.x; j < end; j += kThreads) {
-        const float4 r = rec[j];
-        const float q[3] = {r.x, r.y, r.z};
-        const int32_t idx = __float_as_int(r.w);
-        AxisLoc L[DIM];
-        locate<DIM>(g, q, L);
-        const AxisFactors<DIM> F = axis_factors<DIM>(g, L);
-        const float sf = gf ? gf[idx] : 0.0f;
-        float sg[DIM];
+    // this thread's vertex, relative to the brick
+    int v[3];
+    {
+        int r = threadIdx.x;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) sg[a] = (gg && !L[a].clamped) ? gg[(int64_t)idx * DIM + a] : 0.0f;
-        int rel[DIM];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) rel[a] = L[a].cell - base[a];  // in [-1, B - 1]
-
-#pragma unroll
-        for (int b = 0; b < (1 << DIM); ++b) {
-            int lv[DIM];
-            bool owned = true;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                lv[a] = rel[a] + ((b >> a) & 1);
-                owned = owned && lv[a] >= 0 && lv[a] < nown[a];
-            }
-            if (!owned) continue;
-            float w, dw[DIM];
-            corner_weight<DIM>(F, b, w, dw);
-            float d[DIM];
-            corner_offset<DIM>(F, b, d);
-            float s = sf * w;
-            float u[DIM];
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                s = fmaf(sg[a], dw[a], s);
-                u[a] = w * sg[a];
-            }
-            float out[CP];
-            corner_adjoint<DIM, K>(d, s, u, out);
-#pragma unroll
-            for (int k = C; k < CP; ++k) out[k] = 0.0f;
-            int l = lv[0] + B * lv[1];
-            if constexpr (DIM == 3) l += B * B * lv[2];
-            // Claim-protected update, in wave-uniform rounds: in each round every lane that
-            // still has to update tries to claim its vertex; a winner updates and releases
-            // within the same round (the compiler barrier keeps the update and the release
-            // inside the round), so a lane that lost waits at most for holders that are
-            // already inside their bounded update.  Every claim starts at 0.
-            bool done = false;
-            do {
-                bool mine = false;
-                if (!done) {
-                    uint32_t expect = 0u;
-                    mine = __hip_atomic_compare_exchange_strong(&claim[l], &expect, 1u, __ATOMIC_ACQUIRE,
-                                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-                if (mine) {
-                    add_row<C, CP>(acc + l * CP, out);
-                    __hip_atomic_store(&claim[l], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    done = true;
-                }
-                asm volatile("" ::: "memory");
-            } while (__any(!done));
+        for (int a = 0; a < DIM; ++a) {
+            v[a] = r % B;
+            r /= B;
         }
     }
-    __syncthreads();
+    bool mine = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) mine = mine && v[a] < nown[a];
 
-    // Write the owned vertices: each row of nown[0] vertices is C * nown[0] contiguous floats.
-    constexpr int ROWLEN = B * C;
-    for (int e = threadIdx.x; e < NOWN * C; e += kThreads) {
-        const int row = e / ROWLEN;
-        const int rem = e - row * ROWLEN;
-        const int vx = rem / C;
-        const int cc = rem - vx * C;
-        const int ry = DIM == 3 ? row % B : row;
-        const int rz = DIM == 3 ? row / B : 0;
-        bool ok = vx < nown[0] && ry < nown[1];
-        if constexpr (DIM == 3) ok = ok && rz < nown[2];
-        if (!ok) continue;
-        int64_t vert = (int64_t)(base[0] + vx) + (int64_t)(base[1] + ry) * g.stride[1];
-        if constexpr (DIM == 3) vert += (int64_t)(base[2] + rz) * g.stride[2];
-        float* p = grad + vert * C + cc;
-        const float v = acc[(row * B + vx) * CP + cc];
-        if (accumulate) *p += v;
-        else *p = v;
+    float acc[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) acc[k] = 0.0f;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int32_t cbeg = beg; cbeg < end; cbeg += CHUNK) {
+        const int m = min(CHUNK, end - cbeg);
+        for (int e = threadIdx.x; e < NCELL; e += NOWN) ccount[e] = 0u;
+        __syncthreads();
+
+        // Stage: decode records, rank them within their cell.
+        int my_cell[PER];
+        uint32_t my_rank[PER];
+        float4 my_e0[PER], my_e1[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * NOWN;
+            my_cell[u] = -1;
+            if (i < m) {
+                const float4 r = rec[cbeg + i];
+                const float q[3] = {r.x, r.y, r.z};
+                const int32_t idx = __float_as_int(r.w);
+                AxisLoc L[DIM];
+                locate<DIM>(g, q, L);
+                float sg[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) sg[a] = (gg && !L[a].clamped) ? gg[(int64_t)idx * DIM + a] : 0.0f;
+                int cell = 0;
+#pragma unroll
+                for (int a = DIM - 1; a >= 0; --a) cell = cell * NC1 + min(max(L[a].cell - base[a] + 1, 0), B);
+                my_cell[u] = cell;
+                my_e0[u] = make_float4(L[0].t, L[1].t, DIM == 3 ? L[DIM - 1].t : 0.0f, gf ? gf[idx] : 0.0f);
+                my_e1[u] = make_float4(sg[0], sg[1], sg[2], 0.0f);
+                my_rank[u] = atomicAdd(&ccount[cell], 1u);
+            }
+        }
+        __syncthreads();
+        // exclusive scan of the cell counts
+        {
+            constexpr int CPT = (NCELL + NOWN - 1) / NOWN;
+            uint32_t c[CPT];
+            uint32_t s = 0;
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                const int idx = threadIdx.x * CPT + k;
+                c[k] = idx < NCELL ? ccount[idx] : 0u;
+                s += c[k];
+            }
+            uint32_t incl = s;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t o = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += o;
+            }
+            if (lane == 63) wsum[wave] = (int32_t)incl;
+            __syncthreads();
+            uint32_t before = 0;
+            for (int w = 0; w < wave; ++w) before += (uint32_t)wsum[w];
+            uint32_t run = before + incl - s;
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                const int idx = threadIdx.x * CPT + k;
+                if (idx < NCELL) cstart[idx] = run;
+                run += c[k];
+            }
+            if (threadIdx.x == NOWN - 1) cstart[NCELL] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            if (my_cell[u] < 0) continue;
+            const uint32_t pos = cstart[my_cell[u]] + my_rank[u];
+            ent[2 * pos] = my_e0[u];
+            ent[2 * pos + 1] = my_e1[u];
+        }
+        __syncthreads();
+
+        // Gather: every (corner, record) pair of this thread's vertex, one flattened loop.
+        if (mine) {
+            int b = 0;
+            uint32_t e = 0, e_end = 0;
+            for (;;) {
+                while (e == e_end && b < (1 << DIM)) {
+                    int cell = 0;
+#pragma unroll
+                    for (int a = DIM - 1; a >= 0; --a) cell = cell * NC1 + (v[a] - ((b >> a) & 1) + 1);
+                    e = cstart[cell];
+                    e_end = cstart[cell + 1];
+                    if (e == e_end) ++b;
+                }
+                if (b >= (1 << DIM)) break;
+                const float4 e0 = ent[2 * e], e1 = ent[2 * e + 1];
+                const float t[3] = {e0.x, e0.y, e0.z};
+                const float sg[3] = {e1.x, e1.y, e1.z};
+                // weight of this corner and its gradient, and the offset from this vertex
+                float w = 1.0f, d[DIM], fa[DIM], da[DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const int ba = (b >> a) & 1;
+                    fa[a] = ba ? t[a] : 1.0f - t[a];
+                    da[a] = ba ? g.inv_h[a] : -g.inv_h[a];
+                    d[a] = (t[a] - (float)ba) * g.h[a];
+                    w *= fa[a];
+                }
+                float dw[DIM];
+                if constexpr (DIM == 3) {
+                    dw[0] = da[0] * fa[1] * fa[2];
+                    dw[1] = fa[0] * da[1] * fa[2];
+                    dw[2] = fa[0] * fa[1] * da[2];
+                } else {
+                    dw[0] = da[0] * fa[1];
+                    dw[1] = fa[0] * da[1];
+                }
+                float s = e0.w * w;
+                float uu[DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    s = fmaf(sg[a], dw[a], s);
+                    uu[a] = w * sg[a];
+                }
+                float out[C];
+                corner_adjoint<DIM, K>(d, s, uu, out);
+#pragma unroll
+                for (int k = 0; k < C; ++k) acc[k] += out[k];
+                if (++e == e_end) ++b;
+            }
+        }
+        __syncthreads();
     }
+
+    int64_t vert = (int64_t)(base[0] + v[0]) + (int64_t)(base[1] + v[1]) * g.stride[1];
+    if constexpr (DIM == 3) vert += (int64_t)(base[2] + v[2]) * g.stride[2];
+    if (nchunk > 1) {
+        // partial sums of a split brick: slot = item index, laid out [vertex][C] per brick
+        if (mine) {
+            float* slot = parts + (int64_t)item * (NOWN * C) + threadIdx.x * C;
+#pragma unroll
+            for (int k = 0; k < C; ++k) slot[k] = acc[k];
+        }
+        return;
+    }
+    if (mine) store_vertex<C>(grad + vert * C, acc, accumulate);
+}
+
+// Adds the partial sums of every split brick, in slot order, and writes the brick.
+template <int DIM, int K>
+__global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward_merge(Geom g, const int4* __restrict__ items,
+                                                                       const int32_t* __restrict__ meta,
+                                                                       const float* __restrict__ parts,
+                                                                       float* __restrict__ grad, int accumulate)
+{
+    using S = BwdShape<DIM>;
+    constexpr int B = S::B, NOWN = S::NOWN;
+    constexpr int C = NumCoeffs<DIM, K>::value;
+    const int32_t item = blockIdx.x;
+    if (item >= meta[META_BSPLIT]) return;
+    const int4 wi = items[item];
+    if (wi.y != 0) return;  // the brick's first item merges
+    const int32_t brick = wi.x, nchunk = wi.z, first = wi.w;
+    int32_t bc[3];
+    vbrick_coords<DIM>(g, brick, bc);
+    int v[3];
+    {
+        int r = threadIdx.x;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            v[a] = r % B;
+            r /= B;
+        }
+    }
+    bool mine = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) mine = mine && v[a] < min(B, g.res[a] - bc[a] * B);
+    if (!mine) return;
+    float acc[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) acc[k] = 0.0f;
+    for (int j = 0; j < nchunk; ++j) {
+        const float* slot = parts + (int64_t)(first + j) * (NOWN * C) + threadIdx.x * C;
+#pragma unroll
+        for (int k = 0; k < C; ++k) acc[k] += slot[k];
+    }
+    int64_t vert = (int64_t)(bc[0] * B + v[0]) + (int64_t)(bc[1] * B + v[1]) * g.stride[1];
+    if constexpr (DIM == 3) vert += (int64_t)(bc[2] * B + v[2]) * g.stride[2];
+    store_vertex<C>(grad + vert * C, acc, accumulate);
 }
 
 hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
@@ -182,15 +306,20 @@ hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const Ws
     (void)n;
     const float4* rec = reinterpret_cast<const float4*>(ws + L.rec_off);
     const int32_t* offs = reinterpret_cast<const int32_t*>(ws + L.offs_off);
-    const dim3 grid((unsigned)(8 * ((g->nbricks + 7) / 8))), block(kThreads);
+    const int4* items = reinterpret_cast<const int4*>(ws + L.bitems_off);
+    const int32_t* meta = reinterpret_cast<const int32_t*>(ws + L.meta_off);
+    float* parts = reinterpret_cast<float*>(const_cast<char*>(ws) + L.parts_off);
+    const dim3 grid((unsigned)L.max_bitems);
     const int dim = g->desc.dim, K = g->desc.order;
     float* gr = g->bufs.grad;
     const int acc = accumulate ? 1 : 0;
-#define TG_BWD_CASE(D, KK)                                                                                    \
-    if (dim == D && K == KK) {                                                                                \
-        hipLaunchKernelGGL((k_backward<D, KK>), grid, block, 0, s, g->geom, g->nbricks, rec, offs, g_f, g_grad, gr, \
-                           acc);                                                                              \
-        return hipGetLastError();                                                                             \
+#define TG_BWD_CASE(D, KK)                                                                                   \
+    if (dim == D && K == KK) {                                                                               \
+        const dim3 block(BwdShape<D>::NOWN);                                                                 \
+        hipLaunchKernelGGL((k_backward<D, KK>), grid, block, 0, s, g->geom, items, meta, L.max_bitems, parts, rec, \
+                           offs, g_f, g_grad, gr, acc);                                                      \
+        hipLaunchKernelGGL((k_backward_merge<D, KK>), grid, block, 0, s, g->geom, items, meta, parts, gr, acc); \
+        return hipGetLastError();                                                                            \
     }
     TG_BWD_CASE(3, 2) TG_BWD_CASE(3, 1) TG_BWD_CASE(3, 0) TG_BWD_CASE(2, 2) TG_BWD_CASE(2, 1) TG_BWD_CASE(2, 0)
 #undef TG_BWD_CASE

@@ -53,7 +53,8 @@ template <int DIM> __host__ __device__ constexpr int hidx(int a, int c)
 }
 
 template <int DIM, int K, int ST, int MODE>
-__global__ __launch_bounds__(kThreads) void k_forward(Geom g, int64_t nbricks, const void* __restrict__ coeffs,
+__global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int2* __restrict__ items,
+                                                     const int32_t* __restrict__ meta, const void* __restrict__ coeffs,
                                                      const float4* __restrict__ rec,
                                                      const int32_t* __restrict__ offs,
                                                      float* __restrict__ f_out, float* __restrict__ grad_out,
@@ -69,14 +70,19 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, int64_t nbricks, c
     constexpr int NH = DIM == 3 ? 6 : 3;
     __shared__ __align__(16) float lds[NROWS * NV1 * CP];
 
-    // Each XCD (blocks are dealt round-robin to the 8 XCDs) gets a contiguous range of
-    // bricks, so the vertex layers neighbouring bricks share stay in one L2.
-    const int32_t per = (int32_t)((nbricks + 7) / 8);
-    const int32_t brick = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
-    if (brick >= nbricks) return;
-    const int32_t beg = offs[2 * brick];
-    const int32_t end = offs[2 * brick + 1];
-    if (beg == end) return;
+    // Work item = (brick, chunk of up to kFwdChunk primary records).  Each XCD (blocks are
+    // dealt round-robin to the 8 XCDs) takes a contiguous range of items, so the vertex
+    // layers that neighbouring bricks share stay in one L2.
+    const int32_t total = meta[META_FITEMS];
+    const int32_t per = (total + 7) / 8;
+    if ((int32_t)(blockIdx.x / 8) >= per) return;
+    const int32_t item = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
+    if (item >= total) return;
+    const int2 wi = items[item];
+    const int32_t brick = wi.x;
+    const int32_t beg = offs[2 * brick] + wi.y * kFwdChunk;
+    const int32_t end = min(offs[2 * brick + 1], beg + kFwdChunk);
+    if (beg >= end) return;
 
     int32_t bc[3];
     brick_coords<DIM>(g, brick, bc);
@@ -87,40 +93,44 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, int64_t nbricks, c
         nv[a] = min(B, g.res[a] - 1 - v0[a]) + 1;  // >= 2 for a brick that has queries
     }
 
-    // Stage the brick's vertices: rows of NV1 vertices along x are contiguous in HBM.  With
-    // an even coefficient count a pair of coefficients never straddles two vertices, so
-    // rows are copied two coefficients per load.
-    if constexpr (C % 2 == 0) {
-        constexpr int RP = ROWLEN / 2;
-        for (int e = threadIdx.x; e < NROWS * RP; e += kThreads) {
-            const int row = e / RP;
-            const int rem = 2 * (e - row * RP);
-            const int vx = rem / C;
-            const int cc = rem - vx * C;
-            const int ry = DIM == 3 ? row % NV1 : row;
-            const int rz = DIM == 3 ? row / NV1 : 0;
-            bool ok = vx < nv[0] && ry < nv[1];
-            if constexpr (DIM == 3) ok = ok && rz < nv[2];
-            if (ok) {
-                int64_t vert = (int64_t)(v0[0] + vx) + (int64_t)(v0[1] + ry) * g.stride[1];
-                if constexpr (DIM == 3) vert += (int64_t)(v0[2] + rz) * g.stride[2];
-                *reinterpret_cast<float2*>(&lds[(row * NV1 + vx) * CP + cc]) = load_pair<ST>(coeffs, vert * C + cc);
+    // Stage the brick's vertices: each wave copies whole rows of NV1 vertices along x (NV1*C
+    // contiguous values in HBM); with an even coefficient count each lane moves a pair of
+    // coefficients, which never straddles two vertices.  Rows are loaded in batches so that
+    // a wave has several loads in flight.
+    {
+        constexpr int STEP = C % 2 == 0 ? 2 : 1;
+        constexpr int RB = 8;  // rows per batch and wave
+        static_assert(ROWLEN / STEP <= 64, "a row must fit one wave");
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int e = lane * STEP;  // this lane's value index within a row
+        const bool lane_ok = e < nv[0] * C;
+        const int vx = e / C;
+        const int cc = e - vx * C;
+        for (int r0 = wave; r0 < NROWS; r0 += RB * (kThreads / 64)) {
+            float2 v[RB];
+            int row[RB];
+#pragma unroll
+            for (int k = 0; k < RB; ++k) {
+                row[k] = r0 + k * (kThreads / 64);
+                const int ry = DIM == 3 ? row[k] % NV1 : row[k];
+                const int rz = DIM == 3 ? row[k] / NV1 : 0;
+                bool ok = lane_ok && row[k] < NROWS && ry < nv[1];
+                if constexpr (DIM == 3) ok = ok && rz < nv[2];
+                if (!ok) {
+                    row[k] = -1;
+                    continue;
+                }
+                int64_t vrow = (int64_t)v0[0] + (int64_t)(v0[1] + ry) * g.stride[1];
+                if constexpr (DIM == 3) vrow += (int64_t)(v0[2] + rz) * g.stride[2];
+                if constexpr (C % 2 == 0) v[k] = load_pair<ST>(coeffs, vrow * C + e);
+                else v[k].x = load_scalar<ST>(coeffs, vrow * C + e);
             }
-        }
-    } else {
-        for (int e = threadIdx.x; e < NROWS * ROWLEN; e += kThreads) {
-            const int row = e / ROWLEN;
-            const int rem = e - row * ROWLEN;
-            const int vx = rem / C;
-            const int cc = rem - vx * C;
-            const int ry = DIM == 3 ? row % NV1 : row;
-            const int rz = DIM == 3 ? row / NV1 : 0;
-            bool ok = vx < nv[0] && ry < nv[1];
-            if constexpr (DIM == 3) ok = ok && rz < nv[2];
-            if (ok) {
-                int64_t vert = (int64_t)(v0[0] + vx) + (int64_t)(v0[1] + ry) * g.stride[1];
-                if constexpr (DIM == 3) vert += (int64_t)(v0[2] + rz) * g.stride[2];
-                lds[(row * NV1 + vx) * CP + cc] = load_scalar<ST>(coeffs, vert * C + cc);
+#pragma unroll
+            for (int k = 0; k < RB; ++k) {
+                if (row[k] < 0) continue;
+                float* dst = &lds[(row[k] * NV1 + vx) * CP + cc];
+                if constexpr (C % 2 == 0) *reinterpret_cast<float2*>(dst) = v[k];
+                else *dst = v[k].x;
             }
         }
     }
@@ -212,12 +222,14 @@ static hipError_t dispatch(const tg_grid* g, const char* ws, const WsLayout& L, 
 {
     const float4* rec = reinterpret_cast<const float4*>(ws + L.rec_off);
     const int32_t* offs = reinterpret_cast<const int32_t*>(ws + L.offs_off);
-    const dim3 grid((unsigned)(8 * ((g->nbricks + 7) / 8))), block(kThreads);
+    const int2* items = reinterpret_cast<const int2*>(ws + L.fitems_off);
+    const int32_t* meta = reinterpret_cast<const int32_t*>(ws + L.meta_off);
+    const dim3 grid((unsigned)(8 * ((L.max_fitems + 7) / 8))), block(kThreads);
     const void* cf = g->bufs.coeffs;
     const int dim = g->desc.dim, K = g->desc.order, st = g->desc.storage;
 #define TG_FWD_CASE(D, KK, ST)                                                                          \
     if (dim == D && K == KK && st == ST) {                                                              \
-        hipLaunchKernelGGL((k_forward<D, KK, ST, MODE>), grid, block, 0, s, g->geom, g->nbricks, cf, rec, offs, f, \
+        hipLaunchKernelGGL((k_forward<D, KK, ST, MODE>), grid, block, 0, s, g->geom, items, meta, cf, rec, offs, f, \
                            grad_f, gf, gg, dq);                                                         \
         return hipGetLastError();                                                                       \
     }

@@ -28,6 +28,8 @@ constexpr int kThreads = 256;
 constexpr int kSortThreads = 1024;       // threads per block of the LDS-histogram sort
 constexpr int32_t kMaxLdsKeys = 16384;   // keys whose LDS histogram fits 64 KB
 constexpr int kMaxSortBlocks = 128;
+constexpr int kFwdChunk = 1024;          // primary records per forward work item
+constexpr int kBwdItem = 2048;           // records per backward work item
 constexpr int kMaxReduceBlocks = 2048;  // FP64 partials: 4 per block
 constexpr size_t kReduceBytes = (size_t)kMaxReduceBlocks * 4 * sizeof(double);
 constexpr int kScanTile = 4096;          // keys per scan tile (256 threads x 16)
@@ -42,6 +44,11 @@ struct WsLayout {
     size_t offs_off;     // int32 [nkeys_pad]: exclusive bucket offsets (+ total at [nkeys])
     size_t tiles_off;    // int32 [ntiles]: scan tile totals, or the block-arrival counter
     size_t scratch_off;  // int32 [sort_blocks x nkeys]: per-block key counts, then offsets
+    size_t meta_off;     // int32 [16]: work-item totals
+    size_t fitems_off;   // int2 [max_fitems]: forward work items (brick, chunk)
+    size_t bitems_off;   // int4 [max_bitems]: backward items (brick, chunk, chunks, first slot):
+                         // split bricks' items from the front, whole bricks from the back
+    size_t parts_off;    // float [max_slots x brick accumulator]: partial sums of split bricks
     size_t rec_off;      // float4 [n * 2^dim]: sorted query records (x, y, z, index bits)
     size_t total;
     int64_t nkeys;       // 2 * nbricks (primary / secondary bucket of every vertex brick)
@@ -50,7 +57,14 @@ struct WsLayout {
     bool lds_path;       // sort with LDS histograms (else global atomic counters)
     int64_t sort_blocks; // blocks of the LDS-histogram sort
     int64_t sort_slice;  // queries per sort block
+    int64_t max_fitems;  // bound on forward work items
+    int64_t max_bitems;  // bound on backward work items
+    int64_t max_slots;   // bound on partial-sum slots of split backward bricks
+    int64_t acc_floats;  // floats in one brick accumulator (B^dim * C)
 };
+
+// Meta words in the workspace.
+enum { META_FITEMS = 0, META_BSPLIT = 1, META_BWHOLE = 2 };
 
 WsLayout ws_layout(const tg_grid* g, int64_t n);
 

@@ -13,8 +13,8 @@
 //   1. every block takes a contiguous slice of the queries and counts its records per key
 //      in an LDS histogram (LDS integer atomics), writing one row of a [blocks x keys]
 //      matrix;
-//   2. a column scan turns the matrix into per-(block, key) offsets and per-key totals;
-//      the last block to finish scans the totals into the key offsets;
+//   2. a column scan turns the matrix into per-(block, key) offsets and per-key totals,
+//      and one block scans the totals into the key offsets and builds the work lists;
 //   3. every block recomputes its records and places each at key offset + its block's
 //      column offset + a rank drawn from an LDS counter.
 // Grids with more keys than fit an LDS histogram use a slower path with global atomic
@@ -54,11 +54,85 @@ __device__ __forceinline__ void load_query(const float* __restrict__ q, int64_t 
     for (int a = 0; a < DIM; ++a) out[a] = q[i * DIM + a];
 }
 
+// ------------------------------------------------------------------ work lists
+// Splits every brick's buckets into work items so that crowded bricks are shared among
+// several workgroups.  Forward: up to kFwdChunk primary records per item.  Backward: a
+// brick with more than kBwdItem records (primary + secondary) is split into items of
+// kBwdItem records, listed first (they are the longest and start first); every other brick
+// is one item, listed from the end of the array backwards, including bricks no query
+// touches (the item writes their zero gradient).  A split item's index doubles as its
+// partial-sum slot; a merge kernel adds the slots of a brick in order.
+// Runs in one block of kThreads threads after the bucket offsets are final.
+struct WorkPtrs {
+    int2* fitems;
+    int4* bitems;
+    int32_t* meta;
+    int64_t max_bitems;
+};
+
+__device__ void build_work(const int32_t* offs, int64_t nbricks, WorkPtrs W)
+{
+    __shared__ int32_t wtot[3][kThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t carry[3] = {0, 0, 0};
+    for (int64_t tile = 0; tile < nbricks; tile += kThreads) {
+        const int64_t b = tile + threadIdx.x;
+        int32_t cnt[3] = {0, 0, 0};  // forward items, split backward items, unsplit backward item
+        if (b < nbricks) {
+            const int32_t o0 = offs[2 * b], o1 = offs[2 * b + 1], o2 = offs[2 * b + 2];
+            cnt[0] = (o1 - o0 + kFwdChunk - 1) / kFwdChunk;
+            const int32_t nb = (o2 - o0 + kBwdItem - 1) / kBwdItem;
+            cnt[1] = nb > 1 ? nb : 0;
+            cnt[2] = nb > 1 ? 0 : 1;
+        }
+        int32_t incl[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            incl[v] = cnt[v];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int32_t o = __shfl_up(incl[v], d, 64);
+                if (lane >= d) incl[v] += o;
+            }
+            if (lane == 63) wtot[v][wave] = incl[v];
+        }
+        __syncthreads();
+        int32_t start[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            int32_t before = 0, all = 0;
+#pragma unroll
+            for (int w = 0; w < kThreads / 64; ++w) {
+                if (w < wave) before += wtot[v][w];
+                all += wtot[v][w];
+            }
+            start[v] = carry[v] + before + incl[v] - cnt[v];
+            carry[v] += all;
+        }
+        __syncthreads();
+        if (b < nbricks) {
+            for (int32_t k = 0; k < cnt[0]; ++k) W.fitems[start[0] + k] = make_int2((int32_t)b, k);
+            for (int32_t k = 0; k < cnt[1]; ++k) W.bitems[start[1] + k] = make_int4((int32_t)b, k, cnt[1], start[1]);
+            if (cnt[2]) W.bitems[W.max_bitems - 1 - start[2]] = make_int4((int32_t)b, 0, 1, -1);
+        }
+    }
+    if (threadIdx.x == 0) {
+        W.meta[META_FITEMS] = carry[0];
+        W.meta[META_BSPLIT] = carry[1];
+        W.meta[META_BWHOLE] = carry[2];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_build_work(const int32_t* __restrict__ offs, int64_t nbricks, WorkPtrs W)
+{
+    build_work(offs, nbricks, W);
+}
+
 // ------------------------------------------------------------------ LDS-histogram path
 template <int DIM>
 __global__ __launch_bounds__(kSortThreads) void k_sort_count(Geom g, const float* __restrict__ q, int64_t n,
                                                              int64_t slice, int32_t nkeys,
-                                                             int32_t* __restrict__ mat, uint32_t* __restrict__ done)
+                                                             int32_t* __restrict__ mat)
 {
     extern __shared__ uint32_t hist[];
     for (int k = threadIdx.x; k < nkeys; k += kSortThreads) hist[k] = 0u;
@@ -76,46 +150,40 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(Geom g, const float
     __syncthreads();
     int32_t* row = mat + (int64_t)blockIdx.x * nkeys;
     for (int k = threadIdx.x; k < nkeys; k += kSortThreads) row[k] = (int32_t)hist[k];
-    if (blockIdx.x == 0 && threadIdx.x == 0) *done = 0u;
 }
 
-// Column scan of the [nblk x nkeys] matrix (each thread one key), then the last block to
-// arrive scans the per-key totals into offs[0..nkeys].
+// Column scan of the [nblk x nkeys] matrix (each thread one key): per-(block, key) offsets
+// within the key, and per-key totals.
 __global__ __launch_bounds__(kThreads) void k_sort_colscan(int32_t* __restrict__ mat, int32_t nblk, int32_t nkeys,
-                                                          int32_t* __restrict__ total, int32_t* __restrict__ offs,
-                                                          uint32_t* __restrict__ done)
+                                                          int32_t* __restrict__ total)
+{
+    const int32_t key = blockIdx.x * kThreads + threadIdx.x;
+    if (key >= nkeys) return;
+    int32_t run = 0;
+    int32_t b = 0;
+    for (; b + 8 <= nblk; b += 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = mat[(int64_t)(b + u) * nkeys + key];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            mat[(int64_t)(b + u) * nkeys + key] = run;
+            run += v[u];
+        }
+    }
+    for (; b < nblk; ++b) {
+        const int32_t v = mat[(int64_t)b * nkeys + key];
+        mat[(int64_t)b * nkeys + key] = run;
+        run += v;
+    }
+    total[key] = run;
+}
+
+// One block: exclusive scan of the per-key totals into offs[0..nkeys], then the work lists.
+__global__ __launch_bounds__(kThreads) void k_sort_finish(const int32_t* __restrict__ total, int32_t nkeys,
+                                                         int32_t* __restrict__ offs, WorkPtrs W)
 {
     __shared__ int32_t wave_tot[kThreads / 64];
-    __shared__ bool last;
-    const int32_t key = blockIdx.x * kThreads + threadIdx.x;
-    if (key < nkeys) {
-        int32_t run = 0;
-        int32_t b = 0;
-        for (; b + 8 <= nblk; b += 8) {
-            int32_t v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = mat[(int64_t)(b + u) * nkeys + key];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                mat[(int64_t)(b + u) * nkeys + key] = run;
-                run += v[u];
-            }
-        }
-        for (; b < nblk; ++b) {
-            const int32_t v = mat[(int64_t)b * nkeys + key];
-            mat[(int64_t)b * nkeys + key] = run;
-            run += v;
-        }
-        total[key] = run;
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-
-    // exclusive scan of total[0..nkeys) by the last block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int32_t carry = 0;
     for (int32_t base = 0; base < nkeys; base += kThreads * 8) {
@@ -124,7 +192,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_colscan(int32_t* __restrict__
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int32_t k = base + threadIdx.x * 8 + u;
-            v[u] = k < nkeys ? __hip_atomic_load(&total[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+            v[u] = k < nkeys ? total[k] : 0;
             s += v[u];
         }
         int32_t incl = s;
@@ -152,6 +220,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_colscan(int32_t* __restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) offs[nkeys] = carry;
+    __syncthreads();
+    build_work(offs, nkeys / 2, W);
 }
 
 template <int DIM>
@@ -336,19 +406,24 @@ hipError_t launch_sort(const tg_grid* g, const float* q, int64_t n, char* ws, co
     int32_t* offs = reinterpret_cast<int32_t*>(ws + L.offs_off);
     float4* rec = reinterpret_cast<float4*>(ws + L.rec_off);
     const int dim = g->desc.dim;
+    WorkPtrs W;
+    W.fitems = reinterpret_cast<int2*>(ws + L.fitems_off);
+    W.bitems = reinterpret_cast<int4*>(ws + L.bitems_off);
+    W.max_bitems = L.max_bitems;
+    W.meta = reinterpret_cast<int32_t*>(ws + L.meta_off);
     if (L.lds_path) {
         int32_t* mat = reinterpret_cast<int32_t*>(ws + L.scratch_off);
         int32_t* total = reinterpret_cast<int32_t*>(ws + L.counts_off);
-        uint32_t* done = reinterpret_cast<uint32_t*>(ws + L.tiles_off);
         const int32_t nkeys = (int32_t)L.nkeys;
         const size_t lds = (size_t)nkeys * sizeof(uint32_t);
         const dim3 gb((unsigned)L.sort_blocks), tb(kSortThreads);
         if (dim == 3)
-            hipLaunchKernelGGL(k_sort_count<3>, gb, tb, lds, s, g->geom, q, n, L.sort_slice, nkeys, mat, done);
+            hipLaunchKernelGGL(k_sort_count<3>, gb, tb, lds, s, g->geom, q, n, L.sort_slice, nkeys, mat);
         else
-            hipLaunchKernelGGL(k_sort_count<2>, gb, tb, lds, s, g->geom, q, n, L.sort_slice, nkeys, mat, done);
+            hipLaunchKernelGGL(k_sort_count<2>, gb, tb, lds, s, g->geom, q, n, L.sort_slice, nkeys, mat);
         hipLaunchKernelGGL(k_sort_colscan, dim3(blocks_for(nkeys, kThreads)), dim3(kThreads), 0, s, mat,
-                           (int32_t)L.sort_blocks, nkeys, total, offs, done);
+                           (int32_t)L.sort_blocks, nkeys, total);
+        hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(kThreads), 0, s, total, nkeys, offs, W);
         if (n > 0) {
             if (dim == 3)
                 hipLaunchKernelGGL(k_sort_scatter<3>, gb, tb, lds, s, g->geom, q, n, L.sort_slice, nkeys, mat, offs, rec);
@@ -369,6 +444,7 @@ hipError_t launch_sort(const tg_grid* g, const float* q, int64_t n, char* ws, co
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)L.ntiles), dim3(kThreads), 0, s, counts, tiles);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tiles, (int32_t)L.ntiles);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)L.ntiles), dim3(kThreads), 0, s, counts, tiles, offs);
+    hipLaunchKernelGGL(k_build_work, dim3(1), dim3(kThreads), 0, s, offs, g->nbricks, W);
     if (n > 0) {
         if (dim == 3)
             hipLaunchKernelGGL(k_bucket_scatter<3>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, g->geom, q, n, counts, rec);
