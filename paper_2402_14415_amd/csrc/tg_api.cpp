@@ -104,6 +104,8 @@ WsLayout ws_layout(const tg_grid* g, int64_t n)
     off = align_up(off + (size_t)L.max_fitems * 8, 256);
     L.bitems_off = off;
     off = align_up(off + (size_t)L.max_bitems * 16, 256);
+    L.splitb_off = off;
+    off = align_up(off + (size_t)g->nbricks * 4, 256);
     L.parts_off = off;
     off = align_up(off + (size_t)L.max_slots * (size_t)L.acc_floats * 4, 256);
     L.rec_off = off;

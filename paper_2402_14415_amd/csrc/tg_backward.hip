@@ -34,7 +34,7 @@ template <int DIM> struct BwdShape {
     static constexpr int NOWN = DIM == 3 ? B * B * B : B * B;  // vertices = threads
     static constexpr int NC1 = B + 1;                           // cells -1..B-1 per axis
     static constexpr int NCELL = DIM == 3 ? NC1 * NC1 * NC1 : NC1 * NC1;
-    static constexpr int CHUNK = 1024;                          // records staged at a time
+    static constexpr int CHUNK = 512;                           // records staged at a time
 };
 
 // Writes (or adds) one vertex's C coefficients.
@@ -191,19 +191,32 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
         __syncthreads();
 
         // Gather: every (corner, record) pair of this thread's vertex, one flattened loop.
+        // The record ranges of the 2^dim cells around the vertex are read up front (they do
+        // not depend on each other); the loop then picks the corner with register selects.
         if (mine) {
-            int b = 0;
-            uint32_t e = 0, e_end = 0;
-            for (;;) {
-                while (e == e_end && b < (1 << DIM)) {
-                    int cell = 0;
+            constexpr int NB = 1 << DIM;
+            uint32_t cs[NB], pre[NB + 1];
+            pre[0] = 0u;
 #pragma unroll
-                    for (int a = DIM - 1; a >= 0; --a) cell = cell * NC1 + (v[a] - ((b >> a) & 1) + 1);
-                    e = cstart[cell];
-                    e_end = cstart[cell + 1];
-                    if (e == e_end) ++b;
-                }
-                if (b >= (1 << DIM)) break;
+            for (int b = 0; b < NB; ++b) {
+                int cell = 0;
+#pragma unroll
+                for (int a = DIM - 1; a >= 0; --a) cell = cell * NC1 + (v[a] - ((b >> a) & 1) + 1);
+                cs[b] = cstart[cell];
+                pre[b + 1] = cstart[cell + 1];
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) pre[b + 1] = pre[b] + (pre[b + 1] - cs[b]);
+            const uint32_t total = pre[NB];
+            for (uint32_t k = 0; k < total; ++k) {
+                int b = 0;
+                uint32_t e = cs[0] + k;
+#pragma unroll
+                for (int bb = 1; bb < NB; ++bb)
+                    if (k >= pre[bb]) {
+                        b = bb;
+                        e = cs[bb] + (k - pre[bb]);
+                    }
                 const float4 e0 = ent[2 * e], e1 = ent[2 * e + 1];
                 const float t[3] = {e0.x, e0.y, e0.z};
                 const float sg[3] = {e1.x, e1.y, e1.z};
@@ -211,10 +224,10 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
                 float w = 1.0f, d[DIM], fa[DIM], da[DIM];
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
-                    const int ba = (b >> a) & 1;
+                    const bool ba = (b >> a) & 1;
                     fa[a] = ba ? t[a] : 1.0f - t[a];
                     da[a] = ba ? g.inv_h[a] : -g.inv_h[a];
-                    d[a] = (t[a] - (float)ba) * g.h[a];
+                    d[a] = (ba ? t[a] - 1.0f : t[a]) * g.h[a];
                     w *= fa[a];
                 }
                 float dw[DIM];
@@ -236,8 +249,7 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
                 float out[C];
                 corner_adjoint<DIM, K>(d, s, uu, out);
 #pragma unroll
-                for (int k = 0; k < C; ++k) acc[k] += out[k];
-                if (++e == e_end) ++b;
+                for (int k2 = 0; k2 < C; ++k2) acc[k2] += out[k2];
             }
         }
         __syncthreads();
@@ -260,6 +272,7 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
 // Adds the partial sums of every split brick, in slot order, and writes the brick.
 template <int DIM, int K>
 __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward_merge(Geom g, const int4* __restrict__ items,
+                                                                       const int32_t* __restrict__ split_first,
                                                                        const int32_t* __restrict__ meta,
                                                                        const float* __restrict__ parts,
                                                                        float* __restrict__ grad, int accumulate)
@@ -267,10 +280,8 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward_merge(Geom g, 
     using S = BwdShape<DIM>;
     constexpr int B = S::B, NOWN = S::NOWN;
     constexpr int C = NumCoeffs<DIM, K>::value;
-    const int32_t item = blockIdx.x;
-    if (item >= meta[META_BSPLIT]) return;
-    const int4 wi = items[item];
-    if (wi.y != 0) return;  // the brick's first item merges
+    if ((int32_t)blockIdx.x >= meta[META_NSPLITB]) return;
+    const int4 wi = items[split_first[blockIdx.x]];
     const int32_t brick = wi.x, nchunk = wi.z, first = wi.w;
     int32_t bc[3];
     vbrick_coords<DIM>(g, brick, bc);
@@ -309,6 +320,7 @@ hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const Ws
     const int4* items = reinterpret_cast<const int4*>(ws + L.bitems_off);
     const int32_t* meta = reinterpret_cast<const int32_t*>(ws + L.meta_off);
     float* parts = reinterpret_cast<float*>(const_cast<char*>(ws) + L.parts_off);
+    const int32_t* split_first = reinterpret_cast<const int32_t*>(ws + L.splitb_off);
     const dim3 grid((unsigned)L.max_bitems);
     const int dim = g->desc.dim, K = g->desc.order;
     float* gr = g->bufs.grad;
@@ -318,7 +330,8 @@ hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const Ws
         const dim3 block(BwdShape<D>::NOWN);                                                                 \
         hipLaunchKernelGGL((k_backward<D, KK>), grid, block, 0, s, g->geom, items, meta, L.max_bitems, parts, rec, \
                            offs, g_f, g_grad, gr, acc);                                                      \
-        hipLaunchKernelGGL((k_backward_merge<D, KK>), grid, block, 0, s, g->geom, items, meta, parts, gr, acc); \
+        hipLaunchKernelGGL((k_backward_merge<D, KK>), dim3((unsigned)g->nbricks), block, 0, s, g->geom, items, \
+                           split_first, meta, parts, gr, acc);                                               \
         return hipGetLastError();                                                                            \
     }
     TG_BWD_CASE(3, 2) TG_BWD_CASE(3, 1) TG_BWD_CASE(3, 0) TG_BWD_CASE(2, 2) TG_BWD_CASE(2, 1) TG_BWD_CASE(2, 0)

@@ -29,7 +29,7 @@ constexpr int kSortThreads = 1024;       // threads per block of the LDS-histogr
 constexpr int32_t kMaxLdsKeys = 16384;   // keys whose LDS histogram fits 64 KB
 constexpr int kMaxSortBlocks = 128;
 constexpr int kFwdChunk = 1024;          // primary records per forward work item
-constexpr int kBwdItem = 2048;           // records per backward work item
+constexpr int kBwdItem = 512;            // records per backward work item
 constexpr int kMaxReduceBlocks = 2048;  // FP64 partials: 4 per block
 constexpr size_t kReduceBytes = (size_t)kMaxReduceBlocks * 4 * sizeof(double);
 constexpr int kScanTile = 4096;          // keys per scan tile (256 threads x 16)
@@ -48,6 +48,7 @@ struct WsLayout {
     size_t fitems_off;   // int2 [max_fitems]: forward work items (brick, chunk)
     size_t bitems_off;   // int4 [max_bitems]: backward items (brick, chunk, chunks, first slot):
                          // split bricks' items from the front, whole bricks from the back
+    size_t splitb_off;   // int32 [nbricks]: first backward item of each split brick
     size_t parts_off;    // float [max_slots x brick accumulator]: partial sums of split bricks
     size_t rec_off;      // float4 [n * 2^dim]: sorted query records (x, y, z, index bits)
     size_t total;
@@ -64,7 +65,7 @@ struct WsLayout {
 };
 
 // Meta words in the workspace.
-enum { META_FITEMS = 0, META_BSPLIT = 1, META_BWHOLE = 2 };
+enum { META_FITEMS = 0, META_BSPLIT = 1, META_BWHOLE = 2, META_NSPLITB = 3 };
 
 WsLayout ws_layout(const tg_grid* g, int64_t n);
 

@@ -47,6 +47,8 @@ __device__ __forceinline__ void query_keys(const Geom& g, const float* q, int32_
     }
 }
 
+constexpr int kSortUnroll = 8;  // queries per thread whose loads are issued together
+
 template <int DIM>
 __device__ __forceinline__ void load_query(const float* __restrict__ q, int64_t i, float* out)
 {
@@ -66,64 +68,103 @@ __device__ __forceinline__ void load_query(const float* __restrict__ q, int64_t 
 struct WorkPtrs {
     int2* fitems;
     int4* bitems;
+    int32_t* split_first;  // first item of each split brick, in order
     int32_t* meta;
     int64_t max_bitems;
 };
 
+constexpr int kFinishThreads = 1024;
+constexpr int kFinishPer = 8;  // bricks per thread and pass
+
+// Block-wide exclusive scan of NV values per thread; returns this thread's exclusive
+// offsets in start[] and the block totals in total[].
+template <int NV>
+__device__ __forceinline__ void block_scan_multi(const int32_t* val, int32_t* start, int32_t* total)
+{
+    __shared__ int32_t wt[NV][kFinishThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t incl[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        incl[v] = val[v];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t o = __shfl_up(incl[v], d, 64);
+            if (lane >= d) incl[v] += o;
+        }
+        if (lane == 63) wt[v][wave] = incl[v];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        int32_t before = 0, all = 0;
+        for (int w = 0; w < kFinishThreads / 64; ++w) {
+            if (w < wave) before += wt[v][w];
+            all += wt[v][w];
+        }
+        start[v] = before + incl[v] - val[v];
+        total[v] = all;
+    }
+    __syncthreads();
+}
+
 __device__ void build_work(const int32_t* offs, int64_t nbricks, WorkPtrs W)
 {
-    __shared__ int32_t wtot[3][kThreads / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int32_t carry[3] = {0, 0, 0};
-    for (int64_t tile = 0; tile < nbricks; tile += kThreads) {
-        const int64_t b = tile + threadIdx.x;
-        int32_t cnt[3] = {0, 0, 0};  // forward items, split backward items, unsplit backward item
-        if (b < nbricks) {
-            const int32_t o0 = offs[2 * b], o1 = offs[2 * b + 1], o2 = offs[2 * b + 2];
-            cnt[0] = (o1 - o0 + kFwdChunk - 1) / kFwdChunk;
-            const int32_t nb = (o2 - o0 + kBwdItem - 1) / kBwdItem;
-            cnt[1] = nb > 1 ? nb : 0;
-            cnt[2] = nb > 1 ? 0 : 1;
-        }
-        int32_t incl[3];
+    int32_t carry[4] = {0, 0, 0, 0};  // forward items, split items, whole items, split bricks
+    for (int64_t tile = 0; tile < nbricks; tile += (int64_t)kFinishThreads * kFinishPer) {
+        const int64_t b0 = tile + (int64_t)threadIdx.x * kFinishPer;
+        int32_t o[kFinishPer + 1][3];
 #pragma unroll
-        for (int v = 0; v < 3; ++v) {
-            incl[v] = cnt[v];
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int32_t o = __shfl_up(incl[v], d, 64);
-                if (lane >= d) incl[v] += o;
+        for (int k = 0; k < kFinishPer; ++k) {
+            const int64_t b = b0 + k;
+            o[k][0] = o[k][1] = o[k][2] = 0;
+            if (b < nbricks) {
+                o[k][0] = offs[2 * b];
+                o[k][1] = offs[2 * b + 1];
+                o[k][2] = offs[2 * b + 2];
             }
-            if (lane == 63) wtot[v][wave] = incl[v];
         }
-        __syncthreads();
-        int32_t start[3];
+        int32_t cnt[kFinishPer][3], tot[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int v = 0; v < 3; ++v) {
-            int32_t before = 0, all = 0;
+        for (int k = 0; k < kFinishPer; ++k) {
+            const bool ok = b0 + k < nbricks;
+            cnt[k][0] = ok ? (o[k][1] - o[k][0] + kFwdChunk - 1) / kFwdChunk : 0;
+            const int32_t nb = ok ? (o[k][2] - o[k][0] + kBwdItem - 1) / kBwdItem : 0;
+            cnt[k][1] = nb > 1 ? nb : 0;
+            cnt[k][2] = ok && nb <= 1 ? 1 : 0;
+            tot[0] += cnt[k][0];
+            tot[1] += cnt[k][1];
+            tot[2] += cnt[k][2];
+            tot[3] += nb > 1 ? 1 : 0;
+        }
+        int32_t start[4], all[4];
+        block_scan_multi<4>(tot, start, all);
+        int32_t pos[4];
 #pragma unroll
-            for (int w = 0; w < kThreads / 64; ++w) {
-                if (w < wave) before += wtot[v][w];
-                all += wtot[v][w];
-            }
-            start[v] = carry[v] + before + incl[v] - cnt[v];
-            carry[v] += all;
+        for (int v = 0; v < 4; ++v) pos[v] = carry[v] + start[v];
+#pragma unroll
+        for (int k = 0; k < kFinishPer; ++k) {
+            const int32_t b = (int32_t)(b0 + k);
+            for (int32_t j = 0; j < cnt[k][0]; ++j) W.fitems[pos[0] + j] = make_int2(b, j);
+            for (int32_t j = 0; j < cnt[k][1]; ++j) W.bitems[pos[1] + j] = make_int4(b, j, cnt[k][1], pos[1]);
+            if (cnt[k][1]) W.split_first[pos[3]++] = pos[1];
+            if (cnt[k][2]) W.bitems[W.max_bitems - 1 - pos[2]] = make_int4(b, 0, 1, -1);
+            pos[0] += cnt[k][0];
+            pos[1] += cnt[k][1];
+            pos[2] += cnt[k][2];
         }
-        __syncthreads();
-        if (b < nbricks) {
-            for (int32_t k = 0; k < cnt[0]; ++k) W.fitems[start[0] + k] = make_int2((int32_t)b, k);
-            for (int32_t k = 0; k < cnt[1]; ++k) W.bitems[start[1] + k] = make_int4((int32_t)b, k, cnt[1], start[1]);
-            if (cnt[2]) W.bitems[W.max_bitems - 1 - start[2]] = make_int4((int32_t)b, 0, 1, -1);
-        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) carry[v] += all[v];
     }
     if (threadIdx.x == 0) {
         W.meta[META_FITEMS] = carry[0];
         W.meta[META_BSPLIT] = carry[1];
         W.meta[META_BWHOLE] = carry[2];
+        W.meta[META_NSPLITB] = carry[3];
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_build_work(const int32_t* __restrict__ offs, int64_t nbricks, WorkPtrs W)
+__global__ __launch_bounds__(kFinishThreads) void k_build_work(const int32_t* __restrict__ offs, int64_t nbricks, WorkPtrs W)
 {
     build_work(offs, nbricks, W);
 }
@@ -139,13 +180,23 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(Geom g, const float
     __syncthreads();
     const int64_t beg = (int64_t)blockIdx.x * slice;
     const int64_t end = min(n, beg + slice);
-    for (int64_t i = beg + threadIdx.x; i < end; i += kSortThreads) {
-        float x[3] = {0.0f, 0.0f, 0.0f};
-        load_query<DIM>(q, i, x);
-        int32_t keys[1 << DIM];
-        int nk;
-        query_keys<DIM>(g, x, keys, nk);
-        for (int k = 0; k < nk; ++k) atomicAdd(&hist[keys[k]], 1u);
+    for (int64_t i0 = beg; i0 < end; i0 += (int64_t)kSortThreads * kSortUnroll) {
+        float x[kSortUnroll][3];
+#pragma unroll
+        for (int u = 0; u < kSortUnroll; ++u) {
+            const int64_t i = i0 + threadIdx.x + (int64_t)u * kSortThreads;
+            x[u][0] = x[u][1] = x[u][2] = 0.0f;
+            if (i < end) load_query<DIM>(q, i, x[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kSortUnroll; ++u) {
+            const int64_t i = i0 + threadIdx.x + (int64_t)u * kSortThreads;
+            if (i >= end) continue;
+            int32_t keys[1 << DIM];
+            int nk;
+            query_keys<DIM>(g, x[u], keys, nk);
+            for (int k = 0; k < nk; ++k) atomicAdd(&hist[keys[k]], 1u);
+        }
     }
     __syncthreads();
     int32_t* row = mat + (int64_t)blockIdx.x * nkeys;
@@ -180,44 +231,30 @@ __global__ __launch_bounds__(kThreads) void k_sort_colscan(int32_t* __restrict__
 }
 
 // One block: exclusive scan of the per-key totals into offs[0..nkeys], then the work lists.
-__global__ __launch_bounds__(kThreads) void k_sort_finish(const int32_t* __restrict__ total, int32_t nkeys,
-                                                         int32_t* __restrict__ offs, WorkPtrs W)
+__global__ __launch_bounds__(kFinishThreads) void k_sort_finish(const int32_t* __restrict__ total, int32_t nkeys,
+                                                               int32_t* __restrict__ offs, WorkPtrs W)
 {
-    __shared__ int32_t wave_tot[kThreads / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int KP = 16;  // keys per thread and pass
     int32_t carry = 0;
-    for (int32_t base = 0; base < nkeys; base += kThreads * 8) {
-        int32_t v[8];
+    for (int32_t base = 0; base < nkeys; base += kFinishThreads * KP) {
+        int32_t v[KP];
         int32_t s = 0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int32_t k = base + threadIdx.x * 8 + u;
+        for (int u = 0; u < KP; ++u) {
+            const int32_t k = base + threadIdx.x * KP + u;
             v[u] = k < nkeys ? total[k] : 0;
             s += v[u];
         }
-        int32_t incl = s;
+        int32_t start[1], all[1];
+        block_scan_multi<1>(&s, start, all);
+        int32_t run = carry + start[0];
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int32_t o = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += o;
-        }
-        if (lane == 63) wave_tot[wave] = incl;
-        __syncthreads();
-        int32_t before = 0, all = 0;
-#pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) {
-            if (w < wave) before += wave_tot[w];
-            all += wave_tot[w];
-        }
-        int32_t run = carry + before + incl - s;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int32_t k = base + threadIdx.x * 8 + u;
+        for (int u = 0; u < KP; ++u) {
+            const int32_t k = base + threadIdx.x * KP + u;
             if (k < nkeys) offs[k] = run;
             run += v[u];
         }
-        carry += all;
-        __syncthreads();
+        carry += all[0];
     }
     if (threadIdx.x == 0) offs[nkeys] = carry;
     __syncthreads();
@@ -237,14 +274,24 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Geom g, const flo
     __syncthreads();
     const int64_t beg = (int64_t)blockIdx.x * slice;
     const int64_t end = min(n, beg + slice);
-    for (int64_t i = beg + threadIdx.x; i < end; i += kSortThreads) {
-        float x[3] = {0.0f, 0.0f, 0.0f};
-        load_query<DIM>(q, i, x);
-        int32_t keys[1 << DIM];
-        int nk;
-        query_keys<DIM>(g, x, keys, nk);
-        const float4 r = make_float4(x[0], x[1], x[2], __int_as_float((int32_t)i));
-        for (int k = 0; k < nk; ++k) rec[atomicAdd(&cursor[keys[k]], 1u)] = r;
+    for (int64_t i0 = beg; i0 < end; i0 += (int64_t)kSortThreads * kSortUnroll) {
+        float x[kSortUnroll][3];
+#pragma unroll
+        for (int u = 0; u < kSortUnroll; ++u) {
+            const int64_t i = i0 + threadIdx.x + (int64_t)u * kSortThreads;
+            x[u][0] = x[u][1] = x[u][2] = 0.0f;
+            if (i < end) load_query<DIM>(q, i, x[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kSortUnroll; ++u) {
+            const int64_t i = i0 + threadIdx.x + (int64_t)u * kSortThreads;
+            if (i >= end) continue;
+            int32_t keys[1 << DIM];
+            int nk;
+            query_keys<DIM>(g, x[u], keys, nk);
+            const float4 r = make_float4(x[u][0], x[u][1], x[u][2], __int_as_float((int32_t)i));
+            for (int k = 0; k < nk; ++k) rec[atomicAdd(&cursor[keys[k]], 1u)] = r;
+        }
     }
 }
 
@@ -410,6 +457,7 @@ hipError_t launch_sort(const tg_grid* g, const float* q, int64_t n, char* ws, co
     W.fitems = reinterpret_cast<int2*>(ws + L.fitems_off);
     W.bitems = reinterpret_cast<int4*>(ws + L.bitems_off);
     W.max_bitems = L.max_bitems;
+    W.split_first = reinterpret_cast<int32_t*>(ws + L.splitb_off);
     W.meta = reinterpret_cast<int32_t*>(ws + L.meta_off);
     if (L.lds_path) {
         int32_t* mat = reinterpret_cast<int32_t*>(ws + L.scratch_off);
@@ -423,7 +471,7 @@ hipError_t launch_sort(const tg_grid* g, const float* q, int64_t n, char* ws, co
             hipLaunchKernelGGL(k_sort_count<2>, gb, tb, lds, s, g->geom, q, n, L.sort_slice, nkeys, mat);
         hipLaunchKernelGGL(k_sort_colscan, dim3(blocks_for(nkeys, kThreads)), dim3(kThreads), 0, s, mat,
                            (int32_t)L.sort_blocks, nkeys, total);
-        hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(kThreads), 0, s, total, nkeys, offs, W);
+        hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(kFinishThreads), 0, s, total, nkeys, offs, W);
         if (n > 0) {
             if (dim == 3)
                 hipLaunchKernelGGL(k_sort_scatter<3>, gb, tb, lds, s, g->geom, q, n, L.sort_slice, nkeys, mat, offs, rec);
@@ -444,7 +492,7 @@ hipError_t launch_sort(const tg_grid* g, const float* q, int64_t n, char* ws, co
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)L.ntiles), dim3(kThreads), 0, s, counts, tiles);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tiles, (int32_t)L.ntiles);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)L.ntiles), dim3(kThreads), 0, s, counts, tiles, offs);
-    hipLaunchKernelGGL(k_build_work, dim3(1), dim3(kThreads), 0, s, offs, g->nbricks, W);
+    hipLaunchKernelGGL(k_build_work, dim3(1), dim3(kFinishThreads), 0, s, offs, g->nbricks, W);
     if (n > 0) {
         if (dim == 3)
             hipLaunchKernelGGL(k_bucket_scatter<3>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, g->geom, q, n, counts, rec);
