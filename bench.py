@@ -23,6 +23,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2402_14415_amd import synth  # noqa: E402  (input generators only)
+
 METRIC = "queries/s fwd+bwd at 128^3 K=2 (and % HBM peak); served query p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 RES = 128
@@ -72,6 +74,80 @@ def cpu_baseline(C64, q, d):
                       f"{flat.size} coefficients, FP64, {dt:.2f} s"}
 
 
+def serving_bench(dev, batches_dev, n_req=400, fit_steps=20):
+    """Serving form: 16 resident BF16 grids (resolution log-uniform in [64, 256], order 1 or
+    2, each fitted to the scene for a few Adam steps), requests of log-uniform 1e3..4e6
+    uniform points.  Saturated throughput first (all requests queued at once), then Poisson
+    arrivals at 50% and 90% of the saturated request rate; latency = completion - arrival."""
+    import torch
+
+    from paper_2402_14415_amd.grid import TaylorGrid, sdf_loss
+    from paper_2402_14415_amd.serving import Server, run_trace
+
+    rng = np.random.default_rng(2)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2)
+    grids, desc = [], []
+    for k in range(16):
+        res = int(round(np.exp(rng.uniform(np.log(64), np.log(256)))))
+        order = int(rng.integers(1, 3))
+        C = (order + 1) * (order + 2) * (order + 3) // 6
+        C0 = torch.randn((res, res, res, C), generator=gen, device=dev) * 0.05
+        g = TaylorGrid(3, (res,) * 3, order, (-1.0,) * 3, (1.0,) * 3, storage="bf16", coeffs=C0, device=dev)
+        del C0
+        nq = batches_dev[0][0].shape[0]
+        ws = g.workspace(nq)
+        for it in range(fit_steps):
+            q, d = batches_dev[it % len(batches_dev)]
+            g.sort(q, ws)
+            f, gr = g.forward(q, ws)
+            _, gf, gg = sdf_loss(f, gr, d, EIK, ws)
+            g.backward(q, ws, gf, gg)
+            g.adam_step(ws, lr=LR)
+        torch.cuda.synchronize()
+        srv_g = TaylorGrid(3, (res,) * 3, order, (-1.0,) * 3, (1.0,) * 3, storage="bf16", coeffs=g.master,
+                           device=dev, optimizer=False)
+        del g, ws
+        grids.append(srv_g)
+        desc.append({"res": res, "order": order})
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    log(f"bench: serving grids fitted: {desc}")
+    nmax = 4_000_000
+    pool = torch.rand((2 * nmax, 3), generator=gen, device=dev) * 2.0 - 1.0
+
+    def make_requests(seed):
+        r = np.random.default_rng(seed)
+        out = []
+        for _ in range(n_req):
+            n = int(round(np.exp(r.uniform(np.log(1e3), np.log(4e6)))))
+            off = int(r.integers(0, nmax))
+            out.append((int(r.integers(0, 16)), pool[off:off + n]))
+        return out
+
+    res = {"grids": desc, "requests_per_phase": n_req, "budget_bytes": 1 << 30, "fit_steps": fit_steps}
+    srv = Server(grids, budget_bytes=1 << 30, streams=2, depth=4, chunk_points=1 << 20)
+    # warm-up pass (allocator, kernels)
+    run_trace(srv, [(0.0, g, q) for g, q in make_requests(9)[:40]])
+    sat = run_trace(srv, [(0.0, g, q) for g, q in make_requests(10)])
+    torch.cuda.synchronize()
+    log(f"bench: serving saturated: {sat}")
+    res["saturated"] = sat
+    mean_n = sat["points"] / sat["requests"]
+    sat_rate = sat["queries_per_s"] / mean_n
+    for frac, seed in ((0.5, 11), (0.9, 12)):
+        lam = frac * sat_rate
+        r = np.random.default_rng(seed)
+        reqs = make_requests(seed)
+        arr = np.cumsum(r.exponential(1.0 / lam, size=len(reqs)))
+        out = run_trace(srv, [(float(t), g, q) for t, (g, q) in zip(arr, reqs)])
+        torch.cuda.synchronize()
+        out["arrival_rate_per_s"] = lam
+        res[f"poisson_{int(frac * 100)}pct"] = out
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +156,7 @@ def main():
     ap.add_argument("--batches", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this path runs on one GPU only (no multi-GPU path is built); use --gpus 1",
@@ -88,7 +165,6 @@ def main():
 
     import torch
 
-    from paper_2402_14415_amd import synth
     from paper_2402_14415_amd.grid import TaylorGrid, sdf_loss
 
     dev = torch.device("cuda", 0)
@@ -201,6 +277,13 @@ def main():
         out["breakdown_us"] = per_call_us
         out["kernels"] = {nm: {"us": per_call_us[nm], "algorithmic_bytes": alg[nm],
                                "GBs": alg[nm] / (per_call_us[nm] * 1e-6) / 1e9} for nm in names}
+    if not args.no_serving:
+        log("bench: serving")
+        out["serving"] = serving_bench(dev, dev_batches)
+        sv = out["serving"]
+        log("bench: serving saturated %.3e q/s; p50/p99 ms at 50%%: %.3f/%.3f, at 90%%: %.3f/%.3f" % (
+            sv["saturated"]["queries_per_s"], sv["poisson_50pct"]["p50_ms"], sv["poisson_50pct"]["p99_ms"],
+            sv["poisson_90pct"]["p50_ms"], sv["poisson_90pct"]["p99_ms"]))
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         q0, d0 = batches[0]
