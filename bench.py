@@ -148,6 +148,74 @@ def serving_bench(dev, batches_dev, n_req=400, fit_steps=20):
     return res
 
 
+def precision_bench(dev, steps=10, warmup=3, n_batches=2):
+    """Precision form at 256^3, K=2, 2^22 queries per step: the same training step with FP32,
+    BF16 and FP16 coefficient storage (FP32 master and accumulation), timed per call, plus
+    the storage rounding's effect on the field: max / RMS of f(storage) - f(FP32 master) on
+    2^16 held-out scene points, both evaluated by the GPU kernels."""
+    import torch
+
+    from paper_2402_14415_amd.grid import TaylorGrid, sdf_loss
+
+    res, nq = 256, 1 << 22
+    scene = synth.Scene(0)
+    batches = []
+    for b in range(n_batches):
+        q, d = synth.scene_batch(scene, nq, seed=0, step=100 + b)
+        batches.append((torch.tensor(q, dtype=torch.float32, device=dev), torch.tensor(d, dtype=torch.float32, device=dev)))
+    qh, _ = synth.scene_batch(scene, 1 << 16, seed=1, step=0)
+    qh = torch.tensor(qh, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    C0 = torch.randn((res, res, res, 10), generator=gen, device=dev) * 0.05
+    out = {"workload": "sdf_fit_256^3_K2", "queries_per_step": nq, "steps": steps, "forms": {}}
+    for storage in ("f32", "bf16", "f16"):
+        grid = TaylorGrid(3, (res,) * 3, 2, (-1.0,) * 3, (1.0,) * 3, storage=storage, coeffs=C0, device=dev)
+        ws = grid.workspace(nq)
+        f = torch.empty(nq, device=dev)
+        g = torch.empty((nq, 3), device=dev)
+        gf = torch.empty(nq, device=dev)
+        gg = torch.empty((nq, 3), device=dev)
+        loss = torch.empty(3, dtype=torch.float64, device=dev)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+        for it in range(warmup + steps):
+            q, d = batches[it % len(batches)]
+            e = evs[it - warmup] if it >= warmup else None
+            e and e[0].record()
+            grid.sort(q, ws)
+            e and e[1].record()
+            grid.forward(q, ws, out=(f, g))
+            e and e[2].record()
+            sdf_loss(f, g, d, EIK, ws, g_f=gf, g_grad=gg, loss=loss)
+            e and e[3].record()
+            grid.backward(q, ws, gf, gg)
+            e and e[4].record()
+            grid.adam_step(ws, lr=LR)
+            e and e[5].record()
+        torch.cuda.synchronize()
+        names = ["sort", "forward", "loss", "backward", "adam"]
+        us = {nm: 1e3 * float(np.mean([e[k].elapsed_time(e[k + 1]) for e in evs])) for k, nm in enumerate(names)}
+        step_us = 1e3 * float(np.mean([e[0].elapsed_time(e[5]) for e in evs]))
+        # rounding effect on the field: storage form vs an FP32 grid on the same master
+        ref = TaylorGrid(3, (res,) * 3, 2, (-1.0,) * 3, (1.0,) * 3, storage="f32", coeffs=grid.master.clone(),
+                         device=dev, optimizer=False)
+        wsh = grid.workspace(qh.shape[0])
+        grid.sort(qh, wsh)
+        fh, _ = grid.forward(qh, wsh)
+        ref.sort(qh, wsh)
+        fr, _ = ref.forward(qh, wsh)
+        diff = (fh.double() - fr.double()).abs()
+        out["forms"][storage] = {
+            "us_per_call": us, "step_us": step_us, "step_queries_per_s": nq / (step_us * 1e-6),
+            "fwd_bwd_queries_per_s": nq / ((us["forward"] + us["backward"]) * 1e-6),
+            "sdf_diff_vs_fp32_master": {"max": float(diff.max()), "rms": float(diff.pow(2).mean().sqrt())},
+            "final_loss": float(loss[0])}
+        log(f"bench: precision {storage}: {out['forms'][storage]}")
+        del grid, ref, ws, wsh
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +225,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this path runs on one GPU only (no multi-GPU path is built); use --gpus 1",
@@ -277,6 +346,9 @@ def main():
         out["breakdown_us"] = per_call_us
         out["kernels"] = {nm: {"us": per_call_us[nm], "algorithmic_bytes": alg[nm],
                                "GBs": alg[nm] / (per_call_us[nm] * 1e-6) / 1e9} for nm in names}
+    if not args.no_precision:
+        log("bench: precision forms")
+        out["precision"] = precision_bench(dev)
     if not args.no_serving:
         log("bench: serving")
         out["serving"] = serving_bench(dev, dev_batches)
