@@ -9,6 +9,8 @@
 #include <new>
 #include <string>
 
+#include <algorithm>
+
 #include "tg_internal.hpp"
 
 namespace {
@@ -70,26 +72,26 @@ WsLayout ws_layout(const tg_grid* g, int64_t n)
     WsLayout L;
     const int dim = g->desc.dim;
     L.nkeys = 2 * g->nbricks;
-    L.nkeys_pad = (L.nkeys / kScanTile + 1) * kScanTile;
-    L.ntiles = L.nkeys_pad / kScanTile;
-    L.lds_path = L.nkeys <= kMaxLdsKeys;
     L.sort_blocks = 0;
     L.sort_slice = 0;
-    if (L.lds_path) {
-        int64_t nb = (n + 4095) / 4096;
-        nb = nb < 1 ? 1 : (nb > kMaxSortBlocks ? kMaxSortBlocks : nb);
-        L.sort_blocks = nb;
-        L.sort_slice = (n + nb - 1) / nb;
+    const int64_t want = std::max<int64_t>(1, (n + kSortMinSlice - 1) / kSortMinSlice);
+    if (L.nkeys <= kMaxLdsKeys32) {
+        L.sort_mode = SORT_LDS32;
+        L.sort_blocks = std::min<int64_t>(want, kMaxSortBlocks);
+    } else if (L.nkeys <= kMaxLdsKeys16 && (n + kMaxSlice16 - 1) / kMaxSlice16 <= kMaxSortBlocks) {
+        L.sort_mode = SORT_LDS16;
+        L.sort_blocks = std::min<int64_t>(want, kMaxSortBlocks);
+    } else {
+        L.sort_mode = SORT_ATOMIC;
     }
+    if (L.sort_blocks > 0) L.sort_slice = (n + L.sort_blocks - 1) / L.sort_blocks;
     size_t off = 0;
     L.reduce_off = off;
     off = align_up(off + kReduceBytes, 256);
     L.counts_off = off;
-    off = align_up(off + (size_t)L.nkeys_pad * 4, 256);
+    off = align_up(off + (size_t)L.nkeys * 4, 256);
     L.offs_off = off;
-    off = align_up(off + (size_t)L.nkeys_pad * 4, 256);
-    L.tiles_off = off;
-    off = align_up(off + (size_t)L.ntiles * 4, 256);
+    off = align_up(off + (size_t)(L.nkeys + 1) * 4, 256);
     L.scratch_off = off;
     off = align_up(off + (size_t)L.sort_blocks * (size_t)L.nkeys * 4, 256);
     const int64_t fan = (int64_t)1 << dim;  // records per query, at most
@@ -232,7 +234,6 @@ static tg_status check_queries(const char* fn, const tg_grid* grid, const float*
     if (!ws) return fail(TG_ERR_INVALID_ARG, "%s: workspace is NULL", fn);
     if (!aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "%s: workspace must be 256-byte aligned", fn);
     *L = tg::ws_layout(grid, n);
-    if (L->ntiles > tg::kMaxScanTiles) return fail(TG_ERR_UNSUPPORTED, "%s: grid has too many bricks to sort", fn);
     if (ws_bytes < L->total)
         return fail(TG_ERR_CAPACITY, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, L->total);
     return ok();

@@ -26,23 +26,25 @@ namespace tg {
 
 constexpr int kThreads = 256;
 constexpr int kSortThreads = 1024;       // threads per block of the LDS-histogram sort
-constexpr int32_t kMaxLdsKeys = 16384;   // keys whose LDS histogram fits 64 KB
-constexpr int kMaxSortBlocks = 128;
+constexpr int64_t kLdsBytes = 160 * 1024; // LDS one workgroup may allocate on gfx950
+constexpr int64_t kMaxLdsKeys32 = kLdsBytes / 4;  // 32-bit LDS counters
+constexpr int64_t kMaxLdsKeys16 = kLdsBytes / 2;  // packed 16-bit LDS counters
+constexpr int64_t kMaxSlice16 = 65535;   // queries per block with 16-bit counters
+constexpr int kMaxSortBlocks = 256;      // rows of the [blocks x keys] count matrix
+constexpr int64_t kSortMinSlice = 4096;  // queries per sort block, at least
+enum SortMode { SORT_LDS32 = 0, SORT_LDS16 = 1, SORT_ATOMIC = 2 };
 constexpr int kFwdChunk = 1024;          // primary records per forward work item
 constexpr int kBwdItem = 512;            // records per backward work item
 constexpr int kMaxReduceBlocks = 2048;  // FP64 partials: 4 per block
 constexpr size_t kReduceBytes = (size_t)kMaxReduceBlocks * 4 * sizeof(double);
-constexpr int kScanTile = 4096;          // keys per scan tile (256 threads x 16)
-constexpr int64_t kMaxScanTiles = 4096;  // one workgroup scans the tile totals
 constexpr int64_t kMaxQueries = (int64_t)1 << 28;  // sort entries stay below 2^31
 
 // Workspace layout of one grid for n queries.  Offsets are from the workspace base and
 // 256-byte aligned.
 struct WsLayout {
     size_t reduce_off;   // FP64 reduction partials (tg_sdf_loss, tg_adam_step)
-    size_t counts_off;   // int32 [nkeys_pad]: per-key totals, or counts then cursors (atomic path)
-    size_t offs_off;     // int32 [nkeys_pad]: exclusive bucket offsets (+ total at [nkeys])
-    size_t tiles_off;    // int32 [ntiles]: scan tile totals, or the block-arrival counter
+    size_t counts_off;   // int32 [nkeys]: per-key totals, or counts then cursors (atomic path)
+    size_t offs_off;     // int32 [nkeys + 1]: exclusive bucket offsets (+ total at [nkeys])
     size_t scratch_off;  // int32 [sort_blocks x nkeys]: per-block key counts, then offsets
     size_t meta_off;     // int32 [16]: work-item totals
     size_t fitems_off;   // int2 [max_fitems]: forward work items (brick, chunk)
@@ -53,9 +55,7 @@ struct WsLayout {
     size_t rec_off;      // float4 [n * 2^dim]: sorted query records (x, y, z, index bits)
     size_t total;
     int64_t nkeys;       // 2 * nbricks (primary / secondary bucket of every vertex brick)
-    int64_t nkeys_pad;   // multiple of kScanTile, > nkeys
-    int64_t ntiles;
-    bool lds_path;       // sort with LDS histograms (else global atomic counters)
+    int sort_mode;       // SortMode
     int64_t sort_blocks; // blocks of the LDS-histogram sort
     int64_t sort_slice;  // queries per sort block
     int64_t max_fitems;  // bound on forward work items
