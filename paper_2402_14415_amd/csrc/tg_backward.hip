@@ -34,8 +34,12 @@ template <int DIM> struct BwdShape {
     static constexpr int NOWN = DIM == 3 ? B * B * B : B * B;  // vertices = threads
     static constexpr int NC1 = B + 1;                           // cells -1..B-1 per axis
     static constexpr int NCELL = DIM == 3 ? NC1 * NC1 * NC1 : NC1 * NC1;
-    static constexpr int CHUNK = 512;                           // records staged at a time
+    static constexpr int NRUN = 1 << (DIM - 1);                 // runs of 2 x-adjacent cells per vertex
+    static constexpr int PER = kBwdItem / NOWN;                 // records staged per thread
+    static constexpr int NBIN = 256;                            // trip-count bins
 };
+static_assert(kBwdItem % BwdShape<3>::NOWN == 0 && kBwdItem % BwdShape<2>::NOWN == 0,
+              "a backward item must split evenly over the threads");
 
 // Writes (or adds) one vertex's C coefficients.
 template <int C>
@@ -59,6 +63,46 @@ __device__ __forceinline__ void store_vertex(float* __restrict__ dst, const floa
     }
 }
 
+// Adds one (corner, query) pair's contribution to a vertex's coefficient adjoint:
+//   acc_alpha += m_alpha(d) s + sum_a u_a dm_alpha/dd_a(d)
+// with the monomials m of Sec. 3.1 Eq. 1 (1, d_a, d_a^2 / 2, d_a d_c), written as FMAs.
+template <int DIM, int K>
+__device__ __forceinline__ void accumulate_corner(const float* d, float s, const float* u, float* acc)
+{
+    acc[0] += s;
+    if constexpr (K >= 1) {
+        float q[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            q[a] = fmaf(s, d[a], u[a]);  // s d_a + u_a
+            acc[1 + a] += q[a];
+        }
+        if constexpr (K == 2) {
+            const float hs = 0.5f * s;
+            if constexpr (DIM == 3) {
+                acc[4] = fmaf(fmaf(hs, d[0], u[0]), d[0], acc[4]);     // xx: d_x (s d_x / 2 + u_x)
+                acc[5] = fmaf(u[1], d[0], fmaf(q[0], d[1], acc[5]));   // xy: d_y (s d_x + u_x) + u_y d_x
+                acc[6] = fmaf(u[2], d[0], fmaf(q[0], d[2], acc[6]));   // xz
+                acc[7] = fmaf(fmaf(hs, d[1], u[1]), d[1], acc[7]);     // yy
+                acc[8] = fmaf(u[2], d[1], fmaf(q[1], d[2], acc[8]));   // yz
+                acc[9] = fmaf(fmaf(hs, d[2], u[2]), d[2], acc[9]);     // zz
+            } else {
+                acc[3] = fmaf(fmaf(hs, d[0], u[0]), d[0], acc[3]);     // xx
+                acc[4] = fmaf(u[1], d[0], fmaf(q[0], d[1], acc[4]));   // xy
+                acc[5] = fmaf(fmaf(hs, d[1], u[1]), d[1], acc[5]);     // yy
+            }
+        }
+    }
+}
+
+// Linear index of a cell relative to the brick: cell coordinates -1..B-1 map to 0..B.
+template <int DIM>
+__device__ __forceinline__ int rel_cell(const int* c)
+{
+    constexpr int NC1 = BwdShape<DIM>::NC1;
+    return DIM == 3 ? (c[2] * NC1 + c[1]) * NC1 + c[0] : c[1] * NC1 + c[0];
+}
+
 template <int DIM, int K>
 __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const int4* __restrict__ items,
                                                                  const int32_t* __restrict__ meta, int64_t max_items,
@@ -70,12 +114,15 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
                                                                  float* __restrict__ grad, int accumulate)
 {
     using S = BwdShape<DIM>;
-    constexpr int B = S::B, NOWN = S::NOWN, NC1 = S::NC1, NCELL = S::NCELL, CHUNK = S::CHUNK;
+    constexpr int B = S::B, NOWN = S::NOWN, NCELL = S::NCELL, NRUN = S::NRUN, PER = S::PER, NBIN = S::NBIN;
     constexpr int C = NumCoeffs<DIM, K>::value;
-    constexpr int PER = CHUNK / NOWN;
-    __shared__ float4 ent[2 * CHUNK];  // cell-sorted (t, g_f) and (g_grad, -) per record
+    // Per staged record, in cell order: (t, g_f), (1 - t, g_grad_x), (t h, g_grad_y),
+    // ((t - 1) h, g_grad_z): the corner factors of both sides of every axis, precomputed.
+    __shared__ float4 ent[4 * kBwdItem];
     __shared__ uint32_t cstart[NCELL + 1];
     __shared__ uint32_t ccount[NCELL];
+    __shared__ uint32_t bins[NBIN];
+    __shared__ uint16_t perm[NOWN];
     __shared__ int32_t wsum[NOWN / 64];
 
     // Split bricks' items come first (longest first), whole bricks from the array's end.
@@ -89,7 +136,8 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
     const int32_t brick = wi.x, chunk = wi.y, nchunk = wi.z;
     const int32_t beg = offs[2 * brick] + chunk * kBwdItem;
     const int32_t end = min(offs[2 * brick + 2], beg + kBwdItem);
-    if (accumulate && nchunk == 1 && beg >= end) return;
+    const int m = end - beg;  // records of this item, at most kBwdItem
+    if (accumulate && nchunk == 1 && m <= 0) return;
 
     int32_t bc[3];
     vbrick_coords<DIM>(g, brick, bc);
@@ -99,174 +147,204 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
         base[a] = bc[a] * B;
         nown[a] = min(B, g.res[a] - base[a]);
     }
-    // this thread's vertex, relative to the brick
-    int v[3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    for (int e = threadIdx.x; e < NCELL; e += NOWN) ccount[e] = 0u;
+    for (int e = threadIdx.x; e < NBIN; e += NOWN) bins[e] = 0u;
+    __syncthreads();
+
+    // Stage: decode this thread's records and rank each within its cell.
+    int my_cell[PER];
+    uint32_t my_rank[PER];
+    float4 my_e[PER][4];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = threadIdx.x + u * NOWN;
+        my_cell[u] = -1;
+        if (i < m) {
+            const float4 r = rec[beg + i];
+            const float q[3] = {r.x, r.y, r.z};
+            const int32_t idx = __float_as_int(r.w);
+            AxisLoc L[DIM];
+            locate<DIM>(g, q, L);
+            float sg[3] = {0.0f, 0.0f, 0.0f}, t[3] = {0.0f, 0.0f, 0.0f}, h[3] = {0.0f, 0.0f, 0.0f};
+            int c[3] = {0, 0, 0};
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                sg[a] = (gg && !L[a].clamped) ? gg[(int64_t)idx * DIM + a] : 0.0f;
+                t[a] = L[a].t;
+                h[a] = g.h[a];
+                c[a] = min(max(L[a].cell - base[a] + 1, 0), B);
+            }
+            my_cell[u] = rel_cell<DIM>(c);
+            my_e[u][0] = make_float4(t[0], t[1], t[2], gf ? gf[idx] : 0.0f);
+            my_e[u][1] = make_float4(1.0f - t[0], 1.0f - t[1], 1.0f - t[2], sg[0]);
+            my_e[u][2] = make_float4(t[0] * h[0], t[1] * h[1], t[2] * h[2], sg[1]);
+            my_e[u][3] = make_float4((t[0] - 1.0f) * h[0], (t[1] - 1.0f) * h[1], (t[2] - 1.0f) * h[2], sg[2]);
+            my_rank[u] = atomicAdd(&ccount[my_cell[u]], 1u);
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the cell counts
     {
-        int r = threadIdx.x;
+        constexpr int CPT = (NCELL + NOWN - 1) / NOWN;
+        uint32_t c[CPT];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int idx = threadIdx.x * CPT + k;
+            c[k] = idx < NCELL ? ccount[idx] : 0u;
+            sum += c[k];
+        }
+        uint32_t incl = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) wsum[wave] = (int32_t)incl;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += (uint32_t)wsum[w];
+        uint32_t run = before + incl - sum;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int idx = threadIdx.x * CPT + k;
+            if (idx < NCELL) cstart[idx] = run;
+            run += c[k];
+        }
+        if (threadIdx.x == NOWN - 1) cstart[NCELL] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        if (my_cell[u] < 0) continue;
+        const uint32_t pos = cstart[my_cell[u]] + my_rank[u];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ent[4 * pos + k] = my_e[u][k];
+    }
+
+    // The records of the 2^dim cells around vertex v form NRUN runs: for every choice of
+    // the y (and z) corner bits, the two x-adjacent cells (v_x - 1, v_x) are neighbours in
+    // cell order.  A record in the run's first cell sees v as its x-high corner.
+    auto vertex_runs = [&](int vid, int* v, bool& owned, uint32_t* off, uint32_t* mid, uint32_t* pre) {
+        int r = vid;
+        owned = true;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             v[a] = r % B;
             r /= B;
+            owned = owned && v[a] < nown[a];
+        }
+        pre[0] = 0u;
+#pragma unroll
+        for (int j = 0; j < NRUN; ++j) {
+            int c[3] = {v[0], v[1] - (j & 1) + 1, DIM == 3 ? v[2] - (j >> 1) + 1 : 0};
+            const int lo = rel_cell<DIM>(c);
+            const uint32_t s0 = cstart[lo], s1 = cstart[lo + 1], s2 = cstart[lo + 2];
+            mid[j] = s1;
+            pre[j + 1] = pre[j] + (owned ? s2 - s0 : 0u);
+            off[j] = s0 - pre[j];  // record index = off[j] + k for k in [pre[j], pre[j + 1])
+        }
+    };
+
+    // Lane assignment: threads take vertices in decreasing order of their record count, so
+    // the lanes of a wave have similar trip counts (the gather loop runs as long as its
+    // longest lane).
+    int v[3];
+    bool owned;
+    uint32_t off[NRUN], mid[NRUN], pre[NRUN + 1];
+    vertex_runs(threadIdx.x, v, owned, off, mid, pre);
+    const uint32_t key = NBIN - 1 - min(pre[NRUN], (uint32_t)(NBIN - 1));
+    const uint32_t brank = atomicAdd(&bins[key], 1u);
+    __syncthreads();
+    if (wave == 0) {
+        constexpr int BPL = NBIN / 64;
+        uint32_t c[BPL], sum = 0;
+#pragma unroll
+        for (int k = 0; k < BPL; ++k) {
+            c[k] = bins[lane * BPL + k];
+            sum += c[k];
+        }
+        uint32_t incl = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        uint32_t run = incl - sum;
+#pragma unroll
+        for (int k = 0; k < BPL; ++k) {
+            bins[lane * BPL + k] = run;
+            run += c[k];
         }
     }
-    bool mine = true;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) mine = mine && v[a] < nown[a];
+    __syncthreads();
+    perm[bins[key] + brank] = (uint16_t)threadIdx.x;
+    __syncthreads();
+    const int vid = perm[threadIdx.x];
+    vertex_runs(vid, v, owned, off, mid, pre);
 
     float acc[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) acc[k] = 0.0f;
-
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int32_t cbeg = beg; cbeg < end; cbeg += CHUNK) {
-        const int m = min(CHUNK, end - cbeg);
-        for (int e = threadIdx.x; e < NCELL; e += NOWN) ccount[e] = 0u;
-        __syncthreads();
-
-        // Stage: decode records, rank them within their cell.
-        int my_cell[PER];
-        uint32_t my_rank[PER];
-        float4 my_e0[PER], my_e1[PER];
+    const uint32_t total = pre[NRUN];
+    for (uint32_t k = 0; k < total; ++k) {
+        uint32_t e = off[0] + k, md = mid[0];
+        int j = 0;
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int i = threadIdx.x + u * NOWN;
-            my_cell[u] = -1;
-            if (i < m) {
-                const float4 r = rec[cbeg + i];
-                const float q[3] = {r.x, r.y, r.z};
-                const int32_t idx = __float_as_int(r.w);
-                AxisLoc L[DIM];
-                locate<DIM>(g, q, L);
-                float sg[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) sg[a] = (gg && !L[a].clamped) ? gg[(int64_t)idx * DIM + a] : 0.0f;
-                int cell = 0;
-#pragma unroll
-                for (int a = DIM - 1; a >= 0; --a) cell = cell * NC1 + min(max(L[a].cell - base[a] + 1, 0), B);
-                my_cell[u] = cell;
-                my_e0[u] = make_float4(L[0].t, L[1].t, DIM == 3 ? L[DIM - 1].t : 0.0f, gf ? gf[idx] : 0.0f);
-                my_e1[u] = make_float4(sg[0], sg[1], sg[2], 0.0f);
-                my_rank[u] = atomicAdd(&ccount[cell], 1u);
+        for (int jj = 1; jj < NRUN; ++jj)
+            if (k >= pre[jj]) {
+                e = off[jj] + k;
+                md = mid[jj];
+                j = jj;
             }
+        const bool b[3] = {e < md, (j & 1) != 0, (j >> 1) != 0};
+        const float4 E0 = ent[4 * e], E1 = ent[4 * e + 1], E2 = ent[4 * e + 2], E3 = ent[4 * e + 3];
+        const float tt[3] = {E0.x, E0.y, E0.z}, om[3] = {E1.x, E1.y, E1.z};
+        const float th[3] = {E2.x, E2.y, E2.z}, tm[3] = {E3.x, E3.y, E3.z};
+        const float sg[3] = {E1.w, E2.w, E3.w};
+        float fa[DIM], d[DIM], sa[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            fa[a] = b[a] ? tt[a] : om[a];          // this corner's weight factor on axis a
+            d[a] = b[a] ? tm[a] : th[a];           // offset from the vertex, world units
+            sa[a] = b[a] ? g.inv_h[a] : -g.inv_h[a];
         }
-        __syncthreads();
-        // exclusive scan of the cell counts
-        {
-            constexpr int CPT = (NCELL + NOWN - 1) / NOWN;
-            uint32_t c[CPT];
-            uint32_t s = 0;
-#pragma unroll
-            for (int k = 0; k < CPT; ++k) {
-                const int idx = threadIdx.x * CPT + k;
-                c[k] = idx < NCELL ? ccount[idx] : 0u;
-                s += c[k];
-            }
-            uint32_t incl = s;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t o = __shfl_up(incl, d, 64);
-                if (lane >= d) incl += o;
-            }
-            if (lane == 63) wsum[wave] = (int32_t)incl;
-            __syncthreads();
-            uint32_t before = 0;
-            for (int w = 0; w < wave; ++w) before += (uint32_t)wsum[w];
-            uint32_t run = before + incl - s;
-#pragma unroll
-            for (int k = 0; k < CPT; ++k) {
-                const int idx = threadIdx.x * CPT + k;
-                if (idx < NCELL) cstart[idx] = run;
-                run += c[k];
-            }
-            if (threadIdx.x == NOWN - 1) cstart[NCELL] = run;
+        float w, dw[DIM];
+        if constexpr (DIM == 3) {
+            const float fyz = fa[1] * fa[2], fxz = fa[0] * fa[2], fxy = fa[0] * fa[1];
+            w = fa[0] * fyz;
+            dw[0] = sa[0] * fyz;
+            dw[1] = sa[1] * fxz;
+            dw[2] = sa[2] * fxy;
+        } else {
+            w = fa[0] * fa[1];
+            dw[0] = sa[0] * fa[1];
+            dw[1] = sa[1] * fa[0];
         }
-        __syncthreads();
+        float s = E0.w * w;
+        float uu[DIM];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            if (my_cell[u] < 0) continue;
-            const uint32_t pos = cstart[my_cell[u]] + my_rank[u];
-            ent[2 * pos] = my_e0[u];
-            ent[2 * pos + 1] = my_e1[u];
+        for (int a = 0; a < DIM; ++a) {
+            s = fmaf(sg[a], dw[a], s);
+            uu[a] = w * sg[a];
         }
-        __syncthreads();
-
-        // Gather: every (corner, record) pair of this thread's vertex, one flattened loop.
-        // The record ranges of the 2^dim cells around the vertex are read up front (they do
-        // not depend on each other); the loop then picks the corner with register selects.
-        if (mine) {
-            constexpr int NB = 1 << DIM;
-            uint32_t cs[NB], pre[NB + 1];
-            pre[0] = 0u;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                int cell = 0;
-#pragma unroll
-                for (int a = DIM - 1; a >= 0; --a) cell = cell * NC1 + (v[a] - ((b >> a) & 1) + 1);
-                cs[b] = cstart[cell];
-                pre[b + 1] = cstart[cell + 1];
-            }
-#pragma unroll
-            for (int b = 0; b < NB; ++b) pre[b + 1] = pre[b] + (pre[b + 1] - cs[b]);
-            const uint32_t total = pre[NB];
-            for (uint32_t k = 0; k < total; ++k) {
-                int b = 0;
-                uint32_t e = cs[0] + k;
-#pragma unroll
-                for (int bb = 1; bb < NB; ++bb)
-                    if (k >= pre[bb]) {
-                        b = bb;
-                        e = cs[bb] + (k - pre[bb]);
-                    }
-                const float4 e0 = ent[2 * e], e1 = ent[2 * e + 1];
-                const float t[3] = {e0.x, e0.y, e0.z};
-                const float sg[3] = {e1.x, e1.y, e1.z};
-                // weight of this corner and its gradient, and the offset from this vertex
-                float w = 1.0f, d[DIM], fa[DIM], da[DIM];
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    const bool ba = (b >> a) & 1;
-                    fa[a] = ba ? t[a] : 1.0f - t[a];
-                    da[a] = ba ? g.inv_h[a] : -g.inv_h[a];
-                    d[a] = (ba ? t[a] - 1.0f : t[a]) * g.h[a];
-                    w *= fa[a];
-                }
-                float dw[DIM];
-                if constexpr (DIM == 3) {
-                    dw[0] = da[0] * fa[1] * fa[2];
-                    dw[1] = fa[0] * da[1] * fa[2];
-                    dw[2] = fa[0] * fa[1] * da[2];
-                } else {
-                    dw[0] = da[0] * fa[1];
-                    dw[1] = fa[0] * da[1];
-                }
-                float s = e0.w * w;
-                float uu[DIM];
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    s = fmaf(sg[a], dw[a], s);
-                    uu[a] = w * sg[a];
-                }
-                float out[C];
-                corner_adjoint<DIM, K>(d, s, uu, out);
-#pragma unroll
-                for (int k2 = 0; k2 < C; ++k2) acc[k2] += out[k2];
-            }
-        }
-        __syncthreads();
+        accumulate_corner<DIM, K>(d, s, uu, acc);
     }
 
     int64_t vert = (int64_t)(base[0] + v[0]) + (int64_t)(base[1] + v[1]) * g.stride[1];
     if constexpr (DIM == 3) vert += (int64_t)(base[2] + v[2]) * g.stride[2];
     if (nchunk > 1) {
         // partial sums of a split brick: slot = item index, laid out [vertex][C] per brick
-        if (mine) {
-            float* slot = parts + (int64_t)item * (NOWN * C) + threadIdx.x * C;
+        if (owned) {
+            float* slot = parts + (int64_t)item * (NOWN * C) + vid * C;
 #pragma unroll
             for (int k = 0; k < C; ++k) slot[k] = acc[k];
         }
         return;
     }
-    if (mine) store_vertex<C>(grad + vert * C, acc, accumulate);
+    if (owned) store_vertex<C>(grad + vert * C, acc, accumulate);
 }
 
 // Adds the partial sums of every split brick, in slot order, and writes the brick.

@@ -278,35 +278,6 @@ __device__ __forceinline__ void corner_offset(const AxisFactors<DIM>& F, int b, 
     for (int a = 0; a < DIM; ++a) d[a] = F.Dd[a][(b >> a) & 1];
 }
 
-// Adjoint of one corner: the contribution of a query to vertex v_b's coefficient alpha,
-//   m_alpha(d) * s + sum_a u_a dm_alpha/dd_a(d),  s = gf w + gg.dw,  u = w gg,
-// m_alpha(d) = d^alpha / alpha!.  Written into out[C].
-template <int DIM, int K>
-__device__ __forceinline__ void corner_adjoint(const float* d, float s, const float* u, float* out)
-{
-    out[0] = s;
-    if constexpr (K >= 1) {
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) out[1 + a] = fmaf(s, d[a], u[a]);
-    }
-    if constexpr (K == 2) {
-        if constexpr (DIM == 3) {
-            const float hx = 0.5f * d[0], hy = 0.5f * d[1], hz = 0.5f * d[2];
-            out[4] = fmaf(s * hx, d[0], u[0] * d[0]);                       // xx: d^2/2, grad (d, 0, 0)
-            out[5] = fmaf(s * d[0], d[1], fmaf(u[0], d[1], u[1] * d[0]));   // xy
-            out[6] = fmaf(s * d[0], d[2], fmaf(u[0], d[2], u[2] * d[0]));   // xz
-            out[7] = fmaf(s * hy, d[1], u[1] * d[1]);                       // yy
-            out[8] = fmaf(s * d[1], d[2], fmaf(u[1], d[2], u[2] * d[1]));   // yz
-            out[9] = fmaf(s * hz, d[2], u[2] * d[2]);                       // zz
-        } else {
-            const float hx = 0.5f * d[0], hy = 0.5f * d[1];
-            out[3] = fmaf(s * hx, d[0], u[0] * d[0]);                       // xx
-            out[4] = fmaf(s * d[0], d[1], fmaf(u[0], d[1], u[1] * d[0]));   // xy
-            out[5] = fmaf(s * hy, d[1], u[1] * d[1]);                       // yy
-        }
-    }
-}
-
 // Linear brick index (x fastest) of brick coordinates.
 template <int DIM>
 __device__ __forceinline__ int32_t brick_linear(const Geom& g, const int32_t* bc)
