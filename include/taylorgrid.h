@@ -162,6 +162,28 @@ tg_status tg_backward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t
                       const float* g_f, const float* g_grad, float* dq, int32_t flags,
                       void* stream);
 
+/* tg_forward and tg_sdf_loss in one pass, for training: the loss of Sec. 3.2 (Eq. 6
+ * unweighted plus the eikonal term of Eq. 8) is evaluated where f and grad f are computed,
+ * so they need not make a round trip through memory.  Writes g_f [n] and, when g_grad !=
+ * NULL, g_grad [n][dim] exactly as tg_sdf_loss would from tg_forward's outputs, and loss[3]
+ * (device FP64, as tg_sdf_loss; the sums are added in another order).  g_grad == NULL drops
+ * the eikonal term.  f and grad_f (either may be NULL) receive tg_forward's outputs.
+ * d [n] is the target SDF in query order.  Requires the sort of (q, n) in ws. */
+tg_status tg_forward_sdf_loss(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes,
+                              const float* d, float eik_weight, float* g_f, float* g_grad, double* loss,
+                              float* f, float* grad_f, void* stream);
+
+/* tg_backward followed by tg_adam_step in one pass, for training: every vertex brick's
+ * coefficient adjoint (overwrite semantics) is handed straight to the Adam update of that
+ * brick's master, moments and storage copy, so the gradient is never written (bufs.grad is
+ * neither read nor written).  The update is tg_adam_step's, element for element.  If
+ * grad_norm_sq != NULL (device double) it receives sum(dC^2) in FP64.  Requires the sort of
+ * (q, n) in ws, bufs.master, bufs.adam_m, bufs.adam_v (and bufs.coeffs for 16-bit storage).
+ * Must not overlap any other call that touches the same grid's buffers. */
+tg_status tg_backward_adam(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes,
+                           const float* g_f, const float* g_grad, const tg_adam_params* params,
+                           double* grad_norm_sq, void* stream);
+
 /* One Adam step over every coefficient (the paper trains the grid with a fixed learning
  * rate and names no optimizer; this is Adam with bias correction, eps added to the
  * corrected root, and weight decay added to the gradient):

@@ -98,18 +98,23 @@ WsLayout ws_layout(const tg_grid* g, int64_t n)
     const int B = dim == 3 ? BrickEdge<3>::value : BrickEdge<2>::value;
     L.acc_floats = (dim == 3 ? (int64_t)B * B * B : (int64_t)B * B) * g->C;
     L.max_fitems = g->nbricks + (n + kFwdChunk - 1) / kFwdChunk;
+    L.fwd_blocks = 8 * ((L.max_fitems + 7) / 8);
     L.max_bitems = g->nbricks + (n * fan + kBwdItem - 1) / kBwdItem;
     L.max_slots = L.max_bitems;  // a split item's slot is its item index
     L.meta_off = off;
     off = align_up(off + 64, 256);
     L.fitems_off = off;
-    off = align_up(off + (size_t)L.max_fitems * 8, 256);
+    off = align_up(off + (size_t)L.max_fitems * 16, 256);
     L.bitems_off = off;
     off = align_up(off + (size_t)L.max_bitems * 16, 256);
     L.splitb_off = off;
     off = align_up(off + (size_t)g->nbricks * 4, 256);
     L.parts_off = off;
     off = align_up(off + (size_t)L.max_slots * (size_t)L.acc_floats * 4, 256);
+    L.fpart_off = off;
+    off = align_up(off + (size_t)L.fwd_blocks * 2 * sizeof(double), 256);
+    L.bpart_off = off;
+    off = align_up(off + (size_t)(L.max_bitems + g->nbricks) * sizeof(double), 256);
     L.rec_off = off;
     off = align_up(off + (size_t)n * ((size_t)1 << dim) * 16, 256);
     L.total = off;
@@ -302,6 +307,56 @@ tg_status tg_backward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t
     return device_status(e, "tg_backward");
 }
 
+tg_status tg_forward_sdf_loss(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes, const float* d,
+                              float eik_weight, float* g_f, float* g_grad, double* loss, float* f, float* grad_f,
+                              void* stream)
+{
+    tg::WsLayout L;
+    tg_status st = check_queries("tg_forward_sdf_loss", grid, q, n, ws, ws_bytes, &L);
+    if (st != TG_OK) return st;
+    if (n > 0 && (!d || !g_f)) return fail(TG_ERR_INVALID_ARG, "tg_forward_sdf_loss: d and g_f must not be NULL");
+    if (!loss) return fail(TG_ERR_INVALID_ARG, "tg_forward_sdf_loss: loss is NULL");
+    if (!std::isfinite(eik_weight)) return fail(TG_ERR_INVALID_ARG, "tg_forward_sdf_loss: eik_weight is not finite");
+    if (!grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_forward_sdf_loss: grid has no coeffs buffer");
+    st = check_sorted("tg_forward_sdf_loss", grid, q, n, ws);
+    if (st != TG_OK) return st;
+    (void)hipGetLastError();
+    return device_status(tg::launch_forward_loss(grid, n, static_cast<const char*>(ws), L, d, eik_weight, g_f, g_grad,
+                                                 loss, f, grad_f, static_cast<hipStream_t>(stream)),
+                         "tg_forward_sdf_loss");
+}
+
+static tg_status check_adam(const char* fn, const tg_grid* grid, const tg_adam_params* p)
+{
+    if (!grid || !p) return fail(TG_ERR_INVALID_ARG, "%s: grid and params must not be NULL", fn);
+    const tg_grid_buffers& b = grid->bufs;
+    if (!b.master || !b.adam_m || !b.adam_v)
+        return fail(TG_ERR_INVALID_ARG, "%s: master, adam_m and adam_v are required", fn);
+    if (grid->desc.storage != TG_F32 && !b.coeffs)
+        return fail(TG_ERR_INVALID_ARG, "%s: 16-bit storage needs the coeffs buffer", fn);
+    if (p->step < 1) return fail(TG_ERR_INVALID_ARG, "%s: step must be >= 1", fn);
+    if (!std::isfinite(p->lr) || !(p->beta1 >= 0.0f && p->beta1 < 1.0f) || !(p->beta2 >= 0.0f && p->beta2 < 1.0f) ||
+        !(p->eps >= 0.0f) || !std::isfinite(p->weight_decay))
+        return fail(TG_ERR_INVALID_ARG, "%s: hyper-parameters out of range", fn);
+    return ok();
+}
+
+tg_status tg_backward_adam(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes, const float* g_f,
+                           const float* g_grad, const tg_adam_params* params, double* grad_norm_sq, void* stream)
+{
+    tg::WsLayout L;
+    tg_status st = check_queries("tg_backward_adam", grid, q, n, ws, ws_bytes, &L);
+    if (st != TG_OK) return st;
+    st = check_adam("tg_backward_adam", grid, params);
+    if (st != TG_OK) return st;
+    st = check_sorted("tg_backward_adam", grid, q, n, ws);
+    if (st != TG_OK) return st;
+    (void)hipGetLastError();
+    return device_status(tg::launch_backward_adam(grid, n, static_cast<const char*>(ws), L, g_f, g_grad, *params,
+                                                  grad_norm_sq, static_cast<hipStream_t>(stream)),
+                         "tg_backward_adam");
+}
+
 tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_f, const float* d, float eik_weight,
                       float* g_f, float* g_grad, double* loss, void* ws, size_t ws_bytes, void* stream)
 {
@@ -322,17 +377,10 @@ tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_
 tg_status tg_adam_step(tg_grid* grid, const tg_adam_params* p, double* grad_norm_sq, void* ws, size_t ws_bytes,
                        int32_t flags, void* stream)
 {
-    if (!grid || !p) return fail(TG_ERR_INVALID_ARG, "tg_adam_step: grid and params must not be NULL");
+    tg_status st = check_adam("tg_adam_step", grid, p);
+    if (st != TG_OK) return st;
     if (flags & ~TG_ADAM_ZERO_GRAD) return fail(TG_ERR_INVALID_ARG, "tg_adam_step: unknown flags 0x%x", flags);
-    const tg_grid_buffers& b = grid->bufs;
-    if (!b.master || !b.grad || !b.adam_m || !b.adam_v)
-        return fail(TG_ERR_INVALID_ARG, "tg_adam_step: master, grad, adam_m and adam_v are required");
-    if (grid->desc.storage != TG_F32 && !b.coeffs)
-        return fail(TG_ERR_INVALID_ARG, "tg_adam_step: 16-bit storage needs the coeffs buffer");
-    if (p->step < 1) return fail(TG_ERR_INVALID_ARG, "tg_adam_step: step must be >= 1");
-    if (!std::isfinite(p->lr) || !(p->beta1 >= 0.0f && p->beta1 < 1.0f) || !(p->beta2 >= 0.0f && p->beta2 < 1.0f) ||
-        !(p->eps >= 0.0f) || !std::isfinite(p->weight_decay))
-        return fail(TG_ERR_INVALID_ARG, "tg_adam_step: hyper-parameters out of range");
+    if (!grid->bufs.grad) return fail(TG_ERR_INVALID_ARG, "tg_adam_step: master, grad, adam_m and adam_v are required");
     if (!ws || !aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "tg_adam_step: workspace NULL or not 256-byte aligned");
     if (ws_bytes < tg::kReduceBytes) return fail(TG_ERR_CAPACITY, "tg_adam_step: workspace smaller than %zu bytes", tg::kReduceBytes);
     (void)hipGetLastError();

@@ -41,28 +41,6 @@ template <int DIM> struct BwdShape {
 static_assert(kBwdItem % BwdShape<3>::NOWN == 0 && kBwdItem % BwdShape<2>::NOWN == 0,
               "a backward item must split evenly over the threads");
 
-// Writes (or adds) one vertex's C coefficients.
-template <int C>
-__device__ __forceinline__ void store_vertex(float* __restrict__ dst, const float* v, int accumulate)
-{
-    if constexpr (C % 2 == 0) {
-        float2* o = reinterpret_cast<float2*>(dst);
-#pragma unroll
-        for (int k = 0; k < C / 2; ++k) {
-            float2 x = make_float2(v[2 * k], v[2 * k + 1]);
-            if (accumulate) {
-                const float2 old = o[k];
-                x.x += old.x;
-                x.y += old.y;
-            }
-            o[k] = x;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < C; ++k) dst[k] = accumulate ? dst[k] + v[k] : v[k];
-    }
-}
-
 // Adds one (corner, query) pair's contribution to a vertex's coefficient adjoint:
 //   acc_alpha += m_alpha(d) s + sum_a u_a dm_alpha/dd_a(d)
 // with the monomials m of Sec. 3.1 Eq. 1 (1, d_a, d_a^2 / 2, d_a d_c), written as FMAs.
@@ -103,15 +81,65 @@ __device__ __forceinline__ int rel_cell(const int* c)
     return DIM == 3 ? (c[2] * NC1 + c[1]) * NC1 + c[0] : c[1] * NC1 + c[0];
 }
 
-template <int DIM, int K>
+// Optimizer state for the adjoint kernels that apply Adam in the same pass (AD >= 0: the
+// storage type of the coefficient copy).  partials receives one FP64 sum(dC^2) per block.
+struct AdamBuf {
+    AdamArgs A;
+    float* master;
+    float* m;
+    float* v;
+    void* coeffs;
+    double* partials;
+};
+
+// Writes the brick's coefficient adjoint to grad (AD < 0: =, or += when accumulating), or
+// applies Adam to it (AD >= 0), walking the brick row by row so that consecutive threads
+// touch consecutive words.  vk[k] is the value of element e = threadIdx.x + k * NOWN of the
+// brick's [vertex][C] block list (vertex = x + B (y + B z)); a row of B vertices along x is
+// B * C contiguous words in memory.  Returns this thread's share of sum(value^2).
+template <int DIM, int C, int AD>
+__device__ __forceinline__ double brick_epilogue(const Geom& g, const int32_t* base, const int32_t* nown,
+                                                 const float* vk, float* __restrict__ grad, int accumulate,
+                                                 const AdamBuf& AB)
+{
+    using S = BwdShape<DIM>;
+    constexpr int B = S::B, NOWN = S::NOWN, RL = B * C;
+    double ss = 0.0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int e = threadIdx.x + k * NOWN;
+        const int r = e / RL, p = e - r * RL;
+        const int y = r % B, z = r / B;
+        bool ok = p < nown[0] * C && y < nown[1];
+        if constexpr (DIM == 3) ok = ok && z < nown[2];
+        if (!ok) continue;
+        int64_t vrow = (int64_t)base[0] + (int64_t)(base[1] + y) * g.stride[1];
+        if constexpr (DIM == 3) vrow += (int64_t)(base[2] + z) * g.stride[2];
+        const int64_t gi = vrow * C + p;
+        const float val = vk[k];
+        if constexpr (AD >= 0) {
+            float th = AB.master[gi], m = AB.m[gi], v = AB.v[gi];
+            ss += (double)val * (double)val;
+            adam_elem(AB.A, val, th, m, v);
+            AB.master[gi] = th;
+            AB.m[gi] = m;
+            AB.v[gi] = v;
+            store_copy<AD>(AB.coeffs, gi, th);
+        } else {
+            grad[gi] = accumulate ? grad[gi] + val : val;
+        }
+    }
+    return ss;
+}
+
+template <int DIM, int K, int AD>
 __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const int4* __restrict__ items,
                                                                  const int32_t* __restrict__ meta, int64_t max_items,
                                                                  float* __restrict__ parts,
                                                                  const float4* __restrict__ rec,
-                                                                 const int32_t* __restrict__ offs,
                                                                  const float* __restrict__ gf,
                                                                  const float* __restrict__ gg,
-                                                                 float* __restrict__ grad, int accumulate)
+                                                                 float* __restrict__ grad, int accumulate, AdamBuf AB)
 {
     using S = BwdShape<DIM>;
     constexpr int B = S::B, NOWN = S::NOWN, NCELL = S::NCELL, NRUN = S::NRUN, PER = S::PER, NBIN = S::NBIN;
@@ -129,13 +157,18 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
     const int32_t nsplit = meta[META_BSPLIT], nwhole = meta[META_BWHOLE];
     const int32_t bid = blockIdx.x;
     int32_t item;
-    if (bid < nsplit) item = bid;
-    else if (bid < nsplit + nwhole) item = (int32_t)(max_items - 1 - (bid - nsplit));
-    else return;
+    if (bid < nsplit) {
+        item = bid;
+    } else if (bid < nsplit + nwhole) {
+        item = (int32_t)(max_items - 1 - (bid - nsplit));
+    } else {
+        if constexpr (AD >= 0) {
+            if (threadIdx.x == 0) AB.partials[bid] = 0.0;
+        }
+        return;
+    }
     const int4 wi = items[item];
-    const int32_t brick = wi.x, chunk = wi.y, nchunk = wi.z;
-    const int32_t beg = offs[2 * brick] + chunk * kBwdItem;
-    const int32_t end = min(offs[2 * brick + 2], beg + kBwdItem);
+    const int32_t brick = wi.x, beg = wi.y, end = wi.z, nchunk = wi.w;
     const int m = end - beg;  // records of this item, at most kBwdItem
     if (accumulate && nchunk == 1 && m <= 0) return;
 
@@ -333,68 +366,84 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
         accumulate_corner<DIM, K>(d, s, uu, acc);
     }
 
-    int64_t vert = (int64_t)(base[0] + v[0]) + (int64_t)(base[1] + v[1]) * g.stride[1];
-    if constexpr (DIM == 3) vert += (int64_t)(base[2] + v[2]) * g.stride[2];
-    if (nchunk > 1) {
-        // partial sums of a split brick: slot = item index, laid out [vertex][C] per brick
-        if (owned) {
-            float* slot = parts + (int64_t)item * (NOWN * C) + vid * C;
+    // Hand the sums over through LDS in [vertex][C] order (the record table is free now),
+    // then write them row by row.
+    __syncthreads();
+    float* vals = reinterpret_cast<float*>(ent);
 #pragma unroll
-            for (int k = 0; k < C; ++k) slot[k] = acc[k];
+    for (int k = 0; k < C; ++k) vals[vid * C + k] = acc[k];
+    __syncthreads();
+    float vk[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) vk[k] = vals[threadIdx.x + k * NOWN];
+    if (nchunk > 1) {
+        // partial sums of a split brick: slot = item index, laid out [vertex][C]
+        float* slot = parts + (int64_t)item * (NOWN * C);
+#pragma unroll
+        for (int k = 0; k < C; ++k) slot[threadIdx.x + k * NOWN] = vk[k];
+        if constexpr (AD >= 0) {
+            if (threadIdx.x == 0) AB.partials[bid] = 0.0;  // counted by the merge
         }
         return;
     }
-    if (owned) store_vertex<C>(grad + vert * C, acc, accumulate);
+    if constexpr (AD >= 0) {
+        const double tot = block_sum_f64<NOWN>(brick_epilogue<DIM, C, AD>(g, base, nown, vk, grad, 0, AB));
+        if (threadIdx.x == 0) AB.partials[bid] = tot;
+    } else {
+        brick_epilogue<DIM, C, AD>(g, base, nown, vk, grad, accumulate, AB);
+    }
 }
 
-// Adds the partial sums of every split brick, in slot order, and writes the brick.
-template <int DIM, int K>
+// Adds the partial sums of every split brick, in slot order, and writes the brick (or, with
+// AD >= 0, applies Adam to it; block b's sum(dC^2) goes to partials[max_items + b]).
+template <int DIM, int K, int AD>
 __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward_merge(Geom g, const int4* __restrict__ items,
                                                                        const int32_t* __restrict__ split_first,
                                                                        const int32_t* __restrict__ meta,
                                                                        const float* __restrict__ parts,
-                                                                       float* __restrict__ grad, int accumulate)
+                                                                       float* __restrict__ grad, int accumulate,
+                                                                       int64_t max_items, AdamBuf AB)
 {
     using S = BwdShape<DIM>;
     constexpr int B = S::B, NOWN = S::NOWN;
     constexpr int C = NumCoeffs<DIM, K>::value;
-    if ((int32_t)blockIdx.x >= meta[META_NSPLITB]) return;
-    const int4 wi = items[split_first[blockIdx.x]];
-    const int32_t brick = wi.x, nchunk = wi.z, first = wi.w;
-    int32_t bc[3];
-    vbrick_coords<DIM>(g, brick, bc);
-    int v[3];
-    {
-        int r = threadIdx.x;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            v[a] = r % B;
-            r /= B;
+    if ((int32_t)blockIdx.x >= meta[META_NSPLITB]) {
+        if constexpr (AD >= 0) {
+            if (threadIdx.x == 0) AB.partials[max_items + blockIdx.x] = 0.0;
         }
+        return;
     }
-    bool mine = true;
+    const int32_t first = split_first[blockIdx.x];
+    const int4 wi = items[first];
+    const int32_t brick = wi.x, nchunk = wi.w;
+    int32_t bc[3], base[3], nown[3];
+    vbrick_coords<DIM>(g, brick, bc);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) mine = mine && v[a] < min(B, g.res[a] - bc[a] * B);
-    if (!mine) return;
-    float acc[C];
+    for (int a = 0; a < DIM; ++a) {
+        base[a] = bc[a] * B;
+        nown[a] = min(B, g.res[a] - base[a]);
+    }
+    float vk[C];
 #pragma unroll
-    for (int k = 0; k < C; ++k) acc[k] = 0.0f;
+    for (int k = 0; k < C; ++k) vk[k] = 0.0f;
     for (int j = 0; j < nchunk; ++j) {
-        const float* slot = parts + (int64_t)(first + j) * (NOWN * C) + threadIdx.x * C;
+        const float* slot = parts + (int64_t)(first + j) * (NOWN * C);
 #pragma unroll
-        for (int k = 0; k < C; ++k) acc[k] += slot[k];
+        for (int k = 0; k < C; ++k) vk[k] += slot[threadIdx.x + k * NOWN];
     }
-    int64_t vert = (int64_t)(bc[0] * B + v[0]) + (int64_t)(bc[1] * B + v[1]) * g.stride[1];
-    if constexpr (DIM == 3) vert += (int64_t)(bc[2] * B + v[2]) * g.stride[2];
-    store_vertex<C>(grad + vert * C, acc, accumulate);
+    if constexpr (AD >= 0) {
+        const double tot = block_sum_f64<NOWN>(brick_epilogue<DIM, C, AD>(g, base, nown, vk, grad, 0, AB));
+        if (threadIdx.x == 0) AB.partials[max_items + blockIdx.x] = tot;
+    } else {
+        brick_epilogue<DIM, C, AD>(g, base, nown, vk, grad, accumulate, AB);
+    }
 }
 
-hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
-                           const float* g_grad, bool accumulate, hipStream_t s)
+template <int AD>
+static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const WsLayout& L, const float* g_f,
+                                       const float* g_grad, bool accumulate, const AdamBuf& AB, hipStream_t s)
 {
-    (void)n;
     const float4* rec = reinterpret_cast<const float4*>(ws + L.rec_off);
-    const int32_t* offs = reinterpret_cast<const int32_t*>(ws + L.offs_off);
     const int4* items = reinterpret_cast<const int4*>(ws + L.bitems_off);
     const int32_t* meta = reinterpret_cast<const int32_t*>(ws + L.meta_off);
     float* parts = reinterpret_cast<float*>(const_cast<char*>(ws) + L.parts_off);
@@ -406,15 +455,43 @@ hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const Ws
 #define TG_BWD_CASE(D, KK)                                                                                   \
     if (dim == D && K == KK) {                                                                               \
         const dim3 block(BwdShape<D>::NOWN);                                                                 \
-        hipLaunchKernelGGL((k_backward<D, KK>), grid, block, 0, s, g->geom, items, meta, L.max_bitems, parts, rec, \
-                           offs, g_f, g_grad, gr, acc);                                                      \
-        hipLaunchKernelGGL((k_backward_merge<D, KK>), dim3((unsigned)g->nbricks), block, 0, s, g->geom, items, \
-                           split_first, meta, parts, gr, acc);                                               \
+        hipLaunchKernelGGL((k_backward<D, KK, AD>), grid, block, 0, s, g->geom, items, meta, L.max_bitems, parts, \
+                           rec, g_f, g_grad, gr, acc, AB);                                                   \
+        hipLaunchKernelGGL((k_backward_merge<D, KK, AD>), dim3((unsigned)g->nbricks), block, 0, s, g->geom,  \
+                           items, split_first, meta, parts, gr, acc, L.max_bitems, AB);                      \
         return hipGetLastError();                                                                            \
     }
     TG_BWD_CASE(3, 2) TG_BWD_CASE(3, 1) TG_BWD_CASE(3, 0) TG_BWD_CASE(2, 2) TG_BWD_CASE(2, 1) TG_BWD_CASE(2, 0)
 #undef TG_BWD_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
+                           const float* g_grad, bool accumulate, hipStream_t s)
+{
+    (void)n;
+    return launch_backward_impl<-1>(g, ws, L, g_f, g_grad, accumulate, AdamBuf{}, s);
+}
+
+hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
+                                const float* g_grad, const tg_adam_params& p, double* grad_norm_sq, hipStream_t s)
+{
+    (void)n;
+    AdamBuf AB;
+    AB.A = make_adam_args(p);
+    AB.master = g->bufs.master;
+    AB.m = g->bufs.adam_m;
+    AB.v = g->bufs.adam_v;
+    AB.coeffs = g->bufs.coeffs;
+    AB.partials = reinterpret_cast<double*>(const_cast<char*>(ws) + L.bpart_off);
+    hipError_t e;
+    switch (g->desc.storage) {
+    case ST_F32: e = launch_backward_impl<ST_F32>(g, ws, L, g_f, g_grad, false, AB, s); break;
+    case ST_BF16: e = launch_backward_impl<ST_BF16>(g, ws, L, g_f, g_grad, false, AB, s); break;
+    default: e = launch_backward_impl<ST_F16>(g, ws, L, g_f, g_grad, false, AB, s); break;
+    }
+    if (e != hipSuccess || !grad_norm_sq) return e;
+    return launch_sum_finish(AB.partials, L.max_bitems + g->nbricks, grad_norm_sq, s);
 }
 
 }  // namespace tg

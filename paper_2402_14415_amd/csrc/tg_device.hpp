@@ -278,6 +278,49 @@ __device__ __forceinline__ void corner_offset(const AxisFactors<DIM>& F, int b, 
     for (int a = 0; a < DIM; ++a) d[a] = F.Dd[a][(b >> a) & 1];
 }
 
+// ------------------------------------------------------------------ Adam (shared by the
+// stand-alone optimizer kernel and the adjoint kernel that applies it in the same pass)
+struct AdamArgs {
+    float lr_over_bc1;       // lr / (1 - beta1^t)
+    float inv_sqrt_bc2;      // 1 / sqrt(1 - beta2^t)
+    float beta1, beta2, one_minus_beta1, one_minus_beta2, eps, wd;
+};
+
+__device__ __forceinline__ float adam_elem(const AdamArgs& A, float g, float& th, float& m, float& v)
+{
+    const float gp = fmaf(A.wd, th, g);
+    m = fmaf(A.beta1, m, A.one_minus_beta1 * gp);
+    v = fmaf(A.beta2, v, A.one_minus_beta2 * gp * gp);
+    const float denom = fmaf(sqrtf(v), A.inv_sqrt_bc2, A.eps);
+    th = th - A.lr_over_bc1 * (m / denom);
+    return th;
+}
+
+template <int ST>
+__device__ __forceinline__ void store_copy(void* coeffs, int64_t i, float v)
+{
+    if constexpr (ST == ST_BF16) static_cast<uint16_t*>(coeffs)[i] = float_to_bf16_rne(v);
+    else if constexpr (ST == ST_F16) static_cast<uint16_t*>(coeffs)[i] = float_to_f16_rne_sat(v);
+}
+
+// Sum of one double over a block of NT threads (a multiple of 64); valid in thread 0.
+// Fixed reduction order, so the result does not depend on scheduling.
+template <int NT>
+__device__ __forceinline__ double block_sum_f64(double v)
+{
+    __shared__ double part[NT / 64];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) part[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) r += part[w];
+    return r;
+}
+
 // Linear brick index (x fastest) of brick coordinates.
 template <int DIM>
 __device__ __forceinline__ int32_t brick_linear(const Geom& g, const int32_t* bc)

@@ -11,7 +11,20 @@
 
 namespace tg {
 
-enum { MODE_FWD = 0, MODE_DQ = 1 };
+enum { MODE_FWD = 0, MODE_DQ = 1, MODE_LOSS = 2 };
+
+// The SDF objective evaluated in the forward's epilogue (Sec. 3.2 Eq. 6 and the eikonal term
+// of Eq. 8): per query r = f - d, g_f = sign(r) / n, and with an eikonal term
+// g_grad = 2 w (|grad f| - 1) grad f / (|grad f| n) (zero where grad f = 0); per workgroup
+// the FP64 sums of |r| and (|grad f| - 1)^2.
+struct LossArgs {
+    const float* d;     // target SDF, query order
+    float* gf;          // upstream gradient of f, query order
+    float* gg;          // upstream gradient of grad f (NULL: no eikonal term)
+    double* partials;   // [2 x gridDim.x]
+    float w_eik;
+    float inv_n;
+};
 
 template <int C> struct LdsPad { static constexpr int value = C == 1 ? 1 : (C <= 4 ? 4 : (C <= 8 ? 8 : 12)); };
 
@@ -53,13 +66,12 @@ template <int DIM> __host__ __device__ constexpr int hidx(int a, int c)
 }
 
 template <int DIM, int K, int ST, int MODE>
-__global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int2* __restrict__ items,
+__global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __restrict__ items,
                                                      const int32_t* __restrict__ meta, const void* __restrict__ coeffs,
                                                      const float4* __restrict__ rec,
-                                                     const int32_t* __restrict__ offs,
                                                      float* __restrict__ f_out, float* __restrict__ grad_out,
                                                      const float* __restrict__ gf, const float* __restrict__ gg,
-                                                     float* __restrict__ dq_out)
+                                                     float* __restrict__ dq_out, LossArgs LA)
 {
     constexpr int B = BrickEdge<DIM>::value;
     constexpr int C = NumCoeffs<DIM, K>::value;
@@ -75,14 +87,18 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int2* __rest
     // layers that neighbouring bricks share stay in one L2.
     const int32_t total = meta[META_FITEMS];
     const int32_t per = (total + 7) / 8;
-    if ((int32_t)(blockIdx.x / 8) >= per) return;
     const int32_t item = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
-    if (item >= total) return;
-    const int2 wi = items[item];
-    const int32_t brick = wi.x;
-    const int32_t beg = offs[2 * brick] + wi.y * kFwdChunk;
-    const int32_t end = min(offs[2 * brick + 1], beg + kFwdChunk);
-    if (beg >= end) return;
+    const int4 wi = (int32_t)(blockIdx.x / 8) < per && item < total ? items[item] : make_int4(0, 0, 0, 0);
+    const int32_t brick = wi.x, beg = wi.y, end = wi.z;
+    if (beg >= end) {
+        if constexpr (MODE == MODE_LOSS) {
+            if (threadIdx.x == 0) {
+                LA.partials[2 * blockIdx.x] = 0.0;
+                LA.partials[2 * blockIdx.x + 1] = 0.0;
+            }
+        }
+        return;
+    }
 
     int32_t bc[3];
     brick_coords<DIM>(g, brick, bc);
@@ -136,6 +152,7 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int2* __rest
     }
     __syncthreads();
 
+    double sum_r = 0.0, sum_e = 0.0;  // loss sums (MODE_LOSS)
     for (int32_t j = beg + threadIdx.x; j < end; j += kThreads) {
         const float4 r = rec[j];
         const float q[3] = {r.x, r.y, r.z};
@@ -194,13 +211,30 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int2* __rest
         for (int a = 0; a < DIM; ++a)
             if (L[a].clamped) gr[a] = 0.0f;
 
-        if constexpr (MODE == MODE_FWD) {
-            f_out[idx] = f;
+        if constexpr (MODE == MODE_FWD || MODE == MODE_LOSS) {
+            if (f_out) f_out[idx] = f;
             if (grad_out) {
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) grad_out[(int64_t)idx * DIM + a] = gr[a];
             }
-        } else {
+        }
+        if constexpr (MODE == MODE_LOSS) {
+            const float res = f - LA.d[idx];
+            sum_r += (double)fabsf(res);
+            LA.gf[idx] = res > 0.0f ? LA.inv_n : (res < 0.0f ? -LA.inv_n : 0.0f);
+            if (LA.gg) {
+                float n2 = 0.0f;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) n2 = fmaf(gr[a], gr[a], n2);
+                const float nrm = sqrtf(n2);
+                const float e = nrm - 1.0f;
+                sum_e += (double)e * (double)e;
+                const float k = nrm > 0.0f ? 2.0f * LA.w_eik * e / nrm * LA.inv_n : 0.0f;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) LA.gg[(int64_t)idx * DIM + a] = k * gr[a];
+            }
+        }
+        if constexpr (MODE == MODE_DQ) {
             const float sf = gf ? gf[idx] : 0.0f;
             float sg[DIM];
 #pragma unroll
@@ -214,23 +248,30 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int2* __rest
             }
         }
     }
+    if constexpr (MODE == MODE_LOSS) {
+        const double tr = block_sum_f64<kThreads>(sum_r);
+        const double te = block_sum_f64<kThreads>(sum_e);
+        if (threadIdx.x == 0) {
+            LA.partials[2 * blockIdx.x] = tr;
+            LA.partials[2 * blockIdx.x + 1] = te;
+        }
+    }
 }
 
 template <int MODE>
 static hipError_t dispatch(const tg_grid* g, const char* ws, const WsLayout& L, float* f, float* grad_f,
-                           const float* gf, const float* gg, float* dq, hipStream_t s)
+                           const float* gf, const float* gg, float* dq, hipStream_t s, LossArgs LA = LossArgs{})
 {
     const float4* rec = reinterpret_cast<const float4*>(ws + L.rec_off);
-    const int32_t* offs = reinterpret_cast<const int32_t*>(ws + L.offs_off);
-    const int2* items = reinterpret_cast<const int2*>(ws + L.fitems_off);
+    const int4* items = reinterpret_cast<const int4*>(ws + L.fitems_off);
     const int32_t* meta = reinterpret_cast<const int32_t*>(ws + L.meta_off);
-    const dim3 grid((unsigned)(8 * ((L.max_fitems + 7) / 8))), block(kThreads);
+    const dim3 grid((unsigned)L.fwd_blocks), block(kThreads);
     const void* cf = g->bufs.coeffs;
     const int dim = g->desc.dim, K = g->desc.order, st = g->desc.storage;
 #define TG_FWD_CASE(D, KK, ST)                                                                          \
     if (dim == D && K == KK && st == ST) {                                                              \
-        hipLaunchKernelGGL((k_forward<D, KK, ST, MODE>), grid, block, 0, s, g->geom, items, meta, cf, rec, offs, f, \
-                           grad_f, gf, gg, dq);                                                         \
+        hipLaunchKernelGGL((k_forward<D, KK, ST, MODE>), grid, block, 0, s, g->geom, items, meta, cf, rec, f,       \
+                           grad_f, gf, gg, dq, LA);                                                     \
         return hipGetLastError();                                                                       \
     }
 #define TG_FWD_ST(D, KK) TG_FWD_CASE(D, KK, ST_F32) TG_FWD_CASE(D, KK, ST_BF16) TG_FWD_CASE(D, KK, ST_F16)
@@ -245,6 +286,25 @@ hipError_t launch_forward(const tg_grid* g, int64_t n, const char* ws, const WsL
 {
     (void)n;
     return dispatch<MODE_FWD>(g, ws, L, f, grad_f, nullptr, nullptr, nullptr, s);
+}
+
+hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* d,
+                               float eik_weight, float* g_f, float* g_grad, double* loss, float* f, float* grad_f,
+                               hipStream_t s)
+{
+    LossArgs LA;
+    LA.d = d;
+    LA.gf = g_f;
+    LA.gg = g_grad;
+    LA.partials = reinterpret_cast<double*>(const_cast<char*>(ws) + L.fpart_off);
+    LA.w_eik = eik_weight;
+    LA.inv_n = n > 0 ? (float)(1.0 / (double)n) : 0.0f;
+    if (n > 0) {
+        const hipError_t e = dispatch<MODE_LOSS>(g, ws, L, f, grad_f, nullptr, nullptr, nullptr, s, LA);
+        if (e != hipSuccess) return e;
+    }
+    // no partials at n == 0: the finish kernel then writes a zero loss
+    return launch_loss_finish(LA.partials, n > 0 ? L.fwd_blocks : 0, n, g_grad ? eik_weight : 0.0f, loss, s);
 }
 
 hipError_t launch_dq(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,

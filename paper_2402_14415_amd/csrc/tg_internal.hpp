@@ -47,11 +47,13 @@ struct WsLayout {
     size_t offs_off;     // int32 [nkeys + 1]: exclusive bucket offsets (+ total at [nkeys])
     size_t scratch_off;  // int32 [sort_blocks x nkeys]: per-block key counts, then offsets
     size_t meta_off;     // int32 [16]: work-item totals
-    size_t fitems_off;   // int2 [max_fitems]: forward work items (brick, chunk)
-    size_t bitems_off;   // int4 [max_bitems]: backward items (brick, chunk, chunks, first slot):
-                         // split bricks' items from the front, whole bricks from the back
+    size_t fitems_off;   // int4 [max_fitems]: forward work items (brick, first record, end, 0)
+    size_t bitems_off;   // int4 [max_bitems]: backward items (brick, first record, end, items of
+                         // the brick): split bricks' items from the front, whole bricks from the back
     size_t splitb_off;   // int32 [nbricks]: first backward item of each split brick
     size_t parts_off;    // float [max_slots x brick accumulator]: partial sums of split bricks
+    size_t fpart_off;    // double [2 x fwd_blocks]: per-workgroup loss sums of the fused forward
+    size_t bpart_off;    // double [max_bitems + nbricks]: per-workgroup sum(dC^2) of the fused adjoint
     size_t rec_off;      // float4 [n * 2^dim]: sorted query records (x, y, z, index bits)
     size_t total;
     int64_t nkeys;       // 2 * nbricks (primary / secondary bucket of every vertex brick)
@@ -59,6 +61,7 @@ struct WsLayout {
     int64_t sort_blocks; // blocks of the LDS-histogram sort
     int64_t sort_slice;  // queries per sort block
     int64_t max_fitems;  // bound on forward work items
+    int64_t fwd_blocks;  // workgroups of a forward launch
     int64_t max_bitems;  // bound on backward work items
     int64_t max_slots;   // bound on partial-sum slots of split backward bricks
     int64_t acc_floats;  // floats in one brick accumulator (B^dim * C)
@@ -83,6 +86,15 @@ hipError_t launch_sdf_loss(int dim, int64_t n, const float* f, const float* grad
                            hipStream_t s);
 hipError_t launch_adam(const tg_grid* g, const tg_adam_params& p, double* grad_norm_sq, double* partials,
                        bool zero_grad, hipStream_t s);
+hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* d,
+                               float eik_weight, float* g_f, float* g_grad, double* loss, float* f, float* grad_f,
+                               hipStream_t s);
+hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
+                                const float* g_grad, const tg_adam_params& p, double* grad_norm_sq, hipStream_t s);
+hipError_t launch_loss_finish(const double* partials, int64_t nblocks, int64_t n, float eik_weight, double* loss,
+                              hipStream_t s);
+hipError_t launch_sum_finish(const double* partials, int64_t nblocks, double* out, hipStream_t s);
+AdamArgs make_adam_args(const tg_adam_params& p);
 hipError_t launch_query(const tg_grid* const* grids, int32_t n_grids, const tg_request* reqs, int32_t n_reqs,
                         hipStream_t s);
 

@@ -7,20 +7,9 @@
 
 namespace tg {
 
-// Sum of one double across the block (256 threads); valid in thread 0.
 __device__ __forceinline__ double block_sum(double v)
 {
-    __shared__ double part[kThreads / 64];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) part[wave] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kThreads / 64; ++w) r += part[w];
-    return r;
+    return block_sum_f64<kThreads>(v);
 }
 
 static inline unsigned reduce_blocks(int64_t n, int per_thread)
@@ -104,29 +93,6 @@ hipError_t launch_sdf_loss(int dim, int64_t n, const float* f, const float* grad
 }
 
 // ------------------------------------------------------------------ Adam
-struct AdamArgs {
-    float lr_over_bc1;       // lr / (1 - beta1^t)
-    float inv_sqrt_bc2;      // 1 / sqrt(1 - beta2^t)
-    float beta1, beta2, one_minus_beta1, one_minus_beta2, eps, wd;
-};
-
-__device__ __forceinline__ float adam_elem(const AdamArgs& A, float g, float& th, float& m, float& v)
-{
-    const float gp = fmaf(A.wd, th, g);
-    m = fmaf(A.beta1, m, A.one_minus_beta1 * gp);
-    v = fmaf(A.beta2, v, A.one_minus_beta2 * gp * gp);
-    const float denom = fmaf(sqrtf(v), A.inv_sqrt_bc2, A.eps);
-    th = th - A.lr_over_bc1 * (m / denom);
-    return th;
-}
-
-template <int ST>
-__device__ __forceinline__ void store_copy(void* coeffs, int64_t i, float v)
-{
-    if constexpr (ST == ST_BF16) static_cast<uint16_t*>(coeffs)[i] = float_to_bf16_rne(v);
-    else if constexpr (ST == ST_F16) static_cast<uint16_t*>(coeffs)[i] = float_to_f16_rne_sat(v);
-}
-
 // Vectorised by 4 over the first n4*4 elements; the scalar tail is handled by block 0.
 template <int ST>
 __global__ __launch_bounds__(kThreads) void k_adam(int64_t n, AdamArgs A, float* __restrict__ master,
@@ -190,10 +156,8 @@ __global__ __launch_bounds__(kThreads) void k_sum_finish(const double* __restric
     if (threadIdx.x == 0) *out = s;
 }
 
-hipError_t launch_adam(const tg_grid* g, const tg_adam_params& p, double* grad_norm_sq, double* partials,
-                       bool zero_grad, hipStream_t s)
+AdamArgs make_adam_args(const tg_adam_params& p)
 {
-    const int64_t n = g->nvert * g->C;
     const double bc1 = 1.0 - pow((double)p.beta1, (double)p.step);
     const double bc2 = 1.0 - pow((double)p.beta2, (double)p.step);
     AdamArgs A;
@@ -205,6 +169,28 @@ hipError_t launch_adam(const tg_grid* g, const tg_adam_params& p, double* grad_n
     A.one_minus_beta2 = (float)(1.0 - (double)p.beta2);
     A.eps = p.eps;
     A.wd = p.weight_decay;
+    return A;
+}
+
+hipError_t launch_loss_finish(const double* partials, int64_t nblocks, int64_t n, float eik_weight, double* loss,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(kThreads), 0, s, partials, (int)nblocks,
+                       n > 0 ? 1.0 / (double)n : 0.0, (double)eik_weight, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_finish(const double* partials, int64_t nblocks, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kThreads), 0, s, partials, (int)nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const tg_grid* g, const tg_adam_params& p, double* grad_norm_sq, double* partials,
+                       bool zero_grad, hipStream_t s)
+{
+    const int64_t n = g->nvert * g->C;
+    const AdamArgs A = make_adam_args(p);
     const unsigned nb = reduce_blocks(n / 4 + 1, 8);
     const dim3 grid(nb), block(kThreads);
     const int zg = zero_grad ? 1 : 0;

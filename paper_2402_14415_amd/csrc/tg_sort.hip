@@ -60,15 +60,16 @@ __device__ __forceinline__ void load_query(const float* __restrict__ q, int64_t 
 
 // ------------------------------------------------------------------ work lists
 // Splits every brick's buckets into work items so that crowded bricks are shared among
-// several workgroups.  Forward: up to kFwdChunk primary records per item.  Backward: a
+// several workgroups; an item carries its record range.  Forward: up to kFwdChunk primary
+// records per item.  Backward: a
 // brick with more than kBwdItem records (primary + secondary) is split into items of
 // kBwdItem records, listed first (they are the longest and start first); every other brick
 // is one item, listed from the end of the array backwards, including bricks no query
 // touches (the item writes their zero gradient).  A split item's index doubles as its
 // partial-sum slot; a merge kernel adds the slots of a brick in order.
 struct WorkPtrs {
-    int2* fitems;
-    int4* bitems;
+    int4* fitems;  // (brick, first record, end record, 0)
+    int4* bitems;  // (brick, first record, end record, items of the brick)
     int32_t* split_first;  // first item of each split brick, in order
     int32_t* meta;
     int64_t max_bitems;
@@ -147,23 +148,26 @@ __global__ __launch_bounds__(kFinishThreads) void k_sort_finish(const int32_t* t
         for (int k = 0; k < kFinishBricks; ++k) {
             const int64_t b = b0 + k;
             if (b >= nbricks) break;
-            offs[2 * b] = pos[0];
-            offs[2 * b + 1] = pos[0] + tp[k];
+            const int32_t r0 = pos[0], rp = r0 + tp[k], r1 = rp + ts[k];  // primary, secondary ends
+            offs[2 * b] = r0;
+            offs[2 * b + 1] = rp;
             if (cursor) {
-                cursor[2 * b] = pos[0];
-                cursor[2 * b + 1] = pos[0] + tp[k];
+                cursor[2 * b] = r0;
+                cursor[2 * b + 1] = rp;
             }
-            pos[0] += tp[k] + ts[k];
+            pos[0] = r1;
             const int32_t nf = (tp[k] + kFwdChunk - 1) / kFwdChunk;
-            for (int32_t j = 0; j < nf; ++j) W.fitems[pos[1] + j] = make_int2((int32_t)b, j);
+            for (int32_t j = 0; j < nf; ++j)
+                W.fitems[pos[1] + j] = make_int4((int32_t)b, r0 + j * kFwdChunk, min(rp, r0 + (j + 1) * kFwdChunk), 0);
             pos[1] += nf;
             const int32_t nb = (tp[k] + ts[k] + kBwdItem - 1) / kBwdItem;
             if (nb > 1) {
-                for (int32_t j = 0; j < nb; ++j) W.bitems[pos[2] + j] = make_int4((int32_t)b, j, nb, pos[2]);
+                for (int32_t j = 0; j < nb; ++j)
+                    W.bitems[pos[2] + j] = make_int4((int32_t)b, r0 + j * kBwdItem, min(r1, r0 + (j + 1) * kBwdItem), nb);
                 W.split_first[pos[4]++] = pos[2];
                 pos[2] += nb;
             } else {
-                W.bitems[W.max_bitems - 1 - pos[3]] = make_int4((int32_t)b, 0, 1, -1);
+                W.bitems[W.max_bitems - 1 - pos[3]] = make_int4((int32_t)b, r0, r1, 1);
                 ++pos[3];
             }
         }
@@ -390,7 +394,7 @@ hipError_t launch_sort(const tg_grid* g, const float* q, int64_t n, char* ws, co
     float4* rec = reinterpret_cast<float4*>(ws + L.rec_off);
     const int dim = g->desc.dim;
     WorkPtrs W;
-    W.fitems = reinterpret_cast<int2*>(ws + L.fitems_off);
+    W.fitems = reinterpret_cast<int4*>(ws + L.fitems_off);
     W.bitems = reinterpret_cast<int4*>(ws + L.bitems_off);
     W.max_bitems = L.max_bitems;
     W.split_first = reinterpret_cast<int32_t*>(ws + L.splitb_off);

@@ -183,13 +183,55 @@ class TaylorGrid:
                 self.rebind()
         return dq
 
-    def adam_step(self, ws, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0, grad_norm_sq=None,
-                  zero_grad=False, step=None):
-        """One fused Adam step; grad_norm_sq (device float64 [1]) receives sum(grad^2)."""
+    def forward_sdf_loss(self, q, ws, d, eik_weight, g_f=None, g_grad=None, loss=None, eikonal=True, f_out=None,
+                         grad_out=None):
+        """Forward and SDF loss in one pass: returns (loss float64[3], g_f, g_grad or None).
+        ``eikonal=False`` drops the eikonal term; f_out / grad_out optionally receive f and
+        grad f."""
+        n = self._q(q)
+        _check_tensor("d", d, torch.float32, self.device, n)
+        g_f = torch.empty(n, dtype=torch.float32, device=self.device) if g_f is None else g_f
+        _check_tensor("g_f", g_f, torch.float32, self.device, n)
+        if eikonal:
+            if g_grad is None:
+                g_grad = torch.empty((n, self.dim), dtype=torch.float32, device=self.device)
+            _check_tensor("g_grad", g_grad, torch.float32, self.device, n * self.dim)
+        else:
+            g_grad = None
+        loss = torch.empty(3, dtype=torch.float64, device=self.device) if loss is None else loss
+        _check_tensor("loss", loss, torch.float64, self.device, 3)
+        for name, t, k in (("f_out", f_out, n), ("grad_out", grad_out, n * self.dim)):
+            if t is not None:
+                _check_tensor(name, t, torch.float32, self.device, k)
+        _lib.call("tg_forward_sdf_loss", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _ptr(d), float(eik_weight),
+                  _ptr(g_f), _ptr(g_grad), _ptr(loss), _ptr(f_out), _ptr(grad_out), _stream(self.device))
+        return loss, g_f, g_grad
+
+    def _adam_params(self, lr, betas, eps, weight_decay, step):
         if self.adam_m is None:
             raise RuntimeError("grid was created without optimiser state")
         self.step_count = self.step_count + 1 if step is None else int(step)
-        p = _lib.AdamParams(lr, betas[0], betas[1], eps, weight_decay, self.step_count)
+        return _lib.AdamParams(lr, betas[0], betas[1], eps, weight_decay, self.step_count)
+
+    def backward_adam(self, q, ws, g_f=None, g_grad=None, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0,
+                      grad_norm_sq=None, step=None):
+        """Adjoint and Adam step in one pass (``grad`` is not written); grad_norm_sq
+        (device float64 [1]) receives sum(dC^2)."""
+        n = self._q(q)
+        if g_f is not None:
+            _check_tensor("g_f", g_f, torch.float32, self.device, n)
+        if g_grad is not None:
+            _check_tensor("g_grad", g_grad, torch.float32, self.device, n * self.dim)
+        if grad_norm_sq is not None:
+            _check_tensor("grad_norm_sq", grad_norm_sq, torch.float64, self.device)
+        p = self._adam_params(lr, betas, eps, weight_decay, step)
+        _lib.call("tg_backward_adam", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _ptr(g_f), _ptr(g_grad),
+                  ctypes.byref(p), _ptr(grad_norm_sq), _stream(self.device))
+
+    def adam_step(self, ws, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0, grad_norm_sq=None,
+                  zero_grad=False, step=None):
+        """One fused Adam step; grad_norm_sq (device float64 [1]) receives sum(grad^2)."""
+        p = self._adam_params(lr, betas, eps, weight_decay, step)
         if grad_norm_sq is not None:
             _check_tensor("grad_norm_sq", grad_norm_sq, torch.float64, self.device)
         flags = _lib.TG_ADAM_ZERO_GRAD if zero_grad else 0

@@ -1,0 +1,181 @@
+"""The fused training calls against the unfused ones and the oracle:
+  * tg_forward_sdf_loss == tg_forward + tg_sdf_loss (upstream gradients bit for bit; the loss
+    up to the order of the FP64 sums), and against the oracle's forward + loss;
+  * tg_backward_adam == tg_backward + tg_adam_step (master, moments, storage copy and the
+    FP64 gradient norm), including crowded bricks split over several work items."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2402_14415_amd import synth
+from paper_2402_14415_amd.grid import TaylorGrid, sdf_loss
+from parity_util import TOL_GRAD, TOL_VALUE, geometry, nerr, nerr_cols, nudge_off_faces, to_np
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _hot_queries(dim, n, rng, lo=-1.0, hi=1.0):
+    """Uniform queries plus a tenth packed into one small region (crowded bricks)."""
+    q = rng.uniform(lo, hi, size=(n, dim))
+    k = n // 10
+    q[:k] = 0.21 + rng.uniform(0, 0.01, size=(k, dim))
+    return q.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("dim,res,order,eik", [(3, (40, 33, 29), 2, True), (3, (24, 24, 24), 1, True),
+                                                (2, (64, 64), 2, False)])
+def test_forward_sdf_loss_matches_unfused(dim, res, order, eik):
+    rng = np.random.default_rng(11)
+    nc = oracle.Geometry(dim, res, order, (-1.0,) * dim, (1.0,) * dim).num_coeffs
+    shape = tuple(reversed(res)) + (nc,)
+    C32 = rng.normal(0, 0.05, size=shape).astype(np.float32)
+    grid = TaylorGrid(dim, res, order, (-1.0,) * dim, (1.0,) * dim, coeffs=torch.from_numpy(C32), device=DEV)
+    n = 100_003
+    q64 = nudge_off_faces(_hot_queries(dim, n, rng), grid.lo, grid.hi, grid.res)
+    d64 = rng.normal(0, 0.3, size=n).astype(np.float32).astype(np.float64)
+    q = torch.tensor(q64, dtype=torch.float32, device=DEV)
+    d = torch.tensor(d64, dtype=torch.float32, device=DEV)
+    ws = grid.workspace(n)
+    grid.sort(q, ws)
+    f, g = grid.forward(q, ws)
+    loss_u, gf_u, gg_u = sdf_loss(f, g if eik else None, d, 0.1, ws)
+    f2 = torch.empty_like(f)
+    g2 = torch.empty_like(g)
+    loss_f, gf_f, gg_f = grid.forward_sdf_loss(q, ws, d, 0.1, eikonal=eik, f_out=f2, grad_out=g2)
+    torch.cuda.synchronize()
+    assert torch.equal(f2, f) and torch.equal(g2, g)
+    assert torch.equal(gf_f, gf_u)
+    if eik:
+        assert torch.equal(gg_f, gg_u)
+    else:
+        assert gg_f is None
+    np.testing.assert_allclose(to_np(loss_f), to_np(loss_u), rtol=1e-12, atol=0)
+    # against the oracle's forward + loss on the same inputs
+    ref_f, ref_g = oracle.forward(geometry(grid), C32.astype(np.float64), q64)
+    ref_loss, ref_gf, ref_gg = oracle.sdf_loss(ref_f, ref_g if eik else None, d64, 0.1)
+    np.testing.assert_allclose(to_np(loss_f), ref_loss, rtol=TOL_VALUE)
+    # sign(r) may flip where |r| is at rounding level; compare away from r == 0
+    keep = np.abs(ref_f - d64) > 1e-5
+    assert nerr(to_np(gf_f)[keep], ref_gf[keep]) <= TOL_GRAD
+    if eik:
+        assert nerr_cols(to_np(gg_f), ref_gg) <= TOL_GRAD
+
+
+def test_forward_sdf_loss_empty():
+    grid = TaylorGrid(3, (9, 9, 9), 2, (-1.0,) * 3, (1.0,) * 3, device=DEV)
+    q = torch.empty((0, 3), device=DEV)
+    ws = grid.workspace(0)
+    grid.sort(q, ws)
+    loss = torch.full((3,), 7.0, dtype=torch.float64, device=DEV)
+    grid.forward_sdf_loss(q, ws, torch.empty(0, device=DEV), 0.1, loss=loss)
+    torch.cuda.synchronize()
+    assert torch.all(loss == 0)
+
+
+def _twin_grids(dim, res, order, storage, seed):
+    rng = np.random.default_rng(seed)
+    nc = oracle.Geometry(dim, res, order, (-1.0,) * dim, (1.0,) * dim).num_coeffs
+    C32 = rng.normal(0, 0.05, size=tuple(reversed(res)) + (nc,)).astype(np.float32)
+    a = TaylorGrid(dim, res, order, (-1.0,) * dim, (1.0,) * dim, storage=storage,
+                   coeffs=torch.from_numpy(C32), device=DEV)
+    b = TaylorGrid(dim, res, order, (-1.0,) * dim, (1.0,) * dim, storage=storage,
+                   coeffs=torch.from_numpy(C32), device=DEV)
+    # Established moments: the record order inside a bucket (and so the FP32 summation order
+    # of a vertex's gradient) may differ between two sorts, and on a first Adam step a
+    # gradient near zero turns that rounding difference into a step of up to lr.
+    m0 = torch.tensor(rng.normal(0, 1e-5, size=C32.shape), dtype=torch.float32)
+    v0 = torch.tensor(rng.uniform(1e-9, 1e-8, size=C32.shape), dtype=torch.float32)
+    for g_ in (a, b):
+        g_.adam_m.copy_(m0)
+        g_.adam_v.copy_(v0)
+    return a, b, rng
+
+
+@pytest.mark.parametrize("dim,res,order,storage", [(3, (37, 30, 21), 2, "f32"), (3, (37, 30, 21), 2, "bf16"),
+                                                    (3, (20, 20, 20), 1, "f16"), (3, (19, 17, 23), 0, "f32"),
+                                                    (2, (70, 45), 2, "bf16"), (2, (33, 33), 1, "f32")])
+def test_backward_adam_matches_unfused(dim, res, order, storage):
+    a, b, rng = _twin_grids(dim, res, order, storage, seed=21)
+    n = 150_001
+    for step in range(2):
+        q = torch.tensor(_hot_queries(dim, n, rng), dtype=torch.float32, device=DEV)
+        gf = torch.tensor(rng.normal(size=n) / n, dtype=torch.float32, device=DEV)
+        gg = torch.tensor(rng.normal(size=(n, dim)) / n, dtype=torch.float32, device=DEV)
+        ws_a, ws_b = a.workspace(n), b.workspace(n)
+        na = torch.zeros(1, dtype=torch.float64, device=DEV)
+        nb = torch.zeros(1, dtype=torch.float64, device=DEV)
+        a.sort(q, ws_a)
+        a.backward(q, ws_a, gf, gg)
+        a.adam_step(ws_a, lr=1e-2, grad_norm_sq=na, step=10 + step)
+        b.sort(q, ws_b)
+        b.backward_adam(q, ws_b, gf, gg, lr=1e-2, grad_norm_sq=nb, step=10 + step)
+        torch.cuda.synchronize()
+        # A vertex's FP32 gradient is summed in record order, which two sorts may permute:
+        # the moments agree to that rounding (1e-5 of their largest value), the master
+        # (moved by lr * m / sqrt(v)) much closer.
+        for name, tol in (("master", 1e-6), ("adam_m", TOL_VALUE), ("adam_v", TOL_VALUE)):
+            x, y = getattr(b, name), getattr(a, name)
+            e = nerr(to_np(x).reshape(-1), to_np(y).reshape(-1))
+            print(f"step {step} {name}: err {e:.2e}, equal {torch.equal(x, y)}")
+            assert e <= tol
+        if storage != "f32":
+            diff = (b.coeffs.float() - a.coeffs.float()).abs().max().item()
+            scale = a.coeffs.float().abs().max().item()
+            assert diff <= 2 ** -7 * scale  # at most one storage ulp where the masters differ by rounding
+        np.testing.assert_allclose(nb.item(), na.item(), rtol=1e-6)  # FP32 gradients equal up to rounding
+
+
+def test_backward_adam_no_queries():
+    """No queries: every coefficient takes the Adam step of a zero gradient."""
+    a, b, _ = _twin_grids(3, (12, 12, 12), 2, "f32", seed=5)
+    q = torch.empty((0, 3), device=DEV)
+    ws_a, ws_b = a.workspace(0), b.workspace(0)
+    a.sort(q, ws_a)
+    a.backward(q, ws_a)
+    a.adam_step(ws_a)
+    b.sort(q, ws_b)
+    nb = torch.ones(1, dtype=torch.float64, device=DEV)
+    b.backward_adam(q, ws_b, grad_norm_sq=nb)
+    torch.cuda.synchronize()
+    assert torch.equal(a.master, b.master) and torch.equal(a.adam_m, b.adam_m) and torch.equal(a.adam_v, b.adam_v)
+    assert nb.item() == 0.0
+
+
+def test_fused_training_step_config1():
+    """128^3, K=2, 2^20 scene queries: the fused step (sort, forward+loss, adjoint+Adam)
+    against the unfused one, for two steps."""
+    C64, q64, d64, scene = synth.scene3d_inputs(res=128, order=2, n=1 << 20, seed=0)
+    C32 = torch.from_numpy(C64.astype(np.float32))
+    del C64
+    a = TaylorGrid(3, (128,) * 3, 2, (-1.0,) * 3, (1.0,) * 3, coeffs=C32, device=DEV)
+    b = TaylorGrid(3, (128,) * 3, 2, (-1.0,) * 3, (1.0,) * 3, coeffs=C32, device=DEV)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(3)
+    m0 = torch.randn(a.shape, generator=gen, device=DEV) * 1e-5
+    v0 = torch.rand(a.shape, generator=gen, device=DEV) * 9e-9 + 1e-9
+    for g_ in (a, b):  # established moments (see _twin_grids)
+        g_.adam_m.copy_(m0)
+        g_.adam_v.copy_(v0)
+    for step in range(2):
+        qs, ds = (q64, d64) if step == 0 else synth.scene_batch(scene, 1 << 20, seed=0, step=1)
+        q = torch.tensor(qs, dtype=torch.float32, device=DEV)
+        d = torch.tensor(ds, dtype=torch.float32, device=DEV)
+        ws_a, ws_b = a.workspace(q.shape[0]), b.workspace(q.shape[0])
+        a.sort(q, ws_a)
+        f, g = a.forward(q, ws_a)
+        la, gfa, gga = sdf_loss(f, g, d, 0.1, ws_a)
+        a.backward(q, ws_a, gfa, gga)
+        a.adam_step(ws_a, lr=1e-2, step=10 + step)
+        b.sort(q, ws_b)
+        lb, gfb, ggb = b.forward_sdf_loss(q, ws_b, d, 0.1)
+        b.backward_adam(q, ws_b, gfb, ggb, lr=1e-2, step=10 + step)
+        torch.cuda.synchronize()
+        if step == 0:  # same coefficients: same upstream gradients, loss up to FP64 order
+            np.testing.assert_allclose(to_np(lb), to_np(la), rtol=1e-12)
+            assert torch.equal(gfa, gfb) and torch.equal(gga, ggb)
+        else:  # the masters now differ by the rounding of the previous step
+            np.testing.assert_allclose(to_np(lb), to_np(la), rtol=1e-6)
+        for name, tol in (("master", 1e-6), ("adam_m", TOL_VALUE), ("adam_v", TOL_VALUE)):
+            assert nerr(to_np(getattr(b, name)).reshape(-1), to_np(getattr(a, name)).reshape(-1)) <= tol
