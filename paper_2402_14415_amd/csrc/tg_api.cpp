@@ -99,7 +99,7 @@ WsLayout ws_layout(const tg_grid* g, int64_t n)
     L.acc_floats = (dim == 3 ? (int64_t)B * B * B : (int64_t)B * B) * g->C;
     L.max_fitems = g->nbricks + (n + kFwdChunk - 1) / kFwdChunk;
     L.fwd_blocks = 8 * ((L.max_fitems + 7) / 8);
-    L.max_bitems = g->nbricks + (n * fan + kBwdItem - 1) / kBwdItem;
+    L.max_bitems = g->nbricks + (n * fan + kBwdItemMax - 1) / kBwdItemMax;
     L.max_slots = L.max_bitems;  // a split item's slot is its item index
     L.meta_off = off;
     off = align_up(off + 64, 256);

@@ -35,7 +35,7 @@ template <int DIM> struct BwdShape {
     static constexpr int NC1 = B + 1;                           // cells -1..B-1 per axis
     static constexpr int NCELL = DIM == 3 ? NC1 * NC1 * NC1 : NC1 * NC1;
     static constexpr int NRUN = 1 << (DIM - 1);                 // runs of 2 x-adjacent cells per vertex
-    static constexpr int PER = kBwdItem / NOWN;                 // records staged per thread
+    static constexpr int PER = kBwdItem / NOWN;                 // records staged per thread and pass
     static constexpr int NBIN = 256;                            // trip-count bins
 };
 static_assert(kBwdItem % BwdShape<3>::NOWN == 0 && kBwdItem % BwdShape<2>::NOWN == 0,
@@ -133,7 +133,7 @@ __device__ __forceinline__ double brick_epilogue(const Geom& g, const int32_t* b
 }
 
 template <int DIM, int K, int AD>
-__global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const int4* __restrict__ items,
+__global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_per_eu(6))) void k_backward(Geom g, const int4* __restrict__ items,
                                                                  const int32_t* __restrict__ meta, int64_t max_items,
                                                                  float* __restrict__ parts,
                                                                  const float4* __restrict__ rec,
@@ -153,14 +153,15 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
     __shared__ uint16_t perm[NOWN];
     __shared__ int32_t wsum[NOWN / 64];
 
-    // Split bricks' items come first (longest first), whole bricks from the array's end.
-    const int32_t nsplit = meta[META_BSPLIT], nwhole = meta[META_BWHOLE];
+    // Items of bricks with more than one pass of records come first (the longest work
+    // starts first), the others from the array's end.
+    const int32_t nfront = meta[META_BFRONT], nback = meta[META_BBACK];
     const int32_t bid = blockIdx.x;
     int32_t item;
-    if (bid < nsplit) {
+    if (bid < nfront) {
         item = bid;
-    } else if (bid < nsplit + nwhole) {
-        item = (int32_t)(max_items - 1 - (bid - nsplit));
+    } else if (bid < nfront + nback) {
+        item = (int32_t)(max_items - 1 - (bid - nfront));
     } else {
         if constexpr (AD >= 0) {
             if (threadIdx.x == 0) AB.partials[bid] = 0.0;
@@ -169,8 +170,7 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
     }
     const int4 wi = items[item];
     const int32_t brick = wi.x, beg = wi.y, end = wi.z, nchunk = wi.w;
-    const int m = end - beg;  // records of this item, at most kBwdItem
-    if (accumulate && nchunk == 1 && m <= 0) return;
+    if (accumulate && nchunk == 1 && end <= beg) return;
 
     int32_t bc[3];
     vbrick_coords<DIM>(g, brick, bc);
@@ -181,81 +181,6 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
         nown[a] = min(B, g.res[a] - base[a]);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-
-    for (int e = threadIdx.x; e < NCELL; e += NOWN) ccount[e] = 0u;
-    for (int e = threadIdx.x; e < NBIN; e += NOWN) bins[e] = 0u;
-    __syncthreads();
-
-    // Stage: decode this thread's records and rank each within its cell.
-    int my_cell[PER];
-    uint32_t my_rank[PER];
-    float4 my_e[PER][4];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int i = threadIdx.x + u * NOWN;
-        my_cell[u] = -1;
-        if (i < m) {
-            const float4 r = rec[beg + i];
-            const float q[3] = {r.x, r.y, r.z};
-            const int32_t idx = __float_as_int(r.w);
-            AxisLoc L[DIM];
-            locate<DIM>(g, q, L);
-            float sg[3] = {0.0f, 0.0f, 0.0f}, t[3] = {0.0f, 0.0f, 0.0f}, h[3] = {0.0f, 0.0f, 0.0f};
-            int c[3] = {0, 0, 0};
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                sg[a] = (gg && !L[a].clamped) ? gg[(int64_t)idx * DIM + a] : 0.0f;
-                t[a] = L[a].t;
-                h[a] = g.h[a];
-                c[a] = min(max(L[a].cell - base[a] + 1, 0), B);
-            }
-            my_cell[u] = rel_cell<DIM>(c);
-            my_e[u][0] = make_float4(t[0], t[1], t[2], gf ? gf[idx] : 0.0f);
-            my_e[u][1] = make_float4(1.0f - t[0], 1.0f - t[1], 1.0f - t[2], sg[0]);
-            my_e[u][2] = make_float4(t[0] * h[0], t[1] * h[1], t[2] * h[2], sg[1]);
-            my_e[u][3] = make_float4((t[0] - 1.0f) * h[0], (t[1] - 1.0f) * h[1], (t[2] - 1.0f) * h[2], sg[2]);
-            my_rank[u] = atomicAdd(&ccount[my_cell[u]], 1u);
-        }
-    }
-    __syncthreads();
-    // exclusive scan of the cell counts
-    {
-        constexpr int CPT = (NCELL + NOWN - 1) / NOWN;
-        uint32_t c[CPT];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-            const int idx = threadIdx.x * CPT + k;
-            c[k] = idx < NCELL ? ccount[idx] : 0u;
-            sum += c[k];
-        }
-        uint32_t incl = sum;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t o = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += o;
-        }
-        if (lane == 63) wsum[wave] = (int32_t)incl;
-        __syncthreads();
-        uint32_t before = 0;
-        for (int w = 0; w < wave; ++w) before += (uint32_t)wsum[w];
-        uint32_t run = before + incl - sum;
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-            const int idx = threadIdx.x * CPT + k;
-            if (idx < NCELL) cstart[idx] = run;
-            run += c[k];
-        }
-        if (threadIdx.x == NOWN - 1) cstart[NCELL] = run;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        if (my_cell[u] < 0) continue;
-        const uint32_t pos = cstart[my_cell[u]] + my_rank[u];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) ent[4 * pos + k] = my_e[u][k];
-    }
 
     // The records of the 2^dim cells around vertex v form NRUN runs: for every choice of
     // the y (and z) corner bits, the two x-adjacent cells (v_x - 1, v_x) are neighbours in
@@ -281,89 +206,180 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward(Geom g, const 
         }
     };
 
-    // Lane assignment: threads take vertices in decreasing order of their record count, so
-    // the lanes of a wave have similar trip counts (the gather loop runs as long as its
-    // longest lane).
-    int v[3];
-    bool owned;
-    uint32_t off[NRUN], mid[NRUN], pre[NRUN + 1];
-    vertex_runs(threadIdx.x, v, owned, off, mid, pre);
-    const uint32_t key = NBIN - 1 - min(pre[NRUN], (uint32_t)(NBIN - 1));
-    const uint32_t brank = atomicAdd(&bins[key], 1u);
-    __syncthreads();
-    if (wave == 0) {
-        constexpr int BPL = NBIN / 64;
-        uint32_t c[BPL], sum = 0;
-#pragma unroll
-        for (int k = 0; k < BPL; ++k) {
-            c[k] = bins[lane * BPL + k];
-            sum += c[k];
-        }
-        uint32_t incl = sum;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t o = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += o;
-        }
-        uint32_t run = incl - sum;
-#pragma unroll
-        for (int k = 0; k < BPL; ++k) {
-            bins[lane * BPL + k] = run;
-            run += c[k];
-        }
-    }
-    __syncthreads();
-    perm[bins[key] + brank] = (uint16_t)threadIdx.x;
-    __syncthreads();
-    const int vid = perm[threadIdx.x];
-    vertex_runs(vid, v, owned, off, mid, pre);
-
     float acc[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) acc[k] = 0.0f;
-    const uint32_t total = pre[NRUN];
-    for (uint32_t k = 0; k < total; ++k) {
-        uint32_t e = off[0] + k, md = mid[0];
-        int j = 0;
+    int vid = threadIdx.x;  // this thread's vertex (x + B (y + B z) within the brick)
+
+    // One pass per kBwdItem records: stage them in LDS sorted by cell, then every thread
+    // adds the pairs of its vertex.  The lane assignment is chosen in the first pass and kept,
+    // so that a vertex's sums stay in one thread's registers.
+    for (int32_t cbeg = beg; cbeg < end; cbeg += kBwdItem) {
+        const int m = min(kBwdItem, end - cbeg);
+        const bool first_pass = cbeg == beg;
+        if (!first_pass) __syncthreads();  // the previous pass is done with the LDS tables
+        for (int e = threadIdx.x; e < NCELL; e += NOWN) ccount[e] = 0u;
+        if (first_pass)
+            for (int e = threadIdx.x; e < NBIN; e += NOWN) bins[e] = 0u;
+        __syncthreads();
+
+        // Stage: decode this thread's records and rank each within its cell.
+        int my_cell[PER];
+        uint32_t my_rank[PER];
+        float4 my_t[PER], my_g[PER];  // (t, g_f) and (g_grad, -): the rest is derived at placement
 #pragma unroll
-        for (int jj = 1; jj < NRUN; ++jj)
-            if (k >= pre[jj]) {
-                e = off[jj] + k;
-                md = mid[jj];
-                j = jj;
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * NOWN;
+            my_cell[u] = -1;
+            if (i < m) {
+                const float4 r = rec[cbeg + i];
+                const float q[3] = {r.x, r.y, r.z};
+                const int32_t idx = __float_as_int(r.w) & ~kRecSecondary;
+                AxisLoc L[DIM];
+                locate<DIM>(g, q, L);
+                float sg[3] = {0.0f, 0.0f, 0.0f}, t[3] = {0.0f, 0.0f, 0.0f};
+                int c[3] = {0, 0, 0};
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    sg[a] = (gg && !L[a].clamped) ? gg[(int64_t)idx * DIM + a] : 0.0f;
+                    t[a] = L[a].t;
+                    c[a] = min(max(L[a].cell - base[a] + 1, 0), B);
+                }
+                my_cell[u] = rel_cell<DIM>(c);
+                my_t[u] = make_float4(t[0], t[1], t[2], gf ? gf[idx] : 0.0f);
+                my_g[u] = make_float4(sg[0], sg[1], sg[2], 0.0f);
+                my_rank[u] = atomicAdd(&ccount[my_cell[u]], 1u);
             }
-        const bool b[3] = {e < md, (j & 1) != 0, (j >> 1) != 0};
-        const float4 E0 = ent[4 * e], E1 = ent[4 * e + 1], E2 = ent[4 * e + 2], E3 = ent[4 * e + 3];
-        const float tt[3] = {E0.x, E0.y, E0.z}, om[3] = {E1.x, E1.y, E1.z};
-        const float th[3] = {E2.x, E2.y, E2.z}, tm[3] = {E3.x, E3.y, E3.z};
-        const float sg[3] = {E1.w, E2.w, E3.w};
-        float fa[DIM], d[DIM], sa[DIM];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            fa[a] = b[a] ? tt[a] : om[a];          // this corner's weight factor on axis a
-            d[a] = b[a] ? tm[a] : th[a];           // offset from the vertex, world units
-            sa[a] = b[a] ? g.inv_h[a] : -g.inv_h[a];
         }
-        float w, dw[DIM];
-        if constexpr (DIM == 3) {
-            const float fyz = fa[1] * fa[2], fxz = fa[0] * fa[2], fxy = fa[0] * fa[1];
-            w = fa[0] * fyz;
-            dw[0] = sa[0] * fyz;
-            dw[1] = sa[1] * fxz;
-            dw[2] = sa[2] * fxy;
+        __syncthreads();
+        // exclusive scan of the cell counts
+        {
+            constexpr int CPT = (NCELL + NOWN - 1) / NOWN;
+            uint32_t c[CPT];
+            uint32_t sum = 0;
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                const int idx = threadIdx.x * CPT + k;
+                c[k] = idx < NCELL ? ccount[idx] : 0u;
+                sum += c[k];
+            }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t o = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += o;
+            }
+            if (lane == 63) wsum[wave] = (int32_t)incl;
+            __syncthreads();
+            uint32_t before = 0;
+            for (int w = 0; w < wave; ++w) before += (uint32_t)wsum[w];
+            uint32_t run = before + incl - sum;
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                const int idx = threadIdx.x * CPT + k;
+                if (idx < NCELL) cstart[idx] = run;
+                run += c[k];
+            }
+            if (threadIdx.x == NOWN - 1) cstart[NCELL] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            if (my_cell[u] < 0) continue;
+            const uint32_t pos = cstart[my_cell[u]] + my_rank[u];
+            const float4 t = my_t[u], sg = my_g[u];
+            ent[4 * pos] = t;
+            ent[4 * pos + 1] = make_float4(1.0f - t.x, 1.0f - t.y, 1.0f - t.z, sg.x);
+            ent[4 * pos + 2] = make_float4(t.x * g.h[0], t.y * g.h[1], DIM == 3 ? t.z * g.h[2] : 0.0f, sg.y);
+            ent[4 * pos + 3] = make_float4((t.x - 1.0f) * g.h[0], (t.y - 1.0f) * g.h[1],
+                                           DIM == 3 ? (t.z - 1.0f) * g.h[2] : 0.0f, sg.z);
+        }
+
+        int v[3];
+        bool owned;
+        uint32_t off[NRUN], mid[NRUN], pre[NRUN + 1];
+        if (first_pass) {
+            // Lane assignment: threads take vertices in decreasing order of their record
+            // count, so the lanes of a wave have similar trip counts (the gather loop runs as
+            // long as its longest lane).
+            vertex_runs(threadIdx.x, v, owned, off, mid, pre);
+            const uint32_t key = NBIN - 1 - min(pre[NRUN], (uint32_t)(NBIN - 1));
+            const uint32_t brank = atomicAdd(&bins[key], 1u);
+            __syncthreads();
+            if (wave == 0) {
+                constexpr int BPL = NBIN / 64;
+                uint32_t c[BPL], sum = 0;
+#pragma unroll
+                for (int k = 0; k < BPL; ++k) {
+                    c[k] = bins[lane * BPL + k];
+                    sum += c[k];
+                }
+                uint32_t incl = sum;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint32_t o = __shfl_up(incl, d, 64);
+                    if (lane >= d) incl += o;
+                }
+                uint32_t run = incl - sum;
+#pragma unroll
+                for (int k = 0; k < BPL; ++k) {
+                    bins[lane * BPL + k] = run;
+                    run += c[k];
+                }
+            }
+            __syncthreads();
+            perm[bins[key] + brank] = (uint16_t)threadIdx.x;
+            __syncthreads();
+            vid = perm[threadIdx.x];
         } else {
-            w = fa[0] * fa[1];
-            dw[0] = sa[0] * fa[1];
-            dw[1] = sa[1] * fa[0];
+            __syncthreads();  // records placed
         }
-        float s = E0.w * w;
-        float uu[DIM];
+        vertex_runs(vid, v, owned, off, mid, pre);
+
+        const uint32_t total = pre[NRUN];
+        for (uint32_t k = 0; k < total; ++k) {
+            uint32_t e = off[0] + k, md = mid[0];
+            int j = 0;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            s = fmaf(sg[a], dw[a], s);
-            uu[a] = w * sg[a];
+            for (int jj = 1; jj < NRUN; ++jj)
+                if (k >= pre[jj]) {
+                    e = off[jj] + k;
+                    md = mid[jj];
+                    j = jj;
+                }
+            const bool b[3] = {e < md, (j & 1) != 0, (j >> 1) != 0};
+            const float4 E0 = ent[4 * e], E1 = ent[4 * e + 1], E2 = ent[4 * e + 2], E3 = ent[4 * e + 3];
+            const float tt[3] = {E0.x, E0.y, E0.z}, om[3] = {E1.x, E1.y, E1.z};
+            const float th[3] = {E2.x, E2.y, E2.z}, tm[3] = {E3.x, E3.y, E3.z};
+            const float sg[3] = {E1.w, E2.w, E3.w};
+            float fa[DIM], d[DIM], sa[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                fa[a] = b[a] ? tt[a] : om[a];          // this corner's weight factor on axis a
+                d[a] = b[a] ? tm[a] : th[a];           // offset from the vertex, world units
+                sa[a] = b[a] ? g.inv_h[a] : -g.inv_h[a];
+            }
+            float w, dw[DIM];
+            if constexpr (DIM == 3) {
+                const float fyz = fa[1] * fa[2], fxz = fa[0] * fa[2], fxy = fa[0] * fa[1];
+                w = fa[0] * fyz;
+                dw[0] = sa[0] * fyz;
+                dw[1] = sa[1] * fxz;
+                dw[2] = sa[2] * fxy;
+            } else {
+                w = fa[0] * fa[1];
+                dw[0] = sa[0] * fa[1];
+                dw[1] = sa[1] * fa[0];
+            }
+            float s = E0.w * w;
+            float uu[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                s = fmaf(sg[a], dw[a], s);
+                uu[a] = w * sg[a];
+            }
+            accumulate_corner<DIM, K>(d, s, uu, acc);
         }
-        accumulate_corner<DIM, K>(d, s, uu, acc);
     }
 
     // Hand the sums over through LDS in [vertex][C] order (the record table is free now),

@@ -34,7 +34,9 @@ constexpr int kMaxSortBlocks = 256;      // rows of the [blocks x keys] count ma
 constexpr int64_t kSortMinSlice = 4096;  // queries per sort block, at least
 enum SortMode { SORT_LDS32 = 0, SORT_LDS16 = 1, SORT_ATOMIC = 2 };
 constexpr int kFwdChunk = 1024;          // primary records per forward work item
-constexpr int kBwdItem = 512;            // records per backward work item
+constexpr int32_t kRecSecondary = (int32_t)0x80000000;  // record tag bit: secondary bucket copy
+constexpr int kBwdItem = 512;            // records staged per pass of a backward work item
+constexpr int kBwdItemMax = 2048;        // records per backward work item (4 passes)
 constexpr int kMaxReduceBlocks = 2048;  // FP64 partials: 4 per block
 constexpr size_t kReduceBytes = (size_t)kMaxReduceBlocks * 4 * sizeof(double);
 constexpr int64_t kMaxQueries = (int64_t)1 << 28;  // sort entries stay below 2^31
@@ -68,7 +70,11 @@ struct WsLayout {
 };
 
 // Meta words in the workspace.
-enum { META_FITEMS = 0, META_BSPLIT = 1, META_BWHOLE = 2, META_NSPLITB = 3 };
+// Backward items: "front" items belong to bricks with more than one pass of records (listed
+// from the front of the array, heaviest work first), "back" items to the other bricks
+// (listed from the end); a brick with more than kBwdItemMax records is split into several
+// items whose partial sums a merge kernel adds ("split" bricks).
+enum { META_FITEMS = 0, META_BFRONT = 1, META_BBACK = 2, META_NSPLITB = 3 };
 
 WsLayout ws_layout(const tg_grid* g, int64_t n);
 

@@ -56,16 +56,29 @@ __global__ __launch_bounds__(kThreads) void k_sdf_loss(int64_t n, const float* _
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_loss_finish(const double* __restrict__ partials, int nblocks,
-                                                         double inv_n, double w_eik, double* __restrict__ loss)
+// One block of 1024 threads adds the per-block partials (loads issued 8 at a time).
+constexpr int kFinishReduceThreads = 1024;
+
+__global__ __launch_bounds__(kFinishReduceThreads) void k_loss_finish(const double* __restrict__ partials, int nblocks,
+                                                                      double inv_n, double w_eik, double* __restrict__ loss)
 {
     double sr = 0.0, se = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kThreads) {
-        sr += partials[2 * b];
-        se += partials[2 * b + 1];
+    for (int b0 = 0; b0 < nblocks; b0 += 8 * kFinishReduceThreads) {
+        double r[8], e[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + u * kFinishReduceThreads + threadIdx.x;
+            r[u] = b < nblocks ? partials[2 * b] : 0.0;
+            e[u] = b < nblocks ? partials[2 * b + 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            sr += r[u];
+            se += e[u];
+        }
     }
-    sr = block_sum(sr);
-    se = block_sum(se);
+    sr = block_sum_f64<kFinishReduceThreads>(sr);
+    se = block_sum_f64<kFinishReduceThreads>(se);
     if (threadIdx.x == 0) {
         loss[1] = sr * inv_n;
         loss[2] = se * inv_n;
@@ -88,7 +101,8 @@ hipError_t launch_sdf_loss(int dim, int64_t n, const float* f, const float* grad
         hipLaunchKernelGGL((k_sdf_loss<3, false>), grid, block, 0, s, n, f, grad_f, d, eik_weight, inv_n, g_f, g_grad, partials);
     }
     const double w = grad_f ? (double)eik_weight : 0.0;
-    hipLaunchKernelGGL(k_loss_finish, dim3(1), block, 0, s, partials, (int)nb, n > 0 ? 1.0 / (double)n : 0.0, w, loss);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(kFinishReduceThreads), 0, s, partials, (int)nb,
+                       n > 0 ? 1.0 / (double)n : 0.0, w, loss);
     return hipGetLastError();
 }
 
@@ -147,13 +161,22 @@ __global__ __launch_bounds__(kThreads) void k_adam(int64_t n, AdamArgs A, float*
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kThreads) void k_sum_finish(const double* __restrict__ partials, int nblocks,
-                                                        double* __restrict__ out)
+__global__ __launch_bounds__(kFinishReduceThreads) void k_sum_finish(const double* __restrict__ partials, int nblocks,
+                                                                     double* __restrict__ out)
 {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kThreads) s += partials[b];
-    s = block_sum(s);
-    if (threadIdx.x == 0) *out = s;
+    double acc = 0.0;
+    for (int b0 = 0; b0 < nblocks; b0 += 8 * kFinishReduceThreads) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + u * kFinishReduceThreads + threadIdx.x;
+            v[u] = b < nblocks ? partials[b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    acc = block_sum_f64<kFinishReduceThreads>(acc);
+    if (threadIdx.x == 0) *out = acc;
 }
 
 AdamArgs make_adam_args(const tg_adam_params& p)
@@ -175,14 +198,14 @@ AdamArgs make_adam_args(const tg_adam_params& p)
 hipError_t launch_loss_finish(const double* partials, int64_t nblocks, int64_t n, float eik_weight, double* loss,
                               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(kThreads), 0, s, partials, (int)nblocks,
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(kFinishReduceThreads), 0, s, partials, (int)nblocks,
                        n > 0 ? 1.0 / (double)n : 0.0, (double)eik_weight, loss);
     return hipGetLastError();
 }
 
 hipError_t launch_sum_finish(const double* partials, int64_t nblocks, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kThreads), 0, s, partials, (int)nblocks, out);
+    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kFinishReduceThreads), 0, s, partials, (int)nblocks, out);
     return hipGetLastError();
 }
 
@@ -208,7 +231,8 @@ hipError_t launch_adam(const tg_grid* g, const tg_adam_params& p, double* grad_n
                            g->bufs.grad, g->bufs.coeffs, zg, partials);
         break;
     }
-    if (grad_norm_sq) hipLaunchKernelGGL(k_sum_finish, dim3(1), block, 0, s, partials, (int)nb, grad_norm_sq);
+    if (grad_norm_sq)
+        hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kFinishReduceThreads), 0, s, partials, (int)nb, grad_norm_sq);
     return hipGetLastError();
 }
 

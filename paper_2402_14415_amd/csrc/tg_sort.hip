@@ -51,6 +51,14 @@ __device__ __forceinline__ void for_each_key(const Geom& g, const float* x, F&& 
 
 constexpr int kSortUnroll = 8;  // queries per thread whose loads are issued together
 
+// A sorted record: the query's coordinates and its index, with kRecSecondary set on the
+// copies in secondary buckets (the forward reads primary records only).
+__device__ __forceinline__ float4 make_record(const float* x, int64_t i, int32_t key)
+{
+    const int32_t tag = (int32_t)i | ((key & 1) ? kRecSecondary : 0);
+    return make_float4(x[0], x[1], x[2], __int_as_float(tag));
+}
+
 template <int DIM>
 __device__ __forceinline__ void load_query(const float* __restrict__ q, int64_t i, float* out)
 {
@@ -61,12 +69,12 @@ __device__ __forceinline__ void load_query(const float* __restrict__ q, int64_t 
 // ------------------------------------------------------------------ work lists
 // Splits every brick's buckets into work items so that crowded bricks are shared among
 // several workgroups; an item carries its record range.  Forward: up to kFwdChunk primary
-// records per item.  Backward: a
-// brick with more than kBwdItem records (primary + secondary) is split into items of
-// kBwdItem records, listed first (they are the longest and start first); every other brick
-// is one item, listed from the end of the array backwards, including bricks no query
-// touches (the item writes their zero gradient).  A split item's index doubles as its
-// partial-sum slot; a merge kernel adds the slots of a brick in order.
+// records per item.  Backward: up to kBwdItemMax records (primary + secondary) per item; the
+// items of bricks with more than kBwdItem records are listed first (the longest work starts
+// first), every other brick is one item listed from the end of the array backwards,
+// including bricks no query touches (the item writes their zero gradient).  A split brick's
+// item index doubles as its partial-sum slot; a merge kernel adds the slots of a brick in
+// order.
 struct WorkPtrs {
     int4* fitems;  // (brick, first record, end record, 0)
     int4* bitems;  // (brick, first record, end record, items of the brick)
@@ -118,7 +126,7 @@ __device__ __forceinline__ void block_scan_multi(const int32_t* val, int32_t* st
 __global__ __launch_bounds__(kFinishThreads) void k_sort_finish(const int32_t* total, int64_t nbricks,
                                                                int32_t* __restrict__ offs, int32_t* cursor, WorkPtrs W)
 {
-    // running totals: records, forward items, split items, whole items, split bricks
+    // running totals: records, forward items, front and back backward items, split bricks
     int32_t carry[5] = {0, 0, 0, 0, 0};
     for (int64_t pass = 0; pass < nbricks; pass += (int64_t)kFinishThreads * kFinishBricks) {
         const int64_t b0 = pass + (int64_t)threadIdx.x * kFinishBricks;
@@ -132,12 +140,12 @@ __global__ __launch_bounds__(kFinishThreads) void k_sort_finish(const int32_t* t
         int32_t v[5] = {0, 0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < kFinishBricks; ++k) {
-            const int32_t nf = (tp[k] + kFwdChunk - 1) / kFwdChunk;
-            const int32_t nb = (tp[k] + ts[k] + kBwdItem - 1) / kBwdItem;
-            v[0] += tp[k] + ts[k];
-            v[1] += nf;
-            v[2] += nb > 1 ? nb : 0;
-            v[3] += (b0 + k < nbricks && nb <= 1) ? 1 : 0;
+            const int32_t nr = tp[k] + ts[k];
+            const int32_t nb = (nr + kBwdItemMax - 1) / kBwdItemMax;
+            v[0] += nr;
+            v[1] += (tp[k] + kFwdChunk - 1) / kFwdChunk;
+            v[2] += nr > kBwdItem ? nb : 0;
+            v[3] += (b0 + k < nbricks && nr <= kBwdItem) ? 1 : 0;
             v[4] += nb > 1 ? 1 : 0;
         }
         int32_t pos[5], all[5];
@@ -160,11 +168,13 @@ __global__ __launch_bounds__(kFinishThreads) void k_sort_finish(const int32_t* t
             for (int32_t j = 0; j < nf; ++j)
                 W.fitems[pos[1] + j] = make_int4((int32_t)b, r0 + j * kFwdChunk, min(rp, r0 + (j + 1) * kFwdChunk), 0);
             pos[1] += nf;
-            const int32_t nb = (tp[k] + ts[k] + kBwdItem - 1) / kBwdItem;
-            if (nb > 1) {
+            const int32_t nr = tp[k] + ts[k];
+            const int32_t nb = (nr + kBwdItemMax - 1) / kBwdItemMax;
+            if (nr > kBwdItem) {
                 for (int32_t j = 0; j < nb; ++j)
-                    W.bitems[pos[2] + j] = make_int4((int32_t)b, r0 + j * kBwdItem, min(r1, r0 + (j + 1) * kBwdItem), nb);
-                W.split_first[pos[4]++] = pos[2];
+                    W.bitems[pos[2] + j] =
+                        make_int4((int32_t)b, r0 + j * kBwdItemMax, min(r1, r0 + (j + 1) * kBwdItemMax), nb);
+                if (nb > 1) W.split_first[pos[4]++] = pos[2];
                 pos[2] += nb;
             } else {
                 W.bitems[W.max_bitems - 1 - pos[3]] = make_int4((int32_t)b, r0, r1, 1);
@@ -177,8 +187,8 @@ __global__ __launch_bounds__(kFinishThreads) void k_sort_finish(const int32_t* t
     if (threadIdx.x == 0) {
         offs[2 * nbricks] = carry[0];
         W.meta[META_FITEMS] = carry[1];
-        W.meta[META_BSPLIT] = carry[2];
-        W.meta[META_BWHOLE] = carry[3];
+        W.meta[META_BFRONT] = carry[2];
+        W.meta[META_BBACK] = carry[3];
         W.meta[META_NSPLITB] = carry[4];
     }
 }
@@ -313,8 +323,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Geom g, const flo
         for (int u = 0; u < kSortUnroll; ++u) {
             const int64_t i = i0 + threadIdx.x + (int64_t)u * kSortThreads;
             if (i >= end) continue;
-            const float4 r = make_float4(x[u][0], x[u][1], x[u][2], __int_as_float((int32_t)i));
             for_each_key<DIM>(g, x[u], [&](int32_t key) {
+                const float4 r = make_record(x[u], i, key);
                 if constexpr (PACK16) {
                     const int32_t base = offs[key] + row[key];
                     rec[base + (int32_t)lds_count_add<true>(cursor, key)] = r;
@@ -352,8 +362,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(Geom g, const float
     if (i >= n) return;
     float x[3] = {0.0f, 0.0f, 0.0f};
     load_query<DIM>(q, i, x);
-    const float4 r = make_float4(x[0], x[1], x[2], __int_as_float((int32_t)i));
-    for_each_key<DIM>(g, x, [&](int32_t key) { rec[atomicAdd(&cursor[key], 1)] = r; });
+    for_each_key<DIM>(g, x, [&](int32_t key) { rec[atomicAdd(&cursor[key], 1)] = make_record(x, i, key); });
 }
 
 static inline unsigned blocks_for(int64_t n, int per)
