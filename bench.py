@@ -29,6 +29,7 @@ from paper_2402_14415_amd import synth  # noqa: E402  (input generators only)
 
 METRIC = "queries/s fwd+bwd at 128^3 K=2 (and % HBM peak); served query p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+COPY_REF_BYTES = 256 << 20
 RES = 128
 ORDER = 2
 NQ = 1 << 20
@@ -58,6 +59,7 @@ def algorithmic_bytes(nq, U, C, nvert):
     bwd = nq * (12 + 16) + U * C * 4          # read q, g_f, g_grad; write touched gradients
     adam = nvert * C * 4 * 7                  # read master, m, v, grad; write master, m, v
     fwd_loss = nq * (12 + 4 + 16) + U * C * 4  # read q, d; write g_f, g_grad; read touched coefficients
+    # (the training step keeps d and the upstream gradients in bucket order; the bytes are the same)
     bwd_adam = nq * (12 + 16) + nvert * C * 4 * 6  # read q, g_f, g_grad; read and write master, m, v
     return {"sort": 0, "forward": fwd, "loss": loss, "backward": bwd, "adam": adam,
             "forward_loss": fwd_loss, "backward_adam": bwd_adam}
@@ -233,6 +235,9 @@ def main():
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="end with device-to-device copies of 256 MiB (the reference kernel that scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this path runs on one GPU only (no multi-GPU path is built); use --gpus 1",
@@ -266,21 +271,14 @@ def main():
     gns = torch.empty(1, dtype=torch.float64, device=dev)
 
     def step(i, ev=None):
-        """The training step as it runs in production: sort, forward with the loss in its
-        epilogue, adjoint with Adam applied in the same pass."""
+        """The training step as it runs in production: one call that sorts, evaluates the
+        field with the loss in its epilogue and applies the adjoint with Adam in the same
+        pass (the target and the upstream gradients stay in bucket order)."""
         q, d = dev_batches[i % len(dev_batches)]
-        s = torch.cuda.current_stream(dev)
         if ev is not None:
-            ev[0].record(s)
-        grid.sort(q, ws)
-        if ev is not None:
-            ev[1].record(s)
-        grid.forward_sdf_loss(q, ws, d, EIK, g_f=gf, g_grad=gg, loss=loss)
-        if ev is not None:
-            ev[2].record(s)
-        grid.backward_adam(q, ws, gf, gg, lr=LR, grad_norm_sq=gns)
-        if ev is not None:
-            ev[3].record(s)
+            ev[0].record(torch.cuda.current_stream(dev))
+        grid.train_step(q, d, ws, eik_weight=EIK, lr=LR, loss=loss, grad_norm_sq=gns,
+                        stage_events=ev[1:] if ev is not None else None)
 
     def step_unfused(i, ev):
         """The same step through the separate calls (forward, loss, backward, Adam)."""
@@ -323,6 +321,10 @@ def main():
         # Per-call durations from HIP events recorded on the stream the kernels run on.
         reps = max(10, args.steps)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+        for e4 in evs:  # create the events before their handles are passed down
+            for e in e4:
+                e.record()
+        torch.cuda.synchronize()
         for i in range(reps):
             step(i, evs[i])
         torch.cuda.synchronize()
@@ -353,7 +355,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "sdf_fit_128^3_K2_fp32", "grid_vertices": f"{RES}^3", "order": ORDER,
                    "queries_per_step": NQ, "loss": "L1 + 0.1*eikonal", "optimizer": "Adam lr=1e-2",
-                   "step": "sort + forward with loss epilogue + adjoint with Adam in the same pass",
+                   "step": "tg_train_step: sort + forward with loss epilogue + adjoint with Adam in the same pass",
                    "unique_vertices": U},
         "step_hbm": {"algorithmic_bytes": step_alg,
                      "achieved_GBs": step_alg / (ms_per_step * 1e-3) / 1e9,
@@ -387,6 +389,13 @@ def main():
         log("bench: cpu baseline (oracle)")
         q0, d0 = batches[0]
         out["cpu_baseline"] = cpu_baseline(C64.astype(np.float32).astype(np.float64), q0, d0)
+    if args.copy_reference:
+        src = torch.empty(COPY_REF_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_reference_bytes"] = COPY_REF_BYTES
     print(json.dumps(out), flush=True)
 
 

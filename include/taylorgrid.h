@@ -184,6 +184,20 @@ tg_status tg_backward_adam(tg_grid* grid, const float* q, int64_t n, void* ws, s
                            const float* g_f, const float* g_grad, const tg_adam_params* params,
                            double* grad_norm_sq, void* stream);
 
+/* One SDF-fitting step (Sec. 3.2: the grid is optimised directly against the L1 + eikonal
+ * objective) in one call: tg_sort_queries, then tg_forward_sdf_loss, then
+ * tg_backward_adam, except that the upstream gradients are kept in the workspace in bucket
+ * order, so they never make a round trip through memory in query order.  q [n][dim] and d [n] as in those calls; loss[3]
+ * (device FP64) as tg_sdf_loss; grad_norm_sq (device double, may be NULL) receives
+ * sum(dC^2).  Afterwards ws holds the sort of (q, n), so tg_forward / tg_backward may reuse
+ * it.  The same buffer requirements as tg_backward_adam; must not overlap any other call on
+ * the same grid.  ws must hold tg_workspace_bytes(grid, n). */
+tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n, float eik_weight,
+                        const tg_adam_params* params, double* loss, double* grad_norm_sq, void* ws,
+                        size_t ws_bytes, void* const* stage_events, void* stream);
+/* stage_events: NULL, or a host array of 3 hipEvent_t that are recorded on the stream after
+ * the sort, after the forward with the loss and after the adjoint with Adam (for timing). */
+
 /* One Adam step over every coefficient (the paper trains the grid with a fixed learning
  * rate and names no optimizer; this is Adam with bias correction, eps added to the
  * corrected root, and weight decay added to the gradient):

@@ -117,6 +117,8 @@ WsLayout ws_layout(const tg_grid* g, int64_t n)
     off = align_up(off + (size_t)(L.max_bitems + g->nbricks) * sizeof(double), 256);
     L.rec_off = off;
     off = align_up(off + (size_t)n * ((size_t)1 << dim) * 16, 256);
+    L.urec_off = off;
+    off = align_up(off + (size_t)n * ((size_t)1 << dim) * 16, 256);
     L.total = off;
     return L;
 }
@@ -355,6 +357,44 @@ tg_status tg_backward_adam(tg_grid* grid, const float* q, int64_t n, void* ws, s
     return device_status(tg::launch_backward_adam(grid, n, static_cast<const char*>(ws), L, g_f, g_grad, *params,
                                                   grad_norm_sq, static_cast<hipStream_t>(stream)),
                          "tg_backward_adam");
+}
+
+tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n, float eik_weight,
+                        const tg_adam_params* params, double* loss, double* grad_norm_sq, void* ws, size_t ws_bytes,
+                        void* const* stage_events, void* stream)
+{
+    tg::WsLayout L;
+    tg_status st = check_queries("tg_train_step", grid, q, n, ws, ws_bytes, &L);
+    if (st != TG_OK) return st;
+    if (n > 0 && !d) return fail(TG_ERR_INVALID_ARG, "tg_train_step: d is NULL");
+    if (!loss) return fail(TG_ERR_INVALID_ARG, "tg_train_step: loss is NULL");
+    if (!std::isfinite(eik_weight)) return fail(TG_ERR_INVALID_ARG, "tg_train_step: eik_weight is not finite");
+    if (!grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_train_step: grid has no coeffs buffer");
+    st = check_adam("tg_train_step", grid, params);
+    if (st != TG_OK) return st;
+    (void)hipGetLastError();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    grid->sort_valid = false;
+    auto mark = [&](int k) -> hipError_t {
+        return stage_events ? hipEventRecord(static_cast<hipEvent_t>(stage_events[k]), s) : hipSuccess;
+    };
+    hipError_t e = tg::launch_sort(grid, q, n, w, L, s);
+    if (e == hipSuccess) e = mark(0);
+    if (e == hipSuccess)
+        e = tg::launch_forward_loss(grid, n, w, L, d, eik_weight, nullptr, nullptr, loss, nullptr, nullptr, s,
+                                    true);
+    if (e == hipSuccess) e = mark(1);
+    if (e == hipSuccess) e = tg::launch_backward_adam(grid, n, w, L, nullptr, nullptr, *params, grad_norm_sq, s, true);
+    if (e == hipSuccess) e = mark(2);
+    st = device_status(e, "tg_train_step");
+    if (st == TG_OK) {  // the workspace holds this sort: tg_forward / tg_backward may reuse it
+        grid->sort_q = q;
+        grid->sort_n = n;
+        grid->sort_ws = ws;
+        grid->sort_valid = true;
+    }
+    return st;
 }
 
 tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_f, const float* d, float eik_weight,

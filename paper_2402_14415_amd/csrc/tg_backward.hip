@@ -139,6 +139,7 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
                                                                  const float4* __restrict__ rec,
                                                                  const float* __restrict__ gf,
                                                                  const float* __restrict__ gg,
+                                                                 const float4* __restrict__ urec,
                                                                  float* __restrict__ grad, int accumulate, AdamBuf AB)
 {
     using S = BwdShape<DIM>;
@@ -234,19 +235,37 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
             if (i < m) {
                 const float4 r = rec[cbeg + i];
                 const float q[3] = {r.x, r.y, r.z};
-                const int32_t idx = __float_as_int(r.w) & ~kRecSecondary;
+                const int32_t tag = __float_as_int(r.w);
+                // upstream gradients of the record's query: in record order (found through the
+                // primary copy), or in query order (the query index is the primary's tag)
+                float ugf = 0.0f, ugg[3] = {0.0f, 0.0f, 0.0f};
+                const int32_t prim = (tag & kRecSecondary) ? (tag & ~kRecSecondary) : cbeg + i;
+                if (urec) {
+                    const float4 uv = urec[prim];
+                    ugf = uv.x;
+                    ugg[0] = uv.y;
+                    ugg[1] = uv.z;
+                    ugg[2] = uv.w;
+                } else {
+                    const int32_t idx = (tag & kRecSecondary) ? __float_as_int(rec[prim].w) : tag;
+                    if (gf) ugf = gf[idx];
+                    if (gg) {
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) ugg[a] = gg[(int64_t)idx * DIM + a];
+                    }
+                }
                 AxisLoc L[DIM];
                 locate<DIM>(g, q, L);
                 float sg[3] = {0.0f, 0.0f, 0.0f}, t[3] = {0.0f, 0.0f, 0.0f};
                 int c[3] = {0, 0, 0};
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
-                    sg[a] = (gg && !L[a].clamped) ? gg[(int64_t)idx * DIM + a] : 0.0f;
+                    sg[a] = L[a].clamped ? 0.0f : ugg[a];
                     t[a] = L[a].t;
                     c[a] = min(max(L[a].cell - base[a] + 1, 0), B);
                 }
                 my_cell[u] = rel_cell<DIM>(c);
-                my_t[u] = make_float4(t[0], t[1], t[2], gf ? gf[idx] : 0.0f);
+                my_t[u] = make_float4(t[0], t[1], t[2], ugf);
                 my_g[u] = make_float4(sg[0], sg[1], sg[2], 0.0f);
                 my_rank[u] = atomicAdd(&ccount[my_cell[u]], 1u);
             }
@@ -457,7 +476,8 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward_merge(Geom g, 
 
 template <int AD>
 static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const WsLayout& L, const float* g_f,
-                                       const float* g_grad, bool accumulate, const AdamBuf& AB, hipStream_t s)
+                                       const float* g_grad, const float4* urec, bool accumulate, const AdamBuf& AB,
+                                       hipStream_t s)
 {
     const float4* rec = reinterpret_cast<const float4*>(ws + L.rec_off);
     const int4* items = reinterpret_cast<const int4*>(ws + L.bitems_off);
@@ -472,7 +492,7 @@ static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const W
     if (dim == D && K == KK) {                                                                               \
         const dim3 block(BwdShape<D>::NOWN);                                                                 \
         hipLaunchKernelGGL((k_backward<D, KK, AD>), grid, block, 0, s, g->geom, items, meta, L.max_bitems, parts, \
-                           rec, g_f, g_grad, gr, acc, AB);                                                   \
+                           rec, g_f, g_grad, urec, gr, acc, AB);                                             \
         hipLaunchKernelGGL((k_backward_merge<D, KK, AD>), dim3((unsigned)g->nbricks), block, 0, s, g->geom,  \
                            items, split_first, meta, parts, gr, acc, L.max_bitems, AB);                      \
         return hipGetLastError();                                                                            \
@@ -486,12 +506,14 @@ hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const Ws
                            const float* g_grad, bool accumulate, hipStream_t s)
 {
     (void)n;
-    return launch_backward_impl<-1>(g, ws, L, g_f, g_grad, accumulate, AdamBuf{}, s);
+    return launch_backward_impl<-1>(g, ws, L, g_f, g_grad, nullptr, accumulate, AdamBuf{}, s);
 }
 
 hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
-                                const float* g_grad, const tg_adam_params& p, double* grad_norm_sq, hipStream_t s)
+                                const float* g_grad, const tg_adam_params& p, double* grad_norm_sq, hipStream_t s,
+                                bool record_order)
 {
+    const float4* urec = record_order ? reinterpret_cast<const float4*>(ws + L.urec_off) : nullptr;
     (void)n;
     AdamBuf AB;
     AB.A = make_adam_args(p);
@@ -502,9 +524,9 @@ hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, con
     AB.partials = reinterpret_cast<double*>(const_cast<char*>(ws) + L.bpart_off);
     hipError_t e;
     switch (g->desc.storage) {
-    case ST_F32: e = launch_backward_impl<ST_F32>(g, ws, L, g_f, g_grad, false, AB, s); break;
-    case ST_BF16: e = launch_backward_impl<ST_BF16>(g, ws, L, g_f, g_grad, false, AB, s); break;
-    default: e = launch_backward_impl<ST_F16>(g, ws, L, g_f, g_grad, false, AB, s); break;
+    case ST_F32: e = launch_backward_impl<ST_F32>(g, ws, L, g_f, g_grad, urec, false, AB, s); break;
+    case ST_BF16: e = launch_backward_impl<ST_BF16>(g, ws, L, g_f, g_grad, urec, false, AB, s); break;
+    default: e = launch_backward_impl<ST_F16>(g, ws, L, g_f, g_grad, urec, false, AB, s); break;
     }
     if (e != hipSuccess || !grad_norm_sq) return e;
     return launch_sum_finish(AB.partials, L.max_bitems + g->nbricks, grad_norm_sq, s);

@@ -17,13 +17,17 @@ enum { MODE_FWD = 0, MODE_DQ = 1, MODE_LOSS = 2 };
 // of Eq. 8): per query r = f - d, g_f = sign(r) / n, and with an eikonal term
 // g_grad = 2 w (|grad f| - 1) grad f / (|grad f| n) (zero where grad f = 0); per workgroup
 // the FP64 sums of |r| and (|grad f| - 1)^2.
+// With urec != NULL the upstream gradients go to urec, indexed by record position (the
+// training step keeps them in bucket order).
 struct LossArgs {
     const float* d;     // target SDF, query order
     float* gf;          // upstream gradient of f, query order
     float* gg;          // upstream gradient of grad f (NULL: no eikonal term)
+    float4* urec;       // (g_f, g_grad) in record order
     double* partials;   // [2 x gridDim.x]
     float w_eik;
     float inv_n;
+    int eik;            // eikonal term on (record mode; query mode tests gg)
 };
 
 template <int C> struct LdsPad { static constexpr int value = C == 1 ? 1 : (C <= 4 ? 4 : (C <= 8 ? 8 : 12)); };
@@ -219,10 +223,12 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
             }
         }
         if constexpr (MODE == MODE_LOSS) {
+            const bool rec_mode = LA.urec != nullptr;
             const float res = f - LA.d[idx];
             sum_r += (double)fabsf(res);
-            LA.gf[idx] = res > 0.0f ? LA.inv_n : (res < 0.0f ? -LA.inv_n : 0.0f);
-            if (LA.gg) {
+            const float sgf = res > 0.0f ? LA.inv_n : (res < 0.0f ? -LA.inv_n : 0.0f);
+            float sgg[3] = {0.0f, 0.0f, 0.0f};
+            if (rec_mode ? LA.eik != 0 : LA.gg != nullptr) {
                 float n2 = 0.0f;
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) n2 = fmaf(gr[a], gr[a], n2);
@@ -231,7 +237,16 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
                 sum_e += (double)e * (double)e;
                 const float k = nrm > 0.0f ? 2.0f * LA.w_eik * e / nrm * LA.inv_n : 0.0f;
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) LA.gg[(int64_t)idx * DIM + a] = k * gr[a];
+                for (int a = 0; a < DIM; ++a) sgg[a] = k * gr[a];
+            }
+            if (rec_mode) {
+                LA.urec[j] = make_float4(sgf, sgg[0], sgg[1], sgg[2]);
+            } else {
+                LA.gf[idx] = sgf;
+                if (LA.gg) {
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) LA.gg[(int64_t)idx * DIM + a] = sgg[a];
+                }
             }
         }
         if constexpr (MODE == MODE_DQ) {
@@ -290,12 +305,14 @@ hipError_t launch_forward(const tg_grid* g, int64_t n, const char* ws, const WsL
 
 hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* d,
                                float eik_weight, float* g_f, float* g_grad, double* loss, float* f, float* grad_f,
-                               hipStream_t s)
+                               hipStream_t s, bool record_order)
 {
     LossArgs LA;
     LA.d = d;
     LA.gf = g_f;
     LA.gg = g_grad;
+    LA.urec = record_order ? reinterpret_cast<float4*>(const_cast<char*>(ws) + L.urec_off) : nullptr;
+    LA.eik = eik_weight != 0.0f ? 1 : 0;
     LA.partials = reinterpret_cast<double*>(const_cast<char*>(ws) + L.fpart_off);
     LA.w_eik = eik_weight;
     LA.inv_n = n > 0 ? (float)(1.0 / (double)n) : 0.0f;
@@ -304,7 +321,8 @@ hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, cons
         if (e != hipSuccess) return e;
     }
     // no partials at n == 0: the finish kernel then writes a zero loss
-    return launch_loss_finish(LA.partials, n > 0 ? L.fwd_blocks : 0, n, g_grad ? eik_weight : 0.0f, loss, s);
+    const bool eik = record_order ? LA.eik != 0 : g_grad != nullptr;
+    return launch_loss_finish(LA.partials, n > 0 ? L.fwd_blocks : 0, n, eik ? eik_weight : 0.0f, loss, s);
 }
 
 hipError_t launch_dq(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,

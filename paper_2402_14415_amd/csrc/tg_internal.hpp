@@ -56,7 +56,8 @@ struct WsLayout {
     size_t parts_off;    // float [max_slots x brick accumulator]: partial sums of split bricks
     size_t fpart_off;    // double [2 x fwd_blocks]: per-workgroup loss sums of the fused forward
     size_t bpart_off;    // double [max_bitems + nbricks]: per-workgroup sum(dC^2) of the fused adjoint
-    size_t rec_off;      // float4 [n * 2^dim]: sorted query records (x, y, z, index bits)
+    size_t rec_off;      // float4 [n * 2^dim]: sorted query records (x, y, z, tag)
+    size_t urec_off;     // float4 [n * 2^dim]: upstream gradients (g_f, g_grad) in record order
     size_t total;
     int64_t nkeys;       // 2 * nbricks (primary / secondary bucket of every vertex brick)
     int sort_mode;       // SortMode
@@ -94,9 +95,10 @@ hipError_t launch_adam(const tg_grid* g, const tg_adam_params& p, double* grad_n
                        bool zero_grad, hipStream_t s);
 hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* d,
                                float eik_weight, float* g_f, float* g_grad, double* loss, float* f, float* grad_f,
-                               hipStream_t s);
+                               hipStream_t s, bool record_order = false);
 hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
-                                const float* g_grad, const tg_adam_params& p, double* grad_norm_sq, hipStream_t s);
+                                const float* g_grad, const tg_adam_params& p, double* grad_norm_sq, hipStream_t s,
+                                bool record_order = false);
 hipError_t launch_loss_finish(const double* partials, int64_t nblocks, int64_t n, float eik_weight, double* loss,
                               hipStream_t s);
 hipError_t launch_sum_finish(const double* partials, int64_t nblocks, double* out, hipStream_t s);

@@ -51,12 +51,22 @@ __device__ __forceinline__ void for_each_key(const Geom& g, const float* x, F&& 
 
 constexpr int kSortUnroll = 8;  // queries per thread whose loads are issued together
 
-// A sorted record: the query's coordinates and its index, with kRecSecondary set on the
-// copies in secondary buckets (the forward reads primary records only).
-__device__ __forceinline__ float4 make_record(const float* x, int64_t i, int32_t key)
+// Writes one sorted record at pos: the query's coordinates and a tag.  A primary record's
+// tag is the query index; a secondary record's tag is kRecSecondary | (position of the same
+// query's primary record), so that per-query data kept in record order (the training
+// step's upstream gradients) is found from either copy.  for_each_key emits the primary key
+// first, so p0 holds the primary position when the secondaries are written.
+__device__ __forceinline__ void put_record(float4* rec, int32_t pos, const float* x, int64_t i, int32_t key,
+                                           int32_t& p0)
 {
-    const int32_t tag = (int32_t)i | ((key & 1) ? kRecSecondary : 0);
-    return make_float4(x[0], x[1], x[2], __int_as_float(tag));
+    int32_t tag;
+    if (key & 1) {
+        tag = p0 | kRecSecondary;
+    } else {
+        p0 = pos;
+        tag = (int32_t)i;
+    }
+    rec[pos] = make_float4(x[0], x[1], x[2], __int_as_float(tag));
 }
 
 template <int DIM>
@@ -323,14 +333,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Geom g, const flo
         for (int u = 0; u < kSortUnroll; ++u) {
             const int64_t i = i0 + threadIdx.x + (int64_t)u * kSortThreads;
             if (i >= end) continue;
+            int32_t p0 = 0;
             for_each_key<DIM>(g, x[u], [&](int32_t key) {
-                const float4 r = make_record(x[u], i, key);
-                if constexpr (PACK16) {
-                    const int32_t base = offs[key] + row[key];
-                    rec[base + (int32_t)lds_count_add<true>(cursor, key)] = r;
-                } else {
-                    rec[lds_count_add<false>(cursor, key)] = r;
-                }
+                int32_t pos;
+                if constexpr (PACK16) pos = offs[key] + row[key] + (int32_t)lds_count_add<true>(cursor, key);
+                else pos = (int32_t)lds_count_add<false>(cursor, key);
+                put_record(rec, pos, x[u], i, key, p0);
             });
         }
     }
@@ -362,7 +370,8 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(Geom g, const float
     if (i >= n) return;
     float x[3] = {0.0f, 0.0f, 0.0f};
     load_query<DIM>(q, i, x);
-    for_each_key<DIM>(g, x, [&](int32_t key) { rec[atomicAdd(&cursor[key], 1)] = make_record(x, i, key); });
+    int32_t p0 = 0;
+    for_each_key<DIM>(g, x, [&](int32_t key) { put_record(rec, atomicAdd(&cursor[key], 1), x, i, key, p0); });
 }
 
 static inline unsigned blocks_for(int64_t n, int per)

@@ -228,6 +228,28 @@ class TaylorGrid:
         _lib.call("tg_backward_adam", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _ptr(g_f), _ptr(g_grad),
                   ctypes.byref(p), _ptr(grad_norm_sq), _stream(self.device))
 
+    def train_step(self, q, d, ws, eik_weight=0.1, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0,
+                   loss=None, grad_norm_sq=None, step=None, stage_events=None):
+        """One SDF-fitting step (sort, forward + loss, adjoint + Adam) in one call; returns the
+        loss (device float64 [3]: total, L1 mean, eikonal mean).  stage_events: optional three
+        recorded torch.cuda.Events, re-recorded after each stage (for timing)."""
+        n = self._q(q)
+        _check_tensor("d", d, torch.float32, self.device, n)
+        loss = torch.empty(3, dtype=torch.float64, device=self.device) if loss is None else loss
+        _check_tensor("loss", loss, torch.float64, self.device, 3)
+        if grad_norm_sq is not None:
+            _check_tensor("grad_norm_sq", grad_norm_sq, torch.float64, self.device)
+        p = self._adam_params(lr, betas, eps, weight_decay, step)
+        evs = None
+        if stage_events is not None:
+            if len(stage_events) != 3:
+                raise ValueError("stage_events must hold three events")
+            evs = (ctypes.c_void_p * 3)(*[e.cuda_event for e in stage_events])
+        _lib.call("tg_train_step", self._h, _ptr(q), _ptr(d), n, float(eik_weight), ctypes.byref(p), _ptr(loss),
+                  _ptr(grad_norm_sq), _ptr(ws), ws.numel(), evs, _stream(self.device))
+        self._sorted = (q, ws)
+        return loss
+
     def adam_step(self, ws, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0, grad_norm_sq=None,
                   zero_grad=False, step=None):
         """One fused Adam step; grad_norm_sq (device float64 [1]) receives sum(grad^2)."""

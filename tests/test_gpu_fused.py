@@ -179,3 +179,69 @@ def test_fused_training_step_config1():
             np.testing.assert_allclose(to_np(lb), to_np(la), rtol=1e-6)
         for name, tol in (("master", 1e-6), ("adam_m", TOL_VALUE), ("adam_v", TOL_VALUE)):
             assert nerr(to_np(getattr(b, name)).reshape(-1), to_np(getattr(a, name)).reshape(-1)) <= tol
+
+
+@pytest.mark.parametrize("dim,res,order,storage,eik", [(3, (37, 30, 21), 2, "f32", 0.1), (3, (29, 29, 29), 2, "bf16", 0.1),
+                                                        (3, (20, 20, 20), 1, "f32", 0.0), (2, (70, 45), 2, "f32", 0.0)])
+def test_train_step_matches_separate_calls(dim, res, order, storage, eik):
+    """tg_train_step (target and upstream gradients kept in bucket order) against sort +
+    forward_sdf_loss + backward_adam in query order, over two steps."""
+    a, b, rng = _twin_grids(dim, res, order, storage, seed=31)
+    n = 120_007
+    for step in range(2):
+        q = torch.tensor(_hot_queries(dim, n, rng), dtype=torch.float32, device=DEV)
+        d = torch.tensor(rng.normal(0, 0.3, size=n), dtype=torch.float32, device=DEV)
+        ws_a, ws_b = a.workspace(n), b.workspace(n)
+        na = torch.zeros(1, dtype=torch.float64, device=DEV)
+        nb = torch.zeros(1, dtype=torch.float64, device=DEV)
+        a.sort(q, ws_a)
+        la, gfa, gga = a.forward_sdf_loss(q, ws_a, d, eik, eikonal=eik != 0)
+        a.backward_adam(q, ws_a, gfa, gga, lr=1e-2, grad_norm_sq=na, step=10 + step)
+        lb = b.train_step(q, d, ws_b, eik_weight=eik, lr=1e-2, grad_norm_sq=nb, step=10 + step)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(to_np(lb), to_np(la), rtol=1e-12 if step == 0 else 1e-6)
+        for name, tol in (("master", 1e-6), ("adam_m", TOL_VALUE), ("adam_v", TOL_VALUE)):
+            e = nerr(to_np(getattr(b, name)).reshape(-1), to_np(getattr(a, name)).reshape(-1))
+            print(f"step {step} {name}: err {e:.2e}")
+            assert e <= tol
+        np.testing.assert_allclose(nb.item(), na.item(), rtol=1e-6)
+    # the workspace holds the last sort: the separate forward can reuse it
+    f, _ = b.forward(q, ws_b)
+    fa, _ = a.forward(q, ws_a)
+    torch.cuda.synchronize()
+    assert nerr(to_np(f), to_np(fa)) <= 1e-5
+
+
+def test_train_step_config1_and_stage_events():
+    """128^3, K=2, 2^20 scene queries: train_step against the separate calls, and the stage
+    events it records are ordered."""
+    C64, q64, d64, scene = synth.scene3d_inputs(res=128, order=2, n=1 << 20, seed=0)
+    C32 = torch.from_numpy(C64.astype(np.float32))
+    del C64
+    a = TaylorGrid(3, (128,) * 3, 2, (-1.0,) * 3, (1.0,) * 3, coeffs=C32, device=DEV)
+    b = TaylorGrid(3, (128,) * 3, 2, (-1.0,) * 3, (1.0,) * 3, coeffs=C32, device=DEV)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(4)
+    m0 = torch.randn(a.shape, generator=gen, device=DEV) * 1e-5
+    v0 = torch.rand(a.shape, generator=gen, device=DEV) * 9e-9 + 1e-9
+    for g_ in (a, b):
+        g_.adam_m.copy_(m0)
+        g_.adam_v.copy_(v0)
+    q = torch.tensor(q64, dtype=torch.float32, device=DEV)
+    d = torch.tensor(d64, dtype=torch.float32, device=DEV)
+    ws_a, ws_b = a.workspace(q.shape[0]), b.workspace(q.shape[0])
+    a.sort(q, ws_a)
+    la, gfa, gga = a.forward_sdf_loss(q, ws_a, d, 0.1)
+    a.backward_adam(q, ws_a, gfa, gga, lr=1e-2, step=10)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for e in ev:
+        e.record()
+    ev[0].record()
+    lb = b.train_step(q, d, ws_b, eik_weight=0.1, lr=1e-2, step=10, stage_events=ev[1:])
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(to_np(lb), to_np(la), rtol=1e-12)
+    for name, tol in (("master", 1e-6), ("adam_m", TOL_VALUE), ("adam_v", TOL_VALUE)):
+        assert nerr(to_np(getattr(b, name)).reshape(-1), to_np(getattr(a, name)).reshape(-1)) <= tol
+    times = [ev[0].elapsed_time(e) for e in ev[1:]]
+    print("stage ends (ms):", times)
+    assert 0 < times[0] <= times[1] <= times[2]
