@@ -65,6 +65,38 @@ def algorithmic_bytes(nq, U, C, nvert):
             "forward_loss": fwd_loss, "backward_adam": bwd_adam}
 
 
+def kernel_source_sha256():
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_2402_14415_amd", "csrc", "*"))):
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(call):
+    """HBM bytes per launch of `call` from the committed counter summary, or None when the
+    kernels have changed since the counters were taken (source hash mismatch)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_sdf_fit_128_K2_fp32.md")
+    if not os.path.exists(path):
+        return None
+    vals, sha = {}, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic_bytes_per_launch:"):
+                for kv in line.split(":", 1)[1].split():
+                    k, v = kv.split("=")
+                    vals[k] = float(v)
+            elif line.startswith("kernel_source_sha256:"):
+                sha = line.split(":", 1)[1].strip()
+    if sha != kernel_source_sha256():
+        return None
+    return vals.get(call)
+
+
 def cpu_baseline(C64, q, d):
     """The FP64 oracle on the same step: forward + loss + adjoint over the whole batch
     (2^20 queries) and Adam over every coefficient, on the host cores."""
@@ -364,8 +396,11 @@ def main():
     if per_call_us:
         dom = max(per_call_us, key=lambda k: per_call_us[k])
         ach = alg[dom] / (per_call_us[dom] * 1e-6) / 1e9
+        traffic = measured_traffic(dom)
         out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS, "traffic": None}
+                           "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                           "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                           "algorithmic_bytes": alg[dom]}
         fb_us = unfused_us["forward"] + unfused_us["backward"]
         fb_bytes = alg["forward"] + alg["backward"]
         out["fwd_bwd"] = {"queries_per_s": NQ / (fb_us * 1e-6), "us": fb_us,
