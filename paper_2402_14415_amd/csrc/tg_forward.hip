@@ -30,8 +30,6 @@ struct LossArgs {
     int eik;            // eikonal term on (record mode; query mode tests gg)
 };
 
-template <int C> struct LdsPad { static constexpr int value = C == 1 ? 1 : (C <= 4 ? 4 : (C <= 8 ? 8 : 12)); };
-
 template <int DIM> __device__ __forceinline__ void brick_coords(const Geom& g, int32_t brick, int32_t* bc)
 {
     bc[0] = brick % g.nvb[0];
@@ -44,23 +42,46 @@ template <int DIM> __device__ __forceinline__ void brick_coords(const Geom& g, i
     }
 }
 
-template <int CP>
-__device__ __forceinline__ void lds_vertex(const float* lds, int lv, float* c)
+// Staged vertex blocks in LDS, unpadded, in the brick's row order.  FP32 storage and 16-bit
+// storage with an even coefficient count are copied verbatim (LDS_PACKED: two 16-bit values
+// per word, widened when read); 16-bit storage with an odd count is widened while staged.
+template <int ST, int C> struct StageFmt {
+    static constexpr bool PACKED = ST != ST_F32 && C % 2 == 0;
+    static constexpr bool DMA = ST == ST_F32 || PACKED;    // copy global -> LDS directly
+    static constexpr int WPV = PACKED ? C / 2 : C;         // LDS words per vertex
+};
+
+template <int ST, int C>
+__device__ __forceinline__ void lds_vertex(const uint32_t* lds, int lv, float* c)
 {
-    if constexpr (CP == 1) {
-        c[0] = lds[lv];
-    } else {
-        const float4* p = reinterpret_cast<const float4*>(lds + lv * CP);
+    using F = StageFmt<ST, C>;
+    const uint32_t* p = lds + lv * F::WPV;
+    if constexpr (F::PACKED) {
 #pragma unroll
-        for (int k = 0; k < CP / 4; ++k) {
-            const float4 v = p[k];
-            c[4 * k + 0] = v.x;
-            c[4 * k + 1] = v.y;
-            c[4 * k + 2] = v.z;
-            c[4 * k + 3] = v.w;
+        for (int k = 0; k < C / 2; ++k) {
+            const uint32_t w = p[k];
+            if constexpr (ST == ST_BF16) {
+                c[2 * k] = bf16_bits_to_float(w & 0xffffu);
+                c[2 * k + 1] = bf16_bits_to_float(w >> 16);
+            } else {
+                c[2 * k] = f16_bits_to_float(w & 0xffffu);
+                c[2 * k + 1] = f16_bits_to_float(w >> 16);
+            }
         }
+    } else if constexpr (C % 2 == 0) {
+#pragma unroll
+        for (int k = 0; k < C / 2; ++k) {
+            const float2 v = reinterpret_cast<const float2*>(p)[k];  // 8-byte aligned: C even
+            c[2 * k] = v.x;
+            c[2 * k + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < C; ++k) c[k] = __uint_as_float(p[k]);
     }
 }
+
+typedef __attribute__((address_space(3))) void* lds_addr_t;
 
 // Hessian entry index of (a, c) in the packed order xx, xy, xz, yy, yz, zz / xx, xy, yy.
 template <int DIM> __host__ __device__ constexpr int hidx(int a, int c)
@@ -79,12 +100,13 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
 {
     constexpr int B = BrickEdge<DIM>::value;
     constexpr int C = NumCoeffs<DIM, K>::value;
-    constexpr int CP = LdsPad<C>::value;
+    using SF = StageFmt<ST, C>;
     constexpr int NV1 = B + 1;
     constexpr int NROWS = DIM == 3 ? NV1 * NV1 : NV1;
-    constexpr int ROWLEN = NV1 * C;
+    constexpr int ROWW = NV1 * SF::WPV;  // LDS words per row of NV1 vertices along x
+    constexpr int NWIN = (NROWS * ROWW + 63) / 64;
     constexpr int NH = DIM == 3 ? 6 : 3;
-    __shared__ __align__(16) float lds[NROWS * NV1 * CP];
+    __shared__ __align__(16) uint32_t lds[NWIN * 64];
 
     // Work item = (brick, chunk of up to kFwdChunk primary records).  Each XCD (blocks are
     // dealt round-robin to the 8 XCDs) takes a contiguous range of items, so the vertex
@@ -113,45 +135,41 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
         nv[a] = min(B, g.res[a] - 1 - v0[a]) + 1;  // >= 2 for a brick that has queries
     }
 
-    // Stage the brick's vertices: each wave copies whole rows of NV1 vertices along x (NV1*C
-    // contiguous values in HBM); with an even coefficient count each lane moves a pair of
-    // coefficients, which never straddles two vertices.  Rows are loaded in batches so that
-    // a wave has several loads in flight.
-    {
-        constexpr int STEP = C % 2 == 0 ? 2 : 1;
-        constexpr int RB = 8;  // rows per batch and wave
-        static_assert(ROWLEN / STEP <= 64, "a row must fit one wave");
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        const int e = lane * STEP;  // this lane's value index within a row
-        const bool lane_ok = e < nv[0] * C;
-        const int vx = e / C;
-        const int cc = e - vx * C;
-        for (int r0 = wave; r0 < NROWS; r0 += RB * (kThreads / 64)) {
-            float2 v[RB];
-            int row[RB];
-#pragma unroll
-            for (int k = 0; k < RB; ++k) {
-                row[k] = r0 + k * (kThreads / 64);
-                const int ry = DIM == 3 ? row[k] % NV1 : row[k];
-                const int rz = DIM == 3 ? row[k] / NV1 : 0;
-                bool ok = lane_ok && row[k] < NROWS && ry < nv[1];
-                if constexpr (DIM == 3) ok = ok && rz < nv[2];
-                if (!ok) {
-                    row[k] = -1;
-                    continue;
-                }
+    // Stage the brick's vertices.  The (B+1)^dim vertex blocks are NROWS rows of ROWW
+    // contiguous words in memory, kept in the same order in LDS; every wave copies 64-word
+    // windows of the flattened rows straight from global memory into LDS (global_load_lds),
+    // all in flight at once and without passing through registers.  Words of rows or
+    // vertices outside the grid are not loaded (no query reads them).
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if constexpr (SF::DMA) {
+        const uint32_t* src = static_cast<const uint32_t*>(coeffs);
+        for (int w = wave; w < NWIN; w += kThreads / 64) {
+            const int base = w * 64;
+            const int e = base + lane;
+            const int row = e / ROWW, off = e - row * ROWW;
+            const int ry = DIM == 3 ? row % NV1 : row;
+            const int rz = DIM == 3 ? row / NV1 : 0;
+            bool ok = row < NROWS && ry < nv[1] && off < nv[0] * SF::WPV;
+            if constexpr (DIM == 3) ok = ok && rz < nv[2];
+            if (ok) {
                 int64_t vrow = (int64_t)v0[0] + (int64_t)(v0[1] + ry) * g.stride[1];
                 if constexpr (DIM == 3) vrow += (int64_t)(v0[2] + rz) * g.stride[2];
-                if constexpr (C % 2 == 0) v[k] = load_pair<ST>(coeffs, vrow * C + e);
-                else v[k].x = load_scalar<ST>(coeffs, vrow * C + e);
+                __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + vrow * SF::WPV + off),
+                                                 (lds_addr_t)(lds + base), 4, 0, 0);
             }
-#pragma unroll
-            for (int k = 0; k < RB; ++k) {
-                if (row[k] < 0) continue;
-                float* dst = &lds[(row[k] * NV1 + vx) * CP + cc];
-                if constexpr (C % 2 == 0) *reinterpret_cast<float2*>(dst) = v[k];
-                else *dst = v[k].x;
-            }
+        }
+    } else {
+        // 16-bit storage with an odd coefficient count: widen through registers
+        for (int e = threadIdx.x; e < NROWS * ROWW; e += kThreads) {
+            const int row = e / ROWW, off = e - row * ROWW;
+            const int ry = DIM == 3 ? row % NV1 : row;
+            const int rz = DIM == 3 ? row / NV1 : 0;
+            bool ok = ry < nv[1] && off < nv[0] * C;
+            if constexpr (DIM == 3) ok = ok && rz < nv[2];
+            if (!ok) continue;
+            int64_t vrow = (int64_t)v0[0] + (int64_t)(v0[1] + ry) * g.stride[1];
+            if constexpr (DIM == 3) vrow += (int64_t)(v0[2] + rz) * g.stride[2];
+            lds[e] = __float_as_uint(load_scalar<ST>(coeffs, vrow * C + off));
         }
     }
     __syncthreads();
@@ -180,8 +198,8 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
         for (int b = 0; b < (1 << DIM); ++b) {
             int lv = lc[0] + (b & 1) + NV1 * (lc[1] + ((b >> 1) & 1));
             if constexpr (DIM == 3) lv += NV1 * NV1 * (lc[2] + ((b >> 2) & 1));
-            float c[CP];
-            lds_vertex<CP>(lds, lv, c);
+            float c[C];
+            lds_vertex<ST, C>(lds, lv, c);
             float d[DIM];
             corner_offset<DIM>(F, b, d);
             float T, dT[DIM];
