@@ -92,22 +92,34 @@ struct AdamBuf {
     double* partials;
 };
 
+// Element of the brick's [vertex][C] block list that register k of this thread holds in the
+// epilogue: with an even C, pairs of neighbouring elements (never split by a row of B*C), so
+// that global memory is accessed in 8-byte words.
+template <int DIM, int C>
+__device__ __forceinline__ int epi_elem(int k)
+{
+    constexpr int NOWN = BwdShape<DIM>::NOWN;
+    if constexpr (C % 2 == 0) return 2 * ((int)threadIdx.x + (k >> 1) * NOWN) + (k & 1);
+    else return (int)threadIdx.x + k * NOWN;
+}
+
 // Writes the brick's coefficient adjoint to grad (AD < 0: =, or += when accumulating), or
 // applies Adam to it (AD >= 0), walking the brick row by row so that consecutive threads
-// touch consecutive words.  vk[k] is the value of element e = threadIdx.x + k * NOWN of the
-// brick's [vertex][C] block list (vertex = x + B (y + B z)); a row of B vertices along x is
-// B * C contiguous words in memory.  Returns this thread's share of sum(value^2).
+// touch consecutive words.  vk[k] is the value of element epi_elem(k) of the brick's
+// [vertex][C] block list (vertex = x + B (y + B z)); a row of B vertices along x is B * C
+// contiguous words in memory.  Returns this thread's share of sum(value^2).
 template <int DIM, int C, int AD>
 __device__ __forceinline__ double brick_epilogue(const Geom& g, const int32_t* base, const int32_t* nown,
                                                  const float* vk, float* __restrict__ grad, int accumulate,
                                                  const AdamBuf& AB)
 {
     using S = BwdShape<DIM>;
-    constexpr int B = S::B, NOWN = S::NOWN, RL = B * C;
+    constexpr int B = S::B, RL = B * C;
+    constexpr int W = C % 2 == 0 ? 2 : 1;  // elements per access
     double ss = 0.0;
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const int e = threadIdx.x + k * NOWN;
+    for (int k = 0; k < C; k += W) {
+        const int e = epi_elem<DIM, C>(k);
         const int r = e / RL, p = e - r * RL;
         const int y = r % B, z = r / B;
         bool ok = p < nown[0] * C && y < nown[1];
@@ -116,17 +128,46 @@ __device__ __forceinline__ double brick_epilogue(const Geom& g, const int32_t* b
         int64_t vrow = (int64_t)base[0] + (int64_t)(base[1] + y) * g.stride[1];
         if constexpr (DIM == 3) vrow += (int64_t)(base[2] + z) * g.stride[2];
         const int64_t gi = vrow * C + p;
-        const float val = vk[k];
-        if constexpr (AD >= 0) {
-            float th = AB.master[gi], m = AB.m[gi], v = AB.v[gi];
-            ss += (double)val * (double)val;
-            adam_elem(AB.A, val, th, m, v);
-            AB.master[gi] = th;
-            AB.m[gi] = m;
-            AB.v[gi] = v;
-            store_copy<AD>(AB.coeffs, gi, th);
+        if constexpr (W == 2) {
+            // 8-byte aligned: C and p are even
+            if constexpr (AD >= 0) {
+                float2 th = *reinterpret_cast<const float2*>(AB.master + gi);
+                float2 m = *reinterpret_cast<const float2*>(AB.m + gi);
+                float2 v = *reinterpret_cast<const float2*>(AB.v + gi);
+                ss += (double)vk[k] * (double)vk[k] + (double)vk[k + 1] * (double)vk[k + 1];
+                adam_elem(AB.A, vk[k], th.x, m.x, v.x);
+                adam_elem(AB.A, vk[k + 1], th.y, m.y, v.y);
+                *reinterpret_cast<float2*>(AB.master + gi) = th;
+                *reinterpret_cast<float2*>(AB.m + gi) = m;
+                *reinterpret_cast<float2*>(AB.v + gi) = v;
+                if constexpr (AD == ST_BF16)
+                    *reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(AB.coeffs) + gi) =
+                        (uint32_t)float_to_bf16_rne(th.x) | ((uint32_t)float_to_bf16_rne(th.y) << 16);
+                else if constexpr (AD == ST_F16)
+                    *reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(AB.coeffs) + gi) =
+                        (uint32_t)float_to_f16_rne_sat(th.x) | ((uint32_t)float_to_f16_rne_sat(th.y) << 16);
+            } else {
+                float2 o = make_float2(vk[k], vk[k + 1]);
+                if (accumulate) {
+                    const float2 old = *reinterpret_cast<const float2*>(grad + gi);
+                    o.x += old.x;
+                    o.y += old.y;
+                }
+                *reinterpret_cast<float2*>(grad + gi) = o;
+            }
         } else {
-            grad[gi] = accumulate ? grad[gi] + val : val;
+            const float val = vk[k];
+            if constexpr (AD >= 0) {
+                float th = AB.master[gi], m = AB.m[gi], v = AB.v[gi];
+                ss += (double)val * (double)val;
+                adam_elem(AB.A, val, th, m, v);
+                AB.master[gi] = th;
+                AB.m[gi] = m;
+                AB.v[gi] = v;
+                store_copy<AD>(AB.coeffs, gi, th);
+            } else {
+                grad[gi] = accumulate ? grad[gi] + val : val;
+            }
         }
     }
     return ss;
@@ -410,12 +451,12 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
     __syncthreads();
     float vk[C];
 #pragma unroll
-    for (int k = 0; k < C; ++k) vk[k] = vals[threadIdx.x + k * NOWN];
+    for (int k = 0; k < C; ++k) vk[k] = vals[epi_elem<DIM, C>(k)];
     if (nchunk > 1) {
         // partial sums of a split brick: slot = item index, laid out [vertex][C]
         float* slot = parts + (int64_t)item * (NOWN * C);
 #pragma unroll
-        for (int k = 0; k < C; ++k) slot[threadIdx.x + k * NOWN] = vk[k];
+        for (int k = 0; k < C; ++k) slot[epi_elem<DIM, C>(k)] = vk[k];
         if constexpr (AD >= 0) {
             if (threadIdx.x == 0) AB.partials[bid] = 0.0;  // counted by the merge
         }
@@ -464,7 +505,7 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward_merge(Geom g, 
     for (int j = 0; j < nchunk; ++j) {
         const float* slot = parts + (int64_t)(first + j) * (NOWN * C);
 #pragma unroll
-        for (int k = 0; k < C; ++k) vk[k] += slot[threadIdx.x + k * NOWN];
+        for (int k = 0; k < C; ++k) vk[k] += slot[epi_elem<DIM, C>(k)];
     }
     if constexpr (AD >= 0) {
         const double tot = block_sum_f64<NOWN>(brick_epilogue<DIM, C, AD>(g, base, nown, vk, grad, 0, AB));
