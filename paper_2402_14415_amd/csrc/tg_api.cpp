@@ -100,7 +100,12 @@ WsLayout ws_layout(const tg_grid* g, int64_t n)
     L.max_fitems = g->nbricks + (n + kFwdChunk - 1) / kFwdChunk;
     L.fwd_blocks = 8 * ((L.max_fitems + 7) / 8);
     L.max_bitems = g->nbricks + (n * fan + kBwdItemMax - 1) / kBwdItemMax;
-    L.max_slots = L.max_bitems;  // a split item's slot is its item index
+    // A split item's slot is its item index, and split items are among the front items, of
+    // which there are fewer than (records / kBwdItem): a front brick has more than kBwdItem
+    // records and at most one item per kBwdItem of them.
+    L.max_slots = std::min<int64_t>(L.max_bitems, (n * fan + kBwdItem - 1) / kBwdItem);
+    // split bricks have more than kBwdItemMax records each
+    L.merge_blocks = std::max<int64_t>(1, std::min<int64_t>({g->nbricks, (n * fan) / (kBwdItemMax + 1), 256}));
     L.meta_off = off;
     off = align_up(off + 64, 256);
     L.fitems_off = off;
@@ -114,7 +119,7 @@ WsLayout ws_layout(const tg_grid* g, int64_t n)
     L.fpart_off = off;
     off = align_up(off + (size_t)L.fwd_blocks * 2 * sizeof(double), 256);
     L.bpart_off = off;
-    off = align_up(off + (size_t)(L.max_bitems + g->nbricks) * sizeof(double), 256);
+    off = align_up(off + (size_t)(L.max_bitems + L.merge_blocks) * sizeof(double), 256);
     L.rec_off = off;
     off = align_up(off + (size_t)n * ((size_t)1 << dim) * 16, 256);
     L.urec_off = off;

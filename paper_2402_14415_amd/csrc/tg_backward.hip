@@ -174,7 +174,7 @@ __device__ __forceinline__ double brick_epilogue(const Geom& g, const int32_t* b
 }
 
 template <int DIM, int K, int AD>
-__global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_per_eu(6))) void k_backward(Geom g, const int4* __restrict__ items,
+__global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_per_eu(DIM == 3 ? 6 : 4))) void k_backward(Geom g, const int4* __restrict__ items,
                                                                  const int32_t* __restrict__ meta, int64_t max_items,
                                                                  float* __restrict__ parts,
                                                                  const float4* __restrict__ rec,
@@ -471,7 +471,8 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
 }
 
 // Adds the partial sums of every split brick, in slot order, and writes the brick (or, with
-// AD >= 0, applies Adam to it; block b's sum(dC^2) goes to partials[max_items + b]).
+// AD >= 0, applies Adam to it).  Block b takes split bricks b, b + G, ... (G blocks); its
+// sum(dC^2) goes to partials[max_items + b].
 template <int DIM, int K, int AD>
 __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward_merge(Geom g, const int4* __restrict__ items,
                                                                        const int32_t* __restrict__ split_first,
@@ -483,35 +484,32 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward_merge(Geom g, 
     using S = BwdShape<DIM>;
     constexpr int B = S::B, NOWN = S::NOWN;
     constexpr int C = NumCoeffs<DIM, K>::value;
-    if ((int32_t)blockIdx.x >= meta[META_NSPLITB]) {
-        if constexpr (AD >= 0) {
-            if (threadIdx.x == 0) AB.partials[max_items + blockIdx.x] = 0.0;
+    const int32_t nsplit = meta[META_NSPLITB];
+    double ss = 0.0;
+    for (int32_t sb = blockIdx.x; sb < nsplit; sb += gridDim.x) {
+        const int32_t first = split_first[sb];
+        const int4 wi = items[first];
+        const int32_t brick = wi.x, nchunk = wi.w;
+        int32_t bc[3], base[3], nown[3];
+        vbrick_coords<DIM>(g, brick, bc);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            base[a] = bc[a] * B;
+            nown[a] = min(B, g.res[a] - base[a]);
         }
-        return;
-    }
-    const int32_t first = split_first[blockIdx.x];
-    const int4 wi = items[first];
-    const int32_t brick = wi.x, nchunk = wi.w;
-    int32_t bc[3], base[3], nown[3];
-    vbrick_coords<DIM>(g, brick, bc);
+        float vk[C];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        base[a] = bc[a] * B;
-        nown[a] = min(B, g.res[a] - base[a]);
-    }
-    float vk[C];
+        for (int k = 0; k < C; ++k) vk[k] = 0.0f;
+        for (int j = 0; j < nchunk; ++j) {
+            const float* slot = parts + (int64_t)(first + j) * (NOWN * C);
 #pragma unroll
-    for (int k = 0; k < C; ++k) vk[k] = 0.0f;
-    for (int j = 0; j < nchunk; ++j) {
-        const float* slot = parts + (int64_t)(first + j) * (NOWN * C);
-#pragma unroll
-        for (int k = 0; k < C; ++k) vk[k] += slot[epi_elem<DIM, C>(k)];
+            for (int k = 0; k < C; ++k) vk[k] += slot[epi_elem<DIM, C>(k)];
+        }
+        ss += brick_epilogue<DIM, C, AD>(g, base, nown, vk, grad, accumulate, AB);
     }
     if constexpr (AD >= 0) {
-        const double tot = block_sum_f64<NOWN>(brick_epilogue<DIM, C, AD>(g, base, nown, vk, grad, 0, AB));
+        const double tot = block_sum_f64<NOWN>(ss);
         if (threadIdx.x == 0) AB.partials[max_items + blockIdx.x] = tot;
-    } else {
-        brick_epilogue<DIM, C, AD>(g, base, nown, vk, grad, accumulate, AB);
     }
 }
 
@@ -534,7 +532,7 @@ static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const W
         const dim3 block(BwdShape<D>::NOWN);                                                                 \
         hipLaunchKernelGGL((k_backward<D, KK, AD>), grid, block, 0, s, g->geom, items, meta, L.max_bitems, parts, \
                            rec, g_f, g_grad, urec, gr, acc, AB);                                             \
-        hipLaunchKernelGGL((k_backward_merge<D, KK, AD>), dim3((unsigned)g->nbricks), block, 0, s, g->geom,  \
+        hipLaunchKernelGGL((k_backward_merge<D, KK, AD>), dim3((unsigned)L.merge_blocks), block, 0, s, g->geom, \
                            items, split_first, meta, parts, gr, acc, L.max_bitems, AB);                      \
         return hipGetLastError();                                                                            \
     }
@@ -570,7 +568,7 @@ hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, con
     default: e = launch_backward_impl<ST_F16>(g, ws, L, g_f, g_grad, urec, false, AB, s); break;
     }
     if (e != hipSuccess || !grad_norm_sq) return e;
-    return launch_sum_finish(AB.partials, L.max_bitems + g->nbricks, grad_norm_sq, s);
+    return launch_sum_finish(AB.partials, L.max_bitems + L.merge_blocks, grad_norm_sq, s);
 }
 
 }  // namespace tg

@@ -27,7 +27,7 @@ namespace tg {
 constexpr int kThreads = 256;
 constexpr int kSortThreads = 1024;       // threads per block of the LDS-histogram sort
 constexpr int64_t kLdsBytes = 160 * 1024; // LDS one workgroup may allocate on gfx950
-constexpr int64_t kMaxLdsKeys32 = kLdsBytes / 4;  // 32-bit LDS counters
+constexpr int64_t kMaxLdsKeys32 = (kLdsBytes - 1024) / 4;  // 32-bit LDS counters (1 KB left for a scan)
 constexpr int64_t kMaxLdsKeys16 = kLdsBytes / 2;  // packed 16-bit LDS counters
 constexpr int64_t kMaxSlice16 = 65535;   // queries per block with 16-bit counters
 constexpr int kMaxSortBlocks = 256;      // rows of the [blocks x keys] count matrix
@@ -55,7 +55,7 @@ struct WsLayout {
     size_t splitb_off;   // int32 [nbricks]: first backward item of each split brick
     size_t parts_off;    // float [max_slots x brick accumulator]: partial sums of split bricks
     size_t fpart_off;    // double [2 x fwd_blocks]: per-workgroup loss sums of the fused forward
-    size_t bpart_off;    // double [max_bitems + nbricks]: per-workgroup sum(dC^2) of the fused adjoint
+    size_t bpart_off;    // double [max_bitems + merge_blocks]: per-workgroup sum(dC^2) of the fused adjoint
     size_t rec_off;      // float4 [n * 2^dim]: sorted query records (x, y, z, tag)
     size_t urec_off;     // float4 [n * 2^dim]: upstream gradients (g_f, g_grad) in record order
     size_t total;
@@ -67,6 +67,7 @@ struct WsLayout {
     int64_t fwd_blocks;  // workgroups of a forward launch
     int64_t max_bitems;  // bound on backward work items
     int64_t max_slots;   // bound on partial-sum slots of split backward bricks
+    int64_t merge_blocks;  // workgroups of the merge launch (each takes split bricks in turn)
     int64_t acc_floats;  // floats in one brick accumulator (B^dim * C)
 };
 

@@ -12,12 +12,14 @@
 // Counting sort without global atomics (device-scope atomics are slow on this GPU):
 //   1. every block takes a contiguous slice of the queries and counts its records per key
 //      in an LDS histogram (LDS integer atomics), writing one row of a [blocks x keys]
-//      matrix.  Up to 40960 keys the counters are 32-bit; up to 81920 keys two 16-bit
+//      matrix.  Up to 40704 keys the counters are 32-bit; up to 81920 keys two 16-bit
 //      counters share a word (a block then takes at most 65535 queries, and a query adds
 //      at most one record to a key, so a counter cannot overflow);
-//   2. a column scan turns the matrix into per-(block, key) offsets and per-key totals,
-//      and one block scans the totals into the key offsets and builds the work lists;
-//   3. every block recomputes its records and places each at key offset + its block's
+//   2. a column scan turns the matrix into per-(block, key) offsets and per-key totals;
+//   3. the key totals are scanned into key offsets and the work lists are built: with
+//      32-bit counters by every block of step 4 itself (so no separate pass), with packed
+//      counters by one block;
+//   4. every block recomputes its records and places each at key offset + its block's
 //      column offset + a rank drawn from an LDS counter.
 // Grids with more keys than that use a slower path with global atomic counters.
 #include "tg_internal.hpp"
@@ -97,11 +99,14 @@ constexpr int kFinishThreads = 512;
 constexpr int kFinishBricks = 8;  // bricks per thread and pass
 
 // Block-wide exclusive scan of NV values per thread; returns this thread's exclusive
-// offsets in start[] and the block totals in total[].
-template <int NV>
+// offsets in start[] and the block totals in total[].  The waves' totals are scanned by
+// the first wave, so that a thread reads two words per value from LDS.
+template <int NV, int NT>
 __device__ __forceinline__ void block_scan_multi(const int32_t* val, int32_t* start, int32_t* total)
 {
-    __shared__ int32_t wt[NV][kFinishThreads / 64];
+    constexpr int NW = NT / 64;
+    static_assert(NW <= 64, "one wave scans the wave totals");
+    __shared__ int32_t wt[NV][NW + 1];  // wave totals, then their exclusive prefix; [NW]: block total
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int32_t incl[NV];
 #pragma unroll
@@ -115,19 +120,79 @@ __device__ __forceinline__ void block_scan_multi(const int32_t* val, int32_t* st
         if (lane == 63) wt[v][wave] = incl[v];
     }
     __syncthreads();
+    if (wave == 0) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        int32_t before = 0, all = 0;
+        for (int v = 0; v < NV; ++v) {
+            const int32_t t = lane < NW ? wt[v][lane] : 0;
+            int32_t it = t;
 #pragma unroll
-        for (int w = 0; w < kFinishThreads / 64; ++w) {
-            const int32_t t = wt[v][w];
-            before += w < wave ? t : 0;
-            all += t;
+            for (int d = 1; d < NW; d <<= 1) {
+                const int32_t o = __shfl_up(it, d, 64);
+                if (lane >= d) it += o;
+            }
+            if (lane < NW) wt[v][lane] = it - t;
+            if (lane == NW - 1) wt[v][NW] = it;
         }
-        start[v] = before + incl[v] - val[v];
-        total[v] = all;
     }
     __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        start[v] = wt[v][wave] + incl[v] - val[v];
+        total[v] = wt[v][NW];
+    }
+    __syncthreads();  // wt is reused by the next call
+}
+
+// The five work-list quantities of a brick with tp primary and ts secondary records:
+// records, forward items, front backward items, back backward items, split bricks.
+__device__ __forceinline__ void brick_counts(int32_t tp, int32_t ts, bool exists, int32_t* v)
+{
+    const int32_t nr = tp + ts;
+    const int32_t nb = (nr + kBwdItemMax - 1) / kBwdItemMax;
+    v[0] += nr;
+    v[1] += (tp + kFwdChunk - 1) / kFwdChunk;
+    v[2] += nr > kBwdItem ? nb : 0;
+    v[3] += (exists && nr <= kBwdItem) ? 1 : 0;
+    v[4] += nb > 1 ? 1 : 0;
+}
+
+// Writes the work items of brick b (when emit), whose running positions (the exclusive
+// scan of brick_counts over the bricks before it) are pos[]; advances pos[] past the brick.
+__device__ __forceinline__ void brick_items(int64_t b, int32_t tp, int32_t ts, int32_t* pos, const WorkPtrs& W,
+                                            bool emit = true)
+{
+    const int32_t r0 = pos[0], rp = r0 + tp, r1 = rp + ts;  // primary, secondary ends
+    pos[0] = r1;
+    const int32_t nf = (tp + kFwdChunk - 1) / kFwdChunk;
+    if (emit)
+        for (int32_t j = 0; j < nf; ++j)
+            W.fitems[pos[1] + j] = make_int4((int32_t)b, r0 + j * kFwdChunk, min(rp, r0 + (j + 1) * kFwdChunk), 0);
+    pos[1] += nf;
+    const int32_t nr = tp + ts;
+    const int32_t nb = (nr + kBwdItemMax - 1) / kBwdItemMax;
+    const bool front = nr > kBwdItem;
+    if (emit) {
+        if (front) {
+            for (int32_t j = 0; j < nb; ++j)
+                W.bitems[pos[2] + j] =
+                    make_int4((int32_t)b, r0 + j * kBwdItemMax, min(r1, r0 + (j + 1) * kBwdItemMax), nb);
+            if (nb > 1) W.split_first[pos[4]] = pos[2];
+        } else {
+            W.bitems[W.max_bitems - 1 - pos[3]] = make_int4((int32_t)b, r0, r1, 1);
+        }
+    }
+    // written without branches, so that the positions stay in registers
+    pos[2] += front ? nb : 0;
+    pos[3] += front ? 0 : 1;
+    pos[4] += nb > 1 ? 1 : 0;
+}
+
+__device__ __forceinline__ void write_meta(const int32_t* carry, const WorkPtrs& W)
+{
+    W.meta[META_FITEMS] = carry[1];
+    W.meta[META_BFRONT] = carry[2];
+    W.meta[META_BBACK] = carry[3];
+    W.meta[META_NSPLITB] = carry[4];
 }
 
 // One block: from the per-key totals, the exclusive key offsets offs[0..nkeys] (and a
@@ -136,7 +201,6 @@ __device__ __forceinline__ void block_scan_multi(const int32_t* val, int32_t* st
 __global__ __launch_bounds__(kFinishThreads) void k_sort_finish(const int32_t* total, int64_t nbricks,
                                                                int32_t* __restrict__ offs, int32_t* cursor, WorkPtrs W)
 {
-    // running totals: records, forward items, front and back backward items, split bricks
     int32_t carry[5] = {0, 0, 0, 0, 0};
     for (int64_t pass = 0; pass < nbricks; pass += (int64_t)kFinishThreads * kFinishBricks) {
         const int64_t b0 = pass + (int64_t)threadIdx.x * kFinishBricks;
@@ -149,57 +213,29 @@ __global__ __launch_bounds__(kFinishThreads) void k_sort_finish(const int32_t* t
         }
         int32_t v[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-        for (int k = 0; k < kFinishBricks; ++k) {
-            const int32_t nr = tp[k] + ts[k];
-            const int32_t nb = (nr + kBwdItemMax - 1) / kBwdItemMax;
-            v[0] += nr;
-            v[1] += (tp[k] + kFwdChunk - 1) / kFwdChunk;
-            v[2] += nr > kBwdItem ? nb : 0;
-            v[3] += (b0 + k < nbricks && nr <= kBwdItem) ? 1 : 0;
-            v[4] += nb > 1 ? 1 : 0;
-        }
+        for (int k = 0; k < kFinishBricks; ++k) brick_counts(tp[k], ts[k], b0 + k < nbricks, v);
         int32_t pos[5], all[5];
-        block_scan_multi<5>(v, pos, all);
+        block_scan_multi<5, kFinishThreads>(v, pos, all);
 #pragma unroll
         for (int u = 0; u < 5; ++u) pos[u] += carry[u];
 #pragma unroll
         for (int k = 0; k < kFinishBricks; ++k) {
             const int64_t b = b0 + k;
             if (b >= nbricks) break;
-            const int32_t r0 = pos[0], rp = r0 + tp[k], r1 = rp + ts[k];  // primary, secondary ends
-            offs[2 * b] = r0;
-            offs[2 * b + 1] = rp;
+            offs[2 * b] = pos[0];
+            offs[2 * b + 1] = pos[0] + tp[k];
             if (cursor) {
-                cursor[2 * b] = r0;
-                cursor[2 * b + 1] = rp;
+                cursor[2 * b] = pos[0];
+                cursor[2 * b + 1] = pos[0] + tp[k];
             }
-            pos[0] = r1;
-            const int32_t nf = (tp[k] + kFwdChunk - 1) / kFwdChunk;
-            for (int32_t j = 0; j < nf; ++j)
-                W.fitems[pos[1] + j] = make_int4((int32_t)b, r0 + j * kFwdChunk, min(rp, r0 + (j + 1) * kFwdChunk), 0);
-            pos[1] += nf;
-            const int32_t nr = tp[k] + ts[k];
-            const int32_t nb = (nr + kBwdItemMax - 1) / kBwdItemMax;
-            if (nr > kBwdItem) {
-                for (int32_t j = 0; j < nb; ++j)
-                    W.bitems[pos[2] + j] =
-                        make_int4((int32_t)b, r0 + j * kBwdItemMax, min(r1, r0 + (j + 1) * kBwdItemMax), nb);
-                if (nb > 1) W.split_first[pos[4]++] = pos[2];
-                pos[2] += nb;
-            } else {
-                W.bitems[W.max_bitems - 1 - pos[3]] = make_int4((int32_t)b, r0, r1, 1);
-                ++pos[3];
-            }
+            brick_items(b, tp[k], ts[k], pos, W);
         }
 #pragma unroll
         for (int u = 0; u < 5; ++u) carry[u] += all[u];
     }
     if (threadIdx.x == 0) {
         offs[2 * nbricks] = carry[0];
-        W.meta[META_FITEMS] = carry[1];
-        W.meta[META_BFRONT] = carry[2];
-        W.meta[META_BBACK] = carry[3];
-        W.meta[META_NSPLITB] = carry[4];
+        write_meta(carry, W);
     }
 }
 
@@ -258,9 +294,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(Geom g, const float
 
 // Column scan of the [nblk x nkeys] matrix: per-(block, key) offsets within the key, and
 // per-key totals.  A workgroup takes 64 keys (one per lane) and splits the rows among its
-// waves: each wave sums its rows, the waves' sums are scanned through LDS, and each wave
-// rewrites its rows as running offsets.
+// waves: each wave sums its rows (kept in registers), the waves' sums are scanned through
+// LDS, and each wave rewrites its rows as running offsets.
 constexpr int kColWaves = 16;
+constexpr int kColRows = kMaxSortBlocks / kColWaves;  // rows per wave at most
+static_assert(kMaxSortBlocks % kColWaves == 0, "the matrix rows must split evenly over the waves");
 __global__ __launch_bounds__(64 * kColWaves) void k_sort_colscan(int32_t* __restrict__ mat, int32_t nblk,
                                                                 int32_t nkeys, int32_t* __restrict__ total)
 {
@@ -270,13 +308,12 @@ __global__ __launch_bounds__(64 * kColWaves) void k_sort_colscan(int32_t* __rest
     const bool ok = key < nkeys;
     const int32_t per = (nblk + kColWaves - 1) / kColWaves;
     const int32_t r0 = min(nblk, wave * per), r1 = min(nblk, r0 + per);
+    int32_t v[kColRows];
     int32_t s = 0;
-    for (int32_t r = r0; r < r1; r += 8) {
-        int32_t v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = (ok && r + u < r1) ? mat[(int64_t)(r + u) * nkeys + key] : 0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) s += v[u];
+    for (int u = 0; u < kColRows; ++u) {
+        v[u] = (ok && r0 + u < r1) ? mat[(int64_t)(r0 + u) * nkeys + key] : 0;
+        s += v[u];
     }
     gsum[wave][lane] = s;
     __syncthreads();
@@ -289,38 +326,21 @@ __global__ __launch_bounds__(64 * kColWaves) void k_sort_colscan(int32_t* __rest
     }
     if (!ok) return;
     if (wave == 0) total[key] = all;
-    for (int32_t r = r0; r < r1; r += 8) {
-        int32_t v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = r + u < r1 ? mat[(int64_t)(r + u) * nkeys + key] : 0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (r + u < r1) mat[(int64_t)(r + u) * nkeys + key] = run;
-            run += v[u];
-        }
+    for (int u = 0; u < kColRows; ++u) {
+        if (r0 + u < r1) mat[(int64_t)(r0 + u) * nkeys + key] = run;
+        run += v[u];
     }
 }
 
-// Places the records.  32-bit counters start at the block's cursor for each key; packed
-// 16-bit counters hold ranks only, and the key's base (bucket offset + block offset) is
-// read from global memory.
+// Places the records of queries [beg, end).  32-bit counters (cursor) start at the block's
+// position for each key; packed 16-bit counters hold ranks only, and the key's base (bucket
+// offset + block offset) is read from global memory.
 template <int DIM, bool PACK16>
-__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Geom g, const float* __restrict__ q, int64_t n,
-                                                               int64_t slice, int32_t nkeys,
-                                                               const int32_t* __restrict__ mat,
-                                                               const int32_t* __restrict__ offs,
-                                                               float4* __restrict__ rec)
+__device__ __forceinline__ void place_queries(const Geom& g, const float* __restrict__ q, int64_t beg, int64_t end,
+                                              const int32_t* __restrict__ row, const int32_t* __restrict__ offs,
+                                              uint32_t* cursor, float4* __restrict__ rec)
 {
-    extern __shared__ uint32_t cursor[];
-    const int32_t* row = mat + (int64_t)blockIdx.x * nkeys;
-    if constexpr (PACK16) {
-        for (int k = threadIdx.x; k < lds_words<true>(nkeys); k += kSortThreads) cursor[k] = 0u;
-    } else {
-        for (int k = threadIdx.x; k < nkeys; k += kSortThreads) cursor[k] = (uint32_t)(offs[k] + row[k]);
-    }
-    __syncthreads();
-    const int64_t beg = (int64_t)blockIdx.x * slice;
-    const int64_t end = min(n, beg + slice);
     for (int64_t i0 = beg; i0 < end; i0 += (int64_t)kSortThreads * kSortUnroll) {
         float x[kSortUnroll][3];
 #pragma unroll
@@ -342,6 +362,76 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Geom g, const flo
             });
         }
     }
+}
+
+// Packed 16-bit path: places the records after k_sort_finish has written the key offsets.
+template <int DIM>
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter16(Geom g, const float* __restrict__ q, int64_t n,
+                                                                 int64_t slice, int32_t nkeys,
+                                                                 const int32_t* __restrict__ mat,
+                                                                 const int32_t* __restrict__ offs,
+                                                                 float4* __restrict__ rec)
+{
+    extern __shared__ uint32_t cursor[];
+    for (int k = threadIdx.x; k < lds_words<true>(nkeys); k += kSortThreads) cursor[k] = 0u;
+    __syncthreads();
+    const int64_t beg = (int64_t)blockIdx.x * slice;
+    place_queries<DIM, true>(g, q, beg, min(n, beg + slice), mat + (int64_t)blockIdx.x * nkeys, offs, cursor, rec);
+}
+
+// 32-bit path: places the records and builds the work lists on the way.  Every block scans
+// the key totals itself (the same integer arithmetic in every block, so all agree), which
+// gives the offsets of all keys, and starts its LDS cursor of a key at the key's offset plus
+// the block's column offset; block b writes the work items of its share of bricks
+// [b s, (b + 1) s), s = ceil(bricks / blocks), and block 0 the list sizes.  This takes the
+// place of a separate single-block pass over the totals.
+constexpr int kPlaceBricks = 4;  // bricks per thread and pass of the key scan
+template <int DIM>
+__global__ __launch_bounds__(kSortThreads) void k_sort_place(Geom g, const float* __restrict__ q, int64_t n,
+                                                             int64_t slice, int64_t nbricks,
+                                                             const int32_t* __restrict__ mat,
+                                                             const int32_t* __restrict__ total,
+                                                             float4* __restrict__ rec, WorkPtrs W)
+{
+    extern __shared__ uint32_t cursor[];
+    const int64_t nkeys = 2 * nbricks;
+    const int32_t* row = mat + (int64_t)blockIdx.x * nkeys;
+    const int64_t share = (nbricks + gridDim.x - 1) / gridDim.x;
+    const int64_t s0 = (int64_t)blockIdx.x * share, s1 = min(nbricks, s0 + share);
+    int32_t carry[5] = {0, 0, 0, 0, 0};
+    for (int64_t pass = 0; pass < nbricks; pass += (int64_t)kSortThreads * kPlaceBricks) {
+        const int64_t b0 = pass + (int64_t)threadIdx.x * kPlaceBricks;
+        int32_t tp[kPlaceBricks], ts[kPlaceBricks], cp[kPlaceBricks], cs[kPlaceBricks];
+#pragma unroll
+        for (int k = 0; k < kPlaceBricks; ++k) {
+            const bool ok = b0 + k < nbricks;
+            tp[k] = ok ? total[2 * (b0 + k)] : 0;
+            ts[k] = ok ? total[2 * (b0 + k) + 1] : 0;
+            cp[k] = ok ? row[2 * (b0 + k)] : 0;
+            cs[k] = ok ? row[2 * (b0 + k) + 1] : 0;
+        }
+        int32_t v[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < kPlaceBricks; ++k) brick_counts(tp[k], ts[k], b0 + k < nbricks, v);
+        int32_t pos[5], all[5];
+        block_scan_multi<5, kSortThreads>(v, pos, all);
+#pragma unroll
+        for (int u = 0; u < 5; ++u) pos[u] += carry[u];
+#pragma unroll
+        for (int k = 0; k < kPlaceBricks; ++k) {
+            const int64_t b = b0 + k;
+            if (b >= nbricks) break;
+            cursor[2 * b] = (uint32_t)(pos[0] + cp[k]);
+            cursor[2 * b + 1] = (uint32_t)(pos[0] + tp[k] + cs[k]);
+            brick_items(b, tp[k], ts[k], pos, W, b >= s0 && b < s1);
+        }
+#pragma unroll
+        for (int u = 0; u < 5; ++u) carry[u] += all[u];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) write_meta(carry, W);
+    __syncthreads();
+    const int64_t beg = (int64_t)blockIdx.x * slice;
+    place_queries<DIM, false>(g, q, beg, min(n, beg + slice), row, nullptr, cursor, rec);
 }
 
 // ------------------------------------------------------------------ global-atomic path
@@ -386,22 +476,32 @@ static hipError_t launch_lds_sort(const tg_grid* g, const float* q, int64_t n, c
     const int32_t nkeys = (int32_t)L.nkeys;
     const size_t lds = (size_t)lds_words<PACK16>(nkeys) * sizeof(uint32_t);
     const dim3 gb((unsigned)L.sort_blocks), tb(kSortThreads);
+    const void* place = PACK16 ? (const void*)k_sort_scatter16<DIM> : (const void*)k_sort_place<DIM>;
     if (lds > 65536) {
-        // allow the full LDS of a CU for these kernels (idempotent, so a race is harmless)
-        hipError_t e = hipFuncSetAttribute((const void*)k_sort_count<DIM, PACK16>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_sort_scatter<DIM, PACK16>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-        if (e != hipSuccess) return e;
+        // allow the full LDS of a CU, less the kernel's static LDS, for these kernels (the
+        // same value every time, so a race between threads is harmless)
+        for (const void* f : {(const void*)k_sort_count<DIM, PACK16>, place}) {
+            hipFuncAttributes fa;
+            hipError_t e = hipFuncGetAttributes(&fa, f);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)(kLdsBytes - (int64_t)fa.sharedSizeBytes));
+            if (e != hipSuccess) return e;
+        }
     }
     hipLaunchKernelGGL((k_sort_count<DIM, PACK16>), gb, tb, lds, s, g->geom, q, n, L.sort_slice, nkeys, mat);
     hipLaunchKernelGGL(k_sort_colscan, dim3(blocks_for(nkeys, 64)), dim3(64 * kColWaves), 0, s, mat,
                        (int32_t)L.sort_blocks, nkeys, total);
-    hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(kFinishThreads), 0, s, total, g->nbricks, offs, nullptr, W);
-    if (n > 0)
-        hipLaunchKernelGGL((k_sort_scatter<DIM, PACK16>), gb, tb, lds, s, g->geom, q, n, L.sort_slice, nkeys, mat,
-                           offs, rec);
+    if constexpr (PACK16) {
+        hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(kFinishThreads), 0, s, total, g->nbricks, offs, nullptr, W);
+        if (n > 0)
+            hipLaunchKernelGGL(k_sort_scatter16<DIM>, gb, tb, lds, s, g->geom, q, n, L.sort_slice, nkeys, mat, offs,
+                               rec);
+    } else {
+        // also when there are no queries: it writes the work lists
+        hipLaunchKernelGGL(k_sort_place<DIM>, gb, tb, lds, s, g->geom, q, n, L.sort_slice, g->nbricks, mat, total,
+                           rec, W);
+    }
     return hipGetLastError();
 }
 
