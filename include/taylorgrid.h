@@ -196,7 +196,8 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
                         const tg_adam_params* params, double* loss, double* grad_norm_sq, void* ws,
                         size_t ws_bytes, void* const* stage_events, void* stream);
 /* stage_events: NULL, or a host array of 3 hipEvent_t that are recorded on the stream after
- * the sort, after the forward with the loss and after the adjoint with Adam (for timing). */
+ * the sort, after the forward with the loss terms and after the adjoint with Adam and the
+ * final FP64 reductions of the loss and the gradient norm (for timing). */
 
 /* One Adam step over every coefficient (the paper trains the grid with a fixed learning
  * rate and names no optimizer; this is Adam with bias correction, eps added to the

@@ -388,9 +388,15 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
     if (e == hipSuccess) e = mark(0);
     if (e == hipSuccess)
         e = tg::launch_forward_loss(grid, n, w, L, d, eik_weight, nullptr, nullptr, loss, nullptr, nullptr, s,
-                                    true);
+                                    true, false);
     if (e == hipSuccess) e = mark(1);
-    if (e == hipSuccess) e = tg::launch_backward_adam(grid, n, w, L, nullptr, nullptr, *params, grad_norm_sq, s, true);
+    if (e == hipSuccess) e = tg::launch_backward_adam(grid, n, w, L, nullptr, nullptr, *params, nullptr, s, true);
+    // both FP64 reductions (the loss and sum(dC^2)) in one launch
+    if (e == hipSuccess)
+        e = tg::launch_loss_finish(reinterpret_cast<const double*>(w + L.fpart_off), n > 0 ? L.fwd_blocks : 0, n,
+                                   eik_weight, loss, s,
+                                   grad_norm_sq ? reinterpret_cast<const double*>(w + L.bpart_off) : nullptr,
+                                   L.max_bitems + L.merge_blocks, grad_norm_sq);
     if (e == hipSuccess) e = mark(2);
     st = device_status(e, "tg_train_step");
     if (st == TG_OK) {  // the workspace holds this sort: tg_forward / tg_backward may reuse it

@@ -94,14 +94,17 @@ hipError_t launch_sdf_loss(int dim, int64_t n, const float* f, const float* grad
                            hipStream_t s);
 hipError_t launch_adam(const tg_grid* g, const tg_adam_params& p, double* grad_norm_sq, double* partials,
                        bool zero_grad, hipStream_t s);
+// With finish = false the loss partials stay in the workspace (fpart_off, fwd_blocks pairs)
+// for a later launch_loss_finish.
 hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* d,
                                float eik_weight, float* g_f, float* g_grad, double* loss, float* f, float* grad_f,
-                               hipStream_t s, bool record_order = false);
+                               hipStream_t s, bool record_order = false, bool finish = true);
 hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
                                 const float* g_grad, const tg_adam_params& p, double* grad_norm_sq, hipStream_t s,
                                 bool record_order = false);
+// Also sums ng sum(dC^2) partials into *gnorm when gpart is given.
 hipError_t launch_loss_finish(const double* partials, int64_t nblocks, int64_t n, float eik_weight, double* loss,
-                              hipStream_t s);
+                              hipStream_t s, const double* gpart = nullptr, int64_t ng = 0, double* gnorm = nullptr);
 hipError_t launch_sum_finish(const double* partials, int64_t nblocks, double* out, hipStream_t s);
 AdamArgs make_adam_args(const tg_adam_params& p);
 hipError_t launch_query(const tg_grid* const* grids, int32_t n_grids, const tg_request* reqs, int32_t n_reqs,

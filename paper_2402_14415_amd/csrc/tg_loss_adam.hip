@@ -59,30 +59,63 @@ __global__ __launch_bounds__(kThreads) void k_sdf_loss(int64_t n, const float* _
 // One block of 1024 threads adds the per-block partials (loads issued 8 at a time).
 constexpr int kFinishReduceThreads = 1024;
 
-__global__ __launch_bounds__(kFinishReduceThreads) void k_loss_finish(const double* __restrict__ partials, int nblocks,
-                                                                      double inv_n, double w_eik, double* __restrict__ loss)
+// This thread's share of sum_b p[S b + k] (k < S) over the blocks b < nblocks, added to acc.
+template <int S>
+__device__ __forceinline__ void thread_partial_sums(const double* __restrict__ p, int nblocks, double* acc)
 {
-    double sr = 0.0, se = 0.0;
     for (int b0 = 0; b0 < nblocks; b0 += 8 * kFinishReduceThreads) {
-        double r[8], e[8];
+        double v[8][S];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int b = b0 + u * kFinishReduceThreads + threadIdx.x;
-            r[u] = b < nblocks ? partials[2 * b] : 0.0;
-            e[u] = b < nblocks ? partials[2 * b + 1] : 0.0;
+#pragma unroll
+            for (int k = 0; k < S; ++k) v[u][k] = b < nblocks ? p[(int64_t)S * b + k] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            sr += r[u];
-            se += e[u];
+#pragma unroll
+            for (int k = 0; k < S; ++k) acc[k] += v[u][k];
         }
     }
-    sr = block_sum_f64<kFinishReduceThreads>(sr);
-    se = block_sum_f64<kFinishReduceThreads>(se);
+}
+
+// loss[1] = mean |r|, loss[2] = mean (|grad f| - 1)^2, loss[0] = loss[1] + w_eik loss[2] from
+// the (sum |r|, sum (|grad f| - 1)^2) pairs of nl blocks; with gpart, also *gnorm = the sum of
+// ng sum(dC^2) partials (the training step finishes both reductions in one launch).
+__global__ __launch_bounds__(kFinishReduceThreads) void k_loss_finish(const double* __restrict__ partials, int nblocks,
+                                                                      double inv_n, double w_eik, double* __restrict__ loss,
+                                                                      const double* __restrict__ gpart, int ng,
+                                                                      double* __restrict__ gnorm)
+{
+    // both sets of partials are loaded in the same rounds (thread_partial_sums' order per set)
+    double acc[2] = {0.0, 0.0}, sg = 0.0;
+    if (!gpart) ng = 0;
+    for (int b0 = 0; b0 < max(nblocks, ng); b0 += 8 * kFinishReduceThreads) {
+        double v[8][2], w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + u * kFinishReduceThreads + threadIdx.x;
+            v[u][0] = b < nblocks ? partials[2 * (int64_t)b] : 0.0;
+            v[u][1] = b < nblocks ? partials[2 * (int64_t)b + 1] : 0.0;
+            w[u] = b < ng ? gpart[b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            acc[0] += v[u][0];
+            acc[1] += v[u][1];
+            sg += w[u];
+        }
+    }
+    const double sr = block_sum_f64<kFinishReduceThreads>(acc[0]);
+    const double se = block_sum_f64<kFinishReduceThreads>(acc[1]);
     if (threadIdx.x == 0) {
         loss[1] = sr * inv_n;
         loss[2] = se * inv_n;
         loss[0] = loss[1] + w_eik * loss[2];
+    }
+    if (gpart) {
+        sg = block_sum_f64<kFinishReduceThreads>(sg);
+        if (threadIdx.x == 0 && gnorm) *gnorm = sg;
     }
 }
 
@@ -102,7 +135,7 @@ hipError_t launch_sdf_loss(int dim, int64_t n, const float* f, const float* grad
     }
     const double w = grad_f ? (double)eik_weight : 0.0;
     hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(kFinishReduceThreads), 0, s, partials, (int)nb,
-                       n > 0 ? 1.0 / (double)n : 0.0, w, loss);
+                       n > 0 ? 1.0 / (double)n : 0.0, w, loss, nullptr, 0, nullptr);
     return hipGetLastError();
 }
 
@@ -165,16 +198,7 @@ __global__ __launch_bounds__(kFinishReduceThreads) void k_sum_finish(const doubl
                                                                      double* __restrict__ out)
 {
     double acc = 0.0;
-    for (int b0 = 0; b0 < nblocks; b0 += 8 * kFinishReduceThreads) {
-        double v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int b = b0 + u * kFinishReduceThreads + threadIdx.x;
-            v[u] = b < nblocks ? partials[b] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc += v[u];
-    }
+    thread_partial_sums<1>(partials, nblocks, &acc);
     acc = block_sum_f64<kFinishReduceThreads>(acc);
     if (threadIdx.x == 0) *out = acc;
 }
@@ -196,10 +220,10 @@ AdamArgs make_adam_args(const tg_adam_params& p)
 }
 
 hipError_t launch_loss_finish(const double* partials, int64_t nblocks, int64_t n, float eik_weight, double* loss,
-                              hipStream_t s)
+                              hipStream_t s, const double* gpart, int64_t ng, double* gnorm)
 {
     hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(kFinishReduceThreads), 0, s, partials, (int)nblocks,
-                       n > 0 ? 1.0 / (double)n : 0.0, (double)eik_weight, loss);
+                       n > 0 ? 1.0 / (double)n : 0.0, (double)eik_weight, loss, gpart, (int)ng, gnorm);
     return hipGetLastError();
 }
 
