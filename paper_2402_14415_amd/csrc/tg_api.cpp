@@ -98,7 +98,7 @@ WsLayout ws_layout(const tg_grid* g, int64_t n)
     const int B = dim == 3 ? BrickEdge<3>::value : BrickEdge<2>::value;
     L.acc_floats = (dim == 3 ? (int64_t)B * B * B : (int64_t)B * B) * g->C;
     L.max_fitems = g->nbricks + (n + kFwdChunk - 1) / kFwdChunk;
-    L.fwd_blocks = 8 * ((L.max_fitems + 7) / 8);
+    L.fwd_blocks = L.max_fitems;
     L.max_bitems = g->nbricks + (n * fan + kBwdItemMax - 1) / kBwdItemMax;
     // A split item's slot is its item index, and split items are among the front items, of
     // which there are fewer than (records / kBwdItem): a front brick has more than kBwdItem

@@ -108,13 +108,13 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
     constexpr int NH = DIM == 3 ? 6 : 3;
     __shared__ __align__(16) uint32_t lds[NWIN * 64];
 
-    // Work item = (brick, chunk of up to kFwdChunk primary records).  Each XCD (blocks are
-    // dealt round-robin to the 8 XCDs) takes a contiguous range of items, so the vertex
-    // layers that neighbouring bricks share stay in one L2.
+    // Work item = (brick, chunk of up to kFwdChunk primary records), in list order.  Blocks
+    // are dealt round-robin to the 8 XCDs, so the crowded bricks of a surface, which are
+    // neighbours in the list, spread over all of them (giving each XCD a contiguous range of
+    // items instead was measured slower: the XCDs holding the surface finished last).
     const int32_t total = meta[META_FITEMS];
-    const int32_t per = (total + 7) / 8;
-    const int32_t item = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
-    const int4 wi = (int32_t)(blockIdx.x / 8) < per && item < total ? items[item] : make_int4(0, 0, 0, 0);
+    const int32_t item = (int32_t)blockIdx.x;
+    const int4 wi = item < total ? items[item] : make_int4(0, 0, 0, 0);
     const int32_t brick = wi.x, beg = wi.y, end = wi.z;
     if (beg >= end) {
         if constexpr (MODE == MODE_LOSS) {
