@@ -148,6 +148,26 @@ tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_
                       float eik_weight, float* g_f, float* g_grad, double* loss, void* ws,
                       size_t ws_bytes, void* stream);
 
+/* Radiance-field compositing (Sec. 3.3): the Max optical model of Eq. 10 along n_rays rays
+ * of n_samples samples each, with a ReLU density, and the photometric loss of Eq. 11 with
+ * its adjoint, in one launch.  Sample i of ray r is element r*n_samples + i of:
+ *   f [N]      the density grid's value (N = n_rays * n_samples; tg_forward output),
+ *   c [3][N]   the three colour channels (channel-major: one tg_forward output per channel),
+ *   delta [N]  the distance to the next sample along the ray (>= 0),
+ * and per ray
+ *   sigma_i = max(f_i, 0), T_i = exp(-sum_{j<i} sigma_j delta_j),
+ *   C(r) = sum_i T_i (1 - exp(-sigma_i delta_i)) c_i.
+ * rgb (may be NULL) [n_rays][3] receives C(r).  With loss != NULL (then target [n_rays][3],
+ * g_f and g_c are required unless n_rays == 0):
+ *   loss (device FP64) = (1/n_rays) sum_r |C(r) - target_r|^2 (0 for no rays),
+ *   g_f [N] = dL/df_i (0 where f_i <= 0) and g_c [3][N] = dL/dc_i, the upstream gradients
+ *   of the density and colour grids' adjoints (tg_backward's g_f).
+ * 1 <= n_samples <= 1024.  All arrays are device memory and must not overlap the outputs.
+ * ws must hold tg_reduce_workspace_bytes(). */
+tg_status tg_composite(int64_t n_rays, int32_t n_samples, const float* f, const float* c,
+                       const float* delta, const float* target, float* rgb, double* loss,
+                       float* g_f, float* g_c, void* ws, size_t ws_bytes, void* stream);
+
 /* Adjoint of tg_forward (the exact transpose of the map C -> (f, grad f), which is linear
  * in the coefficients; the paper prints no formula).  For upstream gradients g_f [n] and
  * g_grad [n][dim] (either may be NULL = zero) it writes, for every vertex of the grid,

@@ -71,6 +71,8 @@ _SIGS = {
                          ctypes.c_int),
     "tg_train_step": ([_P, _P, _P, ctypes.c_int64, ctypes.c_float, ctypes.POINTER(AdamParams), _P, _P, _P,
                        ctypes.c_size_t, ctypes.POINTER(_P), _P], ctypes.c_int),
+    "tg_composite": ([ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
+                     ctypes.c_int),
     "tg_adam_step": ([_P, ctypes.POINTER(AdamParams), _P, _P, ctypes.c_size_t, ctypes.c_int32, _P], ctypes.c_int),
     "tg_query": ([ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(Request), ctypes.c_int32, _P], ctypes.c_int),
     "tg_status_string": ([ctypes.c_int], ctypes.c_char_p),

@@ -425,6 +425,26 @@ tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_
                          "tg_sdf_loss");
 }
 
+tg_status tg_composite(int64_t n_rays, int32_t n_samples, const float* f, const float* c, const float* delta,
+                       const float* target, float* rgb, double* loss, float* g_f, float* g_c, void* ws,
+                       size_t ws_bytes, void* stream)
+{
+    if (n_rays < 0) return fail(TG_ERR_INVALID_ARG, "tg_composite: n_rays is negative");
+    if (n_samples < 1 || n_samples > 1024) return fail(TG_ERR_INVALID_ARG, "tg_composite: n_samples must be in 1..1024");
+    if (n_rays > tg::kMaxQueries / n_samples)
+        return fail(TG_ERR_CAPACITY, "tg_composite: more than %lld samples", (long long)tg::kMaxQueries);
+    if (n_rays > 0 && (!f || !c || !delta)) return fail(TG_ERR_INVALID_ARG, "tg_composite: f, c and delta must not be NULL");
+    if (target && !loss) return fail(TG_ERR_INVALID_ARG, "tg_composite: a target needs loss");
+    if (loss && n_rays > 0 && (!target || !g_f || !g_c))
+        return fail(TG_ERR_INVALID_ARG, "tg_composite: with loss, target, g_f and g_c must not be NULL");
+    if (!ws || !aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "tg_composite: workspace NULL or not 256-byte aligned");
+    if (ws_bytes < tg::kReduceBytes) return fail(TG_ERR_CAPACITY, "tg_composite: workspace smaller than %zu bytes", tg::kReduceBytes);
+    (void)hipGetLastError();
+    return device_status(tg::launch_composite(n_rays, n_samples, f, c, delta, target, rgb, loss, g_f, g_c,
+                                              static_cast<double*>(ws), static_cast<hipStream_t>(stream)),
+                         "tg_composite");
+}
+
 tg_status tg_adam_step(tg_grid* grid, const tg_adam_params* p, double* grad_norm_sq, void* ws, size_t ws_bytes,
                        int32_t flags, void* stream)
 {

@@ -106,6 +106,9 @@ hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, con
 hipError_t launch_loss_finish(const double* partials, int64_t nblocks, int64_t n, float eik_weight, double* loss,
                               hipStream_t s, const double* gpart = nullptr, int64_t ng = 0, double* gnorm = nullptr);
 hipError_t launch_sum_finish(const double* partials, int64_t nblocks, double* out, hipStream_t s);
+hipError_t launch_composite(int64_t n_rays, int32_t ns, const float* f, const float* col, const float* delta,
+                            const float* target, float* rgb, double* loss, float* g_f, float* g_c, double* partials,
+                            hipStream_t s);
 AdamArgs make_adam_args(const tg_adam_params& p);
 hipError_t launch_query(const tg_grid* const* grids, int32_t n_grids, const tg_request* reqs, int32_t n_reqs,
                         hipStream_t s);

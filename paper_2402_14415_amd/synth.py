@@ -14,6 +14,13 @@ Workloads (shapes follow the paper's SDF-fitting task, Sec. 3.2 and Sec. 4.1):
                uniform points in the box and half points on the union's surface (uniform on
                a uniformly chosen primitive, kept only when no other primitive contains it),
                jittered by N(0, 0.01) per coordinate.
+  * radiance : rays of 400 x 400-pixel pinhole cameras (40 degree field of view) placed on a
+               sphere of radius 4 around the box and looking at its centre (100 Fibonacci-
+               sphere positions); a batch draws random pixels, clips each ray to the box and
+               places stratified samples on the inside segment.  The reference volume is a
+               seeded sum of 32 anisotropic Gaussian blobs, each with a density and an RGB
+               colour (density- and colour-weighted mixture); it stands in for the
+               Synthetic-NeRF scenes.
 Random draws use numpy's PCG64 (``default_rng``) in FP64; callers cast to FP32 for the GPU
 and give the oracle the same FP32-rounded values.
 """
@@ -190,3 +197,85 @@ def scene_taylor_grid(scene: Scene, res, order, lo=-1.0, hi=1.0, device="cpu", e
                                      - sdf(p - E[a] + E[b]) + sdf(p - E[a] - E[b])) / (4 * eps ** 2))
         out[z] = torch.stack(cols, dim=-1).to(torch.float32)
     return out
+
+
+# ----------------------------------------------------------------------------- radiance rays
+def camera_centres(n_cams=100, radius=4.0):
+    """n_cams points spread over the sphere of the given radius (Fibonacci lattice)."""
+    i = np.arange(n_cams) + 0.5
+    z = 1.0 - 2.0 * i / n_cams
+    phi = np.pi * (1.0 + 5.0 ** 0.5) * i
+    rxy = np.sqrt(1.0 - z * z)
+    return radius * np.stack([rxy * np.cos(phi), rxy * np.sin(phi), z], axis=1)
+
+
+def camera_rays(n_rays, seed=0, step=0, n_cams=100, radius=4.0, width=400, fov_deg=40.0):
+    """Origins [n_rays, 3] and unit directions [n_rays, 3] of random pixel rays of pinhole
+    cameras on a sphere looking at the origin.  Draws from ``default_rng([seed, step, 7])``."""
+    rng = np.random.default_rng([seed, step, 7])
+    cams = camera_centres(n_cams, radius)
+    cam = rng.integers(0, n_cams, size=n_rays)
+    px = rng.integers(0, width, size=(n_rays, 2)) + 0.5
+    o = cams[cam]
+    fwd = -o / np.linalg.norm(o, axis=1, keepdims=True)
+    up = np.where(np.abs(fwd[:, 2:3]) < 0.99, np.array([[0.0, 0.0, 1.0]]), np.array([[0.0, 1.0, 0.0]]))
+    right = np.cross(fwd, up)
+    right /= np.linalg.norm(right, axis=1, keepdims=True)
+    up = np.cross(right, fwd)
+    half = np.tan(np.radians(fov_deg) / 2.0)
+    u = (px[:, 0:1] / width * 2.0 - 1.0) * half
+    v = (px[:, 1:2] / width * 2.0 - 1.0) * half
+    d = fwd + u * right + v * up
+    return o, d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def stratified_samples(o, d, n_samples, seed=0, step=0, lo=-1.0, hi=1.0):
+    """Sample positions and spacings along rays (o + t d) inside the box [lo, hi]^3.
+
+    The inside segment [t_in, t_out] comes from the slab test (empty for a ray that misses,
+    which then gets zero spacings); it is cut into n_samples equal strata with one uniform
+    position in each.  delta_i = t_{i+1} - t_i, and the last sample's runs to t_out.
+    Returns q [n_rays * n_samples, 3] and delta [n_rays * n_samples], both exactly
+    representable in FP32 (q ray-major, sample-minor)."""
+    rng = np.random.default_rng([seed, step, 11])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / d
+        t0 = (lo - o) * inv
+        t1 = (hi - o) * inv
+    tmin = np.nanmax(np.minimum(t0, t1), axis=1)
+    tmax = np.nanmin(np.maximum(t0, t1), axis=1)
+    t_in = np.maximum(tmin, 0.0)
+    t_out = np.maximum(tmax, t_in)  # a miss gives an empty segment
+    n = o.shape[0]
+    width = (t_out - t_in) / n_samples
+    t = t_in[:, None] + (np.arange(n_samples)[None, :] + rng.uniform(size=(n, n_samples))) * width[:, None]
+    t = t.astype(np.float32).astype(np.float64)
+    nxt = np.concatenate([t[:, 1:], t_out[:, None]], axis=1)
+    delta = np.maximum(nxt - t, 0.0).astype(np.float32).astype(np.float64)
+    q = o[:, None, :] + t[:, :, None] * d[:, None, :]
+    q = np.clip(q, lo, hi).astype(np.float32).astype(np.float64)
+    return q.reshape(-1, 3), delta.reshape(-1)
+
+
+class BlobVolume:
+    """A seeded sum of anisotropic Gaussian blobs: density(x) = sum_k a_k exp(-|A_k (x - m_k)|^2 / 2)
+    and colour(x) = the density-weighted mean of the blobs' RGB colours."""
+
+    def __init__(self, seed=0, n_blobs=32):
+        rng = np.random.default_rng([seed, 13])
+        self.m = rng.uniform(-0.6, 0.6, size=(n_blobs, 3))
+        scales = rng.uniform(4.0, 12.0, size=(n_blobs, 3))
+        rot = np.linalg.qr(rng.normal(size=(n_blobs, 3, 3)))[0]
+        self.A = scales[:, :, None] * np.transpose(rot, (0, 2, 1))
+        self.a = rng.uniform(5.0, 30.0, size=n_blobs)
+        self.rgb = rng.uniform(0.05, 0.95, size=(n_blobs, 3))
+
+    def density_and_colour(self, x):
+        x = np.asarray(x, dtype=np.float64)
+        g = np.zeros((x.shape[0], len(self.a)))
+        for k in range(len(self.a)):
+            y = (x - self.m[k]) @ self.A[k].T
+            g[:, k] = self.a[k] * np.exp(-0.5 * np.sum(y * y, axis=1))
+        dens = g.sum(axis=1)
+        col = (g @ self.rgb) / np.maximum(dens, 1e-12)[:, None]
+        return dens, col

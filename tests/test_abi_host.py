@@ -150,6 +150,22 @@ def test_loss_validation():
     assert L().tg_sdf_loss(3, 10, fake, fake, fake, 0.1, fake, fake, fake, fake, 8, None) == 4
 
 
+def test_composite_validation():
+    """Argument errors of tg_composite come back before any launch (no GPU needed)."""
+    fake = ctypes.c_void_p(0x100000)
+    big = L().tg_reduce_workspace_bytes()
+
+    def call(n_rays=4, ns=256, f=fake, c=fake, delta=fake, target=None, loss=fake, g_f=fake, g_c=fake, ws=fake, wsb=big):
+        return L().tg_composite(n_rays, ns, f, c, delta, target, None, loss, g_f, g_c, ws, wsb, None)
+
+    assert call(ns=0) == 1 and call(ns=1025) == 1 and call(n_rays=-1) == 1
+    assert call(f=None) == 1 and call(c=None) == 1 and call(delta=None) == 1
+    assert call(target=fake, loss=None) == 1 and call(target=fake, g_c=None) == 1 and call(target=None) == 1
+    assert call(ws=None) == 1 and call(ws=ctypes.c_void_p(0x100010)) == 1
+    assert call(wsb=8) == 4
+    assert call(n_rays=1 << 30, ns=1024) == 4  # more samples than the library takes
+
+
 def test_query_validation():
     b = _lib.GridBuffers()
     b.coeffs = b.master = 0x1000
