@@ -155,7 +155,8 @@ def test_composite_validation():
     fake = ctypes.c_void_p(0x100000)
     big = L().tg_reduce_workspace_bytes()
 
-    def call(n_rays=4, ns=256, f=fake, c=fake, delta=fake, target=None, loss=fake, g_f=fake, g_c=fake, ws=fake, wsb=big):
+    # every call below changes one argument of a valid set to an invalid value
+    def call(n_rays=4, ns=256, f=fake, c=fake, delta=fake, target=fake, loss=fake, g_f=fake, g_c=fake, ws=fake, wsb=big):
         return L().tg_composite(n_rays, ns, f, c, delta, target, None, loss, g_f, g_c, ws, wsb, None)
 
     assert call(ns=0) == 1 and call(ns=1025) == 1 and call(n_rays=-1) == 1
