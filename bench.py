@@ -265,6 +265,62 @@ def precision_bench(dev, steps=10, warmup=3, n_batches=2):
     return out
 
 
+def radiance_bench(dev, steps=10, warmup=3, n_batches=2, n_rays=4096, n_samples=256, res=160):
+    """Radiance-field form: a 160^3 density grid (K=2, ReLU) and three K=1 colour grids,
+    4096 rays x 256 stratified samples per step from cameras on a radius-4 sphere.  Targets
+    are the ray colours of the seeded blob volume, rendered by the library's own compositing
+    from the volume's density and colour at the samples.  One step evaluates the four grids
+    (sort + forward each), composites with the photometric loss and its adjoint, and applies
+    the fused adjoint + Adam to each grid."""
+    import torch
+
+    from paper_2402_14415_amd.radiance import RadianceField, composite
+
+    vol = synth.BlobVolume(0)
+    rng = np.random.default_rng(0)
+    field = RadianceField((res,) * 3, coeffs=(
+        torch.from_numpy((0.5 + 0.05 * rng.standard_normal((res, res, res, 10))).astype(np.float32)),
+        [torch.from_numpy((0.5 + 0.05 * rng.standard_normal((res, res, res, 4))).astype(np.float32))
+         for _ in range(3)]), device=dev)
+    batches = []
+    for b in range(n_batches):
+        o, d = synth.camera_rays(n_rays, seed=0, step=b)
+        q64, delta64 = synth.stratified_samples(o, d, n_samples, seed=0, step=b)
+        dens, col = vol.density_and_colour(q64)
+        q = torch.tensor(q64, dtype=torch.float32, device=dev)
+        delta = torch.tensor(delta64, dtype=torch.float32, device=dev)
+        rgb = composite(torch.tensor(dens, dtype=torch.float32, device=dev),
+                        torch.tensor(np.ascontiguousarray(col.T), dtype=torch.float32, device=dev),
+                        delta, n_samples, field.reduce_ws)[0]
+        batches.append((q, delta, rgb))
+    n = n_rays * n_samples
+    ws = field.workspaces(n)
+    bufs = (torch.empty(n, device=dev), torch.empty((3, n), device=dev), torch.empty((n_rays, 3), device=dev),
+            torch.empty(1, dtype=torch.float64, device=dev), torch.empty(n, device=dev),
+            torch.empty((3, n), device=dev))
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps + warmup)]
+    for e4 in ev:
+        for e in e4:
+            e.record()
+    torch.cuda.synchronize()
+    losses = []
+    for i in range(steps + warmup):
+        q, delta, target = batches[i % n_batches]
+        ev[i][0].record()
+        loss = field.train_step(q, delta, n_samples, target, ws, lr=1e-2, bufs=bufs, stage_events=ev[i][1:])
+        if i == 0 or i == steps + warmup - 1:
+            losses.append(float(loss[0]))
+    torch.cuda.synchronize()
+    stage = lambda k: float(np.median([ev[i][k].elapsed_time(ev[i][k + 1]) * 1e3 for i in range(warmup, warmup + steps)]))
+    step_us = float(np.median([ev[i][0].elapsed_time(ev[i][3]) * 1e3 for i in range(warmup, warmup + steps)]))
+    return {"workload": f"radiance_{res}^3_density_K2_relu_colour_3xK1", "rays_per_step": n_rays,
+            "samples_per_ray": n_samples, "step_us": step_us, "rays_per_s": n_rays / (step_us * 1e-6),
+            "samples_per_s": n / (step_us * 1e-6),
+            "stage_us": {"sort_and_evaluate_4_grids": stage(0), "composite_loss_adjoint": stage(1),
+                         "adjoint_adam_4_grids": stage(2)},
+            "loss_first_last": losses}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +331,7 @@ def main():
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-radiance", action="store_true")
     ap.add_argument("--copy-reference", action="store_true",
                     help="end with device-to-device copies of 256 MiB (the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
@@ -421,6 +478,10 @@ def main():
     if not args.no_precision:
         log("bench: precision forms")
         out["precision"] = precision_bench(dev)
+    if not args.no_radiance:
+        log("bench: radiance form")
+        out["radiance"] = radiance_bench(dev)
+        log(f"bench: radiance {json.dumps(out['radiance'])}")
     if not args.no_serving:
         log("bench: serving")
         out["serving"] = serving_bench(dev, dev_batches)

@@ -16,8 +16,9 @@ Workloads (shapes follow the paper's SDF-fitting task, Sec. 3.2 and Sec. 4.1):
                jittered by N(0, 0.01) per coordinate.
   * radiance : rays of 400 x 400-pixel pinhole cameras (40 degree field of view) placed on a
                sphere of radius 4 around the box and looking at its centre (100 Fibonacci-
-               sphere positions); a batch draws random pixels, clips each ray to the box and
-               places stratified samples on the inside segment.  The reference volume is a
+               sphere positions); a batch draws random pixels among those whose ray crosses
+               the box, clips each ray to the box and places stratified samples on the inside
+               segment.  The reference volume is a
                seeded sum of 32 anisotropic Gaussian blobs, each with a density and an RGB
                colour (density- and colour-weighted mixture); it stands in for the
                Synthetic-NeRF scenes.
@@ -209,10 +210,37 @@ def camera_centres(n_cams=100, radius=4.0):
     return radius * np.stack([rxy * np.cos(phi), rxy * np.sin(phi), z], axis=1)
 
 
-def camera_rays(n_rays, seed=0, step=0, n_cams=100, radius=4.0, width=400, fov_deg=40.0):
+def box_segment(o, d, lo=-1.0, hi=1.0):
+    """Entry and exit parameters (t_in <= t_out) of the rays o + t d (t >= 0) through the box
+    [lo, hi]^3 (slab test); t_in == t_out for a ray that misses it."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / d
+        t0 = (lo - o) * inv
+        t1 = (hi - o) * inv
+    tmin = np.nanmax(np.minimum(t0, t1), axis=1)
+    tmax = np.nanmin(np.maximum(t0, t1), axis=1)
+    t_in = np.maximum(tmin, 0.0)
+    return t_in, np.maximum(tmax, t_in)
+
+
+def camera_rays(n_rays, seed=0, step=0, n_cams=100, radius=4.0, width=400, fov_deg=40.0, lo=-1.0, hi=1.0):
     """Origins [n_rays, 3] and unit directions [n_rays, 3] of random pixel rays of pinhole
-    cameras on a sphere looking at the origin.  Draws from ``default_rng([seed, step, 7])``."""
+    cameras on a sphere looking at the origin, drawn among the pixels whose ray crosses the
+    box [lo, hi]^3 (a ray that misses it carries no samples).  Draws from
+    ``default_rng([seed, step, 7])``."""
     rng = np.random.default_rng([seed, step, 7])
+    out_o, out_d, have = [], [], 0
+    while have < n_rays:
+        o, d = _pixel_rays(rng, 2 * (n_rays - have) + 16, n_cams, radius, width, fov_deg)
+        t_in, t_out = box_segment(o, d, lo, hi)
+        hit = t_out > t_in
+        out_o.append(o[hit])
+        out_d.append(d[hit])
+        have += int(hit.sum())
+    return np.concatenate(out_o)[:n_rays], np.concatenate(out_d)[:n_rays]
+
+
+def _pixel_rays(rng, n_rays, n_cams, radius, width, fov_deg):
     cams = camera_centres(n_cams, radius)
     cam = rng.integers(0, n_cams, size=n_rays)
     px = rng.integers(0, width, size=(n_rays, 2)) + 0.5
@@ -238,14 +266,7 @@ def stratified_samples(o, d, n_samples, seed=0, step=0, lo=-1.0, hi=1.0):
     Returns q [n_rays * n_samples, 3] and delta [n_rays * n_samples], both exactly
     representable in FP32 (q ray-major, sample-minor)."""
     rng = np.random.default_rng([seed, step, 11])
-    with np.errstate(divide="ignore", invalid="ignore"):
-        inv = 1.0 / d
-        t0 = (lo - o) * inv
-        t1 = (hi - o) * inv
-    tmin = np.nanmax(np.minimum(t0, t1), axis=1)
-    tmax = np.nanmin(np.maximum(t0, t1), axis=1)
-    t_in = np.maximum(tmin, 0.0)
-    t_out = np.maximum(tmax, t_in)  # a miss gives an empty segment
+    t_in, t_out = box_segment(o, d, lo, hi)  # a miss gives an empty segment
     n = o.shape[0]
     width = (t_out - t_in) / n_samples
     t = t_in[:, None] + (np.arange(n_samples)[None, :] + rng.uniform(size=(n, n_samples))) * width[:, None]
