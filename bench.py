@@ -294,7 +294,7 @@ def radiance_bench(dev, steps=10, warmup=3, n_batches=2, n_rays=4096, n_samples=
                         delta, n_samples, field.reduce_ws)[0]
         batches.append((q, delta, rgb))
     n = n_rays * n_samples
-    ws = field.workspaces(n)
+    ws = field.workspace(n)
     bufs = (torch.empty(n, device=dev), torch.empty((3, n), device=dev), torch.empty((n_rays, 3), device=dev),
             torch.empty(1, dtype=torch.float64, device=dev), torch.empty(n, device=dev),
             torch.empty((3, n), device=dev))

@@ -126,10 +126,27 @@ size_t tg_reduce_workspace_bytes(void);
 /* Bucket the queries by brick of cells (an implementation step that makes the grid
  * gathers of tg_forward and the adjoint scatter of tg_backward local; it has no
  * counterpart in the paper).  Writes the sort into `ws`, and records (q, n, ws) in the
- * handle: tg_forward and tg_backward on the same (q, n, ws) reuse it.  The queries must
- * not change between this call and the calls that reuse the sort. */
+ * handle: tg_forward and tg_backward on the same (q, n, ws) reuse it, until another sort
+ * is written into ws (by any handle).  The queries must not change between this call and
+ * the calls that reuse the sort. */
 tg_status tg_sort_queries(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes,
                           void* stream);
+
+/* Let `grid` reuse the sort of (q, n) that `sorted` holds in ws (host only; nothing is
+ * enqueued).  The bucketing depends only on the cell geometry, so grids with the same dim,
+ * res, lo and hi (compared exactly) bucket the same queries identically, whatever their
+ * order or storage; a field with several grids on one vertex lattice (the density and
+ * colour grids of the radiance form, Sec. 3.3) sorts its samples once.  ws_bytes must cover
+ * tg_workspace_bytes(grid, n), which grows with the coefficient count: size a shared
+ * workspace for the grid with the most coefficients per vertex.  Errors: TG_ERR_INVALID_ARG
+ * for a NULL handle or different geometry, TG_ERR_CAPACITY for a short workspace,
+ * TG_ERR_STATE when ws does not hold sorted's current sort of (q, n).  A workspace is known
+ * by its address: any later tg_sort_queries or tg_train_step into ws supersedes the sort
+ * for every handle that shares it (their calls then fail with TG_ERR_STATE).  Calls that
+ * share a workspace must be ordered on one stream: each uses its reduction and partial-sum
+ * sections. */
+tg_status tg_share_sort(tg_grid* grid, const tg_grid* sorted, const float* q, int64_t n, const void* ws,
+                        size_t ws_bytes);
 
 /* Field value and spatial gradient at each query (Sec. 3.1, Eq. 2-4):
  *   f[i] = sum over the 2^dim corners b of the cell of w_b(x) T_b(x - v_b),

@@ -61,6 +61,7 @@ _SIGS = {
     "tg_workspace_bytes": ([_P, ctypes.c_int64], ctypes.c_size_t),
     "tg_reduce_workspace_bytes": ([], ctypes.c_size_t),
     "tg_sort_queries": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "tg_share_sort": ([_P, _P, _P, ctypes.c_int64, _P, ctypes.c_size_t], ctypes.c_int),
     "tg_forward": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "tg_sdf_loss": ([ctypes.c_int32, ctypes.c_int64, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P, ctypes.c_size_t, _P],
                     ctypes.c_int),

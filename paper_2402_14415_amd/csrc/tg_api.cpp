@@ -10,12 +10,36 @@
 #include <string>
 
 #include <algorithm>
+#include <mutex>
+#include <unordered_map>
 
 #include "tg_internal.hpp"
 
 namespace {
 
 thread_local std::string g_last_error;
+
+// Sort generation of every workspace a sort was written into.  A handle's recorded sort is
+// current only while its generation is the workspace's: a later sort into the same
+// workspace, by any handle, supersedes it.
+std::mutex g_ws_mutex;
+std::unordered_map<const void*, uint64_t> g_ws_gen;
+uint64_t g_next_gen = 0;
+
+uint64_t ws_new_generation(const void* ws)
+{
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    const uint64_t gen = ++g_next_gen;
+    g_ws_gen[ws] = gen;
+    return gen;
+}
+
+bool ws_generation_is(const void* ws, uint64_t gen)
+{
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    const auto it = g_ws_gen.find(ws);
+    return it != g_ws_gen.end() && it->second == gen;
+}
 
 tg_status fail(tg_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 tg_status fail(tg_status st, const char* fmt, ...)
@@ -114,8 +138,6 @@ WsLayout ws_layout(const tg_grid* g, int64_t n)
     off = align_up(off + (size_t)L.max_bitems * 16, 256);
     L.splitb_off = off;
     off = align_up(off + (size_t)g->nbricks * 4, 256);
-    L.parts_off = off;
-    off = align_up(off + (size_t)L.max_slots * (size_t)L.acc_floats * 4, 256);
     L.fpart_off = off;
     off = align_up(off + (size_t)L.fwd_blocks * 2 * sizeof(double), 256);
     L.bpart_off = off;
@@ -124,6 +146,10 @@ WsLayout ws_layout(const tg_grid* g, int64_t n)
     off = align_up(off + (size_t)n * ((size_t)1 << dim) * 16, 256);
     L.urec_off = off;
     off = align_up(off + (size_t)n * ((size_t)1 << dim) * 16, 256);
+    // Everything above depends only on the brick geometry and n, so grids of one geometry
+    // can share a sort (tg_share_sort); the split bricks' partial sums depend on C and come last.
+    L.parts_off = off;
+    off = align_up(off + (size_t)L.max_slots * (size_t)L.acc_floats * 4, 256);
     L.total = off;
     return L;
 }
@@ -253,7 +279,8 @@ static tg_status check_queries(const char* fn, const tg_grid* grid, const float*
 
 static tg_status check_sorted(const char* fn, const tg_grid* grid, const float* q, int64_t n, const void* ws)
 {
-    if (!grid->sort_valid || grid->sort_q != q || grid->sort_n != n || grid->sort_ws != ws)
+    if (!grid->sort_valid || grid->sort_q != q || grid->sort_n != n || grid->sort_ws != ws ||
+        !ws_generation_is(ws, grid->sort_gen))
         return fail(TG_ERR_STATE, "%s: workspace does not hold the sort of these queries (call tg_sort_queries first)", fn);
     return ok();
 }
@@ -265,15 +292,40 @@ tg_status tg_sort_queries(tg_grid* grid, const float* q, int64_t n, void* ws, si
     if (st != TG_OK) return st;
     (void)hipGetLastError();
     grid->sort_valid = false;
+    // a new generation before anything is enqueued: every earlier sort in ws is superseded
+    const uint64_t gen = ws_new_generation(ws);
     const hipError_t e = tg::launch_sort(grid, q, n, static_cast<char*>(ws), L, static_cast<hipStream_t>(stream));
     st = device_status(e, "tg_sort_queries");
     if (st == TG_OK) {
         grid->sort_q = q;
         grid->sort_n = n;
         grid->sort_ws = ws;
+        grid->sort_gen = gen;
         grid->sort_valid = true;
     }
     return st;
+}
+
+tg_status tg_share_sort(tg_grid* grid, const tg_grid* sorted, const float* q, int64_t n, const void* ws,
+                        size_t ws_bytes)
+{
+    if (!grid || !sorted) return fail(TG_ERR_INVALID_ARG, "tg_share_sort: NULL grid");
+    const tg_grid_desc &a = grid->desc, &b = sorted->desc;
+    bool same = a.dim == b.dim;
+    for (int k = 0; same && k < a.dim; ++k)
+        same = a.res[k] == b.res[k] && a.lo[k] == b.lo[k] && a.hi[k] == b.hi[k];
+    if (!same) return fail(TG_ERR_INVALID_ARG, "tg_share_sort: the grids differ in dim, res, lo or hi");
+    tg::WsLayout L;
+    tg_status st = check_queries("tg_share_sort", grid, q, n, ws, ws_bytes, &L);
+    if (st != TG_OK) return st;
+    st = check_sorted("tg_share_sort", sorted, q, n, ws);
+    if (st != TG_OK) return st;
+    grid->sort_q = q;
+    grid->sort_n = n;
+    grid->sort_ws = ws;
+    grid->sort_gen = sorted->sort_gen;
+    grid->sort_valid = true;
+    return ok();
 }
 
 tg_status tg_forward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes, float* f, float* grad_f,
@@ -381,6 +433,7 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(ws);
     grid->sort_valid = false;
+    const uint64_t gen = ws_new_generation(ws);
     auto mark = [&](int k) -> hipError_t {
         return stage_events ? hipEventRecord(static_cast<hipEvent_t>(stage_events[k]), s) : hipSuccess;
     };
@@ -403,6 +456,7 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
         grid->sort_q = q;
         grid->sort_n = n;
         grid->sort_ws = ws;
+        grid->sort_gen = gen;
         grid->sort_valid = true;
     }
     return st;

@@ -15,10 +15,12 @@ struct tg_grid {
     int32_t C;          // coefficients per vertex
     int64_t nvert;      // vertices
     int64_t nbricks;    // vertex bricks (launch size of the forward and backward)
-    // last sort written by tg_sort_queries on this handle
+    // last sort written by tg_sort_queries (or taken over by tg_share_sort) on this handle;
+    // current while sort_gen is the workspace's sort generation
     const float* sort_q;
     int64_t sort_n;
     const void* sort_ws;
+    uint64_t sort_gen;
     bool sort_valid;
 };
 

@@ -22,6 +22,17 @@ def coeffs_per_vertex(dim: int, order: int) -> int:
     return int(c)
 
 
+_sort_generations = iter(range(1, 1 << 62))
+
+
+def _new_sort(q, ws):
+    """Record that ws now holds the sort of q; any earlier sort in ws is superseded (the
+    library checks the same rule by the workspace's address)."""
+    gen = next(_sort_generations)
+    ws._tg_sort_generation = gen
+    return (q, ws, gen)
+
+
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -96,7 +107,7 @@ class TaylorGrid:
         handle = ctypes.c_void_p()
         _lib.call("tg_create", ctypes.byref(desc), ctypes.byref(self._buffers()), ctypes.byref(handle))
         self._h = handle
-        self._sorted = None  # (q tensor, ws tensor) of the last sort
+        self._sorted = None  # (q tensor, ws tensor, sort generation) of the last sort
 
     # ------------------------------------------------------------------ plumbing
     def _buffers(self, grad=None):
@@ -144,10 +155,17 @@ class TaylorGrid:
     def sort(self, q, ws):
         n = self._q(q)
         _lib.call("tg_sort_queries", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _stream(self.device))
-        self._sorted = (q, ws)
+        self._sorted = _new_sort(q, ws)
+
+    def share_sort(self, other, q, ws):
+        """Reuse the sort of q that ``other`` (a grid of the same dim, res, lo and hi) holds in ws."""
+        n = self._q(q)
+        _lib.call("tg_share_sort", self._h, other._h, _ptr(q), n, _ptr(ws), ws.numel())
+        self._sorted = other._sorted
 
     def ensure_sorted(self, q, ws):
-        if self._sorted is None or self._sorted[0] is not q or self._sorted[1] is not ws:
+        s = self._sorted
+        if s is None or s[0] is not q or s[1] is not ws or getattr(ws, "_tg_sort_generation", None) != s[2]:
             self.sort(q, ws)
 
     def forward(self, q, ws, want_grad=True, out=None):
@@ -247,7 +265,7 @@ class TaylorGrid:
             evs = (ctypes.c_void_p * 3)(*[e.cuda_event for e in stage_events])
         _lib.call("tg_train_step", self._h, _ptr(q), _ptr(d), n, float(eik_weight), ctypes.byref(p), _ptr(loss),
                   _ptr(grad_norm_sq), _ptr(ws), ws.numel(), evs, _stream(self.device))
-        self._sorted = (q, ws)
+        self._sorted = _new_sort(q, ws)
         return loss
 
     def adam_step(self, ws, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0, grad_norm_sq=None,

@@ -2,9 +2,10 @@
 field (three K=1 TaylorGrids on the same vertices), rendered along rays by the Max optical
 model (Eq. 10) and fitted to observed ray colours by the photometric loss (Eq. 11).
 
-Argument marshalling only: the bucketing, the grid evaluations, the compositing with its
-adjoint and the fused adjoint + Adam of every grid run in the library (``tg_sort_queries``,
-``tg_forward``, ``tg_composite``, ``tg_backward_adam``).
+Argument marshalling only: the bucketing (once per batch, shared by the four grids), the grid
+evaluations, the compositing with its adjoint and the fused adjoint + Adam of every grid run in
+the library (``tg_sort_queries``, ``tg_share_sort``, ``tg_forward``, ``tg_composite``,
+``tg_backward_adam``).
 """
 from __future__ import annotations
 
@@ -60,18 +61,22 @@ class RadianceField:
     def grids(self):
         return [self.density] + self.colour
 
-    def workspaces(self, n):
-        """One sort workspace per grid (each grid keeps the sort of the samples it was given)."""
-        return [g.workspace(n) for g in self.grids]
+    def workspace(self, n):
+        """One workspace for all four grids: they share one vertex lattice, so the samples are
+        bucketed once (by the density grid, which has the most coefficients per vertex and
+        so needs the largest workspace) and the colour grids reuse that sort."""
+        return self.density.workspace(n)
 
     def evaluate(self, q, ws, f=None, c=None):
-        """Sort the samples for every grid and evaluate it: f [N] density values, c [3, N] colours."""
+        """Sort the samples once and evaluate every grid: f [N] density values, c [3, N] colours."""
         n = q.shape[0]
         f = torch.empty(n, dtype=torch.float32, device=self.device) if f is None else f
         c = torch.empty((3, n), dtype=torch.float32, device=self.device) if c is None else c
-        for k, (g, w) in enumerate(zip(self.grids, ws)):
-            g.sort(q, w)
-            g.forward(q, w, want_grad=False, out=(f if k == 0 else c[k - 1], None))
+        self.density.sort(q, ws)
+        self.density.forward(q, ws, want_grad=False, out=(f, None))
+        for k, g in enumerate(self.colour):
+            g.share_sort(self.density, q, ws)
+            g.forward(q, ws, want_grad=False, out=(c[k], None))
         return f, c
 
     def render(self, q, delta, n_samples, ws):
@@ -91,9 +96,9 @@ class RadianceField:
         _, loss, g_f, g_c = composite(f, c, delta, n_samples, self.reduce_ws, target, rgb, loss, g_f, g_c)
         if stage_events is not None:
             stage_events[1].record()
-        self.density.backward_adam(q, ws[0], g_f, None, lr=lr, step=step)
+        self.density.backward_adam(q, ws, g_f, None, lr=lr, step=step)
         for k in range(3):
-            self.colour[k].backward_adam(q, ws[k + 1], g_c[k], None, lr=lr, step=step)
+            self.colour[k].backward_adam(q, ws, g_c[k], None, lr=lr, step=step)
         if stage_events is not None:
             stage_events[2].record()
         return loss

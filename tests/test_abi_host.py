@@ -118,6 +118,40 @@ def test_workspace_sizes_and_state_errors():
         assert L().tg_destroy(h) == 0
 
 
+def test_share_sort_validation():
+    """Each call departs from a valid set (same lattice, ws large enough for the receiving
+    grid) in one argument; with no sort written anywhere every call is refused."""
+    b = _lib.GridBuffers()
+    b.coeffs = b.master = 0x1000
+    fake = ctypes.c_void_p(0x100000)
+    n = 4096
+    hs = []
+    try:
+        for desc in (_desc(order=2), _desc(order=1), _desc(order=1, hi=(1, 1, 1.5)), _desc(order=1, res=(16, 16, 17))):
+            st, h = _create(desc, b)
+            assert st == 0
+            hs.append(h)
+        dens, col, other_box, other_res = hs
+        ws_d, ws_c = L().tg_workspace_bytes(dens, n), L().tg_workspace_bytes(col, n)
+        # the partial sums of split bricks grow with the coefficient count
+        assert ws_d > ws_c
+        # the sort-independent part of the layout is the same: the K=2 grid's workspace covers K=1
+        assert L().tg_share_sort(col, dens, fake, n, fake, ws_d) == 5       # nothing sorted yet
+        assert L().tg_share_sort(None, dens, fake, n, fake, ws_d) == 1
+        assert L().tg_share_sort(col, None, fake, n, fake, ws_d) == 1
+        assert L().tg_share_sort(other_box, dens, fake, n, fake, ws_d) == 1  # different hi
+        assert L().tg_share_sort(other_res, dens, fake, n, fake, ws_d) == 1  # different res
+        assert L().tg_share_sort(col, dens, fake, n, fake, ws_c - 1) == 4   # short workspace
+        assert L().tg_share_sort(col, dens, fake, n, ctypes.c_void_p(0x100010), ws_d) == 1
+        assert L().tg_share_sort(col, dens, None, n, fake, ws_d) == 1
+        assert L().tg_share_sort(col, dens, fake, -1, fake, ws_d) == 1
+        # a state error leaves the receiver unsorted
+        assert L().tg_forward(col, fake, n, fake, ws_d, fake, None, None) == 5
+    finally:
+        for h in hs:
+            assert L().tg_destroy(h) == 0
+
+
 def test_adam_parameter_validation():
     b = _lib.GridBuffers()
     b.coeffs = b.master = 0x1000

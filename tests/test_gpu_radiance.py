@@ -75,7 +75,7 @@ def test_render_full_size_sampled_rays():
     q64, delta64 = synth.stratified_samples(o, d, 256, seed=1, step=0)
     q = torch.tensor(q64, dtype=torch.float32, device=DEV)
     delta = torch.tensor(delta64, dtype=torch.float32, device=DEV)
-    ws = field.workspaces(q.shape[0])
+    ws = field.workspace(q.shape[0])
     rgb = to_np(field.render(q, delta, 256, ws))
     pick = np.random.default_rng(0).choice(4096, size=64, replace=False)
     qs = q64.reshape(4096, 256, 3)[pick].reshape(-1, 3)
@@ -103,7 +103,7 @@ def test_training_step_matches_oracle():
     q64, delta64 = synth.stratified_samples(o, d, ns, seed=2, step=0)
     target = _f32(rng.uniform(0, 1, size=(n_rays, 3)))
     q = torch.tensor(q64, dtype=torch.float32, device=DEV)
-    ws = field.workspaces(q.shape[0])
+    ws = field.workspace(q.shape[0])
     loss = field.train_step(q, torch.tensor(delta64, dtype=torch.float32, device=DEV), ns,
                             torch.tensor(target, dtype=torch.float32, device=DEV), ws, lr=1e-2, step=10)
     torch.cuda.synchronize()
@@ -123,3 +123,52 @@ def test_training_step_matches_oracle():
         e_m = nerr(to_np(g.adam_m).reshape(-1), mm)
         print(f"order {g.order}: master {e_th:.2e} m {e_m:.2e}", flush=True)
         assert e_th <= TOL_VALUE and e_m <= TOL_GRAD
+
+
+def test_shared_sort():
+    """A K=1 grid reusing a K=2 grid's sort of the same samples (tg_share_sort): forward
+    bitwise equal to its own sort's, adjoint against the oracle with crowded bricks split
+    over several items (their partial sums sit behind the shared sections of the workspace),
+    and a later sort into the workspace supersedes the shared one."""
+    from paper_2402_14415_amd._lib import TaylorGridError
+    from paper_2402_14415_amd.grid import TaylorGrid
+
+    res = (40, 40, 40)
+    rng = np.random.default_rng(7)
+    n = 60000
+    q64 = np.concatenate([rng.uniform(-1, 1, size=(n // 2, 3)),
+                          np.clip(rng.normal(0.3, 0.03, size=(n - n // 2, 3)), -1, 1)])
+    q64 = _f32(q64)
+    cd = _f32(rng.normal(0, 0.05, size=res + (10,)))
+    cc = _f32(rng.normal(0, 0.05, size=res + (4,)))
+    lo, hi = (-1.0,) * 3, (1.0,) * 3
+    dens = TaylorGrid(3, res, 2, lo, hi, coeffs=torch.from_numpy(cd.astype(np.float32)), device=DEV)
+    col = TaylorGrid(3, res, 1, lo, hi, coeffs=torch.from_numpy(cc.astype(np.float32)), device=DEV)
+    q = torch.tensor(q64, dtype=torch.float32, device=DEV)
+    ws = dens.workspace(n)
+    dens.sort(q, ws)
+    col.share_sort(dens, q, ws)
+    f_sh, g_sh = col.forward(q, ws)
+    ws_own = col.workspace(n)
+    col.sort(q, ws_own)
+    f_own, g_own = col.forward(q, ws_own)
+    assert torch.equal(f_sh, f_own) and torch.equal(g_sh, g_own)
+    geom = oracle.Geometry(3, res, 1, lo, hi)
+    f_ref, g_ref = oracle.forward(geom, cc, q64)
+    assert nerr(to_np(f_sh), f_ref) <= TOL_VALUE and nerr(to_np(g_sh), g_ref) <= TOL_GRAD
+
+    gf = _f32(rng.normal(0, 1, size=n))
+    col.share_sort(dens, q, ws)
+    col.backward(q, ws, torch.tensor(gf, dtype=torch.float32, device=DEV))
+    dc_ref = oracle.backward(geom, cc, q64, gf, None)[0]
+    assert nerr(to_np(col.grad).reshape(dc_ref.shape), dc_ref) <= TOL_GRAD
+
+    # the density grid sorts other samples into ws: the colour grid's shared sort is stale
+    q2 = q.flip(0).contiguous()
+    dens.sort(q2, ws)
+    with pytest.raises(TaylorGridError) as err:
+        col.forward(q, ws)
+    assert err.value.status == 5
+    col.ensure_sorted(q, ws)  # the binding sees the same generation rule and sorts again
+    f_again, _ = col.forward(q, ws)
+    assert torch.equal(f_again, f_own)
