@@ -82,6 +82,14 @@ typedef struct {
 
 typedef struct tg_grid tg_grid; /* opaque host-side handle: geometry + buffer pointers */
 
+/* Weights of the SDF objective of Sec. 3.2, Eq. 8 (host struct): L = L_recon (Eq. 6, weighted
+ * by Eq. 7 with k = surface_k; 0 = unweighted) + eik_weight L_eik + tv_weight L_TV. */
+typedef struct {
+    float eik_weight; /* lambda_1 (finite) */
+    float surface_k;  /* k of Eq. 7 (finite, >= 0) */
+    float tv_weight;  /* lambda_2 (finite; 0 = no TV term) */
+} tg_sdf_objective;
+
 /* Adam hyper-parameters (host struct).  step counts from 1. */
 typedef struct {
     float lr, beta1, beta2, eps, weight_decay;
@@ -101,6 +109,8 @@ typedef struct {
 /* Flags. */
 #define TG_BWD_ACCUMULATE 1  /* tg_backward: grad += contribution (default: grad = contribution) */
 #define TG_ADAM_ZERO_GRAD 1  /* tg_adam_step: zero grad after reading it */
+#define TG_BWD_ADD_GRAD 1    /* tg_backward_adam: add bufs.grad (e.g. tg_tv_loss's gradient) to the
+                                adjoint before the update */
 
 /* binom(dim + order, order), or -1 when dim is not 2/3 or order is not 0..2. */
 int32_t tg_coeffs_per_vertex(int32_t dim, int32_t order);
@@ -155,15 +165,44 @@ tg_status tg_share_sort(tg_grid* grid, const tg_grid* sorted, const float* q, in
 tg_status tg_forward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes,
                      float* f, float* grad_f, void* stream);
 
-/* SDF objective (Sec. 3.2, Eq. 6 unweighted, plus the eikonal term of Eq. 8):
- *   L = mean_i |f_i - d_i| + eik_weight * mean_i (|grad_f_i| - 1)^2,
- * written as loss[0] = L, loss[1] = L1 mean, loss[2] = eikonal mean, in FP64 (device).
- * Writes the upstream gradients g_f[i] = dL/df_i and, if grad_f != NULL,
- * g_grad[i][a] = dL/d(grad_f_i)_a.  grad_f == NULL drops the eikonal term (g_grad unused).
- * ws must hold tg_reduce_workspace_bytes(). */
+/* SDF objective (Sec. 3.2, Eq. 6 with the adaptive weight of Eq. 7, plus the eikonal term
+ * of Eq. 8):
+ *   L = mean_i w_i |f_i - d_i| + eik_weight * mean_i (|grad_f_i| - 1)^2,
+ *   w_i = max(w'(f_i), w'(d_i)),  w'(x) = 1 - |2 sigmoid(surface_k x) - 1|,
+ * written as loss[0] = L, loss[1] = weighted L1 mean, loss[2] = eikonal mean, in FP64
+ * (device).  surface_k >= 0 (finite); 0 gives w = 1, the unweighted L1.  The weight is a
+ * per-sample importance: it is held fixed in the gradient.  Writes the upstream gradients
+ * g_f[i] = dL/df_i and, if grad_f != NULL, g_grad[i][a] = dL/d(grad_f_i)_a.  grad_f == NULL
+ * drops the eikonal term (g_grad unused).  ws must hold tg_reduce_workspace_bytes(). */
 tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_f, const float* d,
-                      float eik_weight, float* g_f, float* g_grad, double* loss, void* ws,
-                      size_t ws_bytes, void* stream);
+                      float eik_weight, float surface_k, float* g_f, float* g_grad, double* loss,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Total variation of the coefficient grid (the L_TV term of Sec. 3.2, Eq. 8; the paper
+ * cites the regulariser of Plenoxels and prints no formula).  For every vertex v and stored
+ * coefficient channel c, with Delta_a(v, c) = master(v + e_a, c) - master(v, c) along each
+ * axis a (0 on the grid's last layer along a):
+ *   loss[0] = TV = (1/|V|) sum_v sum_c sqrt(sum_a Delta_a(v, c)^2)   (FP64, device),
+ *   grad (=, or += with TG_BWD_ACCUMULATE) weight * dTV/dC   (0 for terms whose differences
+ *   are all 0).
+ * Reads bufs.master, writes bufs.grad (both required).  One pass: every workgroup stages a
+ * tile of vertices with a one-vertex halo in LDS.  ws must hold tg_reduce_workspace_bytes(). */
+tg_status tg_tv_loss(tg_grid* grid, float weight, double* loss, int32_t flags, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Coarse-to-fine step of the progressive training schedule (Sec. 4.1 trains progressively,
+ * from coarse to fine resolution): the fine grid, over the same box (dim, lo and hi compared
+ * exactly), takes the field the coarse grid represents.  Every fine vertex v stores the
+ * coarse field's value, gradient and Hessian at v (Eq. 2-4 and their exact derivatives) in
+ * the stored order (value; gradient; Hessian xx, xy, xz, yy, yz, zz / xx, xy, yy), truncated
+ * to the fine order: fine master (FP32) and, for 16-bit storage, its round-to-nearest-even
+ * copy in coeffs.  Fine adam_m and adam_v, when present, are zeroed (a new optimisation
+ * stage; the Adam step count is the caller's).  A fine vertex i on axis a lies at
+ * i (res_c - 1) / (res_f - 1) in coarse cell units, located in exact integer arithmetic; on
+ * a coarse face it takes the cell above (the top face: the last cell), where the gradient
+ * and Hessian are that cell's one-sided values.  Reads the coarse master; the fine buffers
+ * must not overlap it.  Any orders and resolutions (finer or not). */
+tg_status tg_upsample(const tg_grid* coarse, tg_grid* fine, void* stream);
 
 /* Radiance-field compositing (Sec. 3.3): the Max optical model of Eq. 10 along n_rays rays
  * of n_samples samples each, with a ReLU density, and the photometric loss of Eq. 11 with
@@ -199,16 +238,16 @@ tg_status tg_backward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t
                       const float* g_f, const float* g_grad, float* dq, int32_t flags,
                       void* stream);
 
-/* tg_forward and tg_sdf_loss in one pass, for training: the loss of Sec. 3.2 (Eq. 6
- * unweighted plus the eikonal term of Eq. 8) is evaluated where f and grad f are computed,
+/* tg_forward and tg_sdf_loss in one pass, for training: the loss of Sec. 3.2 (Eq. 6 with
+ * Eq. 7's weight, plus the eikonal term of Eq. 8) is evaluated where f and grad f are computed,
  * so they need not make a round trip through memory.  Writes g_f [n] and, when g_grad !=
  * NULL, g_grad [n][dim] exactly as tg_sdf_loss would from tg_forward's outputs, and loss[3]
  * (device FP64, as tg_sdf_loss; the sums are added in another order).  g_grad == NULL drops
  * the eikonal term.  f and grad_f (either may be NULL) receive tg_forward's outputs.
  * d [n] is the target SDF in query order.  Requires the sort of (q, n) in ws. */
 tg_status tg_forward_sdf_loss(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes,
-                              const float* d, float eik_weight, float* g_f, float* g_grad, double* loss,
-                              float* f, float* grad_f, void* stream);
+                              const float* d, float eik_weight, float surface_k, float* g_f,
+                              float* g_grad, double* loss, float* f, float* grad_f, void* stream);
 
 /* tg_backward followed by tg_adam_step in one pass, for training: every vertex brick's
  * coefficient adjoint (overwrite semantics) is handed straight to the Adam update of that
@@ -219,21 +258,33 @@ tg_status tg_forward_sdf_loss(tg_grid* grid, const float* q, int64_t n, void* ws
  * Must not overlap any other call that touches the same grid's buffers. */
 tg_status tg_backward_adam(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes,
                            const float* g_f, const float* g_grad, const tg_adam_params* params,
-                           double* grad_norm_sq, void* stream);
+                           double* grad_norm_sq, int32_t flags, void* stream);
+/* flags: 0, or TG_BWD_ADD_GRAD, which adds bufs.grad (required then; read, not written) to
+ * every coefficient's adjoint before its update, and counts it in grad_norm_sq: a gradient
+ * computed beforehand, such as the TV term's from tg_tv_loss. */
 
-/* One SDF-fitting step (Sec. 3.2: the grid is optimised directly against the L1 + eikonal
- * objective) in one call: tg_sort_queries, then tg_forward_sdf_loss, then
+/* One SDF-fitting step (Sec. 3.2: the grid is optimised directly against the objective of
+ * Eq. 8) in one call: tg_sort_queries, then tg_forward_sdf_loss, then
  * tg_backward_adam, except that the upstream gradients are kept in the workspace in bucket
- * order, so they never make a round trip through memory in query order.  q [n][dim] and d [n] as in those calls; loss[3]
- * (device FP64) as tg_sdf_loss; grad_norm_sq (device double, may be NULL) receives
+ * order, so they never make a round trip through memory in query order.  q [n][dim] and d [n]
+ * as in those calls; loss (device FP64) as tg_sdf_loss, with the TV value added as below;
+ * grad_norm_sq (device double, may be NULL) receives
  * sum(dC^2).  Afterwards ws holds the sort of (q, n), so tg_forward / tg_backward may reuse
  * it.  The same buffer requirements as tg_backward_adam; must not overlap any other call on
  * the same grid.  ws must hold tg_workspace_bytes(grid, n). */
-tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n, float eik_weight,
-                        const tg_adam_params* params, double* loss, double* grad_norm_sq, void* ws,
-                        size_t ws_bytes, void* const* stage_events, void* stream);
+tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n,
+                        const tg_sdf_objective* obj, const tg_adam_params* params, double* loss,
+                        double* grad_norm_sq, void* ws, size_t ws_bytes, void* const* stage_events,
+                        void* stream);
+/* obj: the objective's weights (host struct, required).  With obj->tv_weight != 0 the step
+ * first runs tg_tv_loss on the current coefficients into bufs.grad (required then; its
+ * contents are overwritten) and value loss[3], and the adjoint adds it before the update
+ * (TG_BWD_ADD_GRAD); loss then holds 4 doubles and
+ *   loss[0] = loss[1] + eik_weight loss[2] + tv_weight loss[3].
+ * With tv_weight == 0, loss holds 3 doubles and bufs.grad is not touched. */
 /* stage_events: NULL, or a host array of 3 hipEvent_t that are recorded on the stream after
- * the sort, after the forward with the loss terms and after the adjoint with Adam and the
+ * the sort, after the forward with the loss terms (and the TV term) and after the adjoint
+ * with Adam and the
  * final FP64 reductions of the loss and the gradient norm (for timing). */
 
 /* One Adam step over every coefficient (the paper trains the grid with a fixed learning

@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "TG_OK", 1: "TG_ERR_INVALID_ARG", 2: "TG_ERR_UNSUPPORTED", 3:
 TG_F32, TG_BF16, TG_F16 = 0, 1, 2
 TG_BWD_ACCUMULATE = 1
 TG_ADAM_ZERO_GRAD = 1
+TG_BWD_ADD_GRAD = 1
 TG_QUERY_MAX_REQS = 32
 TG_QUERY_MAX_GRIDS = 16
 
@@ -31,6 +32,10 @@ class GridDesc(ctypes.Structure):
 class GridBuffers(ctypes.Structure):
     _fields_ = [("coeffs", ctypes.c_void_p), ("master", ctypes.c_void_p), ("grad", ctypes.c_void_p),
                 ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p)]
+
+
+class SdfObjective(ctypes.Structure):
+    _fields_ = [("eik_weight", ctypes.c_float), ("surface_k", ctypes.c_float), ("tv_weight", ctypes.c_float)]
 
 
 class AdamParams(ctypes.Structure):
@@ -63,15 +68,17 @@ _SIGS = {
     "tg_sort_queries": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "tg_share_sort": ([_P, _P, _P, ctypes.c_int64, _P, ctypes.c_size_t], ctypes.c_int),
     "tg_forward": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
-    "tg_sdf_loss": ([ctypes.c_int32, ctypes.c_int64, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P, ctypes.c_size_t, _P],
-                    ctypes.c_int),
+    "tg_sdf_loss": ([ctypes.c_int32, ctypes.c_int64, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P,
+                     ctypes.c_size_t, _P], ctypes.c_int),
+    "tg_tv_loss": ([_P, ctypes.c_float, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "tg_upsample": ([_P, _P, _P], ctypes.c_int),
     "tg_backward": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
-    "tg_forward_sdf_loss": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P, ctypes.c_float, _P, _P, _P, _P, _P, _P],
-                            ctypes.c_int),
-    "tg_backward_adam": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P, _P, ctypes.POINTER(AdamParams), _P, _P],
-                         ctypes.c_int),
-    "tg_train_step": ([_P, _P, _P, ctypes.c_int64, ctypes.c_float, ctypes.POINTER(AdamParams), _P, _P, _P,
-                       ctypes.c_size_t, ctypes.POINTER(_P), _P], ctypes.c_int),
+    "tg_forward_sdf_loss": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P, ctypes.c_float, ctypes.c_float, _P, _P,
+                             _P, _P, _P, _P], ctypes.c_int),
+    "tg_backward_adam": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P, _P, ctypes.POINTER(AdamParams), _P,
+                          ctypes.c_int32, _P], ctypes.c_int),
+    "tg_train_step": ([_P, _P, _P, ctypes.c_int64, ctypes.POINTER(SdfObjective), ctypes.POINTER(AdamParams), _P, _P,
+                       _P, ctypes.c_size_t, ctypes.POINTER(_P), _P], ctypes.c_int),
     "tg_composite": ([ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
                      ctypes.c_int),
     "tg_adam_step": ([_P, ctypes.POINTER(AdamParams), _P, _P, ctypes.c_size_t, ctypes.c_int32, _P], ctypes.c_int),

@@ -366,9 +366,16 @@ tg_status tg_backward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t
     return device_status(e, "tg_backward");
 }
 
+static tg_status check_surface_k(const char* fn, float surface_k)
+{
+    if (!std::isfinite(surface_k) || surface_k < 0.0f)
+        return fail(TG_ERR_INVALID_ARG, "%s: surface_k must be finite and >= 0", fn);
+    return ok();
+}
+
 tg_status tg_forward_sdf_loss(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes, const float* d,
-                              float eik_weight, float* g_f, float* g_grad, double* loss, float* f, float* grad_f,
-                              void* stream)
+                              float eik_weight, float surface_k, float* g_f, float* g_grad, double* loss, float* f,
+                              float* grad_f, void* stream)
 {
     tg::WsLayout L;
     tg_status st = check_queries("tg_forward_sdf_loss", grid, q, n, ws, ws_bytes, &L);
@@ -376,12 +383,14 @@ tg_status tg_forward_sdf_loss(tg_grid* grid, const float* q, int64_t n, void* ws
     if (n > 0 && (!d || !g_f)) return fail(TG_ERR_INVALID_ARG, "tg_forward_sdf_loss: d and g_f must not be NULL");
     if (!loss) return fail(TG_ERR_INVALID_ARG, "tg_forward_sdf_loss: loss is NULL");
     if (!std::isfinite(eik_weight)) return fail(TG_ERR_INVALID_ARG, "tg_forward_sdf_loss: eik_weight is not finite");
+    st = check_surface_k("tg_forward_sdf_loss", surface_k);
+    if (st != TG_OK) return st;
     if (!grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_forward_sdf_loss: grid has no coeffs buffer");
     st = check_sorted("tg_forward_sdf_loss", grid, q, n, ws);
     if (st != TG_OK) return st;
     (void)hipGetLastError();
-    return device_status(tg::launch_forward_loss(grid, n, static_cast<const char*>(ws), L, d, eik_weight, g_f, g_grad,
-                                                 loss, f, grad_f, static_cast<hipStream_t>(stream)),
+    return device_status(tg::launch_forward_loss(grid, n, static_cast<const char*>(ws), L, d, eik_weight, surface_k,
+                                                 g_f, g_grad, loss, f, grad_f, static_cast<hipStream_t>(stream)),
                          "tg_forward_sdf_loss");
 }
 
@@ -401,22 +410,27 @@ static tg_status check_adam(const char* fn, const tg_grid* grid, const tg_adam_p
 }
 
 tg_status tg_backward_adam(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes, const float* g_f,
-                           const float* g_grad, const tg_adam_params* params, double* grad_norm_sq, void* stream)
+                           const float* g_grad, const tg_adam_params* params, double* grad_norm_sq, int32_t flags,
+                           void* stream)
 {
     tg::WsLayout L;
     tg_status st = check_queries("tg_backward_adam", grid, q, n, ws, ws_bytes, &L);
     if (st != TG_OK) return st;
     st = check_adam("tg_backward_adam", grid, params);
     if (st != TG_OK) return st;
+    if (flags & ~TG_BWD_ADD_GRAD) return fail(TG_ERR_INVALID_ARG, "tg_backward_adam: unknown flags 0x%x", flags);
+    const bool add = (flags & TG_BWD_ADD_GRAD) != 0;
+    if (add && !grid->bufs.grad) return fail(TG_ERR_INVALID_ARG, "tg_backward_adam: TG_BWD_ADD_GRAD needs bufs.grad");
     st = check_sorted("tg_backward_adam", grid, q, n, ws);
     if (st != TG_OK) return st;
     (void)hipGetLastError();
     return device_status(tg::launch_backward_adam(grid, n, static_cast<const char*>(ws), L, g_f, g_grad, *params,
-                                                  grad_norm_sq, static_cast<hipStream_t>(stream)),
+                                                  grad_norm_sq, static_cast<hipStream_t>(stream), false,
+                                                  add ? grid->bufs.grad : nullptr),
                          "tg_backward_adam");
 }
 
-tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n, float eik_weight,
+tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n, const tg_sdf_objective* obj,
                         const tg_adam_params* params, double* loss, double* grad_norm_sq, void* ws, size_t ws_bytes,
                         void* const* stage_events, void* stream)
 {
@@ -425,7 +439,15 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
     if (st != TG_OK) return st;
     if (n > 0 && !d) return fail(TG_ERR_INVALID_ARG, "tg_train_step: d is NULL");
     if (!loss) return fail(TG_ERR_INVALID_ARG, "tg_train_step: loss is NULL");
+    if (!obj) return fail(TG_ERR_INVALID_ARG, "tg_train_step: objective is NULL");
+    const float eik_weight = obj->eik_weight, surface_k = obj->surface_k, tv_weight = obj->tv_weight;
     if (!std::isfinite(eik_weight)) return fail(TG_ERR_INVALID_ARG, "tg_train_step: eik_weight is not finite");
+    st = check_surface_k("tg_train_step", surface_k);
+    if (st != TG_OK) return st;
+    if (!std::isfinite(tv_weight)) return fail(TG_ERR_INVALID_ARG, "tg_train_step: tv_weight is not finite");
+    const bool tv = tv_weight != 0.0f;
+    if (tv && !grid->bufs.grad)
+        return fail(TG_ERR_INVALID_ARG, "tg_train_step: the TV term needs bufs.grad (it holds the TV gradient)");
     if (!grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_train_step: grid has no coeffs buffer");
     st = check_adam("tg_train_step", grid, params);
     if (st != TG_OK) return st;
@@ -439,17 +461,24 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
     };
     hipError_t e = tg::launch_sort(grid, q, n, w, L, s);
     if (e == hipSuccess) e = mark(0);
+    // the TV term reads the coefficients before the update: its gradient goes to bufs.grad,
+    // its value to loss[3]
+    if (e == hipSuccess && tv)
+        e = tg::launch_tv(grid, tv_weight, loss + 3, grid->bufs.grad, false,
+                          reinterpret_cast<double*>(w + L.reduce_off), s);
     if (e == hipSuccess)
-        e = tg::launch_forward_loss(grid, n, w, L, d, eik_weight, nullptr, nullptr, loss, nullptr, nullptr, s,
-                                    true, false);
+        e = tg::launch_forward_loss(grid, n, w, L, d, eik_weight, surface_k, nullptr, nullptr, loss, nullptr, nullptr,
+                                    s, true, false);
     if (e == hipSuccess) e = mark(1);
-    if (e == hipSuccess) e = tg::launch_backward_adam(grid, n, w, L, nullptr, nullptr, *params, nullptr, s, true);
+    if (e == hipSuccess)
+        e = tg::launch_backward_adam(grid, n, w, L, nullptr, nullptr, *params, nullptr, s, true,
+                                     tv ? grid->bufs.grad : nullptr);
     // both FP64 reductions (the loss and sum(dC^2)) in one launch
     if (e == hipSuccess)
         e = tg::launch_loss_finish(reinterpret_cast<const double*>(w + L.fpart_off), n > 0 ? L.fwd_blocks : 0, n,
                                    eik_weight, loss, s,
                                    grad_norm_sq ? reinterpret_cast<const double*>(w + L.bpart_off) : nullptr,
-                                   L.max_bitems + L.merge_blocks, grad_norm_sq);
+                                   L.max_bitems + L.merge_blocks, grad_norm_sq, tv_weight, tv ? loss + 3 : nullptr);
     if (e == hipSuccess) e = mark(2);
     st = device_status(e, "tg_train_step");
     if (st == TG_OK) {  // the workspace holds this sort: tg_forward / tg_backward may reuse it
@@ -463,7 +492,7 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
 }
 
 tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_f, const float* d, float eik_weight,
-                      float* g_f, float* g_grad, double* loss, void* ws, size_t ws_bytes, void* stream)
+                      float surface_k, float* g_f, float* g_grad, double* loss, void* ws, size_t ws_bytes, void* stream)
 {
     if (dim != 2 && dim != 3) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: dim must be 2 or 3");
     if (n < 0) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: n is negative");
@@ -471,12 +500,59 @@ tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_
     if (n > 0 && grad_f && !g_grad) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: g_grad is NULL but grad_f is given");
     if (!loss) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: loss is NULL");
     if (!std::isfinite(eik_weight)) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: eik_weight is not finite");
+    if (check_surface_k("tg_sdf_loss", surface_k) != TG_OK) return TG_ERR_INVALID_ARG;
     if (!ws || !aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss: workspace NULL or not 256-byte aligned");
     if (ws_bytes < tg::kReduceBytes) return fail(TG_ERR_CAPACITY, "tg_sdf_loss: workspace smaller than %zu bytes", tg::kReduceBytes);
     (void)hipGetLastError();
-    return device_status(tg::launch_sdf_loss(dim, n, f, grad_f, d, eik_weight, g_f, g_grad, loss,
+    return device_status(tg::launch_sdf_loss(dim, n, f, grad_f, d, eik_weight, surface_k, g_f, g_grad, loss,
                                              static_cast<double*>(ws), static_cast<hipStream_t>(stream)),
                          "tg_sdf_loss");
+}
+
+tg_status tg_tv_loss(tg_grid* grid, float weight, double* loss, int32_t flags, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!grid) return fail(TG_ERR_INVALID_ARG, "tg_tv_loss: grid is NULL");
+    if (!loss) return fail(TG_ERR_INVALID_ARG, "tg_tv_loss: loss is NULL");
+    if (!std::isfinite(weight)) return fail(TG_ERR_INVALID_ARG, "tg_tv_loss: weight is not finite");
+    if (flags & ~TG_BWD_ACCUMULATE) return fail(TG_ERR_INVALID_ARG, "tg_tv_loss: unknown flags 0x%x", flags);
+    if (!grid->bufs.master || !grid->bufs.grad)
+        return fail(TG_ERR_INVALID_ARG, "tg_tv_loss: master and grad are required");
+    if (!ws || !aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "tg_tv_loss: workspace NULL or not 256-byte aligned");
+    if (ws_bytes < tg::kReduceBytes)
+        return fail(TG_ERR_CAPACITY, "tg_tv_loss: workspace smaller than %zu bytes", tg::kReduceBytes);
+    (void)hipGetLastError();
+    return device_status(tg::launch_tv(grid, weight, loss, grid->bufs.grad, (flags & TG_BWD_ACCUMULATE) != 0,
+                                       static_cast<double*>(ws), static_cast<hipStream_t>(stream)),
+                         "tg_tv_loss");
+}
+
+tg_status tg_upsample(const tg_grid* coarse, tg_grid* fine, void* stream)
+{
+    if (!coarse || !fine) return fail(TG_ERR_INVALID_ARG, "tg_upsample: NULL grid");
+    if (coarse == fine) return fail(TG_ERR_INVALID_ARG, "tg_upsample: coarse and fine are the same handle");
+    const tg_grid_desc &c = coarse->desc, &f = fine->desc;
+    bool same = c.dim == f.dim;
+    for (int k = 0; same && k < c.dim; ++k) same = c.lo[k] == f.lo[k] && c.hi[k] == f.hi[k];
+    if (!same) return fail(TG_ERR_INVALID_ARG, "tg_upsample: the grids differ in dim, lo or hi");
+    if (!coarse->bufs.master) return fail(TG_ERR_INVALID_ARG, "tg_upsample: the coarse grid has no master buffer");
+    if (!fine->bufs.master) return fail(TG_ERR_INVALID_ARG, "tg_upsample: the fine grid has no master buffer");
+    if (f.storage != TG_F32 && !fine->bufs.coeffs)
+        return fail(TG_ERR_INVALID_ARG, "tg_upsample: 16-bit storage of the fine grid needs its coeffs buffer");
+    // the outputs must not overlap the coarse coefficients being read
+    const char* c0 = reinterpret_cast<const char*>(coarse->bufs.master);
+    const char* c1 = c0 + coarse->nvert * coarse->C * sizeof(float);
+    const void* outs[4] = {fine->bufs.master, f.storage != TG_F32 ? fine->bufs.coeffs : nullptr, fine->bufs.adam_m,
+                           fine->bufs.adam_v};
+    const size_t out_bytes[4] = {fine->nvert * fine->C * sizeof(float),
+                                 fine->nvert * fine->C * (f.storage != TG_F32 ? sizeof(uint16_t) : 0),
+                                 fine->nvert * fine->C * sizeof(float), fine->nvert * fine->C * sizeof(float)};
+    for (int k = 0; k < 4; ++k) {
+        const char* o0 = static_cast<const char*>(outs[k]);
+        if (o0 && o0 < c1 && c0 < o0 + out_bytes[k])
+            return fail(TG_ERR_INVALID_ARG, "tg_upsample: a fine buffer overlaps the coarse master");
+    }
+    (void)hipGetLastError();
+    return device_status(tg::launch_upsample(coarse, fine, static_cast<hipStream_t>(stream)), "tg_upsample");
 }
 
 tg_status tg_composite(int64_t n_rays, int32_t n_samples, const float* f, const float* c, const float* delta,

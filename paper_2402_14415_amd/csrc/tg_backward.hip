@@ -90,6 +90,7 @@ struct AdamBuf {
     float* v;
     void* coeffs;
     double* partials;
+    const float* extra;  // gradient added to the adjoint before the update (NULL: none)
 };
 
 // Element of the brick's [vertex][C] block list that register k of this thread holds in the
@@ -134,9 +135,15 @@ __device__ __forceinline__ double brick_epilogue(const Geom& g, const int32_t* b
                 float2 th = *reinterpret_cast<const float2*>(AB.master + gi);
                 float2 m = *reinterpret_cast<const float2*>(AB.m + gi);
                 float2 v = *reinterpret_cast<const float2*>(AB.v + gi);
-                ss += (double)vk[k] * (double)vk[k] + (double)vk[k + 1] * (double)vk[k + 1];
-                adam_elem(AB.A, vk[k], th.x, m.x, v.x);
-                adam_elem(AB.A, vk[k + 1], th.y, m.y, v.y);
+                float2 gk = make_float2(vk[k], vk[k + 1]);
+                if (AB.extra) {
+                    const float2 x = *reinterpret_cast<const float2*>(AB.extra + gi);
+                    gk.x += x.x;
+                    gk.y += x.y;
+                }
+                ss += (double)gk.x * (double)gk.x + (double)gk.y * (double)gk.y;
+                adam_elem(AB.A, gk.x, th.x, m.x, v.x);
+                adam_elem(AB.A, gk.y, th.y, m.y, v.y);
                 *reinterpret_cast<float2*>(AB.master + gi) = th;
                 *reinterpret_cast<float2*>(AB.m + gi) = m;
                 *reinterpret_cast<float2*>(AB.v + gi) = v;
@@ -156,8 +163,9 @@ __device__ __forceinline__ double brick_epilogue(const Geom& g, const int32_t* b
                 *reinterpret_cast<float2*>(grad + gi) = o;
             }
         } else {
-            const float val = vk[k];
+            float val = vk[k];
             if constexpr (AD >= 0) {
+                if (AB.extra) val += AB.extra[gi];
                 float th = AB.master[gi], m = AB.m[gi], v = AB.v[gi];
                 ss += (double)val * (double)val;
                 adam_elem(AB.A, val, th, m, v);
@@ -550,7 +558,7 @@ hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const Ws
 
 hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
                                 const float* g_grad, const tg_adam_params& p, double* grad_norm_sq, hipStream_t s,
-                                bool record_order)
+                                bool record_order, const float* extra_grad)
 {
     const float4* urec = record_order ? reinterpret_cast<const float4*>(ws + L.urec_off) : nullptr;
     (void)n;
@@ -561,6 +569,7 @@ hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, con
     AB.v = g->bufs.adam_v;
     AB.coeffs = g->bufs.coeffs;
     AB.partials = reinterpret_cast<double*>(const_cast<char*>(ws) + L.bpart_off);
+    AB.extra = extra_grad;
     hipError_t e;
     switch (g->desc.storage) {
     case ST_F32: e = launch_backward_impl<ST_F32>(g, ws, L, g_f, g_grad, urec, false, AB, s); break;

@@ -286,6 +286,19 @@ struct AdamArgs {
     float beta1, beta2, one_minus_beta1, one_minus_beta2, eps, wd;
 };
 
+// Eq. 7's surface weight of one distance, 1 - |2 sigmoid(k x) - 1|, evaluated as the equal
+// 2 / (1 + exp(|k x|)) (2 sigmoid(z) - 1 = tanh(z / 2)): 1 on the surface, 0 once exp overflows.
+__device__ __forceinline__ float surface_weight1(float k, float x)
+{
+    return 2.0f / (1.0f + expf(fabsf(k * x)));
+}
+
+// Eq. 7: the larger of the predicted and the true distance's weights; k = 0 weights all by 1.
+__device__ __forceinline__ float surface_weight(float k, float f, float d)
+{
+    return k > 0.0f ? fmaxf(surface_weight1(k, f), surface_weight1(k, d)) : 1.0f;
+}
+
 __device__ __forceinline__ float adam_elem(const AdamArgs& A, float g, float& th, float& m, float& v)
 {
     const float gp = fmaf(A.wd, th, g);

@@ -26,6 +26,7 @@ struct LossArgs {
     float4* urec;       // (g_f, g_grad) in record order
     double* partials;   // [2 x gridDim.x]
     float w_eik;
+    float surf_k;       // Eq. 7's k (0: every sample weighted 1)
     float inv_n;
     int eik;            // eikonal term on (record mode; query mode tests gg)
 };
@@ -242,9 +243,12 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
         }
         if constexpr (MODE == MODE_LOSS) {
             const bool rec_mode = LA.urec != nullptr;
-            const float res = f - LA.d[idx];
-            sum_r += (double)fabsf(res);
-            const float sgf = res > 0.0f ? LA.inv_n : (res < 0.0f ? -LA.inv_n : 0.0f);
+            const float dt = LA.d[idx];
+            const float res = f - dt;
+            const float w = surface_weight(LA.surf_k, f, dt);  // held fixed in the gradient
+            sum_r += (double)w * (double)fabsf(res);
+            const float wn = w * LA.inv_n;
+            const float sgf = res > 0.0f ? wn : (res < 0.0f ? -wn : 0.0f);
             float sgg[3] = {0.0f, 0.0f, 0.0f};
             if (rec_mode ? LA.eik != 0 : LA.gg != nullptr) {
                 float n2 = 0.0f;
@@ -322,8 +326,8 @@ hipError_t launch_forward(const tg_grid* g, int64_t n, const char* ws, const WsL
 }
 
 hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* d,
-                               float eik_weight, float* g_f, float* g_grad, double* loss, float* f, float* grad_f,
-                               hipStream_t s, bool record_order, bool finish)
+                               float eik_weight, float surf_k, float* g_f, float* g_grad, double* loss, float* f,
+                               float* grad_f, hipStream_t s, bool record_order, bool finish)
 {
     LossArgs LA;
     LA.d = d;
@@ -333,6 +337,7 @@ hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, cons
     LA.eik = eik_weight != 0.0f ? 1 : 0;
     LA.partials = reinterpret_cast<double*>(const_cast<char*>(ws) + L.fpart_off);
     LA.w_eik = eik_weight;
+    LA.surf_k = surf_k;
     LA.inv_n = n > 0 ? (float)(1.0 / (double)n) : 0.0f;
     if (n > 0) {
         const hipError_t e = dispatch<MODE_LOSS>(g, ws, L, f, grad_f, nullptr, nullptr, nullptr, s, LA);

@@ -92,22 +92,34 @@ hipError_t launch_dq(const tg_grid* g, int64_t n, const char* ws, const WsLayout
 hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L,
                            const float* g_f, const float* g_grad, bool accumulate, hipStream_t s);
 hipError_t launch_sdf_loss(int dim, int64_t n, const float* f, const float* grad_f, const float* d,
-                           float eik_weight, float* g_f, float* g_grad, double* loss, double* partials,
-                           hipStream_t s);
+                           float eik_weight, float surf_k, float* g_f, float* g_grad, double* loss,
+                           double* partials, hipStream_t s);
 hipError_t launch_adam(const tg_grid* g, const tg_adam_params& p, double* grad_norm_sq, double* partials,
                        bool zero_grad, hipStream_t s);
 // With finish = false the loss partials stay in the workspace (fpart_off, fwd_blocks pairs)
 // for a later launch_loss_finish.
 hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* d,
-                               float eik_weight, float* g_f, float* g_grad, double* loss, float* f, float* grad_f,
-                               hipStream_t s, bool record_order = false, bool finish = true);
+                               float eik_weight, float surf_k, float* g_f, float* g_grad, double* loss, float* f,
+                               float* grad_f, hipStream_t s, bool record_order = false, bool finish = true);
+// extra_grad (may be NULL): a stored gradient added to every coefficient's adjoint before
+// the update (the TV term's, written beforehand).
 hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
                                 const float* g_grad, const tg_adam_params& p, double* grad_norm_sq, hipStream_t s,
-                                bool record_order = false);
-// Also sums ng sum(dC^2) partials into *gnorm when gpart is given.
+                                bool record_order = false, const float* extra_grad = nullptr);
+// Also sums ng sum(dC^2) partials into *gnorm when gpart is given, and adds tv_weight * *tv
+// to the total when tv is given.
 hipError_t launch_loss_finish(const double* partials, int64_t nblocks, int64_t n, float eik_weight, double* loss,
-                              hipStream_t s, const double* gpart = nullptr, int64_t ng = 0, double* gnorm = nullptr);
+                              hipStream_t s, const double* gpart = nullptr, int64_t ng = 0, double* gnorm = nullptr,
+                              float tv_weight = 0.0f, const double* tv = nullptr);
+// TV of the master coefficients: *tv_out = TV (FP64), grad (=, or += when accumulating)
+// weight * dTV/dC.  partials: kMaxReduceBlocks doubles.
+hipError_t launch_tv(const tg_grid* g, float weight, double* tv_out, float* grad, bool accumulate,
+                     double* partials, hipStream_t s);
+// The fine grid's master (and storage copy) from the coarse field's value, gradient and
+// Hessian at the fine vertices; the fine moments (when present) are zeroed.
+hipError_t launch_upsample(const tg_grid* coarse, tg_grid* fine, hipStream_t s);
 hipError_t launch_sum_finish(const double* partials, int64_t nblocks, double* out, hipStream_t s);
+hipError_t launch_sum_finish_scaled(const double* partials, int64_t nblocks, double scale, double* out, hipStream_t s);
 hipError_t launch_composite(int64_t n_rays, int32_t ns, const float* f, const float* col, const float* delta,
                             const float* target, float* rgb, double* loss, float* g_f, float* g_c, double* partials,
                             hipStream_t s);

@@ -24,14 +24,17 @@ static inline unsigned reduce_blocks(int64_t n, int per_thread)
 template <int DIM, bool EIK>
 __global__ __launch_bounds__(kThreads) void k_sdf_loss(int64_t n, const float* __restrict__ f,
                                                       const float* __restrict__ grad, const float* __restrict__ d,
-                                                      float w_eik, float inv_n, float* __restrict__ gf,
+                                                      float w_eik, float surf_k, float inv_n, float* __restrict__ gf,
                                                       float* __restrict__ gg, double* __restrict__ partials)
 {
     double acc_r = 0.0, acc_e = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        const float r = f[i] - d[i];
-        acc_r += (double)fabsf(r);
-        gf[i] = r > 0.0f ? inv_n : (r < 0.0f ? -inv_n : 0.0f);
+        const float fi = f[i], di = d[i];
+        const float r = fi - di;
+        const float w = surface_weight(surf_k, fi, di);  // Eq. 7, held fixed in the gradient
+        acc_r += (double)w * (double)fabsf(r);
+        const float wn = w * inv_n;
+        gf[i] = r > 0.0f ? wn : (r < 0.0f ? -wn : 0.0f);
         if constexpr (EIK) {
             float g[DIM];
             float n2 = 0.0f;
@@ -79,13 +82,15 @@ __device__ __forceinline__ void thread_partial_sums(const double* __restrict__ p
     }
 }
 
-// loss[1] = mean |r|, loss[2] = mean (|grad f| - 1)^2, loss[0] = loss[1] + w_eik loss[2] from
-// the (sum |r|, sum (|grad f| - 1)^2) pairs of nl blocks; with gpart, also *gnorm = the sum of
+// loss[1] = mean w |r|, loss[2] = mean (|grad f| - 1)^2, loss[0] = loss[1] + w_eik loss[2]
+// (+ w_tv *tv when tv is given: a TV value finished earlier on the stream) from the
+// (sum w |r|, sum (|grad f| - 1)^2) pairs of nl blocks; with gpart, also *gnorm = the sum of
 // ng sum(dC^2) partials (the training step finishes both reductions in one launch).
 __global__ __launch_bounds__(kFinishReduceThreads) void k_loss_finish(const double* __restrict__ partials, int nblocks,
                                                                       double inv_n, double w_eik, double* __restrict__ loss,
                                                                       const double* __restrict__ gpart, int ng,
-                                                                      double* __restrict__ gnorm)
+                                                                      double* __restrict__ gnorm, double w_tv,
+                                                                      const double* __restrict__ tv)
 {
     // both sets of partials are loaded in the same rounds (thread_partial_sums' order per set)
     double acc[2] = {0.0, 0.0}, sg = 0.0;
@@ -111,7 +116,7 @@ __global__ __launch_bounds__(kFinishReduceThreads) void k_loss_finish(const doub
     if (threadIdx.x == 0) {
         loss[1] = sr * inv_n;
         loss[2] = se * inv_n;
-        loss[0] = loss[1] + w_eik * loss[2];
+        loss[0] = loss[1] + w_eik * loss[2] + (tv ? w_tv * *tv : 0.0);
     }
     if (gpart) {
         sg = block_sum_f64<kFinishReduceThreads>(sg);
@@ -120,22 +125,22 @@ __global__ __launch_bounds__(kFinishReduceThreads) void k_loss_finish(const doub
 }
 
 hipError_t launch_sdf_loss(int dim, int64_t n, const float* f, const float* grad_f, const float* d, float eik_weight,
-                           float* g_f, float* g_grad, double* loss, double* partials, hipStream_t s)
+                           float surf_k, float* g_f, float* g_grad, double* loss, double* partials, hipStream_t s)
 {
     const unsigned nb = reduce_blocks(n, 4);
     const float inv_n = n > 0 ? (float)(1.0 / (double)n) : 0.0f;
     const dim3 grid(nb), block(kThreads);
     if (grad_f) {
         if (dim == 3)
-            hipLaunchKernelGGL((k_sdf_loss<3, true>), grid, block, 0, s, n, f, grad_f, d, eik_weight, inv_n, g_f, g_grad, partials);
+            hipLaunchKernelGGL((k_sdf_loss<3, true>), grid, block, 0, s, n, f, grad_f, d, eik_weight, surf_k, inv_n, g_f, g_grad, partials);
         else
-            hipLaunchKernelGGL((k_sdf_loss<2, true>), grid, block, 0, s, n, f, grad_f, d, eik_weight, inv_n, g_f, g_grad, partials);
+            hipLaunchKernelGGL((k_sdf_loss<2, true>), grid, block, 0, s, n, f, grad_f, d, eik_weight, surf_k, inv_n, g_f, g_grad, partials);
     } else {
-        hipLaunchKernelGGL((k_sdf_loss<3, false>), grid, block, 0, s, n, f, grad_f, d, eik_weight, inv_n, g_f, g_grad, partials);
+        hipLaunchKernelGGL((k_sdf_loss<3, false>), grid, block, 0, s, n, f, grad_f, d, eik_weight, surf_k, inv_n, g_f, g_grad, partials);
     }
     const double w = grad_f ? (double)eik_weight : 0.0;
     hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(kFinishReduceThreads), 0, s, partials, (int)nb,
-                       n > 0 ? 1.0 / (double)n : 0.0, w, loss, nullptr, 0, nullptr);
+                       n > 0 ? 1.0 / (double)n : 0.0, w, loss, nullptr, 0, nullptr, 0.0, nullptr);
     return hipGetLastError();
 }
 
@@ -195,12 +200,12 @@ __global__ __launch_bounds__(kThreads) void k_adam(int64_t n, AdamArgs A, float*
 }
 
 __global__ __launch_bounds__(kFinishReduceThreads) void k_sum_finish(const double* __restrict__ partials, int nblocks,
-                                                                     double* __restrict__ out)
+                                                                     double scale, double* __restrict__ out)
 {
     double acc = 0.0;
     thread_partial_sums<1>(partials, nblocks, &acc);
     acc = block_sum_f64<kFinishReduceThreads>(acc);
-    if (threadIdx.x == 0) *out = acc;
+    if (threadIdx.x == 0) *out = acc * scale;
 }
 
 AdamArgs make_adam_args(const tg_adam_params& p)
@@ -220,16 +225,23 @@ AdamArgs make_adam_args(const tg_adam_params& p)
 }
 
 hipError_t launch_loss_finish(const double* partials, int64_t nblocks, int64_t n, float eik_weight, double* loss,
-                              hipStream_t s, const double* gpart, int64_t ng, double* gnorm)
+                              hipStream_t s, const double* gpart, int64_t ng, double* gnorm, float tv_weight,
+                              const double* tv)
 {
     hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(kFinishReduceThreads), 0, s, partials, (int)nblocks,
-                       n > 0 ? 1.0 / (double)n : 0.0, (double)eik_weight, loss, gpart, (int)ng, gnorm);
+                       n > 0 ? 1.0 / (double)n : 0.0, (double)eik_weight, loss, gpart, (int)ng, gnorm,
+                       (double)tv_weight, tv);
     return hipGetLastError();
 }
 
 hipError_t launch_sum_finish(const double* partials, int64_t nblocks, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kFinishReduceThreads), 0, s, partials, (int)nblocks, out);
+    return launch_sum_finish_scaled(partials, nblocks, 1.0, out, s);
+}
+
+hipError_t launch_sum_finish_scaled(const double* partials, int64_t nblocks, double scale, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kFinishReduceThreads), 0, s, partials, (int)nblocks, scale, out);
     return hipGetLastError();
 }
 
@@ -256,7 +268,7 @@ hipError_t launch_adam(const tg_grid* g, const tg_adam_params& p, double* grad_n
         break;
     }
     if (grad_norm_sq)
-        hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kFinishReduceThreads), 0, s, partials, (int)nb, grad_norm_sq);
+        hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kFinishReduceThreads), 0, s, partials, (int)nb, 1.0, grad_norm_sq);
     return hipGetLastError();
 }
 

@@ -202,8 +202,9 @@ class TaylorGrid:
         return dq
 
     def forward_sdf_loss(self, q, ws, d, eik_weight, g_f=None, g_grad=None, loss=None, eikonal=True, f_out=None,
-                         grad_out=None):
-        """Forward and SDF loss in one pass: returns (loss float64[3], g_f, g_grad or None).
+                         grad_out=None, surface_k=0.0):
+        """Forward and SDF loss in one pass: returns (loss float64[3], g_f, g_grad or None);
+        ``surface_k`` is Eq. 7's k (0: unweighted L1).
         ``eikonal=False`` drops the eikonal term; f_out / grad_out optionally receive f and
         grad f."""
         n = self._q(q)
@@ -222,7 +223,8 @@ class TaylorGrid:
             if t is not None:
                 _check_tensor(name, t, torch.float32, self.device, k)
         _lib.call("tg_forward_sdf_loss", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _ptr(d), float(eik_weight),
-                  _ptr(g_f), _ptr(g_grad), _ptr(loss), _ptr(f_out), _ptr(grad_out), _stream(self.device))
+                  float(surface_k), _ptr(g_f), _ptr(g_grad), _ptr(loss), _ptr(f_out), _ptr(grad_out),
+                  _stream(self.device))
         return loss, g_f, g_grad
 
     def _adam_params(self, lr, betas, eps, weight_decay, step):
@@ -232,9 +234,10 @@ class TaylorGrid:
         return _lib.AdamParams(lr, betas[0], betas[1], eps, weight_decay, self.step_count)
 
     def backward_adam(self, q, ws, g_f=None, g_grad=None, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0,
-                      grad_norm_sq=None, step=None):
+                      grad_norm_sq=None, step=None, add_grad=False):
         """Adjoint and Adam step in one pass (``grad`` is not written); grad_norm_sq
-        (device float64 [1]) receives sum(dC^2)."""
+        (device float64 [1]) receives sum(dC^2).  ``add_grad`` adds the gradient already in
+        ``grad`` (e.g. the TV term's) to the adjoint before the update."""
         n = self._q(q)
         if g_f is not None:
             _check_tensor("g_f", g_f, torch.float32, self.device, n)
@@ -244,17 +247,36 @@ class TaylorGrid:
             _check_tensor("grad_norm_sq", grad_norm_sq, torch.float64, self.device)
         p = self._adam_params(lr, betas, eps, weight_decay, step)
         _lib.call("tg_backward_adam", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _ptr(g_f), _ptr(g_grad),
-                  ctypes.byref(p), _ptr(grad_norm_sq), _stream(self.device))
+                  ctypes.byref(p), _ptr(grad_norm_sq), _lib.TG_BWD_ADD_GRAD if add_grad else 0, _stream(self.device))
+
+    def upsample_from(self, coarse):
+        """Start this grid (same box) from the field of ``coarse``: value, gradient and Hessian
+        of the coarse field at this grid's vertices, truncated to this grid's order; the Adam
+        moments are zeroed and the step count restarts."""
+        _lib.call("tg_upsample", coarse._h, self._h, _stream(self.device))
+        self.step_count = 0
+
+    def tv_loss(self, weight, ws, accumulate=False, loss=None):
+        """TV of the master coefficients (device float64 [1]); writes (or adds) weight * dTV/dC
+        into ``grad``."""
+        loss = torch.empty(1, dtype=torch.float64, device=self.device) if loss is None else loss
+        _check_tensor("loss", loss, torch.float64, self.device)
+        _lib.call("tg_tv_loss", self._h, float(weight), _ptr(loss), _lib.TG_BWD_ACCUMULATE if accumulate else 0,
+                  _ptr(ws), ws.numel(), _stream(self.device))
+        return loss
 
     def train_step(self, q, d, ws, eik_weight=0.1, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0,
-                   loss=None, grad_norm_sq=None, step=None, stage_events=None):
+                   loss=None, grad_norm_sq=None, step=None, stage_events=None, surface_k=0.0, tv_weight=0.0):
         """One SDF-fitting step (sort, forward + loss, adjoint + Adam) in one call; returns the
-        loss (device float64 [3]: total, L1 mean, eikonal mean).  stage_events: optional three
-        recorded torch.cuda.Events, re-recorded after each stage (for timing)."""
+        loss (device float64 [3]: total, weighted L1 mean, eikonal mean; with a TV term [4],
+        the TV value last).  ``surface_k`` is Eq. 7's k (0: unweighted), ``tv_weight`` the TV
+        term's weight (0: none; else ``grad`` holds the TV gradient).  stage_events: optional
+        three recorded torch.cuda.Events, re-recorded after each stage (for timing)."""
         n = self._q(q)
         _check_tensor("d", d, torch.float32, self.device, n)
-        loss = torch.empty(3, dtype=torch.float64, device=self.device) if loss is None else loss
-        _check_tensor("loss", loss, torch.float64, self.device, 3)
+        nl = 4 if tv_weight != 0.0 else 3
+        loss = torch.empty(nl, dtype=torch.float64, device=self.device) if loss is None else loss
+        _check_tensor("loss", loss, torch.float64, self.device, nl)
         if grad_norm_sq is not None:
             _check_tensor("grad_norm_sq", grad_norm_sq, torch.float64, self.device)
         p = self._adam_params(lr, betas, eps, weight_decay, step)
@@ -263,7 +285,8 @@ class TaylorGrid:
             if len(stage_events) != 3:
                 raise ValueError("stage_events must hold three events")
             evs = (ctypes.c_void_p * 3)(*[e.cuda_event for e in stage_events])
-        _lib.call("tg_train_step", self._h, _ptr(q), _ptr(d), n, float(eik_weight), ctypes.byref(p), _ptr(loss),
+        obj = _lib.SdfObjective(eik_weight, surface_k, tv_weight)
+        _lib.call("tg_train_step", self._h, _ptr(q), _ptr(d), n, ctypes.byref(obj), ctypes.byref(p), _ptr(loss),
                   _ptr(grad_norm_sq), _ptr(ws), ws.numel(), evs, _stream(self.device))
         self._sorted = _new_sort(q, ws)
         return loss
@@ -279,8 +302,9 @@ class TaylorGrid:
                   _stream(self.device))
 
 
-def sdf_loss(f, grad_f, d, eik_weight, ws, g_f=None, g_grad=None, loss=None):
-    """L1 + eikonal SDF objective; returns (loss float64[3] on device, g_f, g_grad)."""
+def sdf_loss(f, grad_f, d, eik_weight, ws, g_f=None, g_grad=None, loss=None, surface_k=0.0):
+    """L1 (weighted by Eq. 7 with k = surface_k; 0 = unweighted) + eikonal SDF objective;
+    returns (loss float64[3] on device, g_f, g_grad)."""
     n = f.numel()
     dev = f.device
     dim = grad_f.shape[1] if grad_f is not None else 3
@@ -292,7 +316,7 @@ def sdf_loss(f, grad_f, d, eik_weight, ws, g_f=None, g_grad=None, loss=None):
     _check_tensor("d", d, torch.float32, dev, n)
     if grad_f is not None:
         _check_tensor("grad_f", grad_f, torch.float32, dev, n * dim)
-    _lib.call("tg_sdf_loss", dim, n, _ptr(f), _ptr(grad_f), _ptr(d), float(eik_weight), _ptr(g_f),
+    _lib.call("tg_sdf_loss", dim, n, _ptr(f), _ptr(grad_f), _ptr(d), float(eik_weight), float(surface_k), _ptr(g_f),
               _ptr(g_grad) if grad_f is not None else None, _ptr(loss), _ptr(ws), ws.numel(), _stream(dev))
     return loss, g_f, g_grad
 

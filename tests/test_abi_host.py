@@ -177,11 +177,57 @@ def test_adam_parameter_validation():
 def test_loss_validation():
     fake = ctypes.c_void_p(0x100000)
     big = L().tg_reduce_workspace_bytes()
-    assert L().tg_sdf_loss(4, 10, fake, fake, fake, 0.1, fake, fake, fake, fake, big, None) == 1
-    assert L().tg_sdf_loss(3, 10, None, fake, fake, 0.1, fake, fake, fake, fake, big, None) == 1
-    assert L().tg_sdf_loss(3, 10, fake, fake, fake, 0.1, fake, None, fake, fake, big, None) == 1
-    assert L().tg_sdf_loss(3, 10, fake, fake, fake, float("inf"), fake, fake, fake, fake, big, None) == 1
-    assert L().tg_sdf_loss(3, 10, fake, fake, fake, 0.1, fake, fake, fake, fake, 8, None) == 4
+    assert L().tg_sdf_loss(4, 10, fake, fake, fake, 0.1, 0.0, fake, fake, fake, fake, big, None) == 1
+    assert L().tg_sdf_loss(3, 10, None, fake, fake, 0.1, 0.0, fake, fake, fake, fake, big, None) == 1
+    assert L().tg_sdf_loss(3, 10, fake, fake, fake, 0.1, 0.0, fake, None, fake, fake, big, None) == 1
+    assert L().tg_sdf_loss(3, 10, fake, fake, fake, float("inf"), 0.0, fake, fake, fake, fake, big, None) == 1
+    assert L().tg_sdf_loss(3, 10, fake, fake, fake, 0.1, 0.0, fake, fake, fake, fake, 8, None) == 4
+    # Eq. 7's k must be finite and non-negative
+    assert L().tg_sdf_loss(3, 10, fake, fake, fake, 0.1, -1.0, fake, fake, fake, fake, big, None) == 1
+    assert L().tg_sdf_loss(3, 10, fake, fake, fake, 0.1, float("nan"), fake, fake, fake, fake, big, None) == 1
+
+
+def test_objective_validation():
+    """TV, the fused adjoint's flags and the training step's objective: each call departs from
+    a valid set in one argument and is refused before anything is enqueued."""
+    fake = ctypes.c_void_p(0x100000)
+    b = _lib.GridBuffers()
+    b.coeffs = b.master = b.adam_m = b.adam_v = 0x1000
+    st, h = _create(_desc(res=(16, 16, 16)), b)
+    assert st == 0
+    b2 = _lib.GridBuffers()
+    b2.coeffs = b2.master = b2.adam_m = b2.adam_v = b2.grad = 0x1000
+    st, hg = _create(_desc(res=(16, 16, 16)), b2)
+    assert st == 0
+    try:
+        red = L().tg_reduce_workspace_bytes()
+        # tg_tv_loss: needs master and grad, a finite weight, known flags, a reduction workspace
+        assert L().tg_tv_loss(h, 1e-3, fake, 0, fake, red, None) == 1              # no grad buffer
+        assert L().tg_tv_loss(None, 1e-3, fake, 0, fake, red, None) == 1
+        assert L().tg_tv_loss(hg, float("inf"), fake, 0, fake, red, None) == 1
+        assert L().tg_tv_loss(hg, 1e-3, None, 0, fake, red, None) == 1
+        assert L().tg_tv_loss(hg, 1e-3, fake, 6, fake, red, None) == 1
+        assert L().tg_tv_loss(hg, 1e-3, fake, 0, fake, red - 1, None) == 4
+        assert L().tg_tv_loss(hg, 1e-3, fake, 0, ctypes.c_void_p(0x100010), red, None) == 1
+        n = 1000
+        ws = L().tg_workspace_bytes(hg, n)
+        p = _lib.AdamParams(1e-2, 0.9, 0.999, 1e-8, 0.0, 1)
+        # tg_backward_adam: TG_BWD_ADD_GRAD needs bufs.grad; unknown flags
+        assert L().tg_backward_adam(h, fake, n, fake, ws, fake, None, ctypes.byref(p), None, 1, None) == 1
+        assert L().tg_backward_adam(hg, fake, n, fake, ws, fake, None, ctypes.byref(p), None, 2, None) == 1
+        # tg_train_step: objective required and finite, k >= 0, TV needs bufs.grad
+        ok = _lib.SdfObjective(0.1, 0.0, 0.0)
+        for obj, handle in ((None, hg), (_lib.SdfObjective(float("nan"), 0.0, 0.0), hg),
+                            (_lib.SdfObjective(0.1, -2.0, 0.0), hg), (_lib.SdfObjective(0.1, 0.0, float("inf")), hg),
+                            (_lib.SdfObjective(0.1, 0.0, 1e-3), h)):
+            ref = ctypes.byref(obj) if obj is not None else None
+            assert L().tg_train_step(handle, fake, fake, n, ref, ctypes.byref(p), fake, None, fake, ws, None, None) == 1
+        # the valid objective only fails on the short workspace, before any launch
+        assert L().tg_train_step(hg, fake, fake, n, ctypes.byref(ok), ctypes.byref(p), fake, None, fake, ws - 1,
+                                 None, None) == 4
+    finally:
+        assert L().tg_destroy(h) == 0
+        assert L().tg_destroy(hg) == 0
 
 
 def test_composite_validation():
