@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -321,6 +322,74 @@ def radiance_bench(dev, steps=10, warmup=3, n_batches=2, n_rays=4096, n_samples=
             "loss_first_last": losses}
 
 
+def objective_bench(dev, C32, dev_batches, U, steps=10, warmup=3):
+    """The paper's full SDF objective at the headline size (128^3, K=2, 2^20 scene queries):
+    L1 weighted by Eq. 7 (k = ln 3 / (2 h): half weight two cells from the surface) + 0.1
+    eikonal + 2e-5 TV (Sec. 4.1's lambda_2), one tg_train_step per step; the TV kernel and the
+    coarse-to-fine transfer (64^3 -> 128^3) timed on their own with HIP events."""
+    import torch
+
+    from paper_2402_14415_amd.grid import TaylorGrid
+
+    h = 2.0 / (RES - 1)
+    k = math.log(3.0) / (2.0 * h)
+    grid = TaylorGrid(3, (RES,) * 3, ORDER, (-1.0,) * 3, (1.0,) * 3, coeffs=C32, device=dev)
+    ws = grid.workspace(NQ)
+    loss = torch.empty(4, dtype=torch.float64, device=dev)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps + warmup)]
+    for e4 in ev:
+        for e in e4:
+            e.record()
+    torch.cuda.synchronize()
+    losses = []
+    for i in range(steps + warmup):
+        q, d = dev_batches[i % len(dev_batches)]
+        ev[i][0].record()
+        grid.train_step(q, d, ws, eik_weight=EIK, lr=LR, loss=loss, surface_k=k, tv_weight=2e-5,
+                        stage_events=ev[i][1:])
+        if i == 0 or i == steps + warmup - 1:
+            losses.append([float(x) for x in loss.cpu()])
+    torch.cuda.synchronize()
+    med = lambda a, b: float(np.median([ev[i][a].elapsed_time(ev[i][b]) * 1e3 for i in range(warmup, warmup + steps)]))
+    step_us = med(0, 3)
+    # the TV kernel alone (reads and writes every coefficient once)
+    red = torch.empty(grid.workspace_bytes(0), dtype=torch.uint8, device=dev)
+    tv_ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    for e in tv_ev:
+        e.record()
+    torch.cuda.synchronize()
+    tv_ev[0].record()
+    for i in range(steps):
+        grid.tv_loss(2e-5, red)
+        tv_ev[i + 1].record()
+    torch.cuda.synchronize()
+    tv_us = float(np.median([tv_ev[i].elapsed_time(tv_ev[i + 1]) * 1e3 for i in range(steps)]))
+    tv_bytes = RES ** 3 * 10 * 8
+    # coarse-to-fine transfer 64^3 -> 128^3
+    coarse = TaylorGrid(3, (64,) * 3, ORDER, (-1.0,) * 3, (1.0,) * 3,
+                        coeffs=C32[::2, ::2, ::2].contiguous(), device=dev)
+    up_ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    for e in up_ev:
+        e.record()
+    torch.cuda.synchronize()
+    up_ev[0].record()
+    for i in range(steps):
+        grid.upsample_from(coarse)
+        up_ev[i + 1].record()
+    torch.cuda.synchronize()
+    up_us = float(np.median([up_ev[i].elapsed_time(up_ev[i + 1]) * 1e3 for i in range(steps)]))
+    up_bytes = RES ** 3 * 10 * 12 + 64 ** 3 * 10 * 4  # master + two moments written, coarse read once
+    return {"workload": "sdf_fit_128^3_K2_fp32_full_objective",
+            "objective": {"eik_weight": EIK, "surface_k": k, "tv_weight": 2e-5},
+            "step_us": step_us, "queries_per_s": NQ / (step_us * 1e-6),
+            "stage_us": {"sort": med(0, 1), "tv_and_forward_loss": med(1, 2), "backward_adam": med(2, 3)},
+            "loss_first_last": losses,
+            "tv_kernel": {"us": tv_us, "algorithmic_bytes": tv_bytes, "GBs": tv_bytes / (tv_us * 1e-6) / 1e9,
+                          "frac": tv_bytes / (tv_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
+            "upsample_64_to_128": {"us": up_us, "algorithmic_bytes": up_bytes,
+                                   "GBs": up_bytes / (up_us * 1e-6) / 1e9}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +401,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-radiance", action="store_true")
+    ap.add_argument("--no-objective", action="store_true")
     ap.add_argument("--copy-reference", action="store_true",
                     help="end with device-to-device copies of 256 MiB (the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
@@ -478,6 +548,10 @@ def main():
     if not args.no_precision:
         log("bench: precision forms")
         out["precision"] = precision_bench(dev)
+    if not args.no_objective:
+        log("bench: full SDF objective")
+        out["full_objective"] = objective_bench(dev, torch.from_numpy(C64.astype(np.float32)), dev_batches, U)
+        log(f"bench: full objective {json.dumps(out['full_objective'])}")
     if not args.no_radiance:
         log("bench: radiance form")
         out["radiance"] = radiance_bench(dev)

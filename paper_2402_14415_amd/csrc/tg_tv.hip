@@ -6,144 +6,87 @@
 // TV = (1 / |V|) sum over v, c of s(v, c).  The gradient at u collects +Delta_a / s from the
 // backward neighbours u - e_a and -Delta_a / s from u itself (0 where s = 0).
 //
-// A workgroup owns a tile of T^dim vertices.  It stages the tile and a one-vertex halo on
-// every side ((T+2)^dim vertex blocks, rows copied contiguously from the [vertex][C] layout)
-// into LDS, computes every owned vertex's gradient from LDS only, stages the results in LDS
-// and writes them row by row.  HBM sees the coefficients once (the halo comes mostly from
-// L2) and the gradient once.
+// One thread per coefficient word, walking the grid by rows along x: a workgroup takes rows
+// (y, z) in turn and its threads the row's res_x * C contiguous words, so each of the up to
+// 13 neighbour reads (u, u + e_a, u - e_a, u - e_a + e_b) is a coalesced wave access at a
+// constant offset, served mostly by L1/L2; HBM sees the coefficients about once and the
+// gradient once.  Norms use the hardware reciprocal square root (|Delta| / s = Delta rsq(s^2)).
 #include "tg_internal.hpp"
 
 namespace tg {
 
-template <int DIM> struct TvShape {
-    static constexpr int T = DIM == 3 ? 8 : 16;          // tile edge in vertices
-    static constexpr int NT = DIM == 3 ? T * T * T : T * T;  // threads = owned vertices
-    static constexpr int E = T + 2;                        // staged edge (with the halo)
-    static constexpr int NROWS = DIM == 3 ? E * E : E;     // staged rows along x
-};
+constexpr int kTvThreads = 256;
+// Squared norms below the smallest normal float count as 0 (the reciprocal square root is
+// not taken of a denormal): only differences under 1e-19 in magnitude are affected.
+constexpr float kTvMinNorm2 = 1.17549435e-38f;
 
 template <int DIM, int C>
-__global__ __launch_bounds__(TvShape<DIM>::NT) void k_tv(Geom g, const float* __restrict__ master,
-                                                        float* __restrict__ grad, int accumulate, float scale,
-                                                        double* __restrict__ partials)
+__global__ __launch_bounds__(kTvThreads) void k_tv(Geom g, const float* __restrict__ master,
+                                                   float* __restrict__ grad, int accumulate, float scale,
+                                                   double* __restrict__ partials)
 {
-    using S = TvShape<DIM>;
-    constexpr int T = S::T, E = S::E, NT = S::NT;
-    constexpr int ROWW = E * C;  // words of one staged row
-    __shared__ float reg[S::NROWS * ROWW];
-    __shared__ float out[NT * C];
-
-    int nt[3] = {1, 1, 1};
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) nt[a] = (g.res[a] + T - 1) / T;
-    const int64_t ntiles = (int64_t)nt[0] * nt[1] * nt[2];
-    const int tx = threadIdx.x % T, ty = (threadIdx.x / T) % T, tz = DIM == 3 ? threadIdx.x / (T * T) : 0;
+    const int rx = g.res[0], ry = g.res[1], rz = DIM == 3 ? g.res[2] : 1;
+    const int64_t sa[3] = {(int64_t)C, (int64_t)rx * C, (int64_t)rx * ry * C};  // word stride of e_a
+    const int64_t rows = (int64_t)ry * rz;
+    const int roww = rx * C;
     double acc = 0.0;
-
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        int v0[3] = {0, 0, 0};
-        v0[0] = (int)(tile % nt[0]) * T;
-        v0[1] = (int)((tile / nt[0]) % nt[1]) * T;
-        if constexpr (DIM == 3) v0[2] = (int)(tile / ((int64_t)nt[0] * nt[1])) * T;
-
-        // stage vertices [v0 - 1, v0 + T] on every axis; words outside the grid are not read
-        for (int e = threadIdx.x; e < S::NROWS * ROWW; e += NT) {
-            const int row = e / ROWW, off = e - row * ROWW;
-            const int gy = v0[1] - 1 + (DIM == 3 ? row % E : row);
-            const int gz = DIM == 3 ? v0[2] - 1 + row / E : 0;
-            const int gx = v0[0] - 1 + off / C;
-            bool ok = gx >= 0 && gx < g.res[0] && gy >= 0 && gy < g.res[1];
-            if constexpr (DIM == 3) ok = ok && gz >= 0 && gz < g.res[2];
-            if (ok) {
-                int64_t vtx = (int64_t)gx + (int64_t)gy * g.stride[1];
-                if constexpr (DIM == 3) vtx += (int64_t)gz * g.stride[2];
-                reg[e] = master[vtx * C + (off - (off / C) * C)];
-            }
-        }
-        __syncthreads();
-
-        const int u[3] = {v0[0] + tx, v0[1] + ty, v0[2] + tz};
-        bool own = u[0] < g.res[0] && u[1] < g.res[1];
-        if constexpr (DIM == 3) own = own && u[2] < g.res[2];
-        if (own) {
-            // staged index of the vertex at local offset (x, y, z) from the tile origin
-            auto at = [&](int x, int y, int z) -> int {
-                return DIM == 3 ? (((z + 1) * E + (y + 1)) * E + (x + 1)) * C : ((y + 1) * E + (x + 1)) * C;
-            };
-            const int l[3] = {tx, ty, tz};
-            bool fwd[3], bwd[3];  // u + e_a, u - e_a inside the grid
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int y = (int)(r % ry), z = (int)(r / ry);
+        const int64_t base = r * roww;
+        for (int w = threadIdx.x; w < roww; w += kTvThreads) {
+            const int x = w / C;
+            const int u[3] = {x, y, z};
+            const int64_t gi = base + w;
+            // Neighbour offsets, 0 where the neighbour is outside the grid: the difference is
+            // then exactly 0, as the definition has it, and every load is unconditional.
+            int64_t of[3], ob[3];  // to u + e_a, u - e_a
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                fwd[a] = u[a] + 1 < g.res[a];
-                bwd[a] = u[a] >= 1;
+                of[a] = u[a] + 1 < g.res[a] ? sa[a] : 0;
+                ob[a] = u[a] >= 1 ? sa[a] : 0;
             }
+            const float cu = master[gi];
+            float fn[DIM], bn[DIM], dn[DIM][DIM];  // C(u + e_a), C(u - e_a), C(u - e_a + e_b)
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const float cu = reg[at(l[0], l[1], l[2]) + c];
-                // s(u) and the forward differences at u
-                float du[3] = {0.0f, 0.0f, 0.0f};
-                float su2 = 0.0f;
+            for (int a = 0; a < DIM; ++a) {
+                fn[a] = master[gi + of[a]];
+                bn[a] = master[gi - ob[a]];
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    if (fwd[a]) {
-                        const int n = at(l[0] + (a == 0), l[1] + (a == 1), l[2] + (a == 2)) + c;
-                        du[a] = reg[n] - cu;
-                    }
-                    su2 = fmaf(du[a], du[a], su2);
-                }
-                const float su = sqrtf(su2);
-                acc += (double)su;
-                float gsum = 0.0f;
-                if (su > 0.0f) {
-                    const float inv = 1.0f / su;
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) gsum -= du[a] * inv;
-                }
-                // the backward neighbours p = u - e_a, whose difference along a ends at u
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    if (!bwd[a]) continue;
-                    const int p[3] = {l[0] - (a == 0), l[1] - (a == 1), l[2] - (a == 2)};
-                    const float cp = reg[at(p[0], p[1], p[2]) + c];
-                    float sp2 = 0.0f, da = 0.0f;
-#pragma unroll
-                    for (int b = 0; b < DIM; ++b) {
-                        float db;
-                        if (b == a) {
-                            db = cu - cp;  // u is inside the grid
-                            da = db;
-                        } else {
-                            // p + e_b is inside the grid when u + e_b is (same index on b)
-                            db = fwd[b] ? reg[at(p[0] + (b == 0), p[1] + (b == 1), p[2] + (b == 2)) + c] - cp : 0.0f;
-                        }
-                        sp2 = fmaf(db, db, sp2);
-                    }
-                    if (sp2 > 0.0f) gsum += da / sqrtf(sp2);
-                }
-                out[threadIdx.x * C + c] = gsum * scale;
+                for (int b = 0; b < DIM; ++b)
+                    if (b != a) dn[a][b] = master[gi - ob[a] + of[b]];  // p + e_b in the grid iff u + e_b is
             }
-        }
-        __syncthreads();
-
-        // write the owned vertices' gradients row by row (T C contiguous words per row)
-        constexpr int OROWS = DIM == 3 ? T * T : T;
-        const int nx = min(T, g.res[0] - v0[0]);
-        for (int e = threadIdx.x; e < OROWS * T * C; e += NT) {
-            const int row = e / (T * C), off = e - row * (T * C);
-            const int y = row % T, z = DIM == 3 ? row / T : 0;
-            bool ok = off < nx * C && v0[1] + y < g.res[1];
-            if constexpr (DIM == 3) ok = ok && v0[2] + z < g.res[2];
-            if (!ok) continue;
-            int64_t vrow = (int64_t)v0[0] + (int64_t)(v0[1] + y) * g.stride[1];
-            if constexpr (DIM == 3) vrow += (int64_t)(v0[2] + z) * g.stride[2];
-            const int64_t gi = vrow * C + off;
-            // out is [owned vertex][C] with vertex = x + T (y + T z): the same row order
-            const float v = out[row * T * C + off];
+            float du[DIM], su2 = 0.0f;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                du[a] = fn[a] - cu;
+                su2 = fmaf(du[a], du[a], su2);
+            }
+            const float inv = su2 >= kTvMinNorm2 ? __builtin_amdgcn_rsqf(su2) : 0.0f;
+            acc += (double)(su2 * inv);  // s(u)
+            float gsum = 0.0f;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) gsum = fmaf(-du[a], inv, gsum);
+            // the backward neighbours p = u - e_a, whose difference along a ends at u (for
+            // u on the first layer p = u and that difference is 0: no term)
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                const float cp = bn[a];
+                const float da = cu - cp;
+                float sp2 = da * da;
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) {
+                    if (b == a) continue;
+                    const float db = dn[a][b] - cp;
+                    sp2 = fmaf(db, db, sp2);
+                }
+                const float ip = sp2 >= kTvMinNorm2 ? __builtin_amdgcn_rsqf(sp2) : 0.0f;
+                gsum = fmaf(da, ip, gsum);
+            }
+            const float v = gsum * scale;
             grad[gi] = accumulate ? grad[gi] + v : v;
         }
-        __syncthreads();  // reg and out are rewritten by the next tile
     }
-    const double tot = block_sum_f64<NT>(acc);
+    const double tot = block_sum_f64<kTvThreads>(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
@@ -151,15 +94,13 @@ hipError_t launch_tv(const tg_grid* g, float weight, double* tv_out, float* grad
                      double* partials, hipStream_t s)
 {
     const int dim = g->desc.dim;
-    const int T = dim == 3 ? TvShape<3>::T : TvShape<2>::T;
-    int64_t ntiles = 1;
-    for (int a = 0; a < dim; ++a) ntiles *= (g->desc.res[a] + T - 1) / T;
-    const unsigned nb = (unsigned)std::min<int64_t>(ntiles, kMaxReduceBlocks);
+    const int64_t rows = (int64_t)g->desc.res[1] * (dim == 3 ? g->desc.res[2] : 1);
+    const unsigned nb = (unsigned)std::min<int64_t>(rows, kMaxReduceBlocks);
     const float scale = (float)((double)weight / (double)g->nvert);
     const int acc = accumulate ? 1 : 0;
 #define TG_TV_CASE(D, CC)                                                                                  \
     if (dim == D && g->C == CC) {                                                                          \
-        hipLaunchKernelGGL((k_tv<D, CC>), dim3(nb), dim3(TvShape<D>::NT), 0, s, g->geom, g->bufs.master, grad, \
+        hipLaunchKernelGGL((k_tv<D, CC>), dim3(nb), dim3(kTvThreads), 0, s, g->geom, g->bufs.master, grad,   \
                            acc, scale, partials);                                                          \
     } else
     TG_TV_CASE(3, 10) TG_TV_CASE(3, 4) TG_TV_CASE(3, 1) TG_TV_CASE(2, 6) TG_TV_CASE(2, 3) TG_TV_CASE(2, 1)

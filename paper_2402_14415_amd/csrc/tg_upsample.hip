@@ -4,7 +4,8 @@
 // exact derivatives) at its position, truncated to the fine order: the series of Eq. 1 of
 // the field being refined.
 //
-// One thread per fine vertex.  The fine vertex i on an axis sits at i (r_c - 1) / (r_f - 1)
+// One thread per fine vertex; a block's results go through LDS so that every output array is
+// written in contiguous runs.  The fine vertex i on an axis sits at i (r_c - 1) / (r_f - 1)
 // in coarse cell units, so its coarse cell and local coordinate come from integer arithmetic:
 // a fine vertex on a coarse face takes the cell above it (the top face the last cell), with
 // no rounding deciding the side.
@@ -20,78 +21,90 @@ __global__ __launch_bounds__(kThreads) void k_upsample(Geom gc, Geom gf, const f
 {
     constexpr int CC = NumCoeffs<DIM, KC>::value;
     constexpr int NH = DIM == 3 ? 6 : 3;
-    for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < nvert; v += (int64_t)gridDim.x * kThreads) {
-        int64_t rem = v;
-        AxisLoc L[DIM];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const int64_t i = rem % gf.res[a];
-            rem /= gf.res[a];
-            const int64_t num = i * (int64_t)(gc.res[a] - 1), den = gf.res[a] - 1;
-            int64_t cell = num / den;
-            float t = (float)((double)(num - cell * den) / (double)den);
-            if (cell > gc.res[a] - 2) {
-                cell = gc.res[a] - 2;
-                t = 1.0f;
-            }
-            L[a].cell = (int32_t)cell;
-            L[a].t = t;
-            L[a].clamped = false;
-        }
-        const AxisFactors<DIM> F = axis_factors<DIM>(gc, L);
-        float f = 0.0f, gr[DIM], hf[NH];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) gr[a] = 0.0f;
-#pragma unroll
-        for (int k = 0; k < NH; ++k) hf[k] = 0.0f;
-#pragma unroll
-        for (int b = 0; b < (1 << DIM); ++b) {
-            int64_t cv = (int64_t)(L[0].cell + (b & 1)) + (int64_t)(L[1].cell + ((b >> 1) & 1)) * gc.stride[1];
-            if constexpr (DIM == 3) cv += (int64_t)(L[2].cell + ((b >> 2) & 1)) * gc.stride[2];
-            float c[CC];
-#pragma unroll
-            for (int k = 0; k < CC; ++k) c[k] = coarse[cv * CC + k];
-            float d[DIM];
-            corner_offset<DIM>(F, b, d);
-            float T, dT[DIM];
-            taylor_eval<DIM, KC>(c, d, T, dT);
-            float w, dw[DIM];
-            corner_weight<DIM>(F, b, w, dw);
-            float H[NH];
-            taylor_hess<DIM, KC>(c, H);
-            float d2w[DIM == 3 ? 3 : 1];
-            corner_weight_d2<DIM>(F, b, d2w);
-            f = fmaf(w, T, f);
-            int k = 0;
+    constexpr int NOUT = 1 + DIM + NH;
+    // A block's kThreads consecutive fine vertices are kThreads * cf consecutive words of every
+    // output array: the results are staged in LDS and written as contiguous runs.
+    __shared__ float sh[kThreads * NOUT];
+    for (int64_t v0 = (int64_t)blockIdx.x * kThreads; v0 < nvert; v0 += (int64_t)gridDim.x * kThreads) {
+        const int64_t v = v0 + threadIdx.x;
+        if (v < nvert) {
+            int64_t rem = v;
+            AxisLoc L[DIM];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                gr[a] = fmaf(dw[a], T, fmaf(w, dT[a], gr[a]));
+                const int64_t i = rem % gf.res[a];
+                rem /= gf.res[a];
+                const int64_t num = i * (int64_t)(gc.res[a] - 1), den = gf.res[a] - 1;
+                int64_t cell = num / den;
+                float t = (float)((double)(num - cell * den) / (double)den);
+                if (cell > gc.res[a] - 2) {
+                    cell = gc.res[a] - 2;
+                    t = 1.0f;
+                }
+                L[a].cell = (int32_t)cell;
+                L[a].t = t;
+                L[a].clamped = false;
+            }
+            const AxisFactors<DIM> F = axis_factors<DIM>(gc, L);
+            float f = 0.0f, gr[DIM], hf[NH];
 #pragma unroll
-                for (int cc = a; cc < DIM; ++cc, ++k) {
-                    // d2(w T)/dx_a dx_cc; the pure second derivatives of w vanish
-                    float h = fmaf(w, H[k], fmaf(dw[a], dT[cc], dw[cc] * dT[a]));
-                    if (a != cc) h = fmaf(d2w[DIM == 3 ? (a == 0 ? cc - 1 : 2) : 0], T, h);
-                    hf[k] += h;
+            for (int a = 0; a < DIM; ++a) gr[a] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < NH; ++k) hf[k] = 0.0f;
+#pragma unroll
+            for (int b = 0; b < (1 << DIM); ++b) {
+                int64_t cv = (int64_t)(L[0].cell + (b & 1)) + (int64_t)(L[1].cell + ((b >> 1) & 1)) * gc.stride[1];
+                if constexpr (DIM == 3) cv += (int64_t)(L[2].cell + ((b >> 2) & 1)) * gc.stride[2];
+                float c[CC];
+#pragma unroll
+                for (int k = 0; k < CC; ++k) c[k] = coarse[cv * CC + k];
+                float d[DIM];
+                corner_offset<DIM>(F, b, d);
+                float T, dT[DIM];
+                taylor_eval<DIM, KC>(c, d, T, dT);
+                float w, dw[DIM];
+                corner_weight<DIM>(F, b, w, dw);
+                float H[NH];
+                taylor_hess<DIM, KC>(c, H);
+                float d2w[DIM == 3 ? 3 : 1];
+                corner_weight_d2<DIM>(F, b, d2w);
+                f = fmaf(w, T, f);
+                int k = 0;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    gr[a] = fmaf(dw[a], T, fmaf(w, dT[a], gr[a]));
+#pragma unroll
+                    for (int cc = a; cc < DIM; ++cc, ++k) {
+                        // d2(w T)/dx_a dx_cc; the pure second derivatives of w vanish
+                        float h = fmaf(w, H[k], fmaf(dw[a], dT[cc], dw[cc] * dT[a]));
+                        if (a != cc) h = fmaf(d2w[DIM == 3 ? (a == 0 ? cc - 1 : 2) : 0], T, h);
+                        hf[k] += h;
+                    }
                 }
             }
+            // stored order: value, gradient, Hessian xx, xy(, xz), yy(, yz, zz); first cf of them
+            float out[1 + DIM + NH];
+            out[0] = f;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) out[1 + a] = gr[a];
+#pragma unroll
+            for (int k = 0; k < NH; ++k) out[1 + DIM + k] = hf[k];
+#pragma unroll
+            for (int k = 0; k < NOUT; ++k)
+                if (k < cf) sh[threadIdx.x * cf + k] = out[k];
         }
-        // stored order: value, gradient, Hessian xx, xy(, xz), yy(, yz, zz); first cf of them
-        float out[1 + DIM + NH];
-        out[0] = f;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) out[1 + a] = gr[a];
-#pragma unroll
-        for (int k = 0; k < NH; ++k) out[1 + DIM + k] = hf[k];
-#pragma unroll
-        for (int k = 0; k < 1 + DIM + NH; ++k) {
-            if (k >= cf) break;
-            const int64_t gi = v * cf + k;
-            master[gi] = out[k];
-            if (st_f == ST_BF16) store_copy<ST_BF16>(coeffs, gi, out[k]);
-            else if (st_f == ST_F16) store_copy<ST_F16>(coeffs, gi, out[k]);
+        __syncthreads();
+        const int64_t nv = min((int64_t)kThreads, nvert - v0);
+        for (int e = threadIdx.x; e < nv * cf; e += kThreads) {
+            const int64_t gi = v0 * cf + e;
+            const float val = sh[e];
+            master[gi] = val;
+            if (st_f == ST_BF16) store_copy<ST_BF16>(coeffs, gi, val);
+            else if (st_f == ST_F16) store_copy<ST_F16>(coeffs, gi, val);
             if (mom1) mom1[gi] = 0.0f;
             if (mom2) mom2[gi] = 0.0f;
         }
+        __syncthreads();  // sh is rewritten by the next chunk
     }
 }
 

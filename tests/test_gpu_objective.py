@@ -194,3 +194,45 @@ def test_upsample_fine_vertices_on_coarse_faces():
     inside = odd[:, None, None] & odd[None, :, None] & odd[None, None, :]
     for k in range(1, 4):
         assert nerr(got[..., k][inside], ref[..., k][inside]) <= TOL_GRAD
+
+
+def test_progressive_fit_continues_from_the_coarse_field():
+    """32^3 -> 64^3 on the scene with the full objective: the fine level starts from the
+    coarse field (its loss is far below the random start's, though above the coarse loss: the
+    coarse field is only C0 across its cell faces, which the fine Taylor series smooth), and
+    fitting at the fine level lowers the loss further."""
+    import math
+
+    from paper_2402_14415_amd import synth
+    from paper_2402_14415_amd.progressive import ProgressiveFit
+
+    scene = synth.Scene(3)
+    k = math.log(3.0) / (2 * 2.0 / 63)
+    fit = ProgressiveFit(3, [32, 64], 2, (-1.0,) * 3, (1.0,) * 3, device=DEV, eik_weight=0.1, surface_k=k,
+                         tv_weight=1e-4, lr=1e-2)
+    batches = []
+    for s in range(4):
+        q, d = synth.scene_batch(scene, 1 << 16, seed=3, step=s)
+        batches.append((torch.tensor(q, dtype=torch.float32, device=DEV),
+                        torch.tensor(d, dtype=torch.float32, device=DEV)))
+    first = None
+    for it in range(60):
+        loss = fit.step(*batches[it % 4])
+        if first is None:
+            first = float(loss[0])
+    lc = to_np(fit.step(*batches[0], lr=0.0))  # lr 0: the loss of the field as it is
+    coarse_last = float(lc[0])
+    fit.advance()
+    assert fit.grid.res == (64, 64, 64) and fit.grid.step_count == 0
+    lf = to_np(fit.step(*batches[0], lr=0.0))
+    fine_first = float(lf[0])
+    print("coarse [total, weighted L1, eikonal, TV]:", lc, " fine start:", lf)
+    for it in range(60):
+        loss = fit.step(*batches[it % 4])
+    fine_last = float(fit.step(*batches[0], lr=0.0)[0])
+    print(f"loss: start {first:.4f}, coarse {coarse_last:.4f}, fine start {fine_first:.4f}, fine {fine_last:.4f}")
+    assert coarse_last < 0.5 * first
+    assert fine_first < 0.5 * first
+    assert fine_last < fine_first
+    with pytest.raises(IndexError):
+        fit.advance()
