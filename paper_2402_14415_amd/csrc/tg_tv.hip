@@ -30,7 +30,18 @@ __global__ __launch_bounds__(kTvThreads) void k_tv(Geom g, const float* __restri
     const int64_t rows = (int64_t)ry * rz;
     const int roww = rx * C;
     double acc = 0.0;
-    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    // XCD-aware rows: workgroups are dealt round-robin to the 8 XCDs, so with a grid that is a
+    // multiple of 8, XCD x (blockIdx % 8) takes the contiguous band x of the rows and its
+    // workgroups stride through that band together; the neighbour rows a row reads (y +- 1,
+    // z +- 1) are then mostly in the same XCD's L2.
+    int64_t r0 = blockIdx.x, r1 = rows, rstep = gridDim.x;
+    if (gridDim.x % 8 == 0) {
+        const int64_t band = (rows + 7) / 8;
+        r0 = (blockIdx.x % 8) * band + blockIdx.x / 8;
+        r1 = min(rows, (int64_t)(blockIdx.x % 8 + 1) * band);
+        rstep = gridDim.x / 8;
+    }
+    for (int64_t r = r0; r < r1; r += rstep) {
         const int y = (int)(r % ry), z = (int)(r / ry);
         const int64_t base = r * roww;
         for (int w = threadIdx.x; w < roww; w += kTvThreads) {
