@@ -204,6 +204,47 @@ tg_status tg_tv_loss(tg_grid* grid, float weight, double* loss, int32_t flags, v
  * must not overlap it.  Any orders and resolutions (finer or not). */
 tg_status tg_upsample(const tg_grid* coarse, tg_grid* fine, void* stream);
 
+/* Quality measures (the paper reports IoU and Chamfer distance of its reconstructions,
+ * Sec. 4.1; these evaluate a fitted grid against a known shape).
+ *
+ * IoU counts of the inside sets A = {i : f[i] < 0} and B = {i : d[i] < 0} over n sample
+ * points (f: the grid's values, e.g. from tg_forward; d: the reference SDF):
+ *   counts[0] = |A and B|, counts[1] = |A or B|   (device int64 [2]; IoU = counts[0] /
+ *   counts[1], 1 when both are empty).  Exact integer counts.  ws must hold
+ *   tg_reduce_workspace_bytes(). */
+tg_status tg_iou_counts(int64_t n, const float* f, const float* d, int64_t* counts, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* Device workspace bytes of tg_mesh for a lattice of n[0] x n[1] x n[2] points (host array);
+ * 0 when n is invalid or the lattice has more than 2^28 cells. */
+size_t tg_mesh_workspace_bytes(const int32_t* n);
+
+/* Zero-level-set mesh of a field sampled on a lattice, by marching tetrahedra.  values
+ * [n[2]][n[1]][n[0]] (device, x fastest) at the points lo + i (hi - lo) / (n - 1) (n, lo, hi
+ * host arrays of 3; every n[a] in 2..65536, at most 2^28 cells).  Every cell is split into 6
+ * tetrahedra around its main diagonal, corner 0 = (0,0,0) to corner 7 = (1,1,1) (corner
+ * index bx + 2 by + 4 bz): (0, a, b, 7) for (a, b) = (1,3), (3,2), (2,6), (6,4), (4,5), (5,1).
+ * Corners with value < 0 are inside.  One corner apart from the other three gives one
+ * triangle on the edges from it to the others (in corner order); two and two give the
+ * quadrilateral (i0 o0, i0 o1, i1 o1, i1 o0) (i0 < i1 inside, o0 < o1 outside corners of the
+ * tetrahedron) as the triangles (q0 q1 q2), (q0 q2 q3).  A vertex on edge (a, b) is
+ * p_a + v_a / (v_a - v_b) (p_b - p_a).  Each triangle is oriented so that its normal
+ * (p1 - p0) x (p2 - p0) points from the inside corners to the outside ones.  Triangles are
+ * written to tri [max_tris][3][3] (device, xyz per vertex) cell by cell (x fastest), then
+ * tetrahedron by tetrahedron; *n_tris (device int64) receives the total, of which only the
+ * first max_tris are written (call again with a larger buffer if it is larger).
+ * ws must hold tg_mesh_workspace_bytes(n). */
+tg_status tg_mesh(const int32_t* n, const float* lo, const float* hi, const float* values,
+                  float* tri, int64_t max_tris, int64_t* n_tris, void* ws, size_t ws_bytes,
+                  void* stream);
+
+/* Chamfer distance between point sets a [na][3] and b [nb][3] (device; na, nb >= 1): out
+ * (device double [3]) = {mean_a min_b |a - b| + mean_b min_a |a - b|, the first mean, the
+ * second mean}.  Brute force (every pair), distances in FP32, means in FP64.  ws must hold
+ * tg_reduce_workspace_bytes(). */
+tg_status tg_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, void* ws,
+                     size_t ws_bytes, void* stream);
+
 /* Radiance-field compositing (Sec. 3.3): the Max optical model of Eq. 10 along n_rays rays
  * of n_samples samples each, with a ReLU density, and the photometric loss of Eq. 11 with
  * its adjoint, in one launch.  Sample i of ray r is element r*n_samples + i of:

@@ -96,18 +96,20 @@ def marching_tetrahedra(values, lo, hi):
     nz, ny, nx = V.shape
     lo = np.asarray(lo, dtype=np.float64)
     h = (np.asarray(hi, dtype=np.float64) - lo) / (np.array([nx, ny, nz]) - 1)
+    # corner values of every cell [nz-1, ny-1, nx-1, 8]; only cells with corners on both
+    # sides produce triangles, visited in cell order (x fastest)
+    corners = np.stack([V[(c >> 2) & 1: nz - 1 + ((c >> 2) & 1), (c >> 1) & 1: ny - 1 + ((c >> 1) & 1),
+                          c & 1: nx - 1 + (c & 1)] for c in range(8)], axis=-1)
+    inside = corners < 0
+    mixed = np.argwhere(inside.any(axis=-1) & ~inside.all(axis=-1))  # rows (k, j, i), C order
     out = []
-    for k in range(nz - 1):
-        for j in range(ny - 1):
-            for i in range(nx - 1):
-                cv = np.array([V[k + ((c >> 2) & 1), j + ((c >> 1) & 1), i + (c & 1)] for c in range(8)])
-                if np.all(cv < 0) or not np.any(cv < 0):
-                    continue
-                base = np.array([i, j, k], dtype=np.float64)
-                cp = np.array([lo + (base + _corner_offset(c)) * h for c in range(8)])
-                for a, b in TET_PAIRS:
-                    idx = [0, a, b, 7]
-                    out.extend(tet_triangles(cp[idx], cv[idx], [_corner_offset(c) for c in idx]))
+    for k, j, i in mixed:
+        cv = corners[k, j, i]
+        base = np.array([i, j, k], dtype=np.float64)
+        cp = np.array([lo + (base + _corner_offset(c)) * h for c in range(8)])
+        for a, b in TET_PAIRS:
+            idx = [0, a, b, 7]
+            out.extend(tet_triangles(cp[idx], cv[idx], [_corner_offset(c) for c in idx]))
     return np.array(out).reshape(-1, 3, 3)
 
 

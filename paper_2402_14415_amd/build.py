@@ -20,7 +20,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtaylorgrid.so")
 ARCH = os.environ.get("TG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["tg_sort.hip", "tg_forward.hip", "tg_backward.hip", "tg_loss_adam.hip", "tg_query.hip", "tg_composite.hip", "tg_tv.hip", "tg_upsample.hip",
+SOURCES = ["tg_sort.hip", "tg_forward.hip", "tg_backward.hip", "tg_loss_adam.hip", "tg_query.hip", "tg_composite.hip", "tg_tv.hip", "tg_upsample.hip", "tg_quality.hip",
            "tg_api.cpp"]
 
 CFLAGS = [

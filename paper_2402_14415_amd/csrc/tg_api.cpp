@@ -555,6 +555,78 @@ tg_status tg_upsample(const tg_grid* coarse, tg_grid* fine, void* stream)
     return device_status(tg::launch_upsample(coarse, fine, static_cast<hipStream_t>(stream)), "tg_upsample");
 }
 
+tg_status tg_iou_counts(int64_t n, const float* f, const float* d, int64_t* counts, void* ws, size_t ws_bytes,
+                        void* stream)
+{
+    if (n < 0 || n > tg::kMaxQueries) return fail(TG_ERR_INVALID_ARG, "tg_iou_counts: n out of range");
+    if (n > 0 && (!f || !d)) return fail(TG_ERR_INVALID_ARG, "tg_iou_counts: f and d must not be NULL");
+    if (!counts) return fail(TG_ERR_INVALID_ARG, "tg_iou_counts: counts is NULL");
+    if (!ws || !aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "tg_iou_counts: workspace NULL or not 256-byte aligned");
+    if (ws_bytes < tg::kReduceBytes)
+        return fail(TG_ERR_CAPACITY, "tg_iou_counts: workspace smaller than %zu bytes", tg::kReduceBytes);
+    (void)hipGetLastError();
+    return device_status(tg::launch_iou(n, f, d, counts, static_cast<int64_t*>(ws), static_cast<hipStream_t>(stream)),
+                         "tg_iou_counts");
+}
+
+static bool mesh_cells(const int32_t* n, int64_t* ncell)
+{
+    if (!n) return false;
+    int64_t c = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] < 2 || n[a] > 65536) return false;
+        c *= n[a] - 1;
+    }
+    *ncell = c;
+    return true;
+}
+
+size_t tg_mesh_workspace_bytes(const int32_t* n)
+{
+    int64_t ncell;
+    if (!mesh_cells(n, &ncell) || ncell > tg::kMaxMeshCells) return 0;
+    return tg::mesh_workspace_bytes(ncell);
+}
+
+tg_status tg_mesh(const int32_t* n, const float* lo, const float* hi, const float* values, float* tri,
+                  int64_t max_tris, int64_t* n_tris, void* ws, size_t ws_bytes, void* stream)
+{
+    int64_t ncell;
+    if (!mesh_cells(n, &ncell)) return fail(TG_ERR_INVALID_ARG, "tg_mesh: every n[a] must be in 2..65536");
+    if (ncell > tg::kMaxMeshCells)
+        return fail(TG_ERR_CAPACITY, "tg_mesh: more than %lld cells", (long long)tg::kMaxMeshCells);
+    if (!lo || !hi) return fail(TG_ERR_INVALID_ARG, "tg_mesh: lo and hi must not be NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]) || !(hi[a] > lo[a]))
+            return fail(TG_ERR_INVALID_ARG, "tg_mesh: need finite lo[%d] < hi[%d]", a, a);
+    if (!values || !n_tris) return fail(TG_ERR_INVALID_ARG, "tg_mesh: values and n_tris must not be NULL");
+    if (max_tris < 0) return fail(TG_ERR_INVALID_ARG, "tg_mesh: max_tris is negative");
+    if (max_tris > 0 && !tri) return fail(TG_ERR_INVALID_ARG, "tg_mesh: tri is NULL");
+    if (!ws || !aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "tg_mesh: workspace NULL or not 256-byte aligned");
+    if (ws_bytes < tg::mesh_workspace_bytes(ncell))
+        return fail(TG_ERR_CAPACITY, "tg_mesh: workspace has %zu bytes, needs %zu", ws_bytes,
+                    tg::mesh_workspace_bytes(ncell));
+    (void)hipGetLastError();
+    return device_status(tg::launch_mesh(n, lo, hi, values, tri, max_tris, n_tris, static_cast<char*>(ws),
+                                         static_cast<hipStream_t>(stream)),
+                         "tg_mesh");
+}
+
+tg_status tg_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, void* ws, size_t ws_bytes,
+                     void* stream)
+{
+    if (na < 1 || nb < 1 || na > tg::kMaxQueries || nb > tg::kMaxQueries)
+        return fail(TG_ERR_INVALID_ARG, "tg_chamfer: point counts must be in 1..%lld", (long long)tg::kMaxQueries);
+    if (!a || !b || !out) return fail(TG_ERR_INVALID_ARG, "tg_chamfer: a, b and out must not be NULL");
+    if (!ws || !aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "tg_chamfer: workspace NULL or not 256-byte aligned");
+    if (ws_bytes < tg::kReduceBytes)
+        return fail(TG_ERR_CAPACITY, "tg_chamfer: workspace smaller than %zu bytes", tg::kReduceBytes);
+    (void)hipGetLastError();
+    return device_status(tg::launch_chamfer(a, na, b, nb, out, static_cast<double*>(ws),
+                                            static_cast<hipStream_t>(stream)),
+                         "tg_chamfer");
+}
+
 tg_status tg_composite(int64_t n_rays, int32_t n_samples, const float* f, const float* c, const float* delta,
                        const float* target, float* rgb, double* loss, float* g_f, float* g_c, void* ws,
                        size_t ws_bytes, void* stream)

@@ -39,6 +39,7 @@ constexpr int kFwdChunk = 1024;          // primary records per forward work ite
 constexpr int32_t kRecSecondary = (int32_t)0x80000000;  // record tag bit: secondary bucket copy
 constexpr int kBwdItem = 512;            // records staged per pass of a backward work item
 constexpr int kBwdItemMax = 2048;        // records per backward work item (4 passes)
+constexpr int64_t kMaxMeshCells = (int64_t)1 << 28;  // 12 triangles per cell stay below 2^32
 constexpr int kMaxReduceBlocks = 2048;  // FP64 partials: 4 per block
 constexpr size_t kReduceBytes = (size_t)kMaxReduceBlocks * 4 * sizeof(double);
 constexpr int64_t kMaxQueries = (int64_t)1 << 28;  // sort entries stay below 2^31
@@ -118,6 +119,15 @@ hipError_t launch_tv(const tg_grid* g, float weight, double* tv_out, float* grad
 // The fine grid's master (and storage copy) from the coarse field's value, gradient and
 // Hessian at the fine vertices; the fine moments (when present) are zeroed.
 hipError_t launch_upsample(const tg_grid* coarse, tg_grid* fine, hipStream_t s);
+// Quality measures: IoU counts (partials: 2 int64 per block, kMaxReduceBlocks blocks at most),
+// the marching-tetrahedra mesh (ws: mesh_workspace_bytes) and the Chamfer distance (partials:
+// kMaxReduceBlocks doubles).
+hipError_t launch_iou(int64_t n, const float* f, const float* d, int64_t* counts, int64_t* partials, hipStream_t s);
+size_t mesh_workspace_bytes(int64_t ncell);
+hipError_t launch_mesh(const int* n, const float* lo, const float* hi, const float* values, float* tri,
+                       int64_t max_tris, int64_t* n_tris, char* ws, hipStream_t s);
+hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, double* partials,
+                          hipStream_t s);
 hipError_t launch_sum_finish(const double* partials, int64_t nblocks, double* out, hipStream_t s);
 hipError_t launch_sum_finish_scaled(const double* partials, int64_t nblocks, double scale, double* out, hipStream_t s);
 hipError_t launch_composite(int64_t n_rays, int32_t ns, const float* f, const float* col, const float* delta,

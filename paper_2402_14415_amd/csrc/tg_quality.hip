@@ -1,0 +1,363 @@
+// SDF quality measures (the paper evaluates reconstructions by IoU and Chamfer distance,
+// Sec. 4.1): IoU counts of the inside sets on sample points, a zero-level-set mesh of a
+// sampled field by marching tetrahedra, and the Chamfer distance between two point sets.
+//
+// Mesh: the lattice cell with corner (i, j, k) is split into 6 tetrahedra around its main
+// diagonal (corner 0 to corner 7, corner index bx + 2 by + 4 bz), tetrahedron t being
+// (0, P_t.a, P_t.b, 7).  Corners with value < 0 are inside.  One corner apart from the other
+// three gives one triangle across the edges leaving it (edges in the order of the other
+// corners); two and two give the quadrilateral (i0 o0, i0 o1, i1 o1, i1 o0) split along its
+// first diagonal.  Each triangle is oriented so that its normal points from the inside
+// corners to the outside ones, decided on the triangle through the edge midpoints in integer
+// cell coordinates (exact; moving the points along their edges never flips it).  Triangles
+// are written cell by cell (x fastest), tetrahedron by tetrahedron: a first pass counts each
+// cell's triangles, an exclusive scan gives every cell its output offset, a second pass
+// writes them.
+#include "tg_internal.hpp"
+
+namespace tg {
+
+constexpr int kMeshThreads = 256;
+constexpr int kMeshCellsPerThread = 8;
+constexpr int kMeshCellsPerBlock = kMeshThreads * kMeshCellsPerThread;
+constexpr int kTetPair[6][2] = {{1, 3}, {3, 2}, {2, 6}, {6, 4}, {4, 5}, {5, 1}};
+
+struct Lattice {
+    int nx, ny, nz;
+    float lo[3], h[3];
+};
+
+__device__ __forceinline__ void cell_of(const Lattice& L, int64_t c, int& i, int& j, int& k)
+{
+    const int cx = L.nx - 1, cy = L.ny - 1;
+    i = (int)(c % cx);
+    j = (int)((c / cx) % cy);
+    k = (int)(c / ((int64_t)cx * cy));
+}
+
+__device__ __forceinline__ void cell_values(const Lattice& L, const float* __restrict__ v, int i, int j, int k,
+                                            float* cv)
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        cv[c] = v[((int64_t)(k + ((c >> 2) & 1)) * L.ny + (j + ((c >> 1) & 1))) * L.nx + (i + (c & 1))];
+}
+
+// triangles of tetrahedron t of a cell with corner values cv
+__device__ __forceinline__ int tet_count(const float* cv, int t)
+{
+    const int idx[4] = {0, kTetPair[t][0], kTetPair[t][1], 7};
+    int nin = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nin += cv[idx[q]] < 0.0f ? 1 : 0;
+    return nin == 2 ? 2 : (nin == 1 || nin == 3 ? 1 : 0);
+}
+
+__device__ __forceinline__ int cell_count(const float* cv)
+{
+    int n = 0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) n += tet_count(cv, t);
+    return n;
+}
+
+// Per thread: the triangle counts of kMeshCellsPerThread consecutive cells, their exclusive
+// prefix within the block (offs), and the block's total (bsum).
+__global__ __launch_bounds__(kMeshThreads) void k_mesh_count(Lattice L, const float* __restrict__ v, int64_t ncell,
+                                                            uint32_t* __restrict__ offs, uint32_t* __restrict__ bsum)
+{
+    __shared__ uint32_t wsum[kMeshThreads / 64];
+    const int64_t c0 = (int64_t)blockIdx.x * kMeshCellsPerBlock + (int64_t)threadIdx.x * kMeshCellsPerThread;
+    uint32_t cnt[kMeshCellsPerThread], tot = 0;
+#pragma unroll
+    for (int q = 0; q < kMeshCellsPerThread; ++q) {
+        cnt[q] = 0;
+        const int64_t c = c0 + q;
+        if (c < ncell) {
+            int i, j, k;
+            cell_of(L, c, i, j, k);
+            float cv[8];
+            cell_values(L, v, i, j, k, cv);
+            cnt[q] = (uint32_t)cell_count(cv);
+        }
+        tot += cnt[q];
+    }
+    // exclusive scan of the thread totals over the block
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = tot;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    uint32_t run = before + incl - tot;
+#pragma unroll
+    for (int q = 0; q < kMeshCellsPerThread; ++q) {
+        const int64_t c = c0 + q;
+        if (c < ncell) offs[c] = run;
+        run += cnt[q];
+    }
+    if (threadIdx.x == kMeshThreads - 1) bsum[blockIdx.x] = run;
+}
+
+// One block: exclusive scan of the block totals in place; *total = their sum.
+__global__ __launch_bounds__(1024) void k_mesh_scan_blocks(uint32_t* __restrict__ bsum, int64_t nb,
+                                                          int64_t* __restrict__ total)
+{
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
+        const int64_t b = b0 + threadIdx.x;
+        const uint32_t x = b < nb ? bsum[b] : 0u;
+        uint32_t incl = x;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (b < nb) bsum[b] = before + incl - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = before + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = (int64_t)carry;
+}
+
+__device__ __forceinline__ void corner_pos(const Lattice& L, int i, int j, int k, int c, float* p)
+{
+    p[0] = L.lo[0] + (float)(i + (c & 1)) * L.h[0];
+    p[1] = L.lo[1] + (float)(j + ((c >> 1) & 1)) * L.h[1];
+    p[2] = L.lo[2] + (float)(k + ((c >> 2) & 1)) * L.h[2];
+}
+
+__global__ __launch_bounds__(kMeshThreads) void k_mesh_emit(Lattice L, const float* __restrict__ v, int64_t ncell,
+                                                           const uint32_t* __restrict__ offs,
+                                                           const uint32_t* __restrict__ bsum, float* __restrict__ tri,
+                                                           int64_t max_tris)
+{
+    for (int64_t c = (int64_t)blockIdx.x * kMeshThreads + threadIdx.x; c < ncell;
+         c += (int64_t)gridDim.x * kMeshThreads) {
+        int i, j, k;
+        cell_of(L, c, i, j, k);
+        float cv[8];
+        cell_values(L, v, i, j, k, cv);
+        if (cell_count(cv) == 0) continue;
+        int64_t out = (int64_t)offs[c] + bsum[c / kMeshCellsPerBlock];
+        for (int t = 0; t < 6; ++t) {
+            const int idx[4] = {0, kTetPair[t][0], kTetPair[t][1], 7};
+            int in[4], ou[4], nin = 0, nout = 0;
+            for (int q = 0; q < 4; ++q) {
+                if (cv[idx[q]] < 0.0f) in[nin++] = q;
+                else ou[nout++] = q;
+            }
+            if (nin == 0 || nout == 0) continue;
+            // corner offsets (0 / 1) in the cell of the tetrahedron's corners
+            int pc[4][3];
+            for (int q = 0; q < 4; ++q) {
+                pc[q][0] = idx[q] & 1;
+                pc[q][1] = (idx[q] >> 1) & 1;
+                pc[q][2] = (idx[q] >> 2) & 1;
+            }
+            // from the inside centroid to the outside one, scaled by nin * nout (integers)
+            int D[3];
+            for (int a = 0; a < 3; ++a) {
+                int si = 0, so = 0;
+                for (int q = 0; q < nin; ++q) si += pc[in[q]][a];
+                for (int q = 0; q < nout; ++q) so += pc[ou[q]][a];
+                D[a] = nin * so - nout * si;
+            }
+            int e[2][3][2];  // up to two triangles, three edges (tetrahedron-local corners)
+            int ntri;
+            if (nin == 2) {
+                const int q[4][2] = {{in[0], ou[0]}, {in[0], ou[1]}, {in[1], ou[1]}, {in[1], ou[0]}};
+                const int sel[2][3] = {{0, 1, 2}, {0, 2, 3}};
+                for (int s = 0; s < 2; ++s)
+                    for (int m = 0; m < 3; ++m) {
+                        e[s][m][0] = q[sel[s][m]][0];
+                        e[s][m][1] = q[sel[s][m]][1];
+                    }
+                ntri = 2;
+            } else {
+                const int lone = nin == 1 ? in[0] : ou[0];
+                int m = 0;
+                for (int q = 0; q < 4; ++q)
+                    if (q != lone) {
+                        e[0][m][0] = lone;
+                        e[0][m][1] = q;
+                        ++m;
+                    }
+                ntri = 1;
+            }
+            for (int s = 0; s < ntri; ++s, ++out) {
+                // orientation on the midpoint triangle, in doubled integer cell coordinates
+                int mp[3][3];
+                for (int m = 0; m < 3; ++m)
+                    for (int a = 0; a < 3; ++a) mp[m][a] = pc[e[s][m][0]][a] + pc[e[s][m][1]][a];
+                const int u[3] = {mp[1][0] - mp[0][0], mp[1][1] - mp[0][1], mp[1][2] - mp[0][2]};
+                const int w[3] = {mp[2][0] - mp[0][0], mp[2][1] - mp[0][1], mp[2][2] - mp[0][2]};
+                const int n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+                const bool keep = n[0] * D[0] + n[1] * D[1] + n[2] * D[2] > 0;
+                if (out >= max_tris) continue;  // past the caller's capacity: counted, not written
+                for (int m = 0; m < 3; ++m) {
+                    const int mm = keep ? m : (m == 0 ? 0 : 3 - m);
+                    const int a = e[s][mm][0], b = e[s][mm][1];
+                    float pa[3], pb[3];
+                    corner_pos(L, i, j, k, idx[a], pa);
+                    corner_pos(L, i, j, k, idx[b], pb);
+                    const float va = cv[idx[a]], vb = cv[idx[b]];
+                    const float tt = va / (va - vb);
+                    for (int x = 0; x < 3; ++x) tri[(out * 3 + m) * 3 + x] = fmaf(tt, pb[x] - pa[x], pa[x]);
+                }
+            }
+        }
+    }
+}
+
+size_t mesh_workspace_bytes(int64_t ncell)
+{
+    const int64_t nb = (ncell + kMeshCellsPerBlock - 1) / kMeshCellsPerBlock;
+    return ((size_t)ncell * 4 + 255) / 256 * 256 + (size_t)std::max<int64_t>(nb, 1) * 4;
+}
+
+hipError_t launch_mesh(const int* n, const float* lo, const float* hi, const float* values, float* tri,
+                       int64_t max_tris, int64_t* n_tris, char* ws, hipStream_t s)
+{
+    Lattice L;
+    L.nx = n[0];
+    L.ny = n[1];
+    L.nz = n[2];
+    for (int a = 0; a < 3; ++a) {
+        L.lo[a] = lo[a];
+        L.h[a] = (float)(((double)hi[a] - (double)lo[a]) / (double)(n[a] - 1));
+    }
+    const int64_t ncell = (int64_t)(n[0] - 1) * (n[1] - 1) * (n[2] - 1);
+    const int64_t nb = (ncell + kMeshCellsPerBlock - 1) / kMeshCellsPerBlock;
+    uint32_t* offs = reinterpret_cast<uint32_t*>(ws);
+    uint32_t* bsum = reinterpret_cast<uint32_t*>(ws + ((size_t)ncell * 4 + 255) / 256 * 256);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_mesh_count, dim3((unsigned)nb), dim3(kMeshThreads), 0, s, L, values, ncell, offs, bsum);
+    hipLaunchKernelGGL(k_mesh_scan_blocks, dim3(1), dim3(1024), 0, s, bsum, nb, n_tris);
+    if (ncell > 0) {
+        const unsigned ne = (unsigned)std::min<int64_t>((ncell + kMeshThreads - 1) / kMeshThreads, 65536);
+        hipLaunchKernelGGL(k_mesh_emit, dim3(ne), dim3(kMeshThreads), 0, s, L, values, ncell, offs, bsum, tri,
+                           max_tris);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ IoU
+__global__ __launch_bounds__(kThreads) void k_iou(int64_t n, const float* __restrict__ f, const float* __restrict__ d,
+                                                 int64_t* __restrict__ partials)
+{
+    int64_t inter = 0, uni = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const bool a = f[i] < 0.0f, b = d[i] < 0.0f;
+        inter += (a && b) ? 1 : 0;
+        uni += (a || b) ? 1 : 0;
+    }
+    // exact integer sums (as doubles: every count is below 2^53)
+    const double si = block_sum_f64<kThreads>((double)inter);
+    const double su = block_sum_f64<kThreads>((double)uni);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = (int64_t)si;
+        partials[2 * blockIdx.x + 1] = (int64_t)su;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_iou_finish(const int64_t* __restrict__ partials, int nb,
+                                                  int64_t* __restrict__ counts)
+{
+    if (threadIdx.x != 0) return;
+    int64_t a = 0, b = 0;
+    for (int k = 0; k < nb; ++k) {
+        a += partials[2 * k];
+        b += partials[2 * k + 1];
+    }
+    counts[0] = a;
+    counts[1] = b;
+}
+
+hipError_t launch_iou(int64_t n, const float* f, const float* d, int64_t* counts, int64_t* partials, hipStream_t s)
+{
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kThreads * 4 - 1) / (kThreads * 4),
+                                                                        kMaxReduceBlocks));
+    hipLaunchKernelGGL(k_iou, dim3(nb), dim3(kThreads), 0, s, n, f, d, partials);
+    hipLaunchKernelGGL(k_iou_finish, dim3(1), dim3(64), 0, s, partials, (int)nb, counts);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Chamfer
+constexpr int kNnThreads = 128;
+constexpr int kNnTile = 2048;  // destination points per LDS tile
+
+// partials[block] = sum over this block's source points of the distance to the nearest
+// destination point (brute force, destination tiles staged in LDS as x, y, z arrays)
+__global__ __launch_bounds__(kNnThreads) void k_nn_sum(const float* __restrict__ src, int64_t ns,
+                                                      const float* __restrict__ dst, int64_t nd,
+                                                      double* __restrict__ partials)
+{
+    __shared__ float tx[kNnTile], ty[kNnTile], tz[kNnTile];
+    double acc = 0.0;
+    for (int64_t s0 = (int64_t)blockIdx.x * kNnThreads; s0 < ns; s0 += (int64_t)gridDim.x * kNnThreads) {
+        const int64_t si = s0 + threadIdx.x;
+        const bool ok = si < ns;
+        const float px = ok ? src[3 * si] : 0.0f, py = ok ? src[3 * si + 1] : 0.0f, pz = ok ? src[3 * si + 2] : 0.0f;
+        float best = INFINITY;
+        for (int64_t d0 = 0; d0 < nd; d0 += kNnTile) {
+            const int cnt = (int)min((int64_t)kNnTile, nd - d0);
+            __syncthreads();
+            for (int q = threadIdx.x; q < cnt; q += kNnThreads) {
+                tx[q] = dst[3 * (d0 + q)];
+                ty[q] = dst[3 * (d0 + q) + 1];
+                tz[q] = dst[3 * (d0 + q) + 2];
+            }
+            __syncthreads();
+            for (int q = 0; q < cnt; ++q) {
+                const float dx = tx[q] - px, dy = ty[q] - py, dz = tz[q] - pz;
+                best = fminf(best, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+            }
+        }
+        if (ok) acc += (double)sqrtf(best);
+    }
+    const double tot = block_sum_f64<kNnThreads>(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(64) void k_chamfer_finish(const double* __restrict__ pa, int na_b, int64_t na,
+                                                      const double* __restrict__ pb, int nb_b, int64_t nb,
+                                                      double* __restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < na_b; ++k) a += pa[k];
+    for (int k = 0; k < nb_b; ++k) b += pb[k];
+    out[1] = a / (double)na;
+    out[2] = b / (double)nb;
+    out[0] = out[1] + out[2];
+}
+
+hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, double* partials,
+                          hipStream_t s)
+{
+    const int half = kMaxReduceBlocks / 2;
+    const unsigned ga = (unsigned)std::min<int64_t>((na + kNnThreads - 1) / kNnThreads, half);
+    const unsigned gb = (unsigned)std::min<int64_t>((nb + kNnThreads - 1) / kNnThreads, half);
+    hipLaunchKernelGGL(k_nn_sum, dim3(ga), dim3(kNnThreads), 0, s, a, na, b, nb, partials);
+    hipLaunchKernelGGL(k_nn_sum, dim3(gb), dim3(kNnThreads), 0, s, b, nb, a, na, partials + half);
+    hipLaunchKernelGGL(k_chamfer_finish, dim3(1), dim3(64), 0, s, partials, (int)ga, na, partials + half, (int)gb, nb,
+                       out);
+    return hipGetLastError();
+}
+
+}  // namespace tg

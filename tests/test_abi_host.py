@@ -266,3 +266,32 @@ def test_query_validation():
         assert L().tg_query(hs, 1, r, -1, None) == 1
     finally:
         L().tg_destroy(h)
+
+
+def test_quality_validation():
+    """IoU, mesh and Chamfer: each call departs from a valid set in one argument."""
+    fake = ctypes.c_void_p(0x100000)
+    red = L().tg_reduce_workspace_bytes()
+    assert L().tg_iou_counts(-1, fake, fake, fake, fake, red, None) == 1
+    assert L().tg_iou_counts(10, None, fake, fake, fake, red, None) == 1
+    assert L().tg_iou_counts(10, fake, fake, None, fake, red, None) == 1
+    assert L().tg_iou_counts(10, fake, fake, fake, fake, red - 1, None) == 4
+    n = (ctypes.c_int32 * 3)(9, 10, 11)
+    lo = (ctypes.c_float * 3)(-1, -1, -1)
+    hi = (ctypes.c_float * 3)(1, 1, 1)
+    wsb = L().tg_mesh_workspace_bytes(n)
+    assert wsb >= 8 * 9 * 10 * 4
+    assert L().tg_mesh_workspace_bytes((ctypes.c_int32 * 3)(1, 10, 11)) == 0
+    assert L().tg_mesh_workspace_bytes((ctypes.c_int32 * 3)(65536, 65536, 65536)) == 0  # over 2^28 cells
+    assert L().tg_mesh((ctypes.c_int32 * 3)(1, 10, 11), lo, hi, fake, fake, 10, fake, fake, wsb, None) == 1
+    assert L().tg_mesh((ctypes.c_int32 * 3)(4097, 4097, 4097), lo, hi, fake, fake, 10, fake, fake, 1 << 40,
+                       None) == 4
+    assert L().tg_mesh(n, lo, lo, fake, fake, 10, fake, fake, wsb, None) == 1          # empty box
+    assert L().tg_mesh(n, lo, hi, None, fake, 10, fake, fake, wsb, None) == 1
+    assert L().tg_mesh(n, lo, hi, fake, None, 10, fake, fake, wsb, None) == 1        # no output buffer
+    assert L().tg_mesh(n, lo, hi, fake, fake, -1, fake, fake, wsb, None) == 1
+    assert L().tg_mesh(n, lo, hi, fake, fake, 10, None, fake, wsb, None) == 1
+    assert L().tg_mesh(n, lo, hi, fake, fake, 10, fake, fake, wsb - 1, None) == 4
+    assert L().tg_chamfer(fake, 0, fake, 5, fake, fake, red, None) == 1
+    assert L().tg_chamfer(fake, 5, None, 5, fake, fake, red, None) == 1
+    assert L().tg_chamfer(fake, 5, fake, 5, fake, fake, red - 1, None) == 4

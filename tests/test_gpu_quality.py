@@ -1,0 +1,126 @@
+"""SDF quality measures on the GPU against the FP64 oracle (oracle/quality.py): exact IoU
+counts, the marching-tetrahedra mesh triangle for triangle in the documented order (ragged
+lattices, exact zeros, a 128^3 scene lattice, a short output buffer, an empty level set),
+the Chamfer distance, and the measures of a fitted grid against the analytic scene."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import quality as qo
+from paper_2402_14415_amd import quality, synth
+from paper_2402_14415_amd.grid import TaylorGrid
+from parity_util import to_np
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=DEV)
+
+
+@pytest.mark.parametrize("n", [1_000_003, 1, 0])
+def test_iou_counts_are_exact(n):
+    rng = np.random.default_rng(n)
+    f = rng.normal(size=n).astype(np.float32)
+    d = (f + rng.normal(0, 0.5, size=n)).astype(np.float32)
+    if n > 10:
+        f[::97] = 0.0  # zero is outside
+        d[::89] = -0.0
+    got = quality.iou(_t(f), _t(d))
+    inter, union = qo.iou_counts(f, d)
+    assert got[1:] == (inter, union)
+    assert got[0] == qo.iou(f, d)
+
+
+def _lattice(fun, n, lo, hi):
+    axes = [np.linspace(lo[a], hi[a], n[a]) for a in range(3)]
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    return np.transpose(fun(X, Y, Z), (2, 1, 0)).astype(np.float32)  # [z, y, x]
+
+
+def _wavy(x, y, z):
+    return np.sqrt(x * x + y * y + z * z) - 0.55 + 0.08 * np.sin(5 * x) * np.cos(4 * y) + 0.05 * np.sin(7 * z)
+
+
+def _check_mesh(values, lo, hi, max_tris=None):
+    tri, total = quality.mesh(_t(values), lo, hi, max_tris=max_tris)
+    ref = qo.marching_tetrahedra(values.astype(np.float64), lo, hi)
+    torch.cuda.synchronize()
+    assert total == len(ref)
+    got = to_np(tri)
+    k = len(got)
+    assert k == (total if max_tris is None else min(total, max_tris))
+    if k:
+        scale = max(np.max(np.abs(hi)), np.max(np.abs(lo)))
+        assert np.max(np.abs(got - ref[:k])) <= 2e-6 * scale
+    return got
+
+
+def test_mesh_matches_oracle_ragged_lattice():
+    lo, hi = (-1.0, -0.9, -1.1), (1.0, 0.8, 1.2)
+    V = _lattice(_wavy, (31, 37, 29), lo, hi)
+    V[5, 6, :] = 0.0  # exact zeros (outside)
+    _check_mesh(V, lo, hi)
+
+
+def test_mesh_full_size_scene_lattice():
+    """The scene SDF on a 128^3 lattice over [-1, 1]^3."""
+    scene = synth.Scene(0)
+    lo, hi = (-1.0,) * 3, (1.0,) * 3
+    axes = np.linspace(-1, 1, 128)
+    Z, Y, X = np.meshgrid(axes, axes, axes, indexing="ij")
+    V = scene.sdf(np.stack([X, Y, Z], -1).reshape(-1, 3)).reshape(128, 128, 128).astype(np.float32)
+    _check_mesh(V, lo, hi)
+
+
+def test_mesh_short_buffer_and_empty_level_set():
+    lo, hi = (-1.0,) * 3, (1.0,) * 3
+    V = _lattice(_wavy, (20, 21, 22), lo, hi)
+    full = _check_mesh(V, lo, hi)
+    part = _check_mesh(V, lo, hi, max_tris=len(full) // 3)
+    assert np.array_equal(part, full[: len(part)])
+    tri, total = quality.mesh(_t(np.ones((5, 6, 7))), lo, hi)
+    assert total == 0 and tri.shape[0] == 0
+
+
+def test_chamfer_matches_oracle():
+    rng = np.random.default_rng(4)
+    a = rng.normal(0, 0.3, size=(20_000, 3)).astype(np.float32)
+    b = (rng.normal(0, 0.3, size=(15_000, 3)) + 0.02).astype(np.float32)
+    got = quality.chamfer(_t(a), _t(b))
+    ref = qo.chamfer(a.astype(np.float64), b.astype(np.float64))
+    assert abs(got[0] - ref) <= 1e-5 * ref
+    assert abs(got[1] + got[2] - got[0]) <= 1e-12 * got[0]
+
+
+def test_quality_of_a_fitted_grid():
+    """Fit 64^3 K=2 to the scene for 150 steps; IoU on 100k uniform points and the Chamfer
+    distance between the mesh of the grid's vertex values and 50k analytic surface points,
+    each against the oracle on the same inputs; the fit is good (IoU > 0.9, Chamfer < 2 cells)."""
+    scene = synth.Scene(0)
+    g = TaylorGrid(3, (64,) * 3, 2, (-1.0,) * 3, (1.0,) * 3, device=DEV)
+    n = 1 << 17
+    ws = g.workspace(n)
+    for s in range(150):
+        q, d = synth.scene_batch(scene, n, seed=5, step=s)
+        g.train_step(_t(q), _t(d), ws, eik_weight=0.1, lr=1e-2)
+    rng = np.random.default_rng(6)
+    pts = rng.uniform(-1, 1, size=(100_000, 3)).astype(np.float32)
+    wq = g.workspace(len(pts))
+    qt = _t(pts)
+    g.sort(qt, wq)
+    f, _ = g.forward(qt, wq, want_grad=False)
+    d = scene.sdf(pts.astype(np.float64)).astype(np.float32)
+    got = quality.iou(f, _t(d))
+    assert got[1:] == qo.iou_counts(to_np(f).astype(np.float32), d)
+    assert got[0] > 0.9, got
+    verts = g.master[..., 0].contiguous()
+    tri, total = quality.mesh(verts, (-1.0,) * 3, (1.0,) * 3)
+    mv = tri.reshape(-1, 3).contiguous()
+    surf = scene.surface_points(np.random.default_rng(7), 50_000).astype(np.float32)
+    ch = quality.chamfer(mv, _t(surf))
+    ref = qo.chamfer(to_np(mv), surf.astype(np.float64))
+    print(f"IoU {got[0]:.4f}, triangles {total}, Chamfer {ch[0]:.5f}")
+    assert abs(ch[0] - ref) <= 1e-5 * ref
+    assert ch[0] < 2 * 2.0 / 63
