@@ -390,6 +390,76 @@ def objective_bench(dev, C32, dev_batches, U, steps=10, warmup=3):
                                    "GBs": up_bytes / (up_us * 1e-6) / 1e9}}
 
 
+def quality_bench(dev, dev_batches, scene, fit_steps=400, n_points=100_000, n_surface=100_000, reps=5):
+    """Quality of a 128^3 K=2 grid fitted to the scene (from zero coefficients, fit_steps
+    training steps of the headline loss over the headline batches) against the analytic
+    scene, with the evaluation kernels timed by HIP events: IoU of the inside sets on uniform
+    points (the forward at the points, then the counts), the zero-level-set mesh of the grid's
+    vertex values (marching tetrahedra on the 128^3 lattice), and the Chamfer distance between
+    the mesh's vertices and points on the scene's surface."""
+    import torch
+
+    from paper_2402_14415_amd import quality
+    from paper_2402_14415_amd.grid import TaylorGrid
+
+    grid = TaylorGrid(3, (RES,) * 3, ORDER, (-1.0,) * 3, (1.0,) * 3, device=dev)
+    wfit = grid.workspace(NQ)
+    loss = torch.empty(3, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(fit_steps):
+        q, dd = dev_batches[i % len(dev_batches)]
+        grid.train_step(q, dd, wfit, eik_weight=EIK, lr=LR, loss=loss)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t0
+    fit_loss = float(loss[0])
+    del wfit
+
+    rng = np.random.default_rng(11)
+    pts = torch.tensor(rng.uniform(-1, 1, size=(n_points, 3)), dtype=torch.float32, device=dev)
+    d = torch.tensor(scene.sdf(pts.cpu().double().numpy()), dtype=torch.float32, device=dev)
+    surf = torch.tensor(scene.surface_points(np.random.default_rng(12), n_surface), dtype=torch.float32, device=dev)
+    ws = grid.workspace(n_points)
+    red = torch.empty(grid.workspace_bytes(0), dtype=torch.uint8, device=dev)
+
+    def timed(fn):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        for e in ev:
+            e.record()
+        torch.cuda.synchronize()
+        ev[0].record()
+        for i in range(reps):
+            r = fn()
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        return r, float(np.median([ev[i].elapsed_time(ev[i + 1]) * 1e3 for i in range(reps)]))
+
+    def evaluate():
+        grid.sort(pts, ws)
+        return grid.forward(pts, ws, want_grad=False)[0]
+
+    f, fwd_us = timed(evaluate)
+    counts = torch.empty(2, dtype=torch.int64, device=dev)
+    _, iou_us = timed(lambda: quality.iou_counts(f, d, red, counts))
+    iou, inter, union = quality.iou(f, d, red)
+    verts = grid.master[..., 0].contiguous()
+    tri, total = quality.mesh(verts, (-1.0,) * 3, (1.0,) * 3)
+    lat = quality.MeshLattice(verts.shape, (-1.0,) * 3, (1.0,) * 3, dev)
+    tri2 = torch.empty_like(tri)
+    _, mesh_us = timed(lambda: lat.run(verts, tri2, total))
+    mv = tri.reshape(-1, 3).contiguous()
+    out = torch.empty(3, dtype=torch.float64, device=dev)
+    _, ch_us = timed(lambda: quality.chamfer_into(mv, surf, out, red))
+    ch = [float(x) for x in out.cpu()]
+    pairs = 2 * mv.shape[0] * surf.shape[0]
+    return {"workload": f"quality_of_sdf_fit_{RES}^3", "fit_steps": fit_steps, "fit_seconds": fit_s,
+            "fit_loss": fit_loss, "iou": iou, "iou_points": n_points,
+            "triangles": total, "chamfer": ch[0], "chamfer_mesh_to_surface": ch[1], "chamfer_surface_to_mesh": ch[2],
+            "surface_points": n_surface,
+            "us": {"sort_and_forward": fwd_us, "iou_counts": iou_us, "mesh": mesh_us, "chamfer": ch_us},
+            "chamfer_distance_evals_per_s": pairs / (ch_us * 1e-6)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,6 +472,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-radiance", action="store_true")
     ap.add_argument("--no-objective", action="store_true")
+    ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--copy-reference", action="store_true",
                     help="end with device-to-device copies of 256 MiB (the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
@@ -548,6 +619,10 @@ def main():
     if not args.no_precision:
         log("bench: precision forms")
         out["precision"] = precision_bench(dev)
+    if not args.no_quality:
+        log("bench: quality of the fitted grid")
+        out["quality"] = quality_bench(dev, dev_batches, scene)
+        log(f"bench: quality {json.dumps(out['quality'])}")
     if not args.no_objective:
         log("bench: full SDF objective")
         out["full_objective"] = objective_bench(dev, torch.from_numpy(C64.astype(np.float32)), dev_batches, U)

@@ -19,51 +19,73 @@ def _reduce_ws(dev):
     return torch.empty(_lib.lib().tg_reduce_workspace_bytes(), dtype=torch.uint8, device=dev)
 
 
-def iou(f, d, ws=None):
-    """IoU of {f < 0} and {d < 0}; returns (iou, |A and B|, |A or B|)."""
+def iou_counts(f, d, ws=None, counts=None):
+    """Device int64 [2]: (|A and B|, |A or B|) of A = {f < 0}, B = {d < 0} (no host sync)."""
     dev = f.device
     n = f.numel()
     _check_tensor("f", f, torch.float32, dev)
     _check_tensor("d", d, torch.float32, dev, n)
     ws = _reduce_ws(dev) if ws is None else ws
-    counts = torch.empty(2, dtype=torch.int64, device=dev)
+    counts = torch.empty(2, dtype=torch.int64, device=dev) if counts is None else counts
     _lib.call("tg_iou_counts", n, _ptr(f), _ptr(d), _ptr(counts), _ptr(ws), ws.numel(), _stream(dev))
-    inter, union = (int(x) for x in counts.cpu())
+    return counts
+
+
+def iou(f, d, ws=None):
+    """IoU of {f < 0} and {d < 0}; returns (iou, |A and B|, |A or B|)."""
+    inter, union = (int(x) for x in iou_counts(f, d, ws).cpu())
     return (1.0 if union == 0 else inter / union), inter, union
+
+
+class MeshLattice:
+    """The lattice arguments and workspace of tg_mesh for values [nz, ny, nx] over [lo, hi]^3."""
+
+    def __init__(self, shape, lo, hi, device):
+        nz, ny, nx = shape
+        self.n = (ctypes.c_int32 * 3)(nx, ny, nz)
+        self.lo = (ctypes.c_float * 3)(*[float(v) for v in lo])
+        self.hi = (ctypes.c_float * 3)(*[float(v) for v in hi])
+        wsb = _lib.lib().tg_mesh_workspace_bytes(self.n)
+        if wsb == 0:
+            raise ValueError("lattice too small or too large")
+        self.ws = torch.empty(wsb, dtype=torch.uint8, device=device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def run(self, values, tri, max_tris):
+        """Enqueue the mesh into tri (capacity max_tris); the total goes to self.count (no sync)."""
+        _check_tensor("values", values, torch.float32, values.device)
+        _lib.call("tg_mesh", self.n, self.lo, self.hi, _ptr(values), _ptr(tri), int(max_tris), _ptr(self.count),
+                  _ptr(self.ws), self.ws.numel(), _stream(values.device))
 
 
 def mesh(values, lo, hi, max_tris=None):
     """Zero-level-set triangles [T, 3, 3] of values [nz, ny, nx] sampled on the lattice over
-    [lo, hi]^3 (marching tetrahedra, in the library's documented order)."""
+    [lo, hi]^3 (marching tetrahedra, in the library's documented order), and the total count."""
     dev = values.device
-    nz, ny, nx = values.shape
-    _check_tensor("values", values, torch.float32, dev)
-    n = (ctypes.c_int32 * 3)(nx, ny, nz)
-    lo_c = (ctypes.c_float * 3)(*[float(v) for v in lo])
-    hi_c = (ctypes.c_float * 3)(*[float(v) for v in hi])
-    wsb = _lib.lib().tg_mesh_workspace_bytes(n)
-    if wsb == 0:
-        raise ValueError("lattice too small or too large")
-    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
-    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    lat = MeshLattice(values.shape, lo, hi, dev)
     cap = 0 if max_tris is None else int(max_tris)
     tri = torch.empty((max(cap, 1), 3, 3), dtype=torch.float32, device=dev)
-    _lib.call("tg_mesh", n, lo_c, hi_c, _ptr(values), _ptr(tri), cap, _ptr(count), _ptr(ws), ws.numel(), _stream(dev))
-    total = int(count.item())
+    lat.run(values, tri, cap)
+    total = int(lat.count.item())
     if max_tris is None and total > 0:  # size the output from the first call's count
         tri = torch.empty((total, 3, 3), dtype=torch.float32, device=dev)
-        _lib.call("tg_mesh", n, lo_c, hi_c, _ptr(values), _ptr(tri), total, _ptr(count), _ptr(ws), ws.numel(),
-                  _stream(dev))
+        lat.run(values, tri, total)
         cap = total
     return tri[: min(total, cap)], total
 
 
-def chamfer(a, b, ws=None):
-    """Chamfer distance of point sets a [Na, 3], b [Nb, 3]: (total, mean a->b, mean b->a)."""
+def chamfer_into(a, b, out, ws):
+    """Enqueue the Chamfer distance of a [Na, 3] and b [Nb, 3] into out (device float64 [3])."""
     dev = a.device
     _check_tensor("a", a, torch.float32, dev)
     _check_tensor("b", b, torch.float32, dev)
-    ws = _reduce_ws(dev) if ws is None else ws
-    out = torch.empty(3, dtype=torch.float64, device=dev)
+    _check_tensor("out", out, torch.float64, dev, 3)
     _lib.call("tg_chamfer", _ptr(a), a.shape[0], _ptr(b), b.shape[0], _ptr(out), _ptr(ws), ws.numel(), _stream(dev))
-    return tuple(float(x) for x in out.cpu())
+    return out
+
+
+def chamfer(a, b, ws=None):
+    """Chamfer distance of point sets a [Na, 3], b [Nb, 3]: (total, mean a->b, mean b->a)."""
+    ws = _reduce_ws(a.device) if ws is None else ws
+    out = torch.empty(3, dtype=torch.float64, device=a.device)
+    return tuple(float(x) for x in chamfer_into(a, b, out, ws).cpu())
