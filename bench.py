@@ -460,6 +460,49 @@ def quality_bench(dev, dev_batches, scene, fit_steps=400, n_points=100_000, n_su
             "chamfer_distance_evals_per_s": pairs / (ch_us * 1e-6)}
 
 
+def order_scaling_bench(dev, dev_batches, steps=10, warmup=3):
+    """Time and bytes against the Taylor order at the headline size (128^3, 2^20 scene queries
+    per step, the headline step): K = 0, 1, 2 and order 2 with the full 3 x 3 Hessian stored
+    (13 coefficients per vertex).  Ratios are to K = 0; the paper's Table 2 reports, for its
+    Linear / 1st Taylor / Taylor grids at 128^3, training times 7.0 / 27.1 / 95.0 s and sizes
+    9.2 / 32.7 / 106.0 MB (ratios 1 : 3.9 : 13.6 and 1 : 3.6 : 11.5)."""
+    import torch
+
+    from paper_2402_14415_amd.grid import TaylorGrid
+
+    rows = {}
+    for name, order, layout in (("K0", 0, "symmetric"), ("K1", 1, "symmetric"), ("K2", 2, "symmetric"),
+                                ("K2_full_hessian", 2, "full")):
+        g = TaylorGrid(3, (RES,) * 3, order, (-1.0,) * 3, (1.0,) * 3, device=dev, hessian=layout)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(0)
+        g.master.copy_(torch.randn(g.shape, generator=gen, device=dev) * 0.05)
+        ws = g.workspace(NQ)
+        loss = torch.empty(3, dtype=torch.float64, device=dev)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        for e in ev:
+            e.record()
+        for i in range(warmup):
+            q, d = dev_batches[i % len(dev_batches)]
+            g.train_step(q, d, ws, eik_weight=EIK, lr=LR, loss=loss)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for i in range(steps):
+            q, d = dev_batches[i % len(dev_batches)]
+            g.train_step(q, d, ws, eik_weight=EIK, lr=LR, loss=loss)
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        us = float(np.median([ev[i].elapsed_time(ev[i + 1]) * 1e3 for i in range(steps)]))
+        rows[name] = {"coeffs_per_vertex": g.C, "coeff_MB": RES ** 3 * g.C * 4 / 1e6, "step_us": us}
+        del g, ws
+    t0, b0 = rows["K0"]["step_us"], rows["K0"]["coeff_MB"]
+    for r in rows.values():
+        r["time_ratio"] = r["step_us"] / t0
+        r["size_ratio"] = r["coeff_MB"] / b0
+    return {"workload": f"sdf_fit_{RES}^3_order_scaling", "rows": rows,
+            "paper_table2_ratios": {"time": [1.0, 27.1 / 7.0, 95.0 / 7.0], "size": [1.0, 32.7 / 9.2, 106.0 / 9.2]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -473,6 +516,7 @@ def main():
     ap.add_argument("--no-radiance", action="store_true")
     ap.add_argument("--no-objective", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--no-order-scaling", action="store_true")
     ap.add_argument("--copy-reference", action="store_true",
                     help="end with device-to-device copies of 256 MiB (the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
@@ -619,6 +663,10 @@ def main():
     if not args.no_precision:
         log("bench: precision forms")
         out["precision"] = precision_bench(dev)
+    if not args.no_order_scaling:
+        log("bench: order scaling")
+        out["order_scaling"] = order_scaling_bench(dev, dev_batches)
+        log(f"bench: order scaling {json.dumps(out['order_scaling'])}")
     if not args.no_quality:
         log("bench: quality of the fitted grid")
         out["quality"] = quality_bench(dev, dev_batches, scene)

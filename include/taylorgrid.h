@@ -65,7 +65,13 @@ typedef struct {
     float lo[3];     /* box corner; lo[2] unused when dim == 2 */
     float hi[3];     /* hi[a] > lo[a], both finite */
     int32_t storage; /* tg_dtype of `coeffs` */
+    int32_t hessian; /* order 2 only: TG_HESSIAN_SYMMETRIC (default, 0) stores the dim(dim+1)/2
+                        distinct entries; TG_HESSIAN_FULL stores all dim^2 entries (row-major),
+                        1 + dim + dim^2 coefficients per vertex (13 in 3D) */
 } tg_grid_desc;
+
+#define TG_HESSIAN_SYMMETRIC 0
+#define TG_HESSIAN_FULL 1
 
 /* Device buffers of one grid, all with the coefficient layout above (host struct).
  * A pointer may be NULL when no call that needs it is made. */

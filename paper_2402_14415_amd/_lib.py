@@ -20,13 +20,15 @@ TG_F32, TG_BF16, TG_F16 = 0, 1, 2
 TG_BWD_ACCUMULATE = 1
 TG_ADAM_ZERO_GRAD = 1
 TG_BWD_ADD_GRAD = 1
+TG_HESSIAN_SYMMETRIC, TG_HESSIAN_FULL = 0, 1
 TG_QUERY_MAX_REQS = 32
 TG_QUERY_MAX_GRIDS = 16
 
 
 class GridDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("res", ctypes.c_int32 * 3), ("order", ctypes.c_int32),
-                ("lo", ctypes.c_float * 3), ("hi", ctypes.c_float * 3), ("storage", ctypes.c_int32)]
+                ("lo", ctypes.c_float * 3), ("hi", ctypes.c_float * 3), ("storage", ctypes.c_int32),
+                ("hessian", ctypes.c_int32)]
 
 
 class GridBuffers(ctypes.Structure):

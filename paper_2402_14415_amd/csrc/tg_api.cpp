@@ -185,7 +185,11 @@ tg_status tg_create(const tg_grid_desc* desc, const tg_grid_buffers* bufs, tg_gr
             return fail(TG_ERR_INVALID_ARG, "tg_create: need finite lo[%d] < hi[%d]", a, a);
         nvert *= d.res[a];
     }
-    const int32_t C = tg_coeffs_per_vertex(d.dim, d.order);
+    if (d.hessian != TG_HESSIAN_SYMMETRIC && d.hessian != TG_HESSIAN_FULL)
+        return fail(TG_ERR_INVALID_ARG, "tg_create: unknown Hessian layout %d", d.hessian);
+    const bool full = d.hessian == TG_HESSIAN_FULL;
+    if (full && d.order != 2) return fail(TG_ERR_INVALID_ARG, "tg_create: the full-Hessian layout needs order 2");
+    const int32_t C = full ? 1 + d.dim + d.dim * d.dim : tg_coeffs_per_vertex(d.dim, d.order);
     if (nvert * C > ((int64_t)1 << 40)) return fail(TG_ERR_CAPACITY, "tg_create: grid too large");
     tg_grid_buffers b;
     memset(&b, 0, sizeof(b));
@@ -199,6 +203,7 @@ tg_status tg_create(const tg_grid_desc* desc, const tg_grid_buffers* bufs, tg_gr
     g->desc = d;
     g->bufs = b;
     g->C = C;
+    g->kord = full ? tg::kOrderFull : d.order;
     g->nvert = nvert;
     constexpr int B3 = tg::BrickEdge<3>::value, B2 = tg::BrickEdge<2>::value;
     const int B = d.dim == 3 ? B3 : B2;
@@ -667,9 +672,12 @@ tg_status tg_query(const tg_grid* const* grids, int32_t n_grids, const tg_reques
     if (n_reqs < 0) return fail(TG_ERR_INVALID_ARG, "tg_query: n_reqs is negative");
     if (n_reqs == 0) return ok();
     if (!grids || n_grids < 1 || !reqs) return fail(TG_ERR_INVALID_ARG, "tg_query: grids and reqs must not be NULL");
-    for (int32_t k = 0; k < n_grids; ++k)
+    for (int32_t k = 0; k < n_grids; ++k) {
         if (!grids[k] || !grids[k]->bufs.coeffs)
             return fail(TG_ERR_INVALID_ARG, "tg_query: grid %d is NULL or has no coeffs", k);
+        if (grids[k]->kord == tg::kOrderFull)
+            return fail(TG_ERR_UNSUPPORTED, "tg_query: grid %d stores the full Hessian (serve the symmetric layout)", k);
+    }
     for (int32_t i = 0; i < n_reqs; ++i) {
         const tg_request& r = reqs[i];
         if (r.grid < 0 || r.grid >= n_grids) return fail(TG_ERR_INVALID_ARG, "tg_query: request %d names grid %d", i, r.grid);

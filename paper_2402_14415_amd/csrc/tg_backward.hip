@@ -55,7 +55,16 @@ __device__ __forceinline__ void accumulate_corner(const float* d, float s, const
             q[a] = fmaf(s, d[a], u[a]);  // s d_a + u_a
             acc[1 + a] += q[a];
         }
-        if constexpr (K == 2) {
+        if constexpr (K == kOrderFull) {
+            // H_ab (row-major): d(T)/dH_ab = d_a d_b / 2, d(grad_c T)/dH_ab = (delta_ca d_b + delta_cb d_a) / 2
+            const float hs = 0.5f * s;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b2 = 0; b2 < DIM; ++b2)
+                    acc[1 + DIM + a * DIM + b2] =
+                        fmaf(0.5f * u[b2], d[a], fmaf(0.5f * u[a], d[b2], fmaf(hs * d[a], d[b2], acc[1 + DIM + a * DIM + b2])));
+        } else if constexpr (K == 2) {
             const float hs = 0.5f * s;
             if constexpr (DIM == 3) {
                 acc[4] = fmaf(fmaf(hs, d[0], u[0]), d[0], acc[4]);     // xx: d_x (s d_x / 2 + u_x)
@@ -532,7 +541,7 @@ static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const W
     float* parts = reinterpret_cast<float*>(const_cast<char*>(ws) + L.parts_off);
     const int32_t* split_first = reinterpret_cast<const int32_t*>(ws + L.splitb_off);
     const dim3 grid((unsigned)L.max_bitems);
-    const int dim = g->desc.dim, K = g->desc.order;
+    const int dim = g->desc.dim, K = g->kord;
     float* gr = g->bufs.grad;
     const int acc = accumulate ? 1 : 0;
 #define TG_BWD_CASE(D, KK)                                                                                   \
@@ -545,6 +554,7 @@ static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const W
         return hipGetLastError();                                                                            \
     }
     TG_BWD_CASE(3, 2) TG_BWD_CASE(3, 1) TG_BWD_CASE(3, 0) TG_BWD_CASE(2, 2) TG_BWD_CASE(2, 1) TG_BWD_CASE(2, 0)
+    TG_BWD_CASE(3, kOrderFull) TG_BWD_CASE(2, kOrderFull)
 #undef TG_BWD_CASE
     return hipErrorInvalidValue;
 }

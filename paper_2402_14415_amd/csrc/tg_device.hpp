@@ -21,9 +21,13 @@ template <int DIM> struct BrickEdge;
 template <> struct BrickEdge<3> { static constexpr int value = 8; };
 template <> struct BrickEdge<2> { static constexpr int value = 16; };
 
-// Coefficients per vertex: binom(DIM + K, K).
+// Kernel order code of order 2 with the full (dim x dim, row-major) Hessian stored.
+constexpr int kOrderFull = 3;
+
+// Coefficients per vertex: binom(DIM + K, K); 1 + DIM + DIM^2 for the full-Hessian layout.
 template <int DIM, int K> struct NumCoeffs {
-    static constexpr int value = DIM == 3 ? (K == 0 ? 1 : K == 1 ? 4 : 10) : (K == 0 ? 1 : K == 1 ? 3 : 6);
+    static constexpr int value = K == kOrderFull ? 1 + DIM + DIM * DIM
+                                 : DIM == 3 ? (K == 0 ? 1 : K == 1 ? 4 : 10) : (K == 0 ? 1 : K == 1 ? 3 : 6);
 };
 
 enum StorageKind { ST_F32 = 0, ST_BF16 = 1, ST_F16 = 2 };
@@ -180,6 +184,26 @@ __device__ __forceinline__ void taylor_eval(const float* c, const float* d, floa
             T = fmaf(c[1 + a], d[a], T);
             dT[a] = c[1 + a];
         }
+    } else if constexpr (K == kOrderFull) {
+        // c: f, g (DIM), H row-major (DIM x DIM); T = f + d.g + d.H d / 2 and
+        // grad T = g + (H + H^T) d / 2
+        float Hd[DIM], HTd[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            Hd[a] = 0.0f;
+            HTd[a] = 0.0f;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) {
+                Hd[a] = fmaf(c[1 + DIM + a * DIM + b], d[b], Hd[a]);
+                HTd[a] = fmaf(c[1 + DIM + b * DIM + a], d[b], HTd[a]);
+            }
+        }
+        T = c[0];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            T = fmaf(d[a], fmaf(0.5f, Hd[a], c[1 + a]), T);
+            dT[a] = c[1 + a] + 0.5f * (Hd[a] + HTd[a]);
+        }
     } else if constexpr (DIM == 3) {
         // c: f, gx, gy, gz, hxx, hxy, hxz, hyy, hyz, hzz
         const float Hx = fmaf(c[4], d[0], fmaf(c[5], d[1], c[6] * d[2]));
@@ -206,8 +230,17 @@ template <int DIM, int K>
 __device__ __forceinline__ void taylor_hess(const float* c, float* H)
 {
     constexpr int NH = DIM == 3 ? 6 : 3;
+    if constexpr (K == kOrderFull) {
+        // the symmetric part (H + H^T) / 2: only it enters the polynomial
+        int k = 0;
 #pragma unroll
-    for (int k = 0; k < NH; ++k) H[k] = (K == 2) ? c[1 + DIM + k] : 0.0f;
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int b = a; b < DIM; ++b, ++k) H[k] = 0.5f * (c[1 + DIM + a * DIM + b] + c[1 + DIM + b * DIM + a]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NH; ++k) H[k] = (K == 2) ? c[1 + DIM + k] : 0.0f;
+    }
 }
 
 // Per-axis interpolation factors of a located query: W[a][b] is the weight factor of the

@@ -304,7 +304,7 @@ static hipError_t dispatch(const tg_grid* g, const char* ws, const WsLayout& L, 
     const int32_t* meta = reinterpret_cast<const int32_t*>(ws + L.meta_off);
     const dim3 grid((unsigned)L.fwd_blocks), block(kThreads);
     const void* cf = g->bufs.coeffs;
-    const int dim = g->desc.dim, K = g->desc.order, st = g->desc.storage;
+    const int dim = g->desc.dim, K = g->kord, st = g->desc.storage;
 #define TG_FWD_CASE(D, KK, ST)                                                                          \
     if (dim == D && K == KK && st == ST) {                                                              \
         hipLaunchKernelGGL((k_forward<D, KK, ST, MODE>), grid, block, 0, s, g->geom, items, meta, cf, rec, f,       \
@@ -313,6 +313,7 @@ static hipError_t dispatch(const tg_grid* g, const char* ws, const WsLayout& L, 
     }
 #define TG_FWD_ST(D, KK) TG_FWD_CASE(D, KK, ST_F32) TG_FWD_CASE(D, KK, ST_BF16) TG_FWD_CASE(D, KK, ST_F16)
     TG_FWD_ST(3, 2) TG_FWD_ST(3, 1) TG_FWD_ST(3, 0) TG_FWD_ST(2, 2) TG_FWD_ST(2, 1) TG_FWD_ST(2, 0)
+    TG_FWD_ST(3, kOrderFull) TG_FWD_ST(2, kOrderFull)
 #undef TG_FWD_ST
 #undef TG_FWD_CASE
     return hipErrorInvalidValue;

@@ -13,6 +13,7 @@ struct tg_grid {
     tg_grid_buffers bufs;
     tg::Geom geom;
     int32_t C;          // coefficients per vertex
+    int32_t kord;       // kernel order code: the order, or kOrderFull for the full Hessian
     int64_t nvert;      // vertices
     int64_t nbricks;    // vertex bricks (launch size of the forward and backward)
     // last sort written by tg_sort_queries (or taken over by tg_share_sort) on this handle;

@@ -115,6 +115,7 @@ hipError_t launch_tv(const tg_grid* g, float weight, double* tv_out, float* grad
                            acc, scale, partials);                                                          \
     } else
     TG_TV_CASE(3, 10) TG_TV_CASE(3, 4) TG_TV_CASE(3, 1) TG_TV_CASE(2, 6) TG_TV_CASE(2, 3) TG_TV_CASE(2, 1)
+    TG_TV_CASE(3, 13) TG_TV_CASE(2, 7)
     {
         return hipErrorInvalidValue;
     }

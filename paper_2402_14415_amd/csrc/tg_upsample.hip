@@ -15,13 +15,13 @@ namespace tg {
 
 template <int DIM, int KC>
 __global__ __launch_bounds__(kThreads) void k_upsample(Geom gc, Geom gf, const float* __restrict__ coarse,
-                                                       int cf, int st_f, float* __restrict__ master,
+                                                       int cf, int ffull, int st_f, float* __restrict__ master,
                                                        void* __restrict__ coeffs, float* __restrict__ mom1,
                                                        float* __restrict__ mom2, int64_t nvert)
 {
     constexpr int CC = NumCoeffs<DIM, KC>::value;
     constexpr int NH = DIM == 3 ? 6 : 3;
-    constexpr int NOUT = 1 + DIM + NH;
+    constexpr int NOUT = 1 + DIM + DIM * DIM;
     // A block's kThreads consecutive fine vertices are kThreads * cf consecutive words of every
     // output array: the results are staged in LDS and written as contiguous runs.
     __shared__ float sh[kThreads * NOUT];
@@ -82,13 +82,26 @@ __global__ __launch_bounds__(kThreads) void k_upsample(Geom gc, Geom gf, const f
                     }
                 }
             }
-            // stored order: value, gradient, Hessian xx, xy(, xz), yy(, yz, zz); first cf of them
-            float out[1 + DIM + NH];
+            // stored order: value, gradient, Hessian xx, xy(, xz), yy(, yz, zz), first cf of
+            // them; or, for the full layout, value, gradient, Hessian row-major
+            float out[1 + DIM + DIM * DIM];
             out[0] = f;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) out[1 + a] = gr[a];
+            if (ffull) {
 #pragma unroll
-            for (int k = 0; k < NH; ++k) out[1 + DIM + k] = hf[k];
+                for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                    for (int b = 0; b < DIM; ++b) {
+                        const int lo = a < b ? a : b, hi = a < b ? b : a;
+                        // index of (lo, hi) in the packed order
+                        const int k = DIM == 3 ? (lo == 0 ? hi : (lo == 1 ? 2 + hi : 5)) : (lo == 0 ? hi : 2);
+                        out[1 + DIM + a * DIM + b] = hf[k];
+                    }
+            } else {
+#pragma unroll
+                for (int k = 0; k < NH; ++k) out[1 + DIM + k] = hf[k];
+            }
 #pragma unroll
             for (int k = 0; k < NOUT; ++k)
                 if (k < cf) sh[threadIdx.x * cf + k] = out[k];
@@ -110,7 +123,8 @@ __global__ __launch_bounds__(kThreads) void k_upsample(Geom gc, Geom gf, const f
 
 hipError_t launch_upsample(const tg_grid* coarse, tg_grid* fine, hipStream_t s)
 {
-    const int dim = coarse->desc.dim, kc = coarse->desc.order;
+    const int dim = coarse->desc.dim, kc = coarse->kord;
+    const int ffull = fine->kord == kOrderFull ? 1 : 0;
     const int64_t nvert = fine->nvert;
     const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nvert + kThreads - 1) / kThreads, 65536));
     const tg_grid_buffers& b = fine->bufs;
@@ -118,11 +132,13 @@ hipError_t launch_upsample(const tg_grid* coarse, tg_grid* fine, hipStream_t s)
 #define TG_UP_CASE(D, K)                                                                                    \
     if (dim == D && kc == K) {                                                                              \
         hipLaunchKernelGGL((k_upsample<D, K>), dim3(nb), dim3(kThreads), 0, s, coarse->geom, fine->geom,     \
-                           coarse->bufs.master, fine->C, fine->desc.storage, b.master, cfs, b.adam_m, b.adam_v, \
+                           coarse->bufs.master, fine->C, ffull, fine->desc.storage, b.master, cfs, b.adam_m,      \
+                           b.adam_v,                                                                        \
                            nvert);                                                                          \
         return hipGetLastError();                                                                           \
     }
     TG_UP_CASE(3, 2) TG_UP_CASE(3, 1) TG_UP_CASE(3, 0) TG_UP_CASE(2, 2) TG_UP_CASE(2, 1) TG_UP_CASE(2, 0)
+    TG_UP_CASE(3, kOrderFull) TG_UP_CASE(2, kOrderFull)
 #undef TG_UP_CASE
     return hipErrorInvalidValue;
 }

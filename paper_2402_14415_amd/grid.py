@@ -64,7 +64,8 @@ class TaylorGrid:
       adam_m, adam_v  FP32 Adam moments
     """
 
-    def __init__(self, dim, res, order, lo, hi, storage="f32", device="cuda", coeffs=None, optimizer=True):
+    def __init__(self, dim, res, order, lo, hi, storage="f32", device="cuda", coeffs=None, optimizer=True,
+                 hessian="symmetric"):
         self.dim = int(dim)
         res = [int(r) for r in (res if hasattr(res, "__len__") else [res] * self.dim)]
         self.res = tuple(res[: self.dim])
@@ -78,7 +79,10 @@ class TaylorGrid:
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        self.C = coeffs_per_vertex(self.dim, self.order)
+        if hessian not in ("symmetric", "full"):
+            raise ValueError(f"unknown Hessian layout {hessian!r}")
+        self.hessian = hessian
+        self.C = 1 + self.dim + self.dim * self.dim if hessian == "full" else coeffs_per_vertex(self.dim, self.order)
         self.shape = tuple(reversed(self.res)) + (self.C,)
 
         if coeffs is not None:
@@ -99,6 +103,7 @@ class TaylorGrid:
         desc.dim = self.dim
         desc.order = self.order
         desc.storage = st
+        desc.hessian = _lib.TG_HESSIAN_FULL if hessian == "full" else _lib.TG_HESSIAN_SYMMETRIC
         for a in range(3):
             desc.res[a] = self.res[a] if a < self.dim else 1
             desc.lo[a] = self.lo[a] if a < self.dim else 0.0

@@ -295,3 +295,33 @@ def test_quality_validation():
     assert L().tg_chamfer(fake, 0, fake, 5, fake, fake, red, None) == 1
     assert L().tg_chamfer(fake, 5, None, 5, fake, fake, red, None) == 1
     assert L().tg_chamfer(fake, 5, fake, 5, fake, fake, red - 1, None) == 4
+
+
+def test_full_hessian_layout_validation():
+    """The full-Hessian layout: order 2 only, a known layout code, 13 coefficients in 3D (a
+    larger workspace), and the serving call refuses it."""
+    b = _lib.GridBuffers()
+    b.coeffs = b.master = 0x1000
+    d = _desc(order=2)
+    d.hessian = 1
+    st, h = _create(d, b)
+    assert st == 0
+    d2 = _desc(order=2)
+    st, hs = _create(d2, b)
+    assert st == 0
+    try:
+        assert L().tg_workspace_bytes(h, 1 << 16) > L().tg_workspace_bytes(hs, 1 << 16)
+        req = (_lib.Request * 1)()
+        req[0].grid = 0
+        req[0].n = 10
+        req[0].q = req[0].sdf = 0x100000
+        grids = (ctypes.c_void_p * 1)(h.value)
+        assert L().tg_query(grids, 1, req, 1, None) == 2  # TG_ERR_UNSUPPORTED
+    finally:
+        assert L().tg_destroy(h) == 0
+        assert L().tg_destroy(hs) == 0
+    for order, layout in ((1, 1), (0, 1), (2, 2), (2, -1)):
+        d = _desc(order=order)
+        d.hessian = layout
+        st, _ = _create(d, b)
+        assert st == 1, (order, layout)
