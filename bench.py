@@ -30,6 +30,7 @@ from paper_2402_14415_amd import synth  # noqa: E402  (input generators only)
 
 METRIC = "queries/s fwd+bwd at 128^3 K=2 (and % HBM peak); served query p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3  # dense FP32 vector
 COPY_REF_BYTES = 256 << 20
 RES = 128
 ORDER = 2
@@ -314,7 +315,12 @@ def radiance_bench(dev, steps=10, warmup=3, n_batches=2, n_rays=4096, n_samples=
     torch.cuda.synchronize()
     stage = lambda k: float(np.median([ev[i][k].elapsed_time(ev[i][k + 1]) * 1e3 for i in range(warmup, warmup + steps)]))
     step_us = float(np.median([ev[i][0].elapsed_time(ev[i][3]) * 1e3 for i in range(warmup, warmup + steps)]))
+    comp_us = stage(1)
+    comp_bytes = n * 36 + n_rays * 24  # f, 3 colours, delta in; g_f, 3 g_c out; target in, colour out
     return {"workload": f"radiance_{res}^3_density_K2_relu_colour_3xK1", "rays_per_step": n_rays,
+            "composite_kernel": {"us": comp_us, "algorithmic_bytes": comp_bytes,
+                                 "GBs": comp_bytes / (comp_us * 1e-6) / 1e9,
+                                 "frac": comp_bytes / (comp_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
             "samples_per_ray": n_samples, "step_us": step_us, "rays_per_s": n_rays / (step_us * 1e-6),
             "samples_per_s": n / (step_us * 1e-6),
             "stage_us": {"sort_and_evaluate_4_grids": stage(0), "composite_loss_adjoint": stage(1),
@@ -452,12 +458,18 @@ def quality_bench(dev, dev_batches, scene, fit_steps=400, n_points=100_000, n_su
     _, ch_us = timed(lambda: quality.chamfer_into(mv, surf, out, red))
     ch = [float(x) for x in out.cpu()]
     pairs = 2 * mv.shape[0] * surf.shape[0]
+    mesh_bytes = 2 * RES ** 3 * 4 + total * 36  # the lattice read by both passes, the triangles written
     return {"workload": f"quality_of_sdf_fit_{RES}^3", "fit_steps": fit_steps, "fit_seconds": fit_s,
             "fit_loss": fit_loss, "iou": iou, "iou_points": n_points,
             "triangles": total, "chamfer": ch[0], "chamfer_mesh_to_surface": ch[1], "chamfer_surface_to_mesh": ch[2],
             "surface_points": n_surface,
             "us": {"sort_and_forward": fwd_us, "iou_counts": iou_us, "mesh": mesh_us, "chamfer": ch_us},
-            "chamfer_distance_evals_per_s": pairs / (ch_us * 1e-6)}
+            "chamfer_distance_evals_per_s": pairs / (ch_us * 1e-6),
+            "mesh_kernel": {"algorithmic_bytes": mesh_bytes, "GBs": mesh_bytes / (mesh_us * 1e-6) / 1e9,
+                            "frac": mesh_bytes / (mesh_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
+            # a pair costs 3 subtractions, 2 FMAs, 1 multiply and 1 min: 9 FP32 operations
+            "chamfer_kernel": {"bound": "alu", "TFLOPs": 9 * pairs / (ch_us * 1e-6) / 1e12,
+                               "peak": FP32_PEAK_TFLOPS, "frac": 9 * pairs / (ch_us * 1e-6) / 1e12 / FP32_PEAK_TFLOPS}}
 
 
 def order_scaling_bench(dev, dev_batches, steps=10, warmup=3):

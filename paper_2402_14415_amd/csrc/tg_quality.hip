@@ -27,12 +27,14 @@ struct Lattice {
     float lo[3], h[3];
 };
 
+// Cell coordinates of cell c (x fastest); cells number below 2^28, so 32-bit division is exact.
 __device__ __forceinline__ void cell_of(const Lattice& L, int64_t c, int& i, int& j, int& k)
 {
-    const int cx = L.nx - 1, cy = L.ny - 1;
-    i = (int)(c % cx);
-    j = (int)((c / cx) % cy);
-    k = (int)(c / ((int64_t)cx * cy));
+    const uint32_t cc = (uint32_t)c, cx = (uint32_t)(L.nx - 1), cy = (uint32_t)(L.ny - 1);
+    const uint32_t row = cc / cx;
+    i = (int)(cc - row * cx);
+    k = (int)(row / cy);
+    j = (int)(row - (uint32_t)k * cy);
 }
 
 __device__ __forceinline__ void cell_values(const Lattice& L, const float* __restrict__ v, int i, int j, int k,
@@ -299,36 +301,59 @@ hipError_t launch_iou(int64_t n, const float* f, const float* d, int64_t* counts
 
 // ------------------------------------------------------------------ Chamfer
 constexpr int kNnThreads = 128;
-constexpr int kNnTile = 2048;  // destination points per LDS tile
+constexpr int kNnPerThread = 4;   // source points per thread (each staged point is read once for all)
+constexpr int kNnTile = 2048;     // destination points per LDS tile (a multiple of 4)
 
 // partials[block] = sum over this block's source points of the distance to the nearest
-// destination point (brute force, destination tiles staged in LDS as x, y, z arrays)
+// destination point.  Brute force: destination tiles are staged in LDS as x, y, z arrays
+// (padded to a multiple of 4 with points at infinity), read 4 points at a time, and every
+// thread compares each with its kNnPerThread source points held in registers.
 __global__ __launch_bounds__(kNnThreads) void k_nn_sum(const float* __restrict__ src, int64_t ns,
                                                       const float* __restrict__ dst, int64_t nd,
                                                       double* __restrict__ partials)
 {
-    __shared__ float tx[kNnTile], ty[kNnTile], tz[kNnTile];
+    __shared__ __align__(16) float tx[kNnTile], ty[kNnTile], tz[kNnTile];
+    constexpr int CHUNK = kNnThreads * kNnPerThread;
     double acc = 0.0;
-    for (int64_t s0 = (int64_t)blockIdx.x * kNnThreads; s0 < ns; s0 += (int64_t)gridDim.x * kNnThreads) {
-        const int64_t si = s0 + threadIdx.x;
-        const bool ok = si < ns;
-        const float px = ok ? src[3 * si] : 0.0f, py = ok ? src[3 * si + 1] : 0.0f, pz = ok ? src[3 * si + 2] : 0.0f;
-        float best = INFINITY;
+    for (int64_t s0 = (int64_t)blockIdx.x * CHUNK; s0 < ns; s0 += (int64_t)gridDim.x * CHUNK) {
+        float px[kNnPerThread], py[kNnPerThread], pz[kNnPerThread], best[kNnPerThread];
+#pragma unroll
+        for (int r = 0; r < kNnPerThread; ++r) {
+            const int64_t si = s0 + threadIdx.x + (int64_t)r * kNnThreads;
+            const bool ok = si < ns;
+            px[r] = ok ? src[3 * si] : 0.0f;
+            py[r] = ok ? src[3 * si + 1] : 0.0f;
+            pz[r] = ok ? src[3 * si + 2] : 0.0f;
+            best[r] = INFINITY;
+        }
         for (int64_t d0 = 0; d0 < nd; d0 += kNnTile) {
             const int cnt = (int)min((int64_t)kNnTile, nd - d0);
+            const int cnt4 = (cnt + 3) & ~3;
             __syncthreads();
-            for (int q = threadIdx.x; q < cnt; q += kNnThreads) {
-                tx[q] = dst[3 * (d0 + q)];
-                ty[q] = dst[3 * (d0 + q) + 1];
-                tz[q] = dst[3 * (d0 + q) + 2];
+            for (int q = threadIdx.x; q < cnt4; q += kNnThreads) {
+                const bool ok = q < cnt;
+                tx[q] = ok ? dst[3 * (d0 + q)] : INFINITY;
+                ty[q] = ok ? dst[3 * (d0 + q) + 1] : INFINITY;
+                tz[q] = ok ? dst[3 * (d0 + q) + 2] : INFINITY;
             }
             __syncthreads();
-            for (int q = 0; q < cnt; ++q) {
-                const float dx = tx[q] - px, dy = ty[q] - py, dz = tz[q] - pz;
-                best = fminf(best, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+            for (int q = 0; q < cnt4; q += 4) {
+                const float4 X = *reinterpret_cast<const float4*>(tx + q);
+                const float4 Y = *reinterpret_cast<const float4*>(ty + q);
+                const float4 Z = *reinterpret_cast<const float4*>(tz + q);
+                const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w}, zs[4] = {Z.x, Z.y, Z.z, Z.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int r = 0; r < kNnPerThread; ++r) {
+                        const float dx = xs[u] - px[r], dy = ys[u] - py[r], dz = zs[u] - pz[r];
+                        best[r] = fminf(best[r], fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+                    }
             }
         }
-        if (ok) acc += (double)sqrtf(best);
+#pragma unroll
+        for (int r = 0; r < kNnPerThread; ++r)
+            if (s0 + threadIdx.x + (int64_t)r * kNnThreads < ns) acc += (double)sqrtf(best[r]);
     }
     const double tot = block_sum_f64<kNnThreads>(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -351,8 +376,9 @@ hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb
                           hipStream_t s)
 {
     const int half = kMaxReduceBlocks / 2;
-    const unsigned ga = (unsigned)std::min<int64_t>((na + kNnThreads - 1) / kNnThreads, half);
-    const unsigned gb = (unsigned)std::min<int64_t>((nb + kNnThreads - 1) / kNnThreads, half);
+    constexpr int CHUNK = kNnThreads * kNnPerThread;
+    const unsigned ga = (unsigned)std::min<int64_t>((na + CHUNK - 1) / CHUNK, half);
+    const unsigned gb = (unsigned)std::min<int64_t>((nb + CHUNK - 1) / CHUNK, half);
     hipLaunchKernelGGL(k_nn_sum, dim3(ga), dim3(kNnThreads), 0, s, a, na, b, nb, partials);
     hipLaunchKernelGGL(k_nn_sum, dim3(gb), dim3(kNnThreads), 0, s, b, nb, a, na, partials + half);
     hipLaunchKernelGGL(k_chamfer_finish, dim3(1), dim3(64), 0, s, partials, (int)ga, na, partials + half, (int)gb, nb,
