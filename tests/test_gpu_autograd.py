@@ -23,12 +23,14 @@ def test_autograd_matches_oracle_adjoints():
     n = 20000
     q64 = nudge_off_faces(rng.uniform(-1.1, 1.1, size=(n, 3)), grid.lo, grid.hi, grid.res)
     q = torch.tensor(q64, dtype=torch.float32, device=DEV, requires_grad=True)
-    a = torch.randn(n, device=DEV)
-    b = torch.randn(n, 3, device=DEV)
+    a64 = rng.normal(size=n).astype(np.float32).astype(np.float64)  # seeded upstream weights
+    b64 = rng.normal(size=(n, 3)).astype(np.float32).astype(np.float64)
+    a = torch.tensor(a64, dtype=torch.float32, device=DEV)
+    b = torch.tensor(b64, dtype=torch.float32, device=DEV)
     f, g = taylor_grid(grid, q)
     ((f * a).sum() + (g * b).sum()).backward()
     torch.cuda.synchronize()
-    ref_dC, ref_dq = oracle.backward(geometry(grid), C32.astype(np.float64), q64, to_np(a), to_np(b), want_dq=True)
+    ref_dC, ref_dq = oracle.backward(geometry(grid), C32.astype(np.float64), q64, a64, b64, want_dq=True)
     assert nerr(to_np(grid.master.grad).reshape(-1), ref_dC.reshape(-1)) <= TOL_GRAD
     assert nerr_cols(to_np(q.grad), ref_dq) <= TOL_GRAD
 
