@@ -68,6 +68,12 @@ typedef struct {
     int32_t hessian; /* order 2 only: TG_HESSIAN_SYMMETRIC (default, 0) stores the dim(dim+1)/2
                         distinct entries; TG_HESSIAN_FULL stores all dim^2 entries (row-major),
                         1 + dim + dim^2 coefficients per vertex (13 in 3D) */
+    int32_t channels; /* 1 (default 0 means 1), or 3 with order 1: a three-channel field such as
+                         the radiance form's colour (Sec. 3.3), each vertex storing the three
+                         channels' series one after the other (3 (1 + dim) coefficients, 12 in
+                         3D); tg_forward writes f [3][n] (grad_f must be NULL) and tg_backward /
+                         tg_backward_adam take g_f [3][n] (g_grad and dq must be NULL).  The SDF
+                         calls, tg_query and tg_upsample refuse it (TG_ERR_UNSUPPORTED). */
 } tg_grid_desc;
 
 #define TG_HESSIAN_SYMMETRIC 0

@@ -28,7 +28,7 @@ TG_QUERY_MAX_GRIDS = 16
 class GridDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("res", ctypes.c_int32 * 3), ("order", ctypes.c_int32),
                 ("lo", ctypes.c_float * 3), ("hi", ctypes.c_float * 3), ("storage", ctypes.c_int32),
-                ("hessian", ctypes.c_int32)]
+                ("hessian", ctypes.c_int32), ("channels", ctypes.c_int32)]
 
 
 class GridBuffers(ctypes.Structure):

@@ -189,7 +189,13 @@ tg_status tg_create(const tg_grid_desc* desc, const tg_grid_buffers* bufs, tg_gr
         return fail(TG_ERR_INVALID_ARG, "tg_create: unknown Hessian layout %d", d.hessian);
     const bool full = d.hessian == TG_HESSIAN_FULL;
     if (full && d.order != 2) return fail(TG_ERR_INVALID_ARG, "tg_create: the full-Hessian layout needs order 2");
-    const int32_t C = full ? 1 + d.dim + d.dim * d.dim : tg_coeffs_per_vertex(d.dim, d.order);
+    const int32_t nch = d.channels == 0 ? 1 : d.channels;
+    if (nch != 1 && nch != 3) return fail(TG_ERR_INVALID_ARG, "tg_create: channels must be 1 or 3 (got %d)", d.channels);
+    const bool rgb = nch == 3;
+    if (rgb && (d.order != 1 || full))
+        return fail(TG_ERR_INVALID_ARG, "tg_create: three channels need order 1 and the symmetric layout");
+    const int32_t C = full ? 1 + d.dim + d.dim * d.dim
+                           : (rgb ? 3 * (1 + d.dim) : tg_coeffs_per_vertex(d.dim, d.order));
     if (nvert * C > ((int64_t)1 << 40)) return fail(TG_ERR_CAPACITY, "tg_create: grid too large");
     tg_grid_buffers b;
     memset(&b, 0, sizeof(b));
@@ -203,7 +209,7 @@ tg_status tg_create(const tg_grid_desc* desc, const tg_grid_buffers* bufs, tg_gr
     g->desc = d;
     g->bufs = b;
     g->C = C;
-    g->kord = full ? tg::kOrderFull : d.order;
+    g->kord = full ? tg::kOrderFull : (rgb ? tg::kOrderRGB1 : d.order);
     g->nvert = nvert;
     constexpr int B3 = tg::BrickEdge<3>::value, B2 = tg::BrickEdge<2>::value;
     const int B = d.dim == 3 ? B3 : B2;
@@ -341,6 +347,8 @@ tg_status tg_forward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t 
     if (st != TG_OK) return st;
     if (n > 0 && !f) return fail(TG_ERR_INVALID_ARG, "tg_forward: f is NULL");
     if (!grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_forward: grid has no coeffs buffer");
+    if (grid->kord == tg::kOrderRGB1 && grad_f)
+        return fail(TG_ERR_UNSUPPORTED, "tg_forward: a three-channel grid has no grad_f output");
     st = check_sorted("tg_forward", grid, q, n, ws);
     if (st != TG_OK) return st;
     if (n == 0) return ok();
@@ -348,6 +356,23 @@ tg_status tg_forward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t 
     return device_status(tg::launch_forward(grid, n, static_cast<const char*>(ws), L, f, grad_f,
                                             static_cast<hipStream_t>(stream)),
                          "tg_forward");
+}
+
+// A three-channel grid's adjoint takes g_f [3][n] and nothing else.
+static tg_status check_rgb_upstream(const char* fn, const tg_grid* grid, int64_t n, const float* g_f,
+                                    const float* g_grad, const float* dq)
+{
+    if (grid->kord != tg::kOrderRGB1) return ok();
+    if (g_grad || dq) return fail(TG_ERR_UNSUPPORTED, "%s: a three-channel grid takes neither g_grad nor dq", fn);
+    if (n > 0 && !g_f) return fail(TG_ERR_INVALID_ARG, "%s: a three-channel grid needs g_f [3][n]", fn);
+    return ok();
+}
+
+static tg_status refuse_rgb(const char* fn, const tg_grid* grid)
+{
+    if (grid && grid->kord == tg::kOrderRGB1)
+        return fail(TG_ERR_UNSUPPORTED, "%s: not defined for a three-channel grid", fn);
+    return ok();
 }
 
 tg_status tg_backward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes, const float* g_f,
@@ -359,6 +384,8 @@ tg_status tg_backward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t
     if (flags & ~TG_BWD_ACCUMULATE) return fail(TG_ERR_INVALID_ARG, "tg_backward: unknown flags 0x%x", flags);
     if (!grid->bufs.grad) return fail(TG_ERR_INVALID_ARG, "tg_backward: grid has no grad buffer");
     if (dq && !grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_backward: dq needs the coeffs buffer");
+    st = check_rgb_upstream("tg_backward", grid, n, g_f, g_grad, dq);
+    if (st != TG_OK) return st;
     st = check_sorted("tg_backward", grid, q, n, ws);
     if (st != TG_OK) return st;
     const bool acc = (flags & TG_BWD_ACCUMULATE) != 0;
@@ -389,6 +416,8 @@ tg_status tg_forward_sdf_loss(tg_grid* grid, const float* q, int64_t n, void* ws
     if (!loss) return fail(TG_ERR_INVALID_ARG, "tg_forward_sdf_loss: loss is NULL");
     if (!std::isfinite(eik_weight)) return fail(TG_ERR_INVALID_ARG, "tg_forward_sdf_loss: eik_weight is not finite");
     st = check_surface_k("tg_forward_sdf_loss", surface_k);
+    if (st != TG_OK) return st;
+    st = refuse_rgb("tg_forward_sdf_loss", grid);
     if (st != TG_OK) return st;
     if (!grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_forward_sdf_loss: grid has no coeffs buffer");
     st = check_sorted("tg_forward_sdf_loss", grid, q, n, ws);
@@ -424,6 +453,8 @@ tg_status tg_backward_adam(tg_grid* grid, const float* q, int64_t n, void* ws, s
     st = check_adam("tg_backward_adam", grid, params);
     if (st != TG_OK) return st;
     if (flags & ~TG_BWD_ADD_GRAD) return fail(TG_ERR_INVALID_ARG, "tg_backward_adam: unknown flags 0x%x", flags);
+    st = check_rgb_upstream("tg_backward_adam", grid, n, g_f, g_grad, nullptr);
+    if (st != TG_OK) return st;
     const bool add = (flags & TG_BWD_ADD_GRAD) != 0;
     if (add && !grid->bufs.grad) return fail(TG_ERR_INVALID_ARG, "tg_backward_adam: TG_BWD_ADD_GRAD needs bufs.grad");
     st = check_sorted("tg_backward_adam", grid, q, n, ws);
@@ -448,6 +479,8 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
     const float eik_weight = obj->eik_weight, surface_k = obj->surface_k, tv_weight = obj->tv_weight;
     if (!std::isfinite(eik_weight)) return fail(TG_ERR_INVALID_ARG, "tg_train_step: eik_weight is not finite");
     st = check_surface_k("tg_train_step", surface_k);
+    if (st != TG_OK) return st;
+    st = refuse_rgb("tg_train_step", grid);
     if (st != TG_OK) return st;
     if (!std::isfinite(tv_weight)) return fail(TG_ERR_INVALID_ARG, "tg_train_step: tv_weight is not finite");
     const bool tv = tv_weight != 0.0f;
@@ -539,6 +572,8 @@ tg_status tg_upsample(const tg_grid* coarse, tg_grid* fine, void* stream)
     bool same = c.dim == f.dim;
     for (int k = 0; same && k < c.dim; ++k) same = c.lo[k] == f.lo[k] && c.hi[k] == f.hi[k];
     if (!same) return fail(TG_ERR_INVALID_ARG, "tg_upsample: the grids differ in dim, lo or hi");
+    if (refuse_rgb("tg_upsample", coarse) != TG_OK || refuse_rgb("tg_upsample", fine) != TG_OK)
+        return TG_ERR_UNSUPPORTED;
     if (!coarse->bufs.master) return fail(TG_ERR_INVALID_ARG, "tg_upsample: the coarse grid has no master buffer");
     if (!fine->bufs.master) return fail(TG_ERR_INVALID_ARG, "tg_upsample: the fine grid has no master buffer");
     if (f.storage != TG_F32 && !fine->bufs.coeffs)
@@ -677,6 +712,8 @@ tg_status tg_query(const tg_grid* const* grids, int32_t n_grids, const tg_reques
             return fail(TG_ERR_INVALID_ARG, "tg_query: grid %d is NULL or has no coeffs", k);
         if (grids[k]->kord == tg::kOrderFull)
             return fail(TG_ERR_UNSUPPORTED, "tg_query: grid %d stores the full Hessian (serve the symmetric layout)", k);
+        if (grids[k]->kord == tg::kOrderRGB1)
+            return fail(TG_ERR_UNSUPPORTED, "tg_query: grid %d has three channels (serving answers SDF queries)", k);
     }
     for (int32_t i = 0; i < n_reqs; ++i) {
         const tg_request& r = reqs[i];

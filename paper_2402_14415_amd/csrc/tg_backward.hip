@@ -198,7 +198,8 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
                                                                  const float* __restrict__ gf,
                                                                  const float* __restrict__ gg,
                                                                  const float4* __restrict__ urec,
-                                                                 float* __restrict__ grad, int accumulate, AdamBuf AB)
+                                                                 float* __restrict__ grad, int accumulate, AdamBuf AB,
+                                                                 int64_t nq)
 {
     using S = BwdShape<DIM>;
     constexpr int B = S::B, NOWN = S::NOWN, NCELL = S::NCELL, NRUN = S::NRUN, PER = S::PER, NBIN = S::NBIN;
@@ -321,6 +322,15 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
                     sg[a] = L[a].clamped ? 0.0f : ugg[a];
                     t[a] = L[a].t;
                     c[a] = min(max(L[a].cell - base[a] + 1, 0), B);
+                }
+                if constexpr (K == kOrderRGB1) {
+                    // three channels' upstream values (g_f is [3][nq]); no gradient terms: the
+                    // slots of the gradient upstream carry channels 1 and 2
+                    const int32_t idx = (tag & kRecSecondary) ? __float_as_int(rec[prim].w) : tag;
+                    ugf = gf[idx];
+                    sg[0] = gf[nq + idx];
+                    sg[1] = gf[2 * nq + idx];
+                    sg[2] = 0.0f;
                 }
                 my_cell[u] = rel_cell<DIM>(c);
                 my_t[u] = make_float4(t[0], t[1], t[2], ugf);
@@ -448,14 +458,22 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
                 dw[0] = sa[0] * fa[1];
                 dw[1] = sa[1] * fa[0];
             }
-            float s = E0.w * w;
-            float uu[DIM];
+            if constexpr (K == kOrderRGB1) {
+                // each channel is an order-1 series with upstream value only
+                const float up[kRGB] = {E0.w, sg[0], sg[1]};
+                const float zero[DIM] = {};
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                s = fmaf(sg[a], dw[a], s);
-                uu[a] = w * sg[a];
+                for (int ch = 0; ch < kRGB; ++ch) accumulate_corner<DIM, 1>(d, up[ch] * w, zero, acc + ch * (1 + DIM));
+            } else {
+                float s = E0.w * w;
+                float uu[DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    s = fmaf(sg[a], dw[a], s);
+                    uu[a] = w * sg[a];
+                }
+                accumulate_corner<DIM, K>(d, s, uu, acc);
             }
-            accumulate_corner<DIM, K>(d, s, uu, acc);
         }
     }
 
@@ -533,7 +551,7 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward_merge(Geom g, 
 template <int AD>
 static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const WsLayout& L, const float* g_f,
                                        const float* g_grad, const float4* urec, bool accumulate, const AdamBuf& AB,
-                                       hipStream_t s)
+                                       hipStream_t s, int64_t nq)
 {
     const float4* rec = reinterpret_cast<const float4*>(ws + L.rec_off);
     const int4* items = reinterpret_cast<const int4*>(ws + L.bitems_off);
@@ -548,13 +566,13 @@ static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const W
     if (dim == D && K == KK) {                                                                               \
         const dim3 block(BwdShape<D>::NOWN);                                                                 \
         hipLaunchKernelGGL((k_backward<D, KK, AD>), grid, block, 0, s, g->geom, items, meta, L.max_bitems, parts, \
-                           rec, g_f, g_grad, urec, gr, acc, AB);                                             \
+                           rec, g_f, g_grad, urec, gr, acc, AB, nq);                                         \
         hipLaunchKernelGGL((k_backward_merge<D, KK, AD>), dim3((unsigned)L.merge_blocks), block, 0, s, g->geom, \
                            items, split_first, meta, parts, gr, acc, L.max_bitems, AB);                      \
         return hipGetLastError();                                                                            \
     }
     TG_BWD_CASE(3, 2) TG_BWD_CASE(3, 1) TG_BWD_CASE(3, 0) TG_BWD_CASE(2, 2) TG_BWD_CASE(2, 1) TG_BWD_CASE(2, 0)
-    TG_BWD_CASE(3, kOrderFull) TG_BWD_CASE(2, kOrderFull)
+    TG_BWD_CASE(3, kOrderFull) TG_BWD_CASE(2, kOrderFull) TG_BWD_CASE(3, kOrderRGB1) TG_BWD_CASE(2, kOrderRGB1)
 #undef TG_BWD_CASE
     return hipErrorInvalidValue;
 }
@@ -562,8 +580,7 @@ static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const W
 hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
                            const float* g_grad, bool accumulate, hipStream_t s)
 {
-    (void)n;
-    return launch_backward_impl<-1>(g, ws, L, g_f, g_grad, nullptr, accumulate, AdamBuf{}, s);
+    return launch_backward_impl<-1>(g, ws, L, g_f, g_grad, nullptr, accumulate, AdamBuf{}, s, n);
 }
 
 hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
@@ -571,7 +588,6 @@ hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, con
                                 bool record_order, const float* extra_grad)
 {
     const float4* urec = record_order ? reinterpret_cast<const float4*>(ws + L.urec_off) : nullptr;
-    (void)n;
     AdamBuf AB;
     AB.A = make_adam_args(p);
     AB.master = g->bufs.master;
@@ -582,9 +598,9 @@ hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, con
     AB.extra = extra_grad;
     hipError_t e;
     switch (g->desc.storage) {
-    case ST_F32: e = launch_backward_impl<ST_F32>(g, ws, L, g_f, g_grad, urec, false, AB, s); break;
-    case ST_BF16: e = launch_backward_impl<ST_BF16>(g, ws, L, g_f, g_grad, urec, false, AB, s); break;
-    default: e = launch_backward_impl<ST_F16>(g, ws, L, g_f, g_grad, urec, false, AB, s); break;
+    case ST_F32: e = launch_backward_impl<ST_F32>(g, ws, L, g_f, g_grad, urec, false, AB, s, n); break;
+    case ST_BF16: e = launch_backward_impl<ST_BF16>(g, ws, L, g_f, g_grad, urec, false, AB, s, n); break;
+    default: e = launch_backward_impl<ST_F16>(g, ws, L, g_f, g_grad, urec, false, AB, s, n); break;
     }
     if (e != hipSuccess || !grad_norm_sq) return e;
     return launch_sum_finish(AB.partials, L.max_bitems + L.merge_blocks, grad_norm_sq, s);

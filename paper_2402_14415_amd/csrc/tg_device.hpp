@@ -23,10 +23,16 @@ template <> struct BrickEdge<2> { static constexpr int value = 16; };
 
 // Kernel order code of order 2 with the full (dim x dim, row-major) Hessian stored.
 constexpr int kOrderFull = 3;
+// Kernel order code of a three-channel order-1 field (a colour): per vertex the three
+// channels' series one after the other, channel-major.
+constexpr int kOrderRGB1 = 4;
+constexpr int kRGB = 3;
 
-// Coefficients per vertex: binom(DIM + K, K); 1 + DIM + DIM^2 for the full-Hessian layout.
+// Coefficients per vertex: binom(DIM + K, K); 1 + DIM + DIM^2 for the full-Hessian layout;
+// 3 (1 + DIM) for the three-channel order-1 layout.
 template <int DIM, int K> struct NumCoeffs {
     static constexpr int value = K == kOrderFull ? 1 + DIM + DIM * DIM
+                                 : K == kOrderRGB1 ? kRGB * (1 + DIM)
                                  : DIM == 3 ? (K == 0 ? 1 : K == 1 ? 4 : 10) : (K == 0 ? 1 : K == 1 ? 3 : 6);
 };
 

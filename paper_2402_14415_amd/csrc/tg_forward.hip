@@ -29,6 +29,7 @@ struct LossArgs {
     float surf_k;       // Eq. 7's k (0: every sample weighted 1)
     float inv_n;
     int eik;            // eikonal term on (record mode; query mode tests gg)
+    int64_t nq;         // queries: the channel stride of a three-channel field's output
 };
 
 template <int DIM> __device__ __forceinline__ void brick_coords(const Geom& g, int32_t brick, int32_t* bc)
@@ -187,6 +188,34 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
         for (int a = 0; a < DIM; ++a) lc[a] = min(max(L[a].cell - v0[a], 0), nv[a] - 2);
         const AxisFactors<DIM> F = axis_factors<DIM>(g, L);
 
+        if constexpr (K == kOrderRGB1) {
+            // three order-1 channels: value only, written channel-major (f_out[ch][query])
+            if constexpr (MODE == MODE_FWD) {
+                float fc[kRGB] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int b = 0; b < (1 << DIM); ++b) {
+                    int lv = lc[0] + (b & 1) + NV1 * (lc[1] + ((b >> 1) & 1));
+                    if constexpr (DIM == 3) lv += NV1 * NV1 * (lc[2] + ((b >> 2) & 1));
+                    float c[C];
+                    lds_vertex<ST, C>(lds, lv, c);
+                    float d[DIM];
+                    corner_offset<DIM>(F, b, d);
+                    float w, dw[DIM];
+                    corner_weight<DIM>(F, b, w, dw);
+#pragma unroll
+                    for (int ch = 0; ch < kRGB; ++ch) {
+                        float T = c[ch * (1 + DIM)];
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) T = fmaf(c[ch * (1 + DIM) + 1 + a], d[a], T);
+                        fc[ch] = fmaf(w, T, fc[ch]);
+                    }
+                }
+#pragma unroll
+                for (int ch = 0; ch < kRGB; ++ch) f_out[ch * LA.nq + idx] = fc[ch];
+            }
+            continue;
+        }
+
         float f = 0.0f;
         float gr[DIM];
         float hf[NH];
@@ -314,6 +343,9 @@ static hipError_t dispatch(const tg_grid* g, const char* ws, const WsLayout& L, 
 #define TG_FWD_ST(D, KK) TG_FWD_CASE(D, KK, ST_F32) TG_FWD_CASE(D, KK, ST_BF16) TG_FWD_CASE(D, KK, ST_F16)
     TG_FWD_ST(3, 2) TG_FWD_ST(3, 1) TG_FWD_ST(3, 0) TG_FWD_ST(2, 2) TG_FWD_ST(2, 1) TG_FWD_ST(2, 0)
     TG_FWD_ST(3, kOrderFull) TG_FWD_ST(2, kOrderFull)
+    if constexpr (MODE == MODE_FWD) {
+        TG_FWD_ST(3, kOrderRGB1) TG_FWD_ST(2, kOrderRGB1)
+    }
 #undef TG_FWD_ST
 #undef TG_FWD_CASE
     return hipErrorInvalidValue;
@@ -322,8 +354,9 @@ static hipError_t dispatch(const tg_grid* g, const char* ws, const WsLayout& L, 
 hipError_t launch_forward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, float* f,
                           float* grad_f, hipStream_t s)
 {
-    (void)n;
-    return dispatch<MODE_FWD>(g, ws, L, f, grad_f, nullptr, nullptr, nullptr, s);
+    LossArgs LA{};
+    LA.nq = n;
+    return dispatch<MODE_FWD>(g, ws, L, f, grad_f, nullptr, nullptr, nullptr, s, LA);
 }
 
 hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* d,

@@ -115,7 +115,7 @@ hipError_t launch_tv(const tg_grid* g, float weight, double* tv_out, float* grad
                            acc, scale, partials);                                                          \
     } else
     TG_TV_CASE(3, 10) TG_TV_CASE(3, 4) TG_TV_CASE(3, 1) TG_TV_CASE(2, 6) TG_TV_CASE(2, 3) TG_TV_CASE(2, 1)
-    TG_TV_CASE(3, 13) TG_TV_CASE(2, 7)
+    TG_TV_CASE(3, 13) TG_TV_CASE(2, 7) TG_TV_CASE(3, 12) TG_TV_CASE(2, 9)
     {
         return hipErrorInvalidValue;
     }

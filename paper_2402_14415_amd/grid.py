@@ -65,7 +65,7 @@ class TaylorGrid:
     """
 
     def __init__(self, dim, res, order, lo, hi, storage="f32", device="cuda", coeffs=None, optimizer=True,
-                 hessian="symmetric"):
+                 hessian="symmetric", channels=1):
         self.dim = int(dim)
         res = [int(r) for r in (res if hasattr(res, "__len__") else [res] * self.dim)]
         self.res = tuple(res[: self.dim])
@@ -82,7 +82,15 @@ class TaylorGrid:
         if hessian not in ("symmetric", "full"):
             raise ValueError(f"unknown Hessian layout {hessian!r}")
         self.hessian = hessian
-        self.C = 1 + self.dim + self.dim * self.dim if hessian == "full" else coeffs_per_vertex(self.dim, self.order)
+        if channels not in (1, 3):
+            raise ValueError("channels must be 1 or 3")
+        self.channels = channels
+        if hessian == "full":
+            self.C = 1 + self.dim + self.dim * self.dim
+        elif channels == 3:
+            self.C = 3 * (1 + self.dim)
+        else:
+            self.C = coeffs_per_vertex(self.dim, self.order)
         self.shape = tuple(reversed(self.res)) + (self.C,)
 
         if coeffs is not None:
@@ -104,6 +112,7 @@ class TaylorGrid:
         desc.order = self.order
         desc.storage = st
         desc.hessian = _lib.TG_HESSIAN_FULL if hessian == "full" else _lib.TG_HESSIAN_SYMMETRIC
+        desc.channels = channels
         for a in range(3):
             desc.res[a] = self.res[a] if a < self.dim else 1
             desc.lo[a] = self.lo[a] if a < self.dim else 0.0
@@ -174,13 +183,18 @@ class TaylorGrid:
             self.sort(q, ws)
 
     def forward(self, q, ws, want_grad=True, out=None):
-        """f [n] and grad f [n, dim] (or None)."""
+        """f [n] and grad f [n, dim] (or None); a three-channel grid gives f [3, n] and no grad f."""
         n = self._q(q)
+        if self.channels == 3:
+            want_grad = False
         if out is None:
-            f = torch.empty(n, dtype=torch.float32, device=self.device)
+            f = torch.empty((n,) if self.channels == 1 else (3, n), dtype=torch.float32, device=self.device)
             g = torch.empty((n, self.dim), dtype=torch.float32, device=self.device) if want_grad else None
         else:
             f, g = out
+        _check_tensor("f", f, torch.float32, self.device, self.channels * n)
+        if g is not None:
+            _check_tensor("grad_f", g, torch.float32, self.device, n * self.dim)
         _lib.call("tg_forward", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _ptr(f), _ptr(g), _stream(self.device))
         return f, g
 
@@ -188,7 +202,7 @@ class TaylorGrid:
         """Writes (or accumulates) dL/dC into ``grad`` (or ``grad_out``); returns dq or None."""
         n = self._q(q)
         if g_f is not None:
-            _check_tensor("g_f", g_f, torch.float32, self.device, n)
+            _check_tensor("g_f", g_f, torch.float32, self.device, self.channels * n)
         if g_grad is not None:
             _check_tensor("g_grad", g_grad, torch.float32, self.device, n * self.dim)
         dq = None
@@ -245,7 +259,7 @@ class TaylorGrid:
         ``grad`` (e.g. the TV term's) to the adjoint before the update."""
         n = self._q(q)
         if g_f is not None:
-            _check_tensor("g_f", g_f, torch.float32, self.device, n)
+            _check_tensor("g_f", g_f, torch.float32, self.device, self.channels * n)
         if g_grad is not None:
             _check_tensor("g_grad", g_grad, torch.float32, self.device, n * self.dim)
         if grad_norm_sq is not None:

@@ -1,8 +1,9 @@
 """Radiance-field form (Sec. 3.3): a density TaylorGrid (K=2, ReLU) and a three-channel colour
-field (three K=1 TaylorGrids on the same vertices), rendered along rays by the Max optical
-model (Eq. 10) and fitted to observed ray colours by the photometric loss (Eq. 11).
+TaylorGrid (K=1, the three channels' series stored per vertex) on the same vertices, rendered
+along rays by the Max optical model (Eq. 10) and fitted to observed ray colours by the
+photometric loss (Eq. 11).
 
-Argument marshalling only: the bucketing (once per batch, shared by the four grids), the grid
+Argument marshalling only: the bucketing (once per batch, shared by both grids), the grid
 evaluations, the compositing with its adjoint and the fused adjoint + Adam of every grid run in
 the library (``tg_sort_queries``, ``tg_share_sort``, ``tg_forward``, ``tg_composite``,
 ``tg_backward_adam``).
@@ -46,37 +47,40 @@ def composite(f, c, delta, n_samples, ws, target=None, rgb=None, loss=None, g_f=
 
 
 class RadianceField:
-    """Density grid (K=2) and three colour grids (K=1) on one vertex lattice over [lo, hi]^3.
-    ``coeffs`` optionally gives the initial FP32 coefficients: (density [res_z, res_y, res_x,
-    10], colour [3, res_z, res_y, res_x, 4])."""
+    """Density grid (K=2) and a three-channel colour grid (K=1, 12 coefficients per vertex in
+    3D) on one vertex lattice over [lo, hi]^3.  ``coeffs`` optionally gives the initial FP32
+    coefficients: (density [res_z, res_y, res_x, 10], colour [res_z, res_y, res_x, 12] or a
+    list of the three channels' [res_z, res_y, res_x, 4])."""
 
     def __init__(self, res=(160, 160, 160), lo=(-1.0,) * 3, hi=(1.0,) * 3, device="cuda", coeffs=None):
-        dens, col = coeffs if coeffs is not None else (None, [None] * 3)
+        dens, col = coeffs if coeffs is not None else (None, None)
+        if isinstance(col, (list, tuple)):
+            col = torch.cat([torch.as_tensor(c) for c in col], dim=-1)
         self.density = TaylorGrid(3, res, 2, lo, hi, coeffs=dens, device=device)
-        self.colour = [TaylorGrid(3, res, 1, lo, hi, coeffs=col[k], device=device) for k in range(3)]
+        self.colour = TaylorGrid(3, res, 1, lo, hi, coeffs=col, device=device, channels=3)
         self.device = self.density.device
         self.reduce_ws = torch.empty(_lib.lib().tg_reduce_workspace_bytes(), dtype=torch.uint8, device=self.device)
 
     @property
     def grids(self):
-        return [self.density] + self.colour
+        return [self.density, self.colour]
 
     def workspace(self, n):
-        """One workspace for all four grids: they share one vertex lattice, so the samples are
-        bucketed once (by the density grid, which has the most coefficients per vertex and
-        so needs the largest workspace) and the colour grids reuse that sort."""
-        return self.density.workspace(n)
+        """One workspace for both grids: they share one vertex lattice, so the samples are
+        bucketed once (by the density grid) and the colour grid reuses that sort.  It is sized
+        for the grid with the most coefficients per vertex."""
+        nb = max(g.workspace_bytes(n) for g in self.grids)
+        return torch.empty(nb, dtype=torch.uint8, device=self.device)
 
     def evaluate(self, q, ws, f=None, c=None):
-        """Sort the samples once and evaluate every grid: f [N] density values, c [3, N] colours."""
+        """Sort the samples once and evaluate both grids: f [N] density values, c [3, N] colours."""
         n = q.shape[0]
         f = torch.empty(n, dtype=torch.float32, device=self.device) if f is None else f
         c = torch.empty((3, n), dtype=torch.float32, device=self.device) if c is None else c
         self.density.sort(q, ws)
         self.density.forward(q, ws, want_grad=False, out=(f, None))
-        for k, g in enumerate(self.colour):
-            g.share_sort(self.density, q, ws)
-            g.forward(q, ws, want_grad=False, out=(c[k], None))
+        self.colour.share_sort(self.density, q, ws)
+        self.colour.forward(q, ws, out=(c, None))
         return f, c
 
     def render(self, q, delta, n_samples, ws):
@@ -85,7 +89,7 @@ class RadianceField:
 
     def train_step(self, q, delta, n_samples, target, ws, lr=1e-2, step=None, bufs=None, stage_events=None):
         """One step: evaluate, composite with the loss and its adjoint, then the fused adjoint
-        + Adam of every grid.  Returns the loss (device float64 [1]).  ``bufs`` optionally
+        + Adam of both grids.  Returns the loss (device float64 [1]).  ``bufs`` optionally
         carries preallocated (f, c, rgb, loss, g_f, g_c); ``stage_events`` optionally three
         recorded torch.cuda.Events, re-recorded after the evaluation, the compositing and the
         updates."""
@@ -97,8 +101,7 @@ class RadianceField:
         if stage_events is not None:
             stage_events[1].record()
         self.density.backward_adam(q, ws, g_f, None, lr=lr, step=step)
-        for k in range(3):
-            self.colour[k].backward_adam(q, ws, g_c[k], None, lr=lr, step=step)
+        self.colour.backward_adam(q, ws, g_c, None, lr=lr, step=step)
         if stage_events is not None:
             stage_events[2].record()
         return loss

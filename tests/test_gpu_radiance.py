@@ -85,9 +85,10 @@ def test_render_full_size_sampled_rays():
 
 
 def test_training_step_matches_oracle():
-    """One step on a 24^3 field: loss, and every grid's master and moments after the fused
-    adjoint + Adam, against the oracle's forward, compositing adjoint, grid adjoint and Adam.
-    Established moments (a first Adam step amplifies rounding where a gradient is near 0)."""
+    """One step on a 24^3 field: loss, and both grids' master and moments after the fused
+    adjoint + Adam, against the oracle's forward, compositing adjoint, grid adjoint (per colour
+    channel) and Adam.  Established moments (a first Adam step amplifies rounding where a
+    gradient is near 0)."""
     res = (24, 24, 24)
     dens, col = _field(res, 2)
     field = RadianceField(res, coeffs=(torch.from_numpy(dens), [torch.from_numpy(col[k]) for k in range(3)]),
@@ -113,9 +114,10 @@ def test_training_step_matches_oracle():
                                                     delta64.reshape(n_rays, ns), target)
     assert abs(float(loss[0]) - ref_loss) <= 1e-5 * ref_loss
     grads = [oracle.backward(geom_d, dens.astype(np.float64), q64, g_f.reshape(-1), None)[0]]
-    grads += [oracle.backward(geom_c, col[k].astype(np.float64), q64, g_c[:, :, k].reshape(-1), None)[0]
-              for k in range(3)]
-    inits = [dens] + [col[k] for k in range(3)]
+    # the colour grid stores the three channels' series per vertex, one after the other
+    grads += [np.concatenate([oracle.backward(geom_c, col[k].astype(np.float64), q64, g_c[:, :, k].reshape(-1),
+                                              None)[0] for k in range(3)], axis=-1)]
+    inits = [dens, np.concatenate([col[k] for k in range(3)], axis=-1)]
     for g, th0, m, v, gr in zip(field.grids, inits, m0, v0, grads):
         th, mm, vv, _ = oracle.adam(th0.astype(np.float64).reshape(-1), m.astype(np.float64).reshape(-1),
                                     v.astype(np.float64).reshape(-1), gr.reshape(-1), 1e-2, step=10)
@@ -172,3 +174,52 @@ def test_shared_sort():
     col.ensure_sorted(q, ws)  # the binding sees the same generation rule and sorts again
     f_again, _ = col.forward(q, ws)
     assert torch.equal(f_again, f_own)
+
+
+def test_three_channel_grid():
+    """The three-channel order-1 grid against the oracle channel by channel: forward (f [3, n]),
+    adjoint from g_f [3, n], and the fused adjoint + Adam, with crowded bricks split over
+    several items; the SDF calls refuse it."""
+    from paper_2402_14415_amd._lib import TaylorGridError
+    from paper_2402_14415_amd.grid import TaylorGrid
+
+    res = (29, 33, 26)
+    rng = np.random.default_rng(31)
+    n = 70000
+    q64 = _f32(np.concatenate([rng.uniform(-1.05, 1.05, size=(n // 2, 3)),
+                               np.clip(rng.normal(-0.2, 0.03, size=(n - n // 2, 3)), -1, 1)]))
+    cc = _f32(rng.normal(0, 0.05, size=res[::-1] + (12,)))
+    g = TaylorGrid(3, res, 1, (-1.0,) * 3, (1.0,) * 3, coeffs=torch.from_numpy(cc.astype(np.float32)), device=DEV,
+                   channels=3)
+    assert g.C == 12
+    q = torch.tensor(q64, dtype=torch.float32, device=DEV)
+    ws = g.workspace(n)
+    g.sort(q, ws)
+    f, grad = g.forward(q, ws)
+    assert grad is None and f.shape == (3, n)
+    gf = _f32(rng.normal(0, 1, size=(3, n)))
+    g.backward(q, ws, torch.tensor(gf, dtype=torch.float32, device=DEV))
+    torch.cuda.synchronize()
+    geom = oracle.Geometry(3, res, 1, (-1.0,) * 3, (1.0,) * 3)
+    dC = []
+    for k in range(3):
+        ck = cc[..., 4 * k: 4 * k + 4]
+        assert nerr(to_np(f)[k], oracle.forward(geom, ck, q64, want_grad=False)) <= TOL_VALUE
+        dC.append(oracle.backward(geom, ck, q64, gf[k], None)[0])
+        assert nerr(to_np(g.grad)[..., 4 * k: 4 * k + 4], dC[k]) <= TOL_GRAD
+    dC = np.concatenate(dC, axis=-1)
+    m0 = _f32(rng.normal(0, 1e-5, size=cc.shape))
+    v0 = _f32(rng.uniform(1e-9, 1e-8, size=cc.shape))
+    g.adam_m.copy_(torch.from_numpy(m0.astype(np.float32)))
+    g.adam_v.copy_(torch.from_numpy(v0.astype(np.float32)))
+    g.backward_adam(q, ws, torch.tensor(gf, dtype=torch.float32, device=DEV), None, lr=1e-2, step=10)
+    torch.cuda.synchronize()
+    th, mm, _, _ = oracle.adam(cc.reshape(-1), m0.reshape(-1), v0.reshape(-1), dC.reshape(-1), 1e-2, step=10)
+    assert nerr(to_np(g.master).reshape(-1), th) <= TOL_VALUE
+    assert nerr(to_np(g.adam_m).reshape(-1), mm) <= TOL_GRAD
+    d = torch.zeros(n, device=DEV)
+    with pytest.raises(TaylorGridError) as err:
+        g.train_step(q, d, ws)
+    assert err.value.status == 2
+    with pytest.raises(TaylorGridError):
+        g.backward(q, ws, torch.zeros((3, n), device=DEV), torch.zeros((n, 3), device=DEV))
