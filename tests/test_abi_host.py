@@ -325,3 +325,41 @@ def test_full_hessian_layout_validation():
         d.hessian = layout
         st, _ = _create(d, b)
         assert st == 1, (order, layout)
+
+
+def test_channels_validation():
+    """Three channels need order 1 and the symmetric layout; 1 and 3 are the only counts; a
+    three-channel grid is refused by serving, and its adjoint takes g_f only."""
+    b = _lib.GridBuffers()
+    b.coeffs = b.master = b.grad = 0x1000
+    for order, ch, hess in ((2, 3, 0), (0, 3, 0), (1, 2, 0), (1, -1, 0)):
+        d = _desc(order=order)
+        d.channels = ch
+        d.hessian = hess
+        st, _ = _create(d, b)
+        assert st == 1, (order, ch)
+    d = _desc(order=1)
+    d.channels = 3
+    st, h = _create(d, b)
+    assert st == 0
+    d1 = _desc(order=1)
+    st, h1 = _create(d1, b)
+    assert st == 0
+    try:
+        n = 1000
+        assert L().tg_workspace_bytes(h, n) > L().tg_workspace_bytes(h1, n)  # 12 coefficients, not 4
+        req = (_lib.Request * 1)()
+        req[0].grid, req[0].n = 0, 10
+        req[0].q = req[0].sdf = 0x100000
+        assert L().tg_query((ctypes.c_void_p * 1)(h.value), 1, req, 1, None) == 2
+        fake = ctypes.c_void_p(0x100000)
+        ws = L().tg_workspace_bytes(h, n)
+        # the adjoint of a three-channel grid takes neither g_grad nor dq, and needs g_f
+        assert L().tg_backward(h, fake, n, fake, ws, fake, fake, None, 0, None) == 2
+        assert L().tg_backward(h, fake, n, fake, ws, fake, None, fake, 0, None) == 2
+        assert L().tg_backward(h, fake, n, fake, ws, None, None, None, 0, None) == 1
+        # tg_forward without a grad_f output only
+        assert L().tg_forward(h, fake, n, fake, ws, fake, fake, None) == 2
+    finally:
+        assert L().tg_destroy(h) == 0
+        assert L().tg_destroy(h1) == 0
