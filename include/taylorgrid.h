@@ -157,8 +157,8 @@ tg_status tg_sort_queries(tg_grid* grid, const float* q, int64_t n, void* ws, si
 /* Let `grid` reuse the sort of (q, n) that `sorted` holds in ws (host only; nothing is
  * enqueued).  The bucketing depends only on the cell geometry, so grids with the same dim,
  * res, lo and hi (compared exactly) bucket the same queries identically, whatever their
- * order or storage; a field with several grids on one vertex lattice (the density and
- * colour grids of the radiance form, Sec. 3.3) sorts its samples once.  ws_bytes must cover
+ * order, channels or storage; a field with several grids on one vertex lattice (the density
+ * and colour grids of the radiance form, Sec. 3.3) sorts its samples once.  ws_bytes must cover
  * tg_workspace_bytes(grid, n), which grows with the coefficient count: size a shared
  * workspace for the grid with the most coefficients per vertex.  Errors: TG_ERR_INVALID_ARG
  * for a NULL handle or different geometry, TG_ERR_CAPACITY for a short workspace,
@@ -261,7 +261,8 @@ tg_status tg_chamfer(const float* a, int64_t na, const float* b, int64_t nb, dou
  * of n_samples samples each, with a ReLU density, and the photometric loss of Eq. 11 with
  * its adjoint, in one launch.  Sample i of ray r is element r*n_samples + i of:
  *   f [N]      the density grid's value (N = n_rays * n_samples; tg_forward output),
- *   c [3][N]   the three colour channels (channel-major: one tg_forward output per channel),
+ *   c [3][N]   the three colour channels (channel-major: the tg_forward output of a
+ *              three-channel colour grid),
  *   delta [N]  the distance to the next sample along the ray (>= 0),
  * and per ray
  *   sigma_i = max(f_i, 0), T_i = exp(-sum_{j<i} sigma_j delta_j),
@@ -270,7 +271,7 @@ tg_status tg_chamfer(const float* a, int64_t na, const float* b, int64_t nb, dou
  * g_f and g_c are required unless n_rays == 0):
  *   loss (device FP64) = (1/n_rays) sum_r |C(r) - target_r|^2 (0 for no rays),
  *   g_f [N] = dL/df_i (0 where f_i <= 0) and g_c [3][N] = dL/dc_i, the upstream gradients
- *   of the density and colour grids' adjoints (tg_backward's g_f).
+ *   of the density grid's and the three-channel colour grid's adjoints (their g_f).
  * 1 <= n_samples <= 1024.  All arrays are device memory and must not overlap the outputs.
  * ws must hold tg_reduce_workspace_bytes(). */
 tg_status tg_composite(int64_t n_rays, int32_t n_samples, const float* f, const float* c,

@@ -1,7 +1,8 @@
 """Radiance-field form on the GPU against the FP64 oracle (oracle/radiance.py and the grid
 oracle): the compositing kernel (Sec. 3.3 Eq. 10-11 and its adjoint) for every sample-count
 shape it dispatches on, rendering at the full 160^3 size on sampled rays, and one whole
-training step (grid evaluation, compositing, fused adjoint + Adam of the four grids)."""
+training step (grid evaluation, compositing, fused adjoint + Adam of the density and the
+three-channel colour grid), the shared sort and the three-channel grid itself."""
 import numpy as np
 import pytest
 import torch
