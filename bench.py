@@ -9,8 +9,11 @@ update of every coefficient applied in the same pass.  The separate calls (forwa
 backward, Adam) are timed too; their forward + backward is the fwd+bwd figure.  Query
 batches are generated on the host before timing and are resident in HBM.
 
-Prints one JSON line.  --gpus must be 1 (the path runs on one GPU; see the design doc for how it
-would shard).
+Further sections (each can be switched off by a flag) time the precision forms, the full
+SDF objective, the quality measures, the order scaling, the radiance-field form and serving;
+the CPU baseline times the FP64 oracle on a bounded sample of the same steps.
+
+Prints one JSON line.  --gpus must be 1: the path runs on one GPU.
 """
 from __future__ import annotations
 
