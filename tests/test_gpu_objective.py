@@ -236,3 +236,47 @@ def test_progressive_fit_continues_from_the_coarse_field():
     assert fine_last < fine_first
     with pytest.raises(IndexError):
         fit.advance()
+
+
+def test_full_objective_train_step_matches_separate_calls_full_size():
+    """128^3 K=2, 2^20 scene queries (the headline shape) with every term of Eq. 8: the
+    one-call step against sort + tg_tv_loss + tg_forward_sdf_loss + tg_backward_adam with the
+    TV gradient added (TG_BWD_ADD_GRAD), over two steps."""
+    import math
+
+    from paper_2402_14415_amd import synth
+
+    C64, q64, d64, scene = synth.scene3d_inputs(res=128, order=2, n=1 << 20, seed=0)
+    C32 = torch.from_numpy(C64.astype(np.float32))
+    del C64
+    a = TaylorGrid(3, (128,) * 3, 2, (-1.0,) * 3, (1.0,) * 3, coeffs=C32, device=DEV)
+    b = TaylorGrid(3, (128,) * 3, 2, (-1.0,) * 3, (1.0,) * 3, coeffs=C32, device=DEV)
+    # established moments: a first Adam step from zero moments divides by |g| itself and so
+    # amplifies the rounding of near-cancelling gradient sums (the two sorts order a bucket's
+    # records differently)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(8)
+    m0 = torch.randn(a.shape, generator=gen, device=DEV) * 1e-5
+    v0 = torch.rand(a.shape, generator=gen, device=DEV) * 9e-9 + 1e-9
+    for g_ in (a, b):
+        g_.adam_m.copy_(m0)
+        g_.adam_v.copy_(v0)
+    k = math.log(3.0) / (2 * 2.0 / 127)
+    n = 1 << 20
+    wa, wb = a.workspace(n), b.workspace(n)
+    for step in range(2):
+        q64, d64 = synth.scene_batch(scene, n, seed=0, step=step)
+        q = torch.tensor(q64, dtype=torch.float32, device=DEV)
+        d = torch.tensor(d64, dtype=torch.float32, device=DEV)
+        la = a.train_step(q, d, wa, eik_weight=0.1, lr=1e-2, surface_k=k, tv_weight=2e-5, step=step + 10)
+        b.sort(q, wb)
+        tv = b.tv_loss(2e-5, wb)
+        lb, gf, gg = b.forward_sdf_loss(q, wb, d, 0.1, surface_k=k)
+        b.backward_adam(q, wb, gf, gg, lr=1e-2, step=step + 10, add_grad=True)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(to_np(la)[:3] - [2e-5 * float(tv[0]), 0, 0], to_np(lb), rtol=1e-6)
+        assert abs(float(la[3]) - float(tv[0])) <= 1e-12 * float(tv[0])
+        for name, tol in (("master", 1e-6), ("adam_m", TOL_VALUE), ("adam_v", TOL_VALUE)):
+            e = nerr(to_np(getattr(a, name)).reshape(-1), to_np(getattr(b, name)).reshape(-1))
+            print(f"step {step} {name}: {e:.2e}")
+            assert e <= tol
