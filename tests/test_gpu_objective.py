@@ -280,3 +280,25 @@ def test_full_objective_train_step_matches_separate_calls_full_size():
             e = nerr(to_np(getattr(a, name)).reshape(-1), to_np(getattr(b, name)).reshape(-1))
             print(f"step {step} {name}: {e:.2e}")
             assert e <= tol
+
+
+def test_train_step_without_queries_applies_tv_alone():
+    """No queries: the step's loss is the TV term alone and every coefficient takes the Adam
+    step of the TV gradient (tg_tv_loss then tg_adam_step)."""
+    rng = np.random.default_rng(12)
+    a, C = _grid(3, (20, 17, 23), 2, rng)
+    b = TaylorGrid(3, (20, 17, 23), 2, (-1.0,) * 3, (1.0,) * 3, coeffs=torch.from_numpy(C.astype(np.float32)),
+                   device=DEV)
+    q = torch.empty((0, 3), device=DEV)
+    d = torch.empty(0, device=DEV)
+    wa = a.workspace(0)
+    loss = a.train_step(q, d, wa, eik_weight=0.1, lr=1e-2, tv_weight=0.5, step=1)
+    wb = b.workspace(0)
+    tv = b.tv_loss(0.5, wb)
+    b.adam_step(wb, lr=1e-2, step=1)
+    torch.cuda.synchronize()
+    ref, _ = obj.tv(C, 3)
+    assert to_np(loss)[1] == 0.0 and to_np(loss)[2] == 0.0
+    assert abs(to_np(loss)[3] - ref) <= TOL_VALUE * ref and abs(to_np(loss)[0] - 0.5 * to_np(loss)[3]) <= 1e-15
+    assert float(tv[0]) == to_np(loss)[3]
+    assert nerr(to_np(a.master).reshape(-1), to_np(b.master).reshape(-1)) <= 1e-6
