@@ -277,17 +277,23 @@ __global__ __launch_bounds__(kThreads) void k_iou(int64_t n, const float* __rest
     }
 }
 
-__global__ __launch_bounds__(64) void k_iou_finish(const int64_t* __restrict__ partials, int nb,
-                                                  int64_t* __restrict__ counts)
+constexpr int kFinishThreads = 256;
+
+__global__ __launch_bounds__(kFinishThreads) void k_iou_finish(const int64_t* __restrict__ partials, int nb,
+                                                              int64_t* __restrict__ counts)
 {
-    if (threadIdx.x != 0) return;
-    int64_t a = 0, b = 0;
-    for (int k = 0; k < nb; ++k) {
-        a += partials[2 * k];
-        b += partials[2 * k + 1];
+    // exact: every count and sum is an integer below 2^53
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nb; k += kFinishThreads) {
+        a += (double)partials[2 * k];
+        b += (double)partials[2 * k + 1];
     }
-    counts[0] = a;
-    counts[1] = b;
+    a = block_sum_f64<kFinishThreads>(a);
+    b = block_sum_f64<kFinishThreads>(b);
+    if (threadIdx.x == 0) {
+        counts[0] = (int64_t)a;
+        counts[1] = (int64_t)b;
+    }
 }
 
 hipError_t launch_iou(int64_t n, const float* f, const float* d, int64_t* counts, int64_t* partials, hipStream_t s)
@@ -295,7 +301,7 @@ hipError_t launch_iou(int64_t n, const float* f, const float* d, int64_t* counts
     const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kThreads * 4 - 1) / (kThreads * 4),
                                                                         kMaxReduceBlocks));
     hipLaunchKernelGGL(k_iou, dim3(nb), dim3(kThreads), 0, s, n, f, d, partials);
-    hipLaunchKernelGGL(k_iou_finish, dim3(1), dim3(64), 0, s, partials, (int)nb, counts);
+    hipLaunchKernelGGL(k_iou_finish, dim3(1), dim3(kFinishThreads), 0, s, partials, (int)nb, counts);
     return hipGetLastError();
 }
 
@@ -359,17 +365,20 @@ __global__ __launch_bounds__(kNnThreads) void k_nn_sum(const float* __restrict__
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(64) void k_chamfer_finish(const double* __restrict__ pa, int na_b, int64_t na,
-                                                      const double* __restrict__ pb, int nb_b, int64_t nb,
-                                                      double* __restrict__ out)
+__global__ __launch_bounds__(kFinishThreads) void k_chamfer_finish(const double* __restrict__ pa, int na_b,
+                                                                  int64_t na, const double* __restrict__ pb,
+                                                                  int nb_b, int64_t nb, double* __restrict__ out)
 {
-    if (threadIdx.x != 0) return;
     double a = 0.0, b = 0.0;
-    for (int k = 0; k < na_b; ++k) a += pa[k];
-    for (int k = 0; k < nb_b; ++k) b += pb[k];
-    out[1] = a / (double)na;
-    out[2] = b / (double)nb;
-    out[0] = out[1] + out[2];
+    for (int k = threadIdx.x; k < na_b; k += kFinishThreads) a += pa[k];
+    for (int k = threadIdx.x; k < nb_b; k += kFinishThreads) b += pb[k];
+    a = block_sum_f64<kFinishThreads>(a);
+    b = block_sum_f64<kFinishThreads>(b);
+    if (threadIdx.x == 0) {
+        out[1] = a / (double)na;
+        out[2] = b / (double)nb;
+        out[0] = out[1] + out[2];
+    }
 }
 
 hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, double* partials,
@@ -381,8 +390,8 @@ hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb
     const unsigned gb = (unsigned)std::min<int64_t>((nb + CHUNK - 1) / CHUNK, half);
     hipLaunchKernelGGL(k_nn_sum, dim3(ga), dim3(kNnThreads), 0, s, a, na, b, nb, partials);
     hipLaunchKernelGGL(k_nn_sum, dim3(gb), dim3(kNnThreads), 0, s, b, nb, a, na, partials + half);
-    hipLaunchKernelGGL(k_chamfer_finish, dim3(1), dim3(64), 0, s, partials, (int)ga, na, partials + half, (int)gb, nb,
-                       out);
+    hipLaunchKernelGGL(k_chamfer_finish, dim3(1), dim3(kFinishThreads), 0, s, partials, (int)ga, na, partials + half,
+                       (int)gb, nb, out);
     return hipGetLastError();
 }
 
