@@ -8,7 +8,10 @@
  * offset from that corner (Eq. 3); the corner values are blended with multilinear weights
  * (Eq. 4).  The grid is optimised directly, with no network (Sec. 3.1, Sec. 4.1), which
  * needs the adjoint of that map; the SDF task adds an L1 reconstruction term (Eq. 6) and
- * an eikonal term (Eq. 8) that needs the field's spatial gradient.
+ * an eikonal term (Eq. 8) that needs the field's spatial gradient.  Beyond that path: the
+ * rest of the SDF objective (Eq. 7's surface weight, the TV term), the coarse-to-fine step of
+ * progressive training, the radiance-field form (Sec. 3.3: compositing, photometric loss,
+ * a three-channel colour grid) and quality measures (IoU, a zero-level-set mesh, Chamfer).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -19,7 +22,10 @@
  *  Coefficient layout: [res_z][res_y][res_x][C] (x fastest; 2D: [res_y][res_x][C]), C =
  *    tg_coeffs_per_vertex(dim, order) values per vertex holding the partial derivatives of
  *    f at the vertex in graded-lexicographic order (3D order 2: f, fx, fy, fz, fxx, fxy,
- *    fxz, fyy, fyz, fzz; 2D order 2: f, fx, fy, fxx, fxy, fyy), in world units.
+ *    fxz, fyy, fyz, fzz; 2D order 2: f, fx, fy, fxx, fxy, fyy), in world units.  Two
+ *    further layouts (tg_grid_desc): the full Hessian (f, the gradient, all dim^2 second
+ *    derivatives row-major) and three channels at order 1 (each channel's f and gradient in
+ *    turn).
  *  Queries: q is [n][dim] FP32, row-major.  Outputs are in the caller's query order.
  *  Memory: every pointer argument is DEVICE memory unless marked (host).  The library
  *    never allocates, copies or frees device memory; buffers belong to the caller and must
