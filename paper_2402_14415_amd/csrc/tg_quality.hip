@@ -63,10 +63,36 @@ __device__ __forceinline__ int cell_count(const float* cv)
     return n;
 }
 
-// Per thread: the triangle counts of kMeshCellsPerThread consecutive cells, their exclusive
-// prefix within the block (offs), and the block's total (bsum).
+// Exclusive scan over the block of one value per thread (kMeshThreads threads); returns the
+// thread's prefix and leaves the block total in *total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* wsum, uint32_t* total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    __syncthreads();  // wsum may still be read by an earlier scan
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < kMeshThreads / 64; ++w) {
+        if (w < wave) before += wsum[w];
+        all += wsum[w];
+    }
+    *total = all;
+    return before + incl - x;
+}
+
+// Per thread: the triangle counts of kMeshCellsPerThread consecutive cells and their
+// exclusive prefix within the block (offs), the block's total (bsum); and the block's cells
+// that cross the level set (count > 0), listed in cell order from blist[block *
+// kMeshCellsPerBlock], with their number in scnt.
 __global__ __launch_bounds__(kMeshThreads) void k_mesh_count(Lattice L, const float* __restrict__ v, int64_t ncell,
-                                                            uint32_t* __restrict__ offs, uint32_t* __restrict__ bsum)
+                                                            uint32_t* __restrict__ offs, uint32_t* __restrict__ bsum,
+                                                            uint32_t* __restrict__ blist, uint32_t* __restrict__ scnt)
 {
     __shared__ uint32_t wsum[kMeshThreads / 64];
     const int64_t c0 = (int64_t)blockIdx.x * kMeshCellsPerBlock + (int64_t)threadIdx.x * kMeshCellsPerThread;
@@ -84,31 +110,43 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_count(Lattice L, const fl
         }
         tot += cnt[q];
     }
-    // exclusive scan of the thread totals over the block
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t incl = tot;
+    uint32_t nstr = 0;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += o;
-    }
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0;
-    for (int w = 0; w < wave; ++w) before += wsum[w];
-    uint32_t run = before + incl - tot;
+    for (int q = 0; q < kMeshCellsPerThread; ++q) nstr += cnt[q] > 0 ? 1u : 0u;
+    uint32_t btot, bstr;
+    uint32_t run = block_exclusive_scan(tot, wsum, &btot);
+    uint32_t srun = block_exclusive_scan(nstr, wsum, &bstr);
+    uint32_t* mine = blist + (int64_t)blockIdx.x * kMeshCellsPerBlock;
 #pragma unroll
     for (int q = 0; q < kMeshCellsPerThread; ++q) {
         const int64_t c = c0 + q;
         if (c < ncell) offs[c] = run;
         run += cnt[q];
+        if (cnt[q] > 0) mine[srun++] = (uint32_t)c;
     }
-    if (threadIdx.x == kMeshThreads - 1) bsum[blockIdx.x] = run;
+    if (threadIdx.x == 0) {
+        bsum[blockIdx.x] = btot;
+        scnt[blockIdx.x] = bstr;
+    }
 }
 
-// One block: exclusive scan of the block totals in place; *total = their sum.
-__global__ __launch_bounds__(1024) void k_mesh_scan_blocks(uint32_t* __restrict__ bsum, int64_t nb,
-                                                          int64_t* __restrict__ total)
+// Gathers every block's list of crossing cells into one list at the block's scanned offset.
+__global__ __launch_bounds__(kMeshThreads) void k_mesh_list(const uint32_t* __restrict__ blist,
+                                                           const uint32_t* __restrict__ scnt,
+                                                           const uint32_t* __restrict__ soff,
+                                                           uint32_t* __restrict__ list, int64_t nb)
+{
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const uint32_t m = scnt[b], base = soff[b];
+        for (uint32_t r = threadIdx.x; r < m; r += kMeshThreads)
+            list[base + r] = blist[b * kMeshCellsPerBlock + r];
+    }
+}
+
+// One block: exclusive scan of the block totals in place; *total = their sum.  Called once
+// for the triangle counts and once for the crossing-cell counts.
+__global__ __launch_bounds__(1024) void k_mesh_scan_blocks(const uint32_t* __restrict__ in, uint32_t* __restrict__ bsum,
+                                                          int64_t nb, int64_t* __restrict__ total)
 {
     __shared__ uint32_t wsum[16];
     __shared__ uint32_t carry;
@@ -117,7 +155,7 @@ __global__ __launch_bounds__(1024) void k_mesh_scan_blocks(uint32_t* __restrict_
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
         const int64_t b = b0 + threadIdx.x;
-        const uint32_t x = b < nb ? bsum[b] : 0u;
+        const uint32_t x = b < nb ? in[b] : 0u;
         uint32_t incl = x;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -143,13 +181,18 @@ __device__ __forceinline__ void corner_pos(const Lattice& L, int i, int j, int k
     p[2] = L.lo[2] + (float)(k + ((c >> 2) & 1)) * L.h[2];
 }
 
-__global__ __launch_bounds__(kMeshThreads) void k_mesh_emit(Lattice L, const float* __restrict__ v, int64_t ncell,
+// One thread per cell that crosses the level set (the compacted list, *nlist of them).
+__global__ __launch_bounds__(kMeshThreads) void k_mesh_emit(Lattice L, const float* __restrict__ v,
+                                                           const uint32_t* __restrict__ list,
+                                                           const int64_t* __restrict__ nlist,
                                                            const uint32_t* __restrict__ offs,
                                                            const uint32_t* __restrict__ bsum, float* __restrict__ tri,
                                                            int64_t max_tris)
 {
-    for (int64_t c = (int64_t)blockIdx.x * kMeshThreads + threadIdx.x; c < ncell;
-         c += (int64_t)gridDim.x * kMeshThreads) {
+    const int64_t nl = *nlist;
+    for (int64_t li = (int64_t)blockIdx.x * kMeshThreads + threadIdx.x; li < nl;
+         li += (int64_t)gridDim.x * kMeshThreads) {
+        const int64_t c = list[li];
         int i, j, k;
         cell_of(L, c, i, j, k);
         float cv[8];
@@ -226,10 +269,40 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_emit(Lattice L, const flo
     }
 }
 
+// Workspace sections: triangle offsets [ncell], per-block crossing-cell lists [nb * cells per
+// block], the compacted list [ncell], per-block triangle totals / offsets, crossing-cell
+// counts and offsets [nb each], the number of crossing cells and of triangles (int64).
+struct MeshWs {
+    size_t offs, blist, list, bsum, scnt, soff, nlist, total;
+};
+
+static MeshWs mesh_ws(int64_t ncell)
+{
+    const int64_t nb = std::max<int64_t>(1, (ncell + kMeshCellsPerBlock - 1) / kMeshCellsPerBlock);
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    MeshWs W;
+    size_t off = 0;
+    W.offs = off;
+    off = up(off + (size_t)ncell * 4);
+    W.blist = off;
+    off = up(off + (size_t)nb * kMeshCellsPerBlock * 4);
+    W.list = off;
+    off = up(off + (size_t)ncell * 4);
+    W.bsum = off;
+    off = up(off + (size_t)nb * 4);
+    W.scnt = off;
+    off = up(off + (size_t)nb * 4);
+    W.soff = off;
+    off = up(off + (size_t)nb * 4);
+    W.nlist = off;
+    off = up(off + 8);
+    W.total = off;
+    return W;
+}
+
 size_t mesh_workspace_bytes(int64_t ncell)
 {
-    const int64_t nb = (ncell + kMeshCellsPerBlock - 1) / kMeshCellsPerBlock;
-    return ((size_t)ncell * 4 + 255) / 256 * 256 + (size_t)std::max<int64_t>(nb, 1) * 4;
+    return mesh_ws(ncell).total;
 }
 
 hipError_t launch_mesh(const int* n, const float* lo, const float* hi, const float* values, float* tri,
@@ -245,14 +318,25 @@ hipError_t launch_mesh(const int* n, const float* lo, const float* hi, const flo
     }
     const int64_t ncell = (int64_t)(n[0] - 1) * (n[1] - 1) * (n[2] - 1);
     const int64_t nb = (ncell + kMeshCellsPerBlock - 1) / kMeshCellsPerBlock;
-    uint32_t* offs = reinterpret_cast<uint32_t*>(ws);
-    uint32_t* bsum = reinterpret_cast<uint32_t*>(ws + ((size_t)ncell * 4 + 255) / 256 * 256);
+    const MeshWs W = mesh_ws(ncell);
+    uint32_t* offs = reinterpret_cast<uint32_t*>(ws + W.offs);
+    uint32_t* blist = reinterpret_cast<uint32_t*>(ws + W.blist);
+    uint32_t* list = reinterpret_cast<uint32_t*>(ws + W.list);
+    uint32_t* bsum = reinterpret_cast<uint32_t*>(ws + W.bsum);
+    uint32_t* scnt = reinterpret_cast<uint32_t*>(ws + W.scnt);
+    uint32_t* soff = reinterpret_cast<uint32_t*>(ws + W.soff);
+    int64_t* nlist = reinterpret_cast<int64_t*>(ws + W.nlist);
     if (nb > 0)
-        hipLaunchKernelGGL(k_mesh_count, dim3((unsigned)nb), dim3(kMeshThreads), 0, s, L, values, ncell, offs, bsum);
-    hipLaunchKernelGGL(k_mesh_scan_blocks, dim3(1), dim3(1024), 0, s, bsum, nb, n_tris);
-    if (ncell > 0) {
-        const unsigned ne = (unsigned)std::min<int64_t>((ncell + kMeshThreads - 1) / kMeshThreads, 65536);
-        hipLaunchKernelGGL(k_mesh_emit, dim3(ne), dim3(kMeshThreads), 0, s, L, values, ncell, offs, bsum, tri,
+        hipLaunchKernelGGL(k_mesh_count, dim3((unsigned)nb), dim3(kMeshThreads), 0, s, L, values, ncell, offs, bsum,
+                           blist, scnt);
+    hipLaunchKernelGGL(k_mesh_scan_blocks, dim3(1), dim3(1024), 0, s, bsum, bsum, nb, n_tris);
+    hipLaunchKernelGGL(k_mesh_scan_blocks, dim3(1), dim3(1024), 0, s, scnt, soff, nb, nlist);
+    if (nb > 0) {
+        const unsigned nlb = (unsigned)std::min<int64_t>(nb, 4096);
+        hipLaunchKernelGGL(k_mesh_list, dim3(nlb), dim3(kMeshThreads), 0, s, blist, scnt, soff, list, nb);
+        // at most every cell crosses; the kernel reads the actual count on the device
+        const unsigned ne = (unsigned)std::min<int64_t>((ncell + kMeshThreads - 1) / kMeshThreads, 4096);
+        hipLaunchKernelGGL(k_mesh_emit, dim3(ne), dim3(kMeshThreads), 0, s, L, values, list, nlist, offs, bsum, tri,
                            max_tris);
     }
     return hipGetLastError();
