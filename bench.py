@@ -458,7 +458,8 @@ def quality_bench(dev, dev_batches, scene, fit_steps=400, n_points=100_000, n_su
     _, mesh_us = timed(lambda: lat.run(verts, tri2, total))
     mv = tri.reshape(-1, 3).contiguous()
     out = torch.empty(3, dtype=torch.float64, device=dev)
-    _, ch_us = timed(lambda: quality.chamfer_into(mv, surf, out, red))
+    chws = quality.chamfer_workspace(mv.shape[0], surf.shape[0], dev)
+    _, ch_us = timed(lambda: quality.chamfer_into(mv, surf, out, chws))
     ch = [float(x) for x in out.cpu()]
     pairs = 2 * mv.shape[0] * surf.shape[0]
     mesh_bytes = 2 * RES ** 3 * 4 + total * 36  # the lattice read by both passes, the triangles written

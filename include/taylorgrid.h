@@ -256,10 +256,14 @@ tg_status tg_mesh(const int32_t* n, const float* lo, const float* hi, const floa
                   float* tri, int64_t max_tris, int64_t* n_tris, void* ws, size_t ws_bytes,
                   void* stream);
 
+/* Bytes of device workspace tg_chamfer needs for na and nb points (per-source minima for each
+ * split of the destination set, and the reduction partials); 0 if a count is out of range. */
+size_t tg_chamfer_workspace_bytes(int64_t na, int64_t nb);
+
 /* Chamfer distance between point sets a [na][3] and b [nb][3] (device; na, nb >= 1): out
  * (device double [3]) = {mean_a min_b |a - b| + mean_b min_a |a - b|, the first mean, the
  * second mean}.  Brute force (every pair), distances in FP32, means in FP64.  ws must hold
- * tg_reduce_workspace_bytes(). */
+ * tg_chamfer_workspace_bytes(na, nb); TG_ERR_CAPACITY if smaller. */
 tg_status tg_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, void* ws,
                      size_t ws_bytes, void* stream);
 

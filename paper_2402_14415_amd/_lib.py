@@ -76,6 +76,7 @@ _SIGS = {
     "tg_upsample": ([_P, _P, _P], ctypes.c_int),
     "tg_iou_counts": ([ctypes.c_int64, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "tg_mesh_workspace_bytes": ([ctypes.POINTER(ctypes.c_int32)], ctypes.c_size_t),
+    "tg_chamfer_workspace_bytes": ([ctypes.c_int64, ctypes.c_int64], ctypes.c_size_t),
     "tg_mesh": ([ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), _P,
                  _P, ctypes.c_int64, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "tg_chamfer": ([_P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),

@@ -652,6 +652,12 @@ tg_status tg_mesh(const int32_t* n, const float* lo, const float* hi, const floa
                          "tg_mesh");
 }
 
+size_t tg_chamfer_workspace_bytes(int64_t na, int64_t nb)
+{
+    if (na < 1 || nb < 1 || na > tg::kMaxQueries || nb > tg::kMaxQueries) return 0;
+    return tg::chamfer_workspace_bytes(na, nb);
+}
+
 tg_status tg_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, void* ws, size_t ws_bytes,
                      void* stream)
 {
@@ -659,10 +665,10 @@ tg_status tg_chamfer(const float* a, int64_t na, const float* b, int64_t nb, dou
         return fail(TG_ERR_INVALID_ARG, "tg_chamfer: point counts must be in 1..%lld", (long long)tg::kMaxQueries);
     if (!a || !b || !out) return fail(TG_ERR_INVALID_ARG, "tg_chamfer: a, b and out must not be NULL");
     if (!ws || !aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "tg_chamfer: workspace NULL or not 256-byte aligned");
-    if (ws_bytes < tg::kReduceBytes)
-        return fail(TG_ERR_CAPACITY, "tg_chamfer: workspace smaller than %zu bytes", tg::kReduceBytes);
+    const size_t need = tg::chamfer_workspace_bytes(na, nb);
+    if (ws_bytes < need) return fail(TG_ERR_CAPACITY, "tg_chamfer: workspace has %zu bytes, needs %zu", ws_bytes, need);
     (void)hipGetLastError();
-    return device_status(tg::launch_chamfer(a, na, b, nb, out, static_cast<double*>(ws),
+    return device_status(tg::launch_chamfer(a, na, b, nb, out, static_cast<char*>(ws),
                                             static_cast<hipStream_t>(stream)),
                          "tg_chamfer");
 }

@@ -121,13 +121,14 @@ hipError_t launch_tv(const tg_grid* g, float weight, double* tv_out, float* grad
 // Hessian at the fine vertices; the fine moments (when present) are zeroed.
 hipError_t launch_upsample(const tg_grid* coarse, tg_grid* fine, hipStream_t s);
 // Quality measures: IoU counts (partials: 2 int64 per block, kMaxReduceBlocks blocks at most),
-// the marching-tetrahedra mesh (ws: mesh_workspace_bytes) and the Chamfer distance (partials:
-// kMaxReduceBlocks doubles).
+// the marching-tetrahedra mesh (ws: mesh_workspace_bytes) and the Chamfer distance (ws:
+// chamfer_workspace_bytes).
 hipError_t launch_iou(int64_t n, const float* f, const float* d, int64_t* counts, int64_t* partials, hipStream_t s);
 size_t mesh_workspace_bytes(int64_t ncell);
 hipError_t launch_mesh(const int* n, const float* lo, const float* hi, const float* values, float* tri,
                        int64_t max_tris, int64_t* n_tris, char* ws, hipStream_t s);
-hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, double* partials,
+size_t chamfer_workspace_bytes(int64_t na, int64_t nb);
+hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, char* ws,
                           hipStream_t s);
 hipError_t launch_sum_finish(const double* partials, int64_t nblocks, double* out, hipStream_t s);
 hipError_t launch_sum_finish_scaled(const double* partials, int64_t nblocks, double scale, double* out, hipStream_t s);

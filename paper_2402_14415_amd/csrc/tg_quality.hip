@@ -390,63 +390,97 @@ hipError_t launch_iou(int64_t n, const float* f, const float* d, int64_t* counts
 }
 
 // ------------------------------------------------------------------ Chamfer
-constexpr int kNnThreads = 128;
+constexpr int kNnThreads = 256;
 constexpr int kNnPerThread = 4;   // source points per thread (each staged point is read once for all)
 constexpr int kNnTile = 2048;     // destination points per LDS tile (a multiple of 4)
 
-// partials[block] = sum over this block's source points of the distance to the nearest
-// destination point.  Brute force: destination tiles are staged in LDS as x, y, z arrays
-// (padded to a multiple of 4 with points at infinity), read 4 points at a time, and every
-// thread compares each with its kNnPerThread source points held in registers.
-__global__ __launch_bounds__(kNnThreads) void k_nn_sum(const float* __restrict__ src, int64_t ns,
-                                                      const float* __restrict__ dst, int64_t nd,
-                                                      double* __restrict__ partials)
+// The destination set of one direction is split over S groups of workgroups (enough
+// workgroups to fill the GPU when the source set is small): mins[split * ns + i] = the
+// smallest squared distance from source i to split `split` of the destinations.  Brute
+// force: destination tiles are staged in LDS as x, y, z arrays (padded to a multiple of 4
+// with points at infinity), read 4 points at a time, and every thread compares each with
+// its kNnPerThread source points held in registers.
+constexpr int kNnTargetBlocks = 2048;
+
+__global__ __launch_bounds__(kNnThreads) void k_nn_min(const float* __restrict__ src, int64_t ns,
+                                                      const float* __restrict__ dst, int64_t nd, int64_t chunks,
+                                                      int64_t tiles_per_split, float* __restrict__ mins)
 {
     __shared__ __align__(16) float tx[kNnTile], ty[kNnTile], tz[kNnTile];
     constexpr int CHUNK = kNnThreads * kNnPerThread;
-    double acc = 0.0;
-    for (int64_t s0 = (int64_t)blockIdx.x * CHUNK; s0 < ns; s0 += (int64_t)gridDim.x * CHUNK) {
-        float px[kNnPerThread], py[kNnPerThread], pz[kNnPerThread], best[kNnPerThread];
+    const int64_t chunk = blockIdx.x % chunks, split = blockIdx.x / chunks;
+    const int64_t s0 = chunk * CHUNK;
+    const int64_t dbeg = split * tiles_per_split * kNnTile, dend = min(nd, dbeg + tiles_per_split * kNnTile);
+    float px[kNnPerThread], py[kNnPerThread], pz[kNnPerThread], best[kNnPerThread];
 #pragma unroll
-        for (int r = 0; r < kNnPerThread; ++r) {
-            const int64_t si = s0 + threadIdx.x + (int64_t)r * kNnThreads;
-            const bool ok = si < ns;
-            px[r] = ok ? src[3 * si] : 0.0f;
-            py[r] = ok ? src[3 * si + 1] : 0.0f;
-            pz[r] = ok ? src[3 * si + 2] : 0.0f;
-            best[r] = INFINITY;
-        }
-        for (int64_t d0 = 0; d0 < nd; d0 += kNnTile) {
-            const int cnt = (int)min((int64_t)kNnTile, nd - d0);
-            const int cnt4 = (cnt + 3) & ~3;
-            __syncthreads();
-            for (int q = threadIdx.x; q < cnt4; q += kNnThreads) {
-                const bool ok = q < cnt;
-                tx[q] = ok ? dst[3 * (d0 + q)] : INFINITY;
-                ty[q] = ok ? dst[3 * (d0 + q) + 1] : INFINITY;
-                tz[q] = ok ? dst[3 * (d0 + q) + 2] : INFINITY;
-            }
-            __syncthreads();
-            for (int q = 0; q < cnt4; q += 4) {
-                const float4 X = *reinterpret_cast<const float4*>(tx + q);
-                const float4 Y = *reinterpret_cast<const float4*>(ty + q);
-                const float4 Z = *reinterpret_cast<const float4*>(tz + q);
-                const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w}, zs[4] = {Z.x, Z.y, Z.z, Z.w};
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int r = 0; r < kNnPerThread; ++r) {
-                        const float dx = xs[u] - px[r], dy = ys[u] - py[r], dz = zs[u] - pz[r];
-                        best[r] = fminf(best[r], fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-                    }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < kNnPerThread; ++r)
-            if (s0 + threadIdx.x + (int64_t)r * kNnThreads < ns) acc += (double)sqrtf(best[r]);
+    for (int r = 0; r < kNnPerThread; ++r) {
+        const int64_t si = s0 + threadIdx.x + (int64_t)r * kNnThreads;
+        const bool ok = si < ns;
+        px[r] = ok ? src[3 * si] : 0.0f;
+        py[r] = ok ? src[3 * si + 1] : 0.0f;
+        pz[r] = ok ? src[3 * si + 2] : 0.0f;
+        best[r] = INFINITY;
     }
-    const double tot = block_sum_f64<kNnThreads>(acc);
+    for (int64_t d0 = dbeg; d0 < dend; d0 += kNnTile) {
+        const int cnt = (int)min((int64_t)kNnTile, dend - d0);
+        const int cnt4 = (cnt + 3) & ~3;
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt4; q += kNnThreads) {
+            const bool ok = q < cnt;
+            tx[q] = ok ? dst[3 * (d0 + q)] : INFINITY;
+            ty[q] = ok ? dst[3 * (d0 + q) + 1] : INFINITY;
+            tz[q] = ok ? dst[3 * (d0 + q) + 2] : INFINITY;
+        }
+        __syncthreads();
+        for (int q = 0; q < cnt4; q += 4) {
+            const float4 X = *reinterpret_cast<const float4*>(tx + q);
+            const float4 Y = *reinterpret_cast<const float4*>(ty + q);
+            const float4 Z = *reinterpret_cast<const float4*>(tz + q);
+            const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w}, zs[4] = {Z.x, Z.y, Z.z, Z.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int r = 0; r < kNnPerThread; ++r) {
+                    const float dx = xs[u] - px[r], dy = ys[u] - py[r], dz = zs[u] - pz[r];
+                    best[r] = fminf(best[r], fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+                }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kNnPerThread; ++r) {
+        const int64_t si = s0 + threadIdx.x + (int64_t)r * kNnThreads;
+        if (si < ns) mins[split * ns + si] = best[r];
+    }
+}
+
+// partials[block] = sum over this block's sources of the distance to the nearest destination
+// (the smallest of the splits' squared distances, then its square root).
+__global__ __launch_bounds__(kThreads) void k_nn_reduce(const float* __restrict__ mins, int64_t ns, int64_t nsplit,
+                                                       double* __restrict__ partials)
+{
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < ns; i += (int64_t)gridDim.x * kThreads) {
+        float m = mins[i];
+        for (int64_t sp = 1; sp < nsplit; ++sp) m = fminf(m, mins[sp * ns + i]);
+        acc += (double)sqrtf(m);
+    }
+    const double tot = block_sum_f64<kThreads>(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// Splits of the destination set for sources ns: enough workgroups to fill the GPU, at least
+// one tile of destinations per split.
+static int64_t nn_splits(int64_t ns, int64_t nd)
+{
+    constexpr int CHUNK = kNnThreads * kNnPerThread;
+    const int64_t chunks = (ns + CHUNK - 1) / CHUNK, tiles = (nd + kNnTile - 1) / kNnTile;
+    return std::max<int64_t>(1, std::min<int64_t>({(kNnTargetBlocks + chunks - 1) / chunks, tiles, 64}));
+}
+
+size_t chamfer_workspace_bytes(int64_t na, int64_t nb)
+{
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    return kReduceBytes + up((size_t)na * nn_splits(na, nb) * 4) + up((size_t)nb * nn_splits(nb, na) * 4);
 }
 
 __global__ __launch_bounds__(kFinishThreads) void k_chamfer_finish(const double* __restrict__ pa, int na_b,
@@ -465,15 +499,25 @@ __global__ __launch_bounds__(kFinishThreads) void k_chamfer_finish(const double*
     }
 }
 
-hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, double* partials,
+hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, char* ws,
                           hipStream_t s)
 {
-    const int half = kMaxReduceBlocks / 2;
+    double* partials = reinterpret_cast<double*>(ws);
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const int64_t sa = nn_splits(na, nb), sb = nn_splits(nb, na);
+    float* mins_a = reinterpret_cast<float*>(ws + kReduceBytes);
+    float* mins_b = reinterpret_cast<float*>(ws + kReduceBytes + up((size_t)na * sa * 4));
     constexpr int CHUNK = kNnThreads * kNnPerThread;
-    const unsigned ga = (unsigned)std::min<int64_t>((na + CHUNK - 1) / CHUNK, half);
-    const unsigned gb = (unsigned)std::min<int64_t>((nb + CHUNK - 1) / CHUNK, half);
-    hipLaunchKernelGGL(k_nn_sum, dim3(ga), dim3(kNnThreads), 0, s, a, na, b, nb, partials);
-    hipLaunchKernelGGL(k_nn_sum, dim3(gb), dim3(kNnThreads), 0, s, b, nb, a, na, partials + half);
+    const int64_t ca = (na + CHUNK - 1) / CHUNK, cb = (nb + CHUNK - 1) / CHUNK;
+    const int64_t ta = ((nb + kNnTile - 1) / kNnTile + sa - 1) / sa;  // destination tiles per split
+    const int64_t tb = ((na + kNnTile - 1) / kNnTile + sb - 1) / sb;
+    hipLaunchKernelGGL(k_nn_min, dim3((unsigned)(ca * sa)), dim3(kNnThreads), 0, s, a, na, b, nb, ca, ta, mins_a);
+    hipLaunchKernelGGL(k_nn_min, dim3((unsigned)(cb * sb)), dim3(kNnThreads), 0, s, b, nb, a, na, cb, tb, mins_b);
+    const int half = kMaxReduceBlocks / 2;
+    const unsigned ga = (unsigned)std::min<int64_t>((na + kThreads - 1) / kThreads, half);
+    const unsigned gb = (unsigned)std::min<int64_t>((nb + kThreads - 1) / kThreads, half);
+    hipLaunchKernelGGL(k_nn_reduce, dim3(ga), dim3(kThreads), 0, s, mins_a, na, sa, partials);
+    hipLaunchKernelGGL(k_nn_reduce, dim3(gb), dim3(kThreads), 0, s, mins_b, nb, sb, partials + half);
     hipLaunchKernelGGL(k_chamfer_finish, dim3(1), dim3(kFinishThreads), 0, s, partials, (int)ga, na, partials + half,
                        (int)gb, nb, out);
     return hipGetLastError();

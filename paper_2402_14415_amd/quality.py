@@ -74,8 +74,17 @@ def mesh(values, lo, hi, max_tris=None):
     return tri[: min(total, cap)], total
 
 
+def chamfer_workspace(na, nb, device):
+    """A workspace for the Chamfer distance of na and nb points (tg_chamfer_workspace_bytes)."""
+    nbytes = _lib.lib().tg_chamfer_workspace_bytes(int(na), int(nb))
+    if nbytes == 0:
+        raise ValueError(f"chamfer: point counts {na}, {nb} out of range")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
 def chamfer_into(a, b, out, ws):
-    """Enqueue the Chamfer distance of a [Na, 3] and b [Nb, 3] into out (device float64 [3])."""
+    """Enqueue the Chamfer distance of a [Na, 3] and b [Nb, 3] into out (device float64 [3]);
+    ws: chamfer_workspace(Na, Nb)."""
     dev = a.device
     _check_tensor("a", a, torch.float32, dev)
     _check_tensor("b", b, torch.float32, dev)
@@ -86,6 +95,6 @@ def chamfer_into(a, b, out, ws):
 
 def chamfer(a, b, ws=None):
     """Chamfer distance of point sets a [Na, 3], b [Nb, 3]: (total, mean a->b, mean b->a)."""
-    ws = _reduce_ws(a.device) if ws is None else ws
+    ws = chamfer_workspace(a.shape[0], b.shape[0], a.device) if ws is None else ws
     out = torch.empty(3, dtype=torch.float64, device=a.device)
     return tuple(float(x) for x in chamfer_into(a, b, out, ws).cpu())

@@ -294,7 +294,10 @@ def test_quality_validation():
     assert L().tg_mesh(n, lo, hi, fake, fake, 10, fake, fake, wsb - 1, None) == 4
     assert L().tg_chamfer(fake, 0, fake, 5, fake, fake, red, None) == 1
     assert L().tg_chamfer(fake, 5, None, 5, fake, fake, red, None) == 1
-    assert L().tg_chamfer(fake, 5, fake, 5, fake, fake, red - 1, None) == 4
+    chb = L().tg_chamfer_workspace_bytes(5, 5)
+    assert chb >= red and L().tg_chamfer_workspace_bytes(0, 5) == 0
+    assert L().tg_chamfer_workspace_bytes(1_000_000, 100_000) > L().tg_chamfer_workspace_bytes(1_000_000, 2048)
+    assert L().tg_chamfer(fake, 5, fake, 5, fake, fake, chb - 1, None) == 4
 
 
 def test_full_hessian_layout_validation():

@@ -94,6 +94,20 @@ def test_chamfer_matches_oracle():
     assert abs(got[1] + got[2] - got[0]) <= 1e-12 * got[0]
 
 
+@pytest.mark.parametrize("na,nb", [(3001, 200_003), (1, 70_000), (5, 1)])
+def test_chamfer_lopsided_sets(na, nb):
+    """A small source set against a large destination set (the destinations split over many
+    workgroups), single points, and ragged tiles."""
+    rng = np.random.default_rng(na)
+    a = rng.uniform(-1, 1, size=(na, 3)).astype(np.float32)
+    b = rng.normal(0, 0.5, size=(nb, 3)).astype(np.float32)
+    got = quality.chamfer(_t(a), _t(b))
+    ref_ab = qo.chamfer(a.astype(np.float64), b.astype(np.float64))
+    assert abs(got[0] - ref_ab) <= 1e-5 * ref_ab
+    swapped = quality.chamfer(_t(b), _t(a))
+    assert abs(swapped[1] - got[2]) <= 1e-12 * got[2] and abs(swapped[2] - got[1]) <= 1e-12 * got[1]
+
+
 def test_quality_of_a_fitted_grid():
     """Fit 64^3 K=2 to the scene for 150 steps; IoU on 100k uniform points and the Chamfer
     distance between the mesh of the grid's vertex values and 50k analytic surface points.
