@@ -214,14 +214,14 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
     __shared__ int32_t wsum[NOWN / 64];
 
     // Items of bricks with more than one pass of records come first (the longest work
-    // starts first), the others from the array's end.
+    // starts first), the others from the array's end; in XCD-aware order.
     const int32_t nfront = meta[META_BFRONT], nback = meta[META_BBACK];
-    const int32_t bid = blockIdx.x;
+    const int32_t bid = blockIdx.x, lb = xcd_grouped<kXcdGroup>(bid, nfront + nback);
     int32_t item;
-    if (bid < nfront) {
-        item = bid;
-    } else if (bid < nfront + nback) {
-        item = (int32_t)(max_items - 1 - (bid - nfront));
+    if (lb < nfront) {
+        item = lb;
+    } else if (lb < nfront + nback) {
+        item = (int32_t)(max_items - 1 - (lb - nfront));
     } else {
         if constexpr (AD >= 0) {
             if (threadIdx.x == 0) AB.partials[bid] = 0.0;

@@ -317,6 +317,21 @@ __device__ __forceinline__ void corner_offset(const AxisFactors<DIM>& F, int b, 
     for (int a = 0; a < DIM; ++a) d[a] = F.Dd[a][(b >> a) & 1];
 }
 
+// XCD-aware order of work items.  The hardware deals workgroups round-robin to the 8 XCDs,
+// each with its own L2; within every run of 8 G workgroups this hands XCD x the G
+// consecutive items x G .. x G + G - 1, so that neighbouring bricks in the list (which share
+// the cache lines at their common face) are processed by one L2, while the runs stay short
+// enough that crowded stretches of the list still spread over all XCDs.  A bijection of
+// [0, n): a trailing partial run and workgroups from n on keep their own index.
+template <int G>
+__device__ __forceinline__ int32_t xcd_grouped(int32_t bid, int32_t n)
+{
+    const int32_t run = bid / (8 * G);
+    if ((run + 1) * (8 * G) > n) return bid;
+    return run * (8 * G) + (bid % 8) * G + (bid / 8) % G;
+}
+constexpr int kXcdGroup = 4;
+
 // ------------------------------------------------------------------ Adam (shared by the
 // stand-alone optimizer kernel and the adjoint kernel that applies it in the same pass)
 struct AdamArgs {

@@ -110,12 +110,12 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
     constexpr int NH = DIM == 3 ? 6 : 3;
     __shared__ __align__(16) uint32_t lds[NWIN * 64];
 
-    // Work item = (brick, chunk of up to kFwdChunk primary records), in list order.  Blocks
-    // are dealt round-robin to the 8 XCDs, so the crowded bricks of a surface, which are
-    // neighbours in the list, spread over all of them (giving each XCD a contiguous range of
-    // items instead was measured slower: the XCDs holding the surface finished last).
+    // Work item = (brick, chunk of up to kFwdChunk primary records), in XCD-aware list order:
+    // short runs of neighbouring items per XCD, so the crowded bricks of a surface, which are
+    // neighbours in the list, still spread over all XCDs (giving each XCD one contiguous
+    // range of items instead was measured slower: the XCDs holding the surface finished last).
     const int32_t total = meta[META_FITEMS];
-    const int32_t item = (int32_t)blockIdx.x;
+    const int32_t item = xcd_grouped<kXcdGroup>((int32_t)blockIdx.x, total);
     const int4 wi = item < total ? items[item] : make_int4(0, 0, 0, 0);
     const int32_t brick = wi.x, beg = wi.y, end = wi.z;
     if (beg >= end) {
