@@ -204,9 +204,16 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
     using S = BwdShape<DIM>;
     constexpr int B = S::B, NOWN = S::NOWN, NCELL = S::NCELL, NRUN = S::NRUN, PER = S::PER, NBIN = S::NBIN;
     constexpr int C = NumCoeffs<DIM, K>::value;
-    // Per staged record, in cell order: (t, g_f), (1 - t, g_grad_x), (t h, g_grad_y),
-    // ((t - 1) h, g_grad_z): the corner factors of both sides of every axis, precomputed.
-    __shared__ float4 ent[4 * kBwdItem];
+    // Per staged record, in cell order: (g_f, g_grad), then per axis the corner factors of
+    // both sides, (1 - t, t h) for the corner below and (t, (t - 1) h) for the corner above
+    // (weight factor, offset from the vertex in world units), so that a visit reads 16 B plus
+    // the one 8 B pair per axis that its corner needs, chosen by address.
+    // In 3D, records are 5 float4 apart (80 B, one unused): at 64 B, the lanes of a wave,
+    // which read different records, all hit the same two groups of 4 LDS banks; at 80 B,
+    // 8 consecutive records start on 8 different groups.  (2D keeps 64 B: its 4 workgroups
+    // per CU would not fit in the LDS at 80 B.)
+    constexpr int kEntStride = DIM == 3 ? 5 : 4;
+    __shared__ float4 ent[kEntStride * kBwdItem];
     __shared__ uint32_t cstart[NCELL + 1];
     __shared__ uint32_t ccount[NCELL];
     __shared__ uint32_t bins[NBIN];
@@ -375,11 +382,12 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
             if (my_cell[u] < 0) continue;
             const uint32_t pos = cstart[my_cell[u]] + my_rank[u];
             const float4 t = my_t[u], sg = my_g[u];
-            ent[4 * pos] = t;
-            ent[4 * pos + 1] = make_float4(1.0f - t.x, 1.0f - t.y, 1.0f - t.z, sg.x);
-            ent[4 * pos + 2] = make_float4(t.x * g.h[0], t.y * g.h[1], DIM == 3 ? t.z * g.h[2] : 0.0f, sg.y);
-            ent[4 * pos + 3] = make_float4((t.x - 1.0f) * g.h[0], (t.y - 1.0f) * g.h[1],
-                                           DIM == 3 ? (t.z - 1.0f) * g.h[2] : 0.0f, sg.z);
+            const float ta[3] = {t.x, t.y, t.z};
+            ent[kEntStride * pos] = make_float4(t.w, sg.x, sg.y, sg.z);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+                ent[kEntStride * pos + 1 + a] =
+                    make_float4(1.0f - ta[a], ta[a] * g.h[a], ta[a], (ta[a] - 1.0f) * g.h[a]);
         }
 
         int v[3];
@@ -434,38 +442,46 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
                     md = mid[jj];
                     j = jj;
                 }
+            // b[a]: the record lies in the cell below the vertex on axis a, so the vertex is
+            // that cell's upper corner
             const bool b[3] = {e < md, (j & 1) != 0, (j >> 1) != 0};
-            const float4 E0 = ent[4 * e], E1 = ent[4 * e + 1], E2 = ent[4 * e + 2], E3 = ent[4 * e + 3];
-            const float tt[3] = {E0.x, E0.y, E0.z}, om[3] = {E1.x, E1.y, E1.z};
-            const float th[3] = {E2.x, E2.y, E2.z}, tm[3] = {E3.x, E3.y, E3.z};
-            const float sg[3] = {E1.w, E2.w, E3.w};
-            float fa[DIM], d[DIM], sa[DIM];
+            // e < kBwdItem: the 24-bit multiply is full rate (a 32-bit one takes 4 passes)
+            const float* er = reinterpret_cast<const float*>(reinterpret_cast<const char*>(ent) +
+                                                             __umul24(e, (uint32_t)sizeof(float4) * kEntStride));
+            const float4 E0 = *reinterpret_cast<const float4*>(er);
+            const float sg[3] = {E0.y, E0.z, E0.w};
+            float fa[DIM], d[DIM];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                fa[a] = b[a] ? tt[a] : om[a];          // this corner's weight factor on axis a
-                d[a] = b[a] ? tm[a] : th[a];           // offset from the vertex, world units
-                sa[a] = b[a] ? g.inv_h[a] : -g.inv_h[a];
+                const float2 P = *reinterpret_cast<const float2*>(er + 4 * (1 + a) + (b[a] ? 2 : 0));
+                fa[a] = P.x;  // this corner's weight factor on axis a
+                d[a] = P.y;   // offset from the vertex, world units
             }
-            float w, dw[DIM];
+            float w, fo[DIM];  // fo[a]: product of the other axes' factors
             if constexpr (DIM == 3) {
-                const float fyz = fa[1] * fa[2], fxz = fa[0] * fa[2], fxy = fa[0] * fa[1];
-                w = fa[0] * fyz;
-                dw[0] = sa[0] * fyz;
-                dw[1] = sa[1] * fxz;
-                dw[2] = sa[2] * fxy;
+                fo[0] = fa[1] * fa[2];
+                fo[1] = fa[0] * fa[2];
+                fo[2] = fa[0] * fa[1];
+                w = fa[0] * fo[0];
             } else {
+                fo[0] = fa[1];
+                fo[1] = fa[0];
                 w = fa[0] * fa[1];
-                dw[0] = sa[0] * fa[1];
-                dw[1] = sa[1] * fa[0];
+            }
+            float dw[DIM];  // d w / d x_a: +-(1/h_a) fo[a], + for the upper corner
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                const float p = g.inv_h[a] * fo[a];
+                dw[a] = b[a] ? p : -p;
             }
             if constexpr (K == kOrderRGB1) {
                 // each channel is an order-1 series with upstream value only
-                const float up[kRGB] = {E0.w, sg[0], sg[1]};
+                const float up[kRGB] = {E0.x, sg[0], sg[1]};
                 const float zero[DIM] = {};
 #pragma unroll
                 for (int ch = 0; ch < kRGB; ++ch) accumulate_corner<DIM, 1>(d, up[ch] * w, zero, acc + ch * (1 + DIM));
             } else {
-                float s = E0.w * w;
+                float s = E0.x * w;
                 float uu[DIM];
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
