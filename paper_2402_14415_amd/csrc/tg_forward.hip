@@ -138,12 +138,36 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
     }
 
     // Stage the brick's vertices.  The (B+1)^dim vertex blocks are NROWS rows of ROWW
-    // contiguous words in memory, kept in the same order in LDS; every wave copies 64-word
-    // windows of the flattened rows straight from global memory into LDS (global_load_lds),
-    // all in flight at once and without passing through registers.  Words of rows or
-    // vertices outside the grid are not loaded (no query reads them).
+    // contiguous words in memory, kept in the same order in LDS; the waves copy them straight
+    // from global memory into LDS (global_load_lds), all in flight at once and without
+    // passing through registers.  Words of rows or vertices outside the grid are not loaded
+    // (no query reads them).
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if constexpr (SF::DMA) {
+    if constexpr (SF::DMA && ROWW >= 32) {
+        // Rows of at least half a wave: a wave copies whole rows, 64 words per load, so the
+        // row's position (wave-uniform) is computed once in scalar registers and a lane only
+        // adds its word offset.  (Per-lane row and column arithmetic in 64-bit cost ~45 vector
+        // instructions per load, most of this kernel's instruction issue.)
+        constexpr int NCH = (ROWW + 63) / 64;
+        const uint32_t* src = static_cast<const uint32_t*>(coeffs);
+        const int nw0 = nv[0] * SF::WPV;  // words of the row inside the grid
+        for (int row = __builtin_amdgcn_readfirstlane(wave); row < NROWS; row += kThreads / 64) {
+            const int ry = DIM == 3 ? row % NV1 : row;
+            const int rz = DIM == 3 ? row / NV1 : 0;
+            if (ry >= nv[1] || (DIM == 3 && rz >= nv[2])) continue;
+            int64_t vrow = (int64_t)v0[0] + (int64_t)(v0[1] + ry) * g.stride[1];
+            if constexpr (DIM == 3) vrow += (int64_t)(v0[2] + rz) * g.stride[2];
+            const uint32_t* rsrc = src + vrow * SF::WPV;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int off = c * 64 + lane;
+                if (off < nw0)
+                    __builtin_amdgcn_global_load_lds(static_cast<const void*>(rsrc + off),
+                                                     (lds_addr_t)(lds + row * ROWW + c * 64), 4, 0, 0);
+            }
+        }
+    } else if constexpr (SF::DMA) {
+        // short rows: 64-word windows of the flattened rows
         const uint32_t* src = static_cast<const uint32_t*>(coeffs);
         for (int w = wave; w < NWIN; w += kThreads / 64) {
             const int base = w * 64;
