@@ -148,23 +148,31 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
         // row's position (wave-uniform) is computed once in scalar registers and a lane only
         // adds its word offset.  (Per-lane row and column arithmetic in 64-bit cost ~45 vector
         // instructions per load, most of this kernel's instruction issue.)
+        // The rows inside the grid are walked z by z, each wave taking every NW-th y row, with
+        // the source pointer advanced by additions (a few scalar instructions per row).
         constexpr int NCH = (ROWW + 63) / 64;
-        const uint32_t* src = static_cast<const uint32_t*>(coeffs);
+        constexpr int NW = kThreads / 64;
         const int nw0 = nv[0] * SF::WPV;  // words of the row inside the grid
-        for (int row = __builtin_amdgcn_readfirstlane(wave); row < NROWS; row += kThreads / 64) {
-            const int ry = DIM == 3 ? row % NV1 : row;
-            const int rz = DIM == 3 ? row / NV1 : 0;
-            if (ry >= nv[1] || (DIM == 3 && rz >= nv[2])) continue;
-            int64_t vrow = (int64_t)v0[0] + (int64_t)(v0[1] + ry) * g.stride[1];
-            if constexpr (DIM == 3) vrow += (int64_t)(v0[2] + rz) * g.stride[2];
-            const uint32_t* rsrc = src + vrow * SF::WPV;
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        const int nz = DIM == 3 ? nv[2] : 1;
+        const int64_t ystep = g.stride[1] * SF::WPV;  // words from one y row to the next
+        int64_t v00 = (int64_t)v0[0] + (int64_t)v0[1] * g.stride[1];
+        if constexpr (DIM == 3) v00 += (int64_t)v0[2] * g.stride[2];
+        const uint32_t* zsrc = static_cast<const uint32_t*>(coeffs) + v00 * SF::WPV;
+        for (int rz = 0; rz < nz; ++rz) {
+            const uint32_t* rsrc = zsrc + wv * ystep;
+            for (int ry = wv; ry < nv[1]; ry += NW) {
+                const int row = rz * NV1 + ry;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                const int off = c * 64 + lane;
-                if (off < nw0)
-                    __builtin_amdgcn_global_load_lds(static_cast<const void*>(rsrc + off),
-                                                     (lds_addr_t)(lds + row * ROWW + c * 64), 4, 0, 0);
+                for (int c = 0; c < NCH; ++c) {
+                    const int off = c * 64 + lane;
+                    if (off < nw0)
+                        __builtin_amdgcn_global_load_lds(static_cast<const void*>(rsrc + off),
+                                                         (lds_addr_t)(lds + row * ROWW + c * 64), 4, 0, 0);
+                }
+                rsrc += NW * ystep;
             }
+            if constexpr (DIM == 3) zsrc += g.stride[2] * SF::WPV;
         }
     } else if constexpr (SF::DMA) {
         // short rows: 64-word windows of the flattened rows
