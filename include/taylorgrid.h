@@ -38,7 +38,11 @@
  *    the call returns a non-zero tg_status and enqueues nothing (outputs untouched).  A
  *    launch failure is reported as TG_ERR_DEVICE.  tg_last_error() returns a thread-local
  *    description of the last failure.  No call aborts or throws.
- *  Sizes: n = 0 is a no-op returning TG_OK.  n must be below 2^31.
+ *  Sizes: n = 0 is a no-op returning TG_OK.  Calls that sort queries take n <= (2^31 - 1) /
+ *    2^dim (a query makes up to 2^dim int32-indexed sort records); the others n <= 2^28.
+ *  Sorting: tg_forward, tg_backward, tg_forward_sdf_loss and tg_backward_adam read the
+ *    bucketing of (q, n) that tg_sort_queries (or tg_train_step) wrote into ws, and fail with
+ *    TG_ERR_STATE without it; one sort serves any number of these calls.
  *  Concurrency: calls on different grid handles may run concurrently.  Calls on one
  *    handle must be serialised by the caller (the handle records the last sort).
  */
@@ -125,7 +129,8 @@ typedef struct {
 } tg_request;
 
 /* Flags. */
-#define TG_BWD_ACCUMULATE 1  /* tg_backward: grad += contribution (default: grad = contribution) */
+#define TG_BWD_ACCUMULATE 1  /* tg_backward: grad += contribution (default: grad = contribution,
+                                which saves the training loop a separate zeroing pass over grad) */
 #define TG_ADAM_ZERO_GRAD 1  /* tg_adam_step: zero grad after reading it */
 #define TG_BWD_ADD_GRAD 1    /* tg_backward_adam: add bufs.grad (e.g. tg_tv_loss's gradient) to the
                                 adjoint before the update */
@@ -351,9 +356,10 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
  * with Adam and the
  * final FP64 reductions of the loss and the gradient norm (for timing). */
 
-/* One Adam step over every coefficient (the paper trains the grid with a fixed learning
- * rate and names no optimizer; this is Adam with bias correction, eps added to the
- * corrected root, and weight decay added to the gradient):
+/* One Adam step over every coefficient.  The grid is optimised directly by gradient descent
+ * with no network (Sec. 3.1); Sec. 4.1 trains it with a fixed learning rate and names no
+ * optimizer.  This is Adam with bias correction, eps added to the corrected root, and weight
+ * decay added to the gradient:
  *   g' = grad + wd*master; m = b1 m + (1-b1) g'; v = b2 v + (1-b2) g'^2;
  *   master -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
  * then, when storage != TG_F32, coeffs = round_to_nearest_even(master) (FP16 saturates to
@@ -362,9 +368,10 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
 tg_status tg_adam_step(tg_grid* grid, const tg_adam_params* params, double* grad_norm_sq,
                        void* ws, size_t ws_bytes, int32_t flags, void* stream);
 
-/* Serving: field value and unit normal for a batch of requests against several resident
- * grids, in one launch per group of up to TG_QUERY_MAX_REQS requests referencing up to
- * TG_QUERY_MAX_GRIDS distinct grids (larger batches are split into several launches).
+/* Serving: field value (Sec. 3.1, Eq. 2-4) and unit normal, the normalised spatial gradient
+ * of that field (the SDF's normal, Sec. 3.2), for a batch of requests against several
+ * resident grids, in one launch per group of up to TG_QUERY_MAX_REQS requests referencing up
+ * to TG_QUERY_MAX_GRIDS distinct grids (larger batches are split into several launches).
  * grids (host array of handles) and reqs (host array) are read during the call only; no
  * workspace or sort is needed.  The arithmetic per query is the same as tg_forward's, so a
  * request's result does not depend on which other requests share the launch. */
@@ -372,6 +379,12 @@ tg_status tg_adam_step(tg_grid* grid, const tg_adam_params* params, double* grad
 #define TG_QUERY_MAX_GRIDS 16
 tg_status tg_query(const tg_grid* const* grids, int32_t n_grids, const tg_request* reqs,
                    int32_t n_reqs, void* stream);
+
+/* Write the storage copy `coeffs` from `master` (16-bit storage): round to nearest even,
+ * FP16 saturating at +-65504 -- the conversion tg_adam_step applies after every update, for a
+ * master set outside the library (initial values, a checkpoint).  FP32 storage: nothing to
+ * do (coeffs is master).  Needs bufs.master and bufs.coeffs for 16-bit storage. */
+tg_status tg_sync_storage(tg_grid* grid, void* stream);
 
 /* Static description of a status code; never NULL. */
 const char* tg_status_string(tg_status status);

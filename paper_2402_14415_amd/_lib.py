@@ -91,6 +91,7 @@ _SIGS = {
                      ctypes.c_int),
     "tg_adam_step": ([_P, ctypes.POINTER(AdamParams), _P, _P, ctypes.c_size_t, ctypes.c_int32, _P], ctypes.c_int),
     "tg_query": ([ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(Request), ctypes.c_int32, _P], ctypes.c_int),
+    "tg_sync_storage": ([_P, _P], ctypes.c_int),
     "tg_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "tg_last_error": ([], ctypes.c_char_p),
 }

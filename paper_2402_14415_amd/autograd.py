@@ -4,7 +4,9 @@
 gradient (needed for normals and the eikonal term of Sec. 3.2, Eq. 8).  Gradients flow to
 ``grid.master`` (the FP32 parameters; with 16-bit storage the forward reads the rounded
 copy and the gradient is applied to the master) and, if requested, to the queries.  Both
-adjoints run in the HIP kernels (tg_backward); this module only routes tensors.
+adjoints run in the HIP kernels (tg_backward); this module only routes tensors.  The
+backward is differentiable once: the adjoint kernels have no adjoint of their own, so a
+second-order graph (``create_graph=True``) raises instead of returning wrong gradients.
 """
 from __future__ import annotations
 
@@ -24,6 +26,7 @@ class TaylorGridFn(torch.autograd.Function):
         return f, g
 
     @staticmethod
+    @torch.autograd.function.once_differentiable
     def backward(ctx, g_f, g_grad):
         (q,) = ctx.saved_tensors
         grid, ws = ctx.grid, ctx.ws

@@ -19,9 +19,13 @@ namespace {
 
 thread_local std::string g_last_error;
 
-// Sort generation of every workspace a sort was written into.  A handle's recorded sort is
-// current only while its generation is the workspace's: a later sort into the same
-// workspace, by any handle, supersedes it.
+// Sort generation of the workspaces sorts were last written into.  A handle's recorded sort
+// is current only while its generation is the workspace's: a later sort into the same
+// workspace, by any handle, supersedes it.  The table is the library's only process-wide
+// state; it keeps the kMaxWorkspaces most recently sorted workspaces, and a workspace that
+// drops out of it reads as holding no sort (calls on it fail with TG_ERR_STATE until it is
+// sorted again), so forgetting an entry can never make a stale sort look current.
+constexpr size_t kMaxWorkspaces = 1024;
 std::mutex g_ws_mutex;
 std::unordered_map<const void*, uint64_t> g_ws_gen;
 uint64_t g_next_gen = 0;
@@ -31,6 +35,12 @@ uint64_t ws_new_generation(const void* ws)
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     const uint64_t gen = ++g_next_gen;
     g_ws_gen[ws] = gen;
+    if (g_ws_gen.size() > kMaxWorkspaces) {
+        auto oldest = g_ws_gen.begin();
+        for (auto it = g_ws_gen.begin(); it != g_ws_gen.end(); ++it)
+            if (it->second < oldest->second) oldest = it;
+        g_ws_gen.erase(oldest);
+    }
     return gen;
 }
 
@@ -225,8 +235,7 @@ tg_status tg_create(const tg_grid_desc* desc, const tg_grid_buffers* bufs, tg_gr
             const double h = ((double)d.hi[a] - (double)d.lo[a]) / (double)(d.res[a] - 1);
             G.h[a] = (float)h;
             G.inv_h[a] = (float)(1.0 / h);
-            G.lo_d[a] = (double)d.lo[a];
-            G.inv_h_d[a] = 1.0 / h;
+            G.inv_h_lo[a] = (float)(1.0 / h - (double)G.inv_h[a]);
             G.stride[a] = stride;
             stride *= d.res[a];
             nb *= G.nvb[a];
@@ -237,8 +246,7 @@ tg_status tg_create(const tg_grid_desc* desc, const tg_grid_buffers* bufs, tg_gr
             G.hi[a] = 1.0f;
             G.h[a] = 1.0f;
             G.inv_h[a] = 1.0f;
-            G.lo_d[a] = 0.0;
-            G.inv_h_d[a] = 1.0;
+            G.inv_h_lo[a] = 0.0f;
             G.stride[a] = stride;
         }
     }
@@ -269,7 +277,7 @@ size_t tg_reduce_workspace_bytes(void)
 
 size_t tg_workspace_bytes(const tg_grid* grid, int64_t n)
 {
-    if (!grid || n < 0 || n > tg::kMaxQueries) return 0;
+    if (!grid || n < 0 || n > tg::max_sorted_queries(grid->desc.dim)) return 0;
     return tg::ws_layout(grid, n).total;
 }
 
@@ -278,7 +286,9 @@ static tg_status check_queries(const char* fn, const tg_grid* grid, const float*
 {
     if (!grid) return fail(TG_ERR_INVALID_ARG, "%s: grid is NULL", fn);
     if (n < 0) return fail(TG_ERR_INVALID_ARG, "%s: n = %lld is negative", fn, (long long)n);
-    if (n > tg::kMaxQueries) return fail(TG_ERR_CAPACITY, "%s: n = %lld exceeds %lld", fn, (long long)n, (long long)tg::kMaxQueries);
+    if (n > tg::max_sorted_queries(grid->desc.dim))
+        return fail(TG_ERR_CAPACITY, "%s: n = %lld exceeds %lld (n 2^dim sort records must stay below 2^31)", fn,
+                    (long long)n, (long long)tg::max_sorted_queries(grid->desc.dim));
     if (n > 0 && !q) return fail(TG_ERR_INVALID_ARG, "%s: q is NULL", fn);
     if (!ws) return fail(TG_ERR_INVALID_ARG, "%s: workspace is NULL", fn);
     if (!aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "%s: workspace must be 256-byte aligned", fn);
@@ -706,6 +716,16 @@ tg_status tg_adam_step(tg_grid* grid, const tg_adam_params* p, double* grad_norm
     return device_status(tg::launch_adam(grid, *p, grad_norm_sq, static_cast<double*>(ws), (flags & TG_ADAM_ZERO_GRAD) != 0,
                                          static_cast<hipStream_t>(stream)),
                          "tg_adam_step");
+}
+
+tg_status tg_sync_storage(tg_grid* grid, void* stream)
+{
+    if (!grid) return fail(TG_ERR_INVALID_ARG, "tg_sync_storage: grid is NULL");
+    if (grid->desc.storage == TG_F32) return ok();
+    if (!grid->bufs.master || !grid->bufs.coeffs)
+        return fail(TG_ERR_INVALID_ARG, "tg_sync_storage: master and coeffs are required");
+    (void)hipGetLastError();
+    return device_status(tg::launch_sync_storage(grid, static_cast<hipStream_t>(stream)), "tg_sync_storage");
 }
 
 tg_status tg_query(const tg_grid* const* grids, int32_t n_grids, const tg_request* reqs, int32_t n_reqs, void* stream)

@@ -45,34 +45,51 @@ struct Geom {
     float lo[3], hi[3];
     float h[3];         // vertex spacing
     float inv_h[3];
-    double lo_d[3];     // FP64 copies for the cell location
-    double inv_h_d[3];
+    float inv_h_lo[3];  // 1/h - inv_h (rounded to FP32): with inv_h, 1/h to about 48 bits
     int64_t stride[3];  // vertex strides (x fastest)
 };
 
-// Cell location of one query on one axis (Eq. 2).  The cell index is computed in FP64 so
-// that it agrees with an FP64 reference except for points within one FP64 rounding of a
-// face; every kernel calls this same function so the sort, the forward and the backward
-// always agree on a query's cell.
+// Cell location of one query on one axis (Eq. 2), in FP32 arithmetic.  The clamped
+// coordinate's offset x - lo is formed exactly as an unevaluated sum of two floats (the
+// two-sum of Knuth), and multiplied by 1/h = inv_h + inv_h_lo with the rounding error of the
+// leading product recovered exactly by an FMA (Dekker's product), so s = (x - lo)/h is held
+// to about 2^-46 of itself.  The cell is the floor of that two-float value (its low part
+// decides when the high part is an integer), so it agrees with a floor taken in FP64
+// except for points within about 2^-46 s of a face, where both adjacent cells are correct
+// (the field is continuous across the face).  t = s - cell keeps the low part.  FMA
+// contraction is off in this function: a fused multiply-add in place of a product or sum
+// would break the error-free transformations.  Every kernel calls this same function, so
+// the sort, the forward and the adjoint always agree on a query's cell.
 struct AxisLoc {
     int32_t cell;  // in [0, res - 2]
     float t;       // local coordinate in [0, 1]
     bool clamped;  // the query lay outside [lo, hi] on this axis
 };
 
-__device__ __forceinline__ AxisLoc locate_axis(float q, float lo, float hi, double lo_d,
-                                               double inv_h_d, int32_t res)
+__device__ __forceinline__ AxisLoc locate_axis(float q, float lo, float hi, float inv_h, float inv_h_lo,
+                                               int32_t res)
 {
+#pragma clang fp contract(off)
     AxisLoc L;
     L.clamped = (q < lo) || (q > hi);
     const float x = fminf(fmaxf(q, lo), hi);  // a NaN query lands on lo
-    const double s = __dmul_rn(__dsub_rn((double)x, lo_d), inv_h_d);
-    double fl = floor(s);
+    // x - lo = dh + dl exactly
+    const float dh = x - lo;
+    const float xb = dh - x;  // the part of dh that came from -lo
+    const float dl = (x - (dh - xb)) + (-lo - xb);
+    // (dh + dl) (inv_h + inv_h_lo) = sh + sl
+    const float p = dh * inv_h;
+    float e = __builtin_fmaf(dh, inv_h, -p);  // exact rounding error of p
+    e = __builtin_fmaf(dh, inv_h_lo, __builtin_fmaf(dl, inv_h, e));
+    const float sh = p + e;
+    const float sl = e - (sh - p);
+    float fl = floorf(sh);
+    if (sh == fl && sl < 0.0f) fl = fl - 1.0f;
     int32_t c = (int32_t)fl;
     c = c < 0 ? 0 : c;
     c = c > res - 2 ? res - 2 : c;
     L.cell = c;
-    L.t = (float)__dsub_rn(s, (double)c);
+    L.t = (sh - (float)c) + sl;  // sh - c is exact for sh in [c, c + 2)
     return L;
 }
 
@@ -80,7 +97,7 @@ template <int DIM>
 __device__ __forceinline__ void locate(const Geom& g, const float* q, AxisLoc* L)
 {
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) L[a] = locate_axis(q[a], g.lo[a], g.hi[a], g.lo_d[a], g.inv_h_d[a], g.res[a]);
+    for (int a = 0; a < DIM; ++a) L[a] = locate_axis(q[a], g.lo[a], g.hi[a], g.inv_h[a], g.inv_h_lo[a], g.res[a]);
 }
 
 // ------------------------------------------------------------------ storage conversions

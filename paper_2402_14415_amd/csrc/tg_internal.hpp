@@ -43,7 +43,13 @@ constexpr int kBwdItemMax = 2048;        // records per backward work item (4 pa
 constexpr int64_t kMaxMeshCells = (int64_t)1 << 28;  // 12 triangles per cell stay below 2^32
 constexpr int kMaxReduceBlocks = 2048;  // FP64 partials: 4 per block
 constexpr size_t kReduceBytes = (size_t)kMaxReduceBlocks * 4 * sizeof(double);
-constexpr int64_t kMaxQueries = (int64_t)1 << 28;  // sort entries stay below 2^31
+constexpr int64_t kMaxQueries = (int64_t)1 << 28;  // points per call of the unsorted measures
+// Queries per sorted call: a query makes up to 2^dim sort records (its primary bucket and the
+// neighbouring vertex bricks that own corners of its cell), whose positions are int32.
+constexpr int64_t max_sorted_queries(int dim)
+{
+    return (int64_t)0x7fffffff >> dim;
+}
 
 // Workspace layout of one grid for n queries.  Offsets are from the workspace base and
 // 256-byte aligned.
@@ -136,6 +142,8 @@ hipError_t launch_composite(int64_t n_rays, int32_t ns, const float* f, const fl
                             const float* target, float* rgb, double* loss, float* g_f, float* g_c, double* partials,
                             hipStream_t s);
 AdamArgs make_adam_args(const tg_adam_params& p);
+// coeffs = the storage rounding of master (16-bit storage; nothing to do for FP32).
+hipError_t launch_sync_storage(const tg_grid* g, hipStream_t s);
 hipError_t launch_query(const tg_grid* const* grids, int32_t n_grids, const tg_request* reqs, int32_t n_reqs,
                         hipStream_t s);
 

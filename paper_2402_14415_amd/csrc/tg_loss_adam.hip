@@ -272,4 +272,39 @@ hipError_t launch_adam(const tg_grid* g, const tg_adam_params& p, double* grad_n
     return hipGetLastError();
 }
 
+// The storage copy of the master coefficients: round to nearest even, FP16 saturating at
+// +-65504 (the conversion the Adam update applies after every step).
+template <int ST>
+__global__ __launch_bounds__(kThreads) void k_sync_storage(int64_t n, const float* __restrict__ master,
+                                                           void* __restrict__ coeffs)
+{
+    const int64_t n4 = n / 4;
+    const float4* th4 = reinterpret_cast<const float4*>(master);
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n4; i += (int64_t)gridDim.x * kThreads) {
+        const float4 t = th4[i];
+        uint2 packed;
+        if constexpr (ST == ST_BF16)
+            packed = make_uint2((uint32_t)float_to_bf16_rne(t.x) | ((uint32_t)float_to_bf16_rne(t.y) << 16),
+                                (uint32_t)float_to_bf16_rne(t.z) | ((uint32_t)float_to_bf16_rne(t.w) << 16));
+        else
+            packed = make_uint2((uint32_t)float_to_f16_rne_sat(t.x) | ((uint32_t)float_to_f16_rne_sat(t.y) << 16),
+                                (uint32_t)float_to_f16_rne_sat(t.z) | ((uint32_t)float_to_f16_rne_sat(t.w) << 16));
+        reinterpret_cast<uint2*>(coeffs)[i] = packed;
+    }
+    if (blockIdx.x == 0)
+        for (int64_t i = n4 * 4 + threadIdx.x; i < n; i += kThreads) store_copy<ST>(coeffs, i, master[i]);
+}
+
+hipError_t launch_sync_storage(const tg_grid* g, hipStream_t s)
+{
+    const int64_t n = g->nvert * g->C;
+    if (g->desc.storage == ST_F32 || n == 0) return hipSuccess;
+    const dim3 grid(reduce_blocks(n / 4 + 1, 8)), block(kThreads);
+    if (g->desc.storage == ST_BF16)
+        hipLaunchKernelGGL(k_sync_storage<ST_BF16>, grid, block, 0, s, n, g->bufs.master, g->bufs.coeffs);
+    else
+        hipLaunchKernelGGL(k_sync_storage<ST_F16>, grid, block, 0, s, n, g->bufs.master, g->bufs.coeffs);
+    return hipGetLastError();
+}
+
 }  // namespace tg

@@ -17,7 +17,7 @@ struct QGrid {
     const void* coeffs;
     int32_t res[3];
     float lo[3], hi[3], h[3], inv_h[3];
-    double inv_h_d[3];
+    float inv_h_lo[3];
     int8_t dim, order, storage, pad_;
 };
 
@@ -49,8 +49,7 @@ __device__ __forceinline__ void serve_point(const QGrid& G, const float* qp, flo
         g.hi[a] = G.hi[a];
         g.h[a] = G.h[a];
         g.inv_h[a] = G.inv_h[a];
-        g.lo_d[a] = (double)G.lo[a];
-        g.inv_h_d[a] = G.inv_h_d[a];
+        g.inv_h_lo[a] = G.inv_h_lo[a];
     }
     float q[3];
 #pragma unroll
@@ -158,7 +157,7 @@ hipError_t launch_query(const tg_grid* const* grids, int32_t n_grids, const tg_r
                     G.hi[a] = gp->geom.hi[a];
                     G.h[a] = gp->geom.h[a];
                     G.inv_h[a] = gp->geom.inv_h[a];
-                    G.inv_h_d[a] = gp->geom.inv_h_d[a];
+                    G.inv_h_lo[a] = gp->geom.inv_h_lo[a];
                 }
             }
             const int64_t nb = (reqs[i].n + kThreads - 1) / kThreads;

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kThreads) void k_upsample(Geom gc, Geom gf, const f
                 rem /= gf.res[a];
                 const int64_t num = i * (int64_t)(gc.res[a] - 1), den = gf.res[a] - 1;
                 int64_t cell = num / den;
-                float t = (float)((double)(num - cell * den) / (double)den);
+                float t = (float)(num - cell * den) / (float)den;  // both below 2^16: exact operands, one rounding
                 if (cell > gc.res[a] - 2) {
                     cell = gc.res[a] - 2;
                     t = 1.0f;

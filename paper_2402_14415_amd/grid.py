@@ -93,12 +93,12 @@ class TaylorGrid:
             self.C = coeffs_per_vertex(self.dim, self.order)
         self.shape = tuple(reversed(self.res)) + (self.C,)
 
+        # the grid owns its master: a copy, never a view of the caller's tensor
+        master = torch.zeros(self.shape, dtype=torch.float32, device=self.device)
         if coeffs is not None:
-            master = torch.as_tensor(coeffs).to(device=self.device, dtype=torch.float32).reshape(self.shape).contiguous()
-        else:
-            master = torch.zeros(self.shape, dtype=torch.float32, device=self.device)
+            master.copy_(torch.as_tensor(coeffs).reshape(self.shape))
         self.master = master
-        self.coeffs = master if storage == "f32" else master.to(sdt)
+        self.coeffs = master if storage == "f32" else torch.empty(self.shape, dtype=sdt, device=self.device)
         self.grad = torch.zeros_like(master)
         if optimizer:
             self.adam_m = torch.zeros_like(master)
@@ -122,6 +122,7 @@ class TaylorGrid:
         _lib.call("tg_create", ctypes.byref(desc), ctypes.byref(self._buffers()), ctypes.byref(handle))
         self._h = handle
         self._sorted = None  # (q tensor, ws tensor, sort generation) of the last sort
+        self.sync_storage()
 
     # ------------------------------------------------------------------ plumbing
     def _buffers(self, grad=None):
@@ -148,9 +149,9 @@ class TaylorGrid:
         return self._h
 
     def sync_storage(self):
-        """Refresh the storage copy from the master (round to nearest even)."""
-        if self.storage != "f32":
-            self.coeffs.copy_(self.master.to(self.coeffs.dtype))
+        """Refresh the storage copy from the master in the library (round to nearest even,
+        FP16 saturating at +-65504); call it after changing ``master`` outside the library."""
+        _lib.call("tg_sync_storage", self._h, _stream(self.device))
 
     def workspace_bytes(self, n):
         return int(_lib.lib().tg_workspace_bytes(self._h, int(n)))

@@ -366,3 +366,29 @@ def test_channels_validation():
     finally:
         assert L().tg_destroy(h) == 0
         assert L().tg_destroy(h1) == 0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sorted_query_count_is_capped(dim):
+    """A query makes up to 2^dim sort records with int32 positions, so the sorted calls
+    accept n <= (2^31 - 1) >> dim and refuse one more before anything is enqueued."""
+    st, h = _create(_desc(dim=dim, res=(16,) * dim))
+    assert st == 0
+    cap = (2 ** 31 - 1) >> dim
+    assert L().tg_workspace_bytes(h, cap) > 0
+    assert L().tg_workspace_bytes(h, cap + 1) == 0
+    big = 1 << 40  # a fake workspace size: validation fails before it is used
+    st = L().tg_sort_queries(h, ctypes.c_void_p(0x1000), cap + 1, ctypes.c_void_p(0x100000), big, None)
+    assert st == 4 and b"2^31" in L().tg_last_error()
+    L().tg_destroy(h)
+
+
+def test_sync_storage_validation():
+    st, h = _create(_desc(storage=1))
+    assert st == 0
+    assert L().tg_sync_storage(None, None) == 1
+    assert L().tg_sync_storage(h, None) == 1  # 16-bit storage without buffers
+    L().tg_destroy(h)
+    st, h = _create(_desc(storage=0))
+    assert L().tg_sync_storage(h, None) == 0  # FP32 storage: nothing to do, nothing enqueued
+    L().tg_destroy(h)

@@ -13,7 +13,7 @@ import torch
 import oracle
 from paper_2402_14415_amd import synth
 from paper_2402_14415_amd.grid import TaylorGrid
-from parity_util import TOL_GRAD, TOL_VALUE, geometry, nerr, nerr_cols, nudge_off_faces, to_np
+from parity_util import TOL_GRAD, TOL_VALUE, FaceRule, geometry, nerr, to_np
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -53,7 +53,6 @@ def test_precision_forward_backward_parity(storage):
     assert not np.array_equal(Cr, C32.astype(np.float64))  # storage really is rounded
     assert np.array_equal(grid.coeffs.float().cpu().double().numpy(), Cr)  # the device copy is that rounding
     q64, _ = synth.scene_batch(scene, 60000, seed=21, step=0)
-    q64 = nudge_off_faces(q64, grid.lo, grid.hi, grid.res)
     n = len(q64)
     q = torch.tensor(q64, dtype=torch.float32, device=DEV)
     ws = grid.workspace(n)
@@ -66,9 +65,11 @@ def test_precision_forward_backward_parity(storage):
     torch.cuda.synchronize()
 
     ref_f, ref_g = oracle.forward(geometry(grid), Cr, q64)
-    ef, eg = nerr(to_np(f), ref_f), nerr_cols(to_np(g), ref_g)
+    rule = FaceRule(geometry(grid), Cr, q64)
+    ef, eg = nerr(to_np(f), ref_f), rule.grad_err(to_np(g), ref_g)
     ref_dC, ref_dq = oracle.backward(geometry(grid), Cr, q64, gf64, gg64, want_dq=True)
-    edc, edq = nerr(to_np(grid.grad).reshape(-1), ref_dC.reshape(-1)), nerr_cols(to_np(dq), ref_dq)
+    edc = rule.dC_err(to_np(grid.grad), ref_dC, gf64, gg64)
+    edq = rule.dq_err(to_np(dq), ref_dq, gf64, gg64)
     print(f"{storage}: arithmetic error f {ef:.2e} grad {eg:.2e} dC {edc:.2e} dq {edq:.2e}")
     assert ef <= TOL_VALUE and eg <= TOL_GRAD and edc <= TOL_GRAD and edq <= TOL_GRAD
 
@@ -94,7 +95,6 @@ def test_config2_full_size_sampled(storage):
                       coeffs=torch.from_numpy(C32), device=DEV)
     scene = synth.Scene(0)
     q64, _ = synth.scene_batch(scene, n, seed=22, step=0)
-    q64 = nudge_off_faces(q64, grid.lo, grid.hi, grid.res)
     q = torch.tensor(q64, dtype=torch.float32, device=DEV)
     ws = grid.workspace(n)
     grid.sort(q, ws)
@@ -111,9 +111,35 @@ def test_config2_full_size_sampled(storage):
     Cr = _rounded(C32, storage)
     ref_f, ref_g = oracle.forward(geometry(grid), Cr, q64[pick])
     ef = nerr(to_np(f)[pick], ref_f)
-    eg = nerr_cols(to_np(g)[pick], ref_g)
+    eg = FaceRule(geometry(grid), Cr, q64[pick]).grad_err(to_np(g)[pick], ref_g)
     ref_dC, _ = oracle.backward(geometry(grid), Cr, q64[sub], gf64[sub], gg64[sub])
-    edc = nerr(to_np(grid.grad).reshape(-1), ref_dC.reshape(-1))
+    edc = FaceRule(geometry(grid), Cr, q64[sub]).dC_err(to_np(grid.grad), ref_dC, gf64[sub], gg64[sub])
     print(f"{storage} 256^3: arithmetic error f {ef:.2e} grad {eg:.2e} dC {edc:.2e}")
     assert ef <= TOL_VALUE and eg <= TOL_GRAD and edc <= TOL_GRAD
     _report(f"{storage} 256^3", grid, q64[pick], f[torch.from_numpy(pick).to(DEV)], C32.astype(np.float64))
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_storage_copy_made_by_the_library(storage):
+    """The constructor's storage copy comes from tg_sync_storage: round to nearest even, FP16
+    saturating at +-65504 (as after every Adam step), checked against the rounding computed
+    here in NumPy.  The grid copies the caller's coefficients: a training step leaves the
+    caller's tensor unchanged."""
+    rng = np.random.default_rng(23)
+    C32 = rng.normal(0, 0.05, size=(9, 10, 11, 10)).astype(np.float32)
+    C32[0, 0, 0, :4] = [1e5, -7e4, 65519.0, 65520.0]  # beyond FP16's range, and the rounding edge
+    C_dev = torch.from_numpy(C32).to(DEV)
+    keep = C_dev.clone()
+    grid = TaylorGrid(3, (11, 10, 9), 2, (-1.0,) * 3, (1.0,) * 3, storage=storage, coeffs=C_dev, device=DEV)
+    torch.cuda.synchronize()
+    expect = _rounded(np.clip(C32, -65504, 65504) if storage == "f16" else C32, storage)
+    assert np.array_equal(grid.coeffs.float().cpu().double().numpy(), expect)
+    assert grid.master.data_ptr() != C_dev.data_ptr()
+    n = 4096
+    q = torch.tensor(rng.uniform(-1, 1, size=(n, 3)), dtype=torch.float32, device=DEV)
+    d = torch.tensor(rng.normal(size=n), dtype=torch.float32, device=DEV)
+    ws = grid.workspace(n)
+    grid.train_step(q, d, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(C_dev, keep)
+    assert not torch.equal(grid.master, keep)  # the step did update the grid's own copy

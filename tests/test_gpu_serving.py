@@ -7,7 +7,7 @@ import torch
 import oracle
 from paper_2402_14415_amd.grid import TaylorGrid, query
 from paper_2402_14415_amd.serving import Server, run_trace
-from parity_util import TOL_GRAD, TOL_VALUE, geometry, nerr, nudge_off_faces, to_np
+from parity_util import TOL_GRAD, TOL_VALUE, FaceRule, geometry, nerr, to_np
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -48,7 +48,7 @@ def test_query_matches_oracle(dim, order, storage):
     reqs, refs = [], []
     for k, n in enumerate(sizes):
         gi = k % len(grids)
-        q64 = nudge_off_faces(_points(dim, n, 100 + k), (-1.0,) * dim, (1.0,) * dim, grids[gi].res)
+        q64 = _points(dim, n, 100 + k)
         q = torch.tensor(q64, dtype=torch.float32, device=DEV).reshape(n, dim)
         sdf = torch.full((n,), float("nan"), device=DEV)
         normal = torch.full((n, dim), float("nan"), device=DEV)
@@ -62,6 +62,7 @@ def test_query_matches_oracle(dim, order, storage):
         f_ref, n_ref, gnorm = _oracle_sdf_normal(grids[gi], q64)
         ef = nerr(to_np(sdf), f_ref)
         ok = gnorm > 1e-3 * gnorm.max()  # the normal is ill-conditioned where the gradient vanishes
+        ok[FaceRule(geometry(grids[gi]), None, q64).idx] = False  # either side's normal on a face
         en = float(np.max(np.abs(to_np(normal)[ok] - n_ref[ok]))) if ok.any() else 0.0
         print(f"grid {gi} n={q64.shape[0]}: f err {ef:.2e}, normal err {en:.2e}")
         assert ef <= TOL_VALUE
