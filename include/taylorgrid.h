@@ -201,6 +201,18 @@ tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_
                       float eik_weight, float surface_k, float* g_f, float* g_grad, double* loss,
                       void* ws, size_t ws_bytes, void* stream);
 
+/* tg_sdf_loss for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops and harnesses that forbid allocation): no workspace argument.  Its FP64
+ * per-block sums go to a static device array of the library (32 KiB, one per GPU, held until
+ * the process ends, looked up on the stream's device at its first use there); nothing is
+ * allocated, and nothing in it needs to start at zero.  Results are identical to
+ * tg_sdf_loss's.  n <= 2^28 (TG_ERR_CAPACITY beyond).  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (on different streams, or from several host
+ * threads without ordering) race and give wrong losses; order them on one stream. */
+tg_status tg_sdf_loss_noalloc(int32_t dim, int64_t n, const float* f, const float* grad_f, const float* d,
+                              float eik_weight, float surface_k, float* g_f, float* g_grad, double* loss,
+                              void* stream);
+
 /* Total variation of the coefficient grid (the L_TV term of Sec. 3.2, Eq. 8; the paper
  * cites the regulariser of Plenoxels and prints no formula).  For every vertex v and stored
  * coefficient channel c, with Delta_a(v, c) = master(v + e_a, c) - master(v, c) along each

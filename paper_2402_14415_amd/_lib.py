@@ -92,6 +92,8 @@ _SIGS = {
     "tg_adam_step": ([_P, ctypes.POINTER(AdamParams), _P, _P, ctypes.c_size_t, ctypes.c_int32, _P], ctypes.c_int),
     "tg_query": ([ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(Request), ctypes.c_int32, _P], ctypes.c_int),
     "tg_sync_storage": ([_P, _P], ctypes.c_int),
+    "tg_sdf_loss_noalloc": ([ctypes.c_int32, ctypes.c_int64, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P,
+                             _P], ctypes.c_int),
     "tg_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "tg_last_error": ([], ctypes.c_char_p),
 }

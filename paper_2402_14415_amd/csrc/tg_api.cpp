@@ -557,6 +557,27 @@ tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_
                          "tg_sdf_loss");
 }
 
+tg_status tg_sdf_loss_noalloc(int32_t dim, int64_t n, const float* f, const float* grad_f, const float* d,
+                              float eik_weight, float surface_k, float* g_f, float* g_grad, double* loss, void* stream)
+{
+    if (dim != 2 && dim != 3) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss_noalloc: dim must be 2 or 3");
+    if (n < 0) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss_noalloc: n is negative");
+    if (n > tg::kMaxQueries)
+        return fail(TG_ERR_CAPACITY, "tg_sdf_loss_noalloc: n = %lld exceeds the maximum %lld", (long long)n,
+                    (long long)tg::kMaxQueries);
+    if (n > 0 && (!f || !d || !g_f))
+        return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss_noalloc: f, d and g_f must not be NULL");
+    if (n > 0 && grad_f && !g_grad)
+        return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss_noalloc: g_grad is NULL but grad_f is given");
+    if (!loss) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss_noalloc: loss is NULL");
+    if (!std::isfinite(eik_weight)) return fail(TG_ERR_INVALID_ARG, "tg_sdf_loss_noalloc: eik_weight is not finite");
+    if (check_surface_k("tg_sdf_loss_noalloc", surface_k) != TG_OK) return TG_ERR_INVALID_ARG;
+    (void)hipGetLastError();
+    return device_status(tg::launch_sdf_loss_noalloc(dim, n, f, grad_f, d, eik_weight, surface_k, g_f, g_grad, loss,
+                                                     static_cast<hipStream_t>(stream)),
+                         "tg_sdf_loss_noalloc");
+}
+
 tg_status tg_tv_loss(tg_grid* grid, float weight, double* loss, int32_t flags, void* ws, size_t ws_bytes, void* stream)
 {
     if (!grid) return fail(TG_ERR_INVALID_ARG, "tg_tv_loss: grid is NULL");

@@ -144,6 +144,12 @@ hipError_t launch_composite(int64_t n_rays, int32_t ns, const float* f, const fl
 AdamArgs make_adam_args(const tg_adam_params& p);
 // coeffs = the storage rounding of master (16-bit storage; nothing to do for FP32).
 hipError_t launch_sync_storage(const tg_grid* g, hipStream_t s);
+// launch_sdf_loss with its FP64 partial sums in the library's static device scratch (the
+// stream's device's copy) instead of a workspace; allocates nothing.
+hipError_t launch_sdf_loss_noalloc(int dim, int64_t n, const float* f, const float* grad_f, const float* d,
+                                   float eik_weight, float surf_k, float* g_f, float* g_grad, double* loss,
+                                   hipStream_t s);
+size_t noalloc_scratch_bytes();
 hipError_t launch_query(const tg_grid* const* grids, int32_t n_grids, const tg_request* reqs, int32_t n_reqs,
                         hipStream_t s);
 

@@ -3,6 +3,8 @@
 // Both are streaming kernels: grid-stride over their elements, FP64 per-block partial sums
 // written to the reduction scratch, then a one-block kernel that adds the partials in a
 // fixed order (deterministic FP64 result on the device).
+#include <mutex>
+
 #include "tg_internal.hpp"
 
 namespace tg {
@@ -305,6 +307,64 @@ hipError_t launch_sync_storage(const tg_grid* g, hipStream_t s)
     else
         hipLaunchKernelGGL(k_sync_storage<ST_F16>, grid, block, 0, s, n, g->bufs.master, g->bufs.coeffs);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ allocation-free loss
+// tg_sdf_loss_noalloc keeps its per-block FP64 sums in this file-scope device array instead
+// of a caller's workspace: the launch uses at most kMaxReduceBlocks blocks, two sums each.
+// Every GPU the library runs on holds its own copy until the process ends; in host code
+// `scratch` names a host-side stand-in, so kernels get the device address that
+// hipGetSymbolAddress returns for the device, looked up once per device.
+constexpr int kNoallocPartials = 2 * kMaxReduceBlocks;
+static __device__ __align__(256) double scratch[kNoallocPartials];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mutex;
+static double* g_scratch_ptr[kMaxScratchDevices] = {};
+
+size_t noalloc_scratch_bytes()
+{
+    return sizeof(scratch);
+}
+
+// The device address of `device`'s copy of the scratch array (that device is made current
+// for the lookup, and the previous current device restored).
+static hipError_t scratch_address(int device, double** out)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_sdf_loss_noalloc(int dim, int64_t n, const float* f, const float* grad_f, const float* d,
+                                   float eik_weight, float surf_k, float* g_f, float* g_grad, double* loss,
+                                   hipStream_t s)
+{
+    static_assert(2 * kMaxReduceBlocks <= kNoallocPartials, "the scratch holds every block's two sums");
+    hipDevice_t device = -1;
+    hipError_t e = hipStreamGetDevice(s, &device);
+    if (e != hipSuccess) return e;
+    double* partials = nullptr;
+    e = scratch_address((int)device, &partials);
+    if (e != hipSuccess) return e;
+    // each block writes its own two sums before the finishing block reads them: nothing in
+    // the scratch needs to start at zero
+    return launch_sdf_loss(dim, n, f, grad_f, d, eik_weight, surf_k, g_f, g_grad, loss, partials, s);
 }
 
 }  // namespace tg
