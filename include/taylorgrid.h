@@ -250,25 +250,36 @@ tg_status tg_upsample(const tg_grid* coarse, tg_grid* fine, void* stream);
 tg_status tg_iou_counts(int64_t n, const float* f, const float* d, int64_t* counts, void* ws,
                         size_t ws_bytes, void* stream);
 
+/* The field of a grid on the lattice s times finer than the grid, for the zero-level-set mesh
+ * of the learned field (Sec. 4.1 meshes its fields with marching cubes): values [nz][ny][nx]
+ * (device FP32, x fastest), n[a] = s (res[a] - 1) + 1, point (i, j, k) at lo + (i, j, k) hl
+ * with hl = (hi - lo) / (n - 1) (in FP32); every s-th point is a grid vertex.  Each value is
+ * the field of Sec. 3.1, Eq. 2-4, evaluated as tg_query does.  3D grids of one channel in the
+ * symmetric layout (TG_ERR_UNSUPPORTED otherwise), 1 <= s <= 64, fewer than 2^31 points
+ * (TG_ERR_CAPACITY).  No workspace. */
+tg_status tg_field_lattice(const tg_grid* grid, int32_t s, float* values, void* stream);
+
 /* Device workspace bytes of tg_mesh for a lattice of n[0] x n[1] x n[2] points (host array);
  * 0 when n is invalid or the lattice has more than 2^28 cells. */
 size_t tg_mesh_workspace_bytes(const int32_t* n);
 
-/* Zero-level-set mesh of a field sampled on a lattice, by marching tetrahedra.  values
- * [n[2]][n[1]][n[0]] (device, x fastest) at the points lo + i (hi - lo) / (n - 1) (n, lo, hi
- * host arrays of 3; every n[a] in 2..65536, at most 2^28 cells).  Every cell is split into 6
- * tetrahedra around its main diagonal, corner 0 = (0,0,0) to corner 7 = (1,1,1) (corner
- * index bx + 2 by + 4 bz): (0, a, b, 7) for (a, b) = (1,3), (3,2), (2,6), (6,4), (4,5), (5,1).
- * Corners with value < 0 are inside.  One corner apart from the other three gives one
- * triangle on the edges from it to the others (in corner order); two and two give the
- * quadrilateral (i0 o0, i0 o1, i1 o1, i1 o0) (i0 < i1 inside, o0 < o1 outside corners of the
- * tetrahedron) as the triangles (q0 q1 q2), (q0 q2 q3).  A vertex on edge (a, b) is
- * p_a + v_a / (v_a - v_b) (p_b - p_a).  Each triangle is oriented so that its normal
- * (p1 - p0) x (p2 - p0) points from the inside corners to the outside ones.  Triangles are
- * written to tri [max_tris][3][3] (device, xyz per vertex) cell by cell (x fastest), then
- * tetrahedron by tetrahedron; *n_tris (device int64) receives the total, of which only the
- * first max_tris are written (call again with a larger buffer if it is larger).
- * ws must hold tg_mesh_workspace_bytes(n). */
+/* Zero-level-set mesh of a field sampled on a lattice, by marching cubes (Sec. 4.1 extracts
+ * its meshes with marching cubes).  values [n[2]][n[1]][n[0]] (device, x fastest) at the
+ * points lo + i (hi - lo) / (n - 1) (n, lo, hi host arrays of 3; every n[a] in 2..65536, at
+ * most 2^28 cells).  A cell's corners are c = bx + 2 by + 4 bz; a corner with value < 0 is
+ * inside.  Edges are numbered axis by axis, each axis's four by increasing lower corner:
+ * (0,1) (2,3) (4,5) (6,7), (0,2) (1,3) (4,6) (5,7), (0,4) (1,5) (2,6) (3,7); an edge whose
+ * ends differ carries the vertex p_a + v_a / (v_a - v_b) (p_b - p_a), a its lower end.  The
+ * triangles of a cell: walk each face counterclockwise as seen from outside the cube and join
+ * every crossing where the walk enters the inside set to the next crossing where it leaves it
+ * (a face with inside corners on a diagonal separates them); the joins form loops; each loop
+ * (e0, e1, ..., started at its smallest edge, loops in increasing order of that edge) gives
+ * the fan (e0, e_i, e_i+1).  Every triangle's normal (p1 - p0) x (p2 - p0) points from the
+ * inside to the outside, and the mesh is closed wherever the inside set is.  Triangles are
+ * written to tri [max_tris][3][3] (device, xyz per vertex) cell by cell (x fastest), then in
+ * that order; *n_tris (device int64) receives the total, of which only the first max_tris are
+ * written (call again with a larger buffer if it is larger).  ws must hold
+ * tg_mesh_workspace_bytes(n). */
 tg_status tg_mesh(const int32_t* n, const float* lo, const float* hi, const float* values,
                   float* tri, int64_t max_tris, int64_t* n_tris, void* ws, size_t ws_bytes,
                   void* stream);
@@ -277,12 +288,14 @@ tg_status tg_mesh(const int32_t* n, const float* lo, const float* hi, const floa
  * split of the destination set, and the reduction partials); 0 if a count is out of range. */
 size_t tg_chamfer_workspace_bytes(int64_t na, int64_t nb);
 
-/* Chamfer distance between point sets a [na][3] and b [nb][3] (device; na, nb >= 1): out
- * (device double [3]) = {mean_a min_b |a - b| + mean_b min_a |a - b|, the first mean, the
- * second mean}.  Brute force (every pair), distances in FP32, means in FP64.  ws must hold
+/* Chamfer distance between point sets a [na][3] and b [nb][3] (device; na, nb >= 1), the CD
+ * of Sec. 4.1 (the paper's "Chamfer-L1", computed there with PyTorch3D's code): out (device
+ * double [3]) = {mean_a min_b |a - b| + mean_b min_a |a - b|, the first mean, the second
+ * mean}, with |.| the L1 norm |dx| + |dy| + |dz| (norm = 1) or the Euclidean norm (norm = 2).
+ * Brute force (every pair), distances in FP32, means in FP64.  ws must hold
  * tg_chamfer_workspace_bytes(na, nb); TG_ERR_CAPACITY if smaller. */
-tg_status tg_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, void* ws,
-                     size_t ws_bytes, void* stream);
+tg_status tg_chamfer(const float* a, int64_t na, const float* b, int64_t nb, int32_t norm, double* out,
+                     void* ws, size_t ws_bytes, void* stream);
 
 /* Radiance-field compositing (Sec. 3.3): the Max optical model of Eq. 10 along n_rays rays
  * of n_samples samples each, with a ReLU density, and the photometric loss of Eq. 11 with

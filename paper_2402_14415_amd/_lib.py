@@ -79,7 +79,7 @@ _SIGS = {
     "tg_chamfer_workspace_bytes": ([ctypes.c_int64, ctypes.c_int64], ctypes.c_size_t),
     "tg_mesh": ([ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), _P,
                  _P, ctypes.c_int64, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
-    "tg_chamfer": ([_P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "tg_chamfer": ([_P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "tg_backward": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
     "tg_forward_sdf_loss": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P, ctypes.c_float, ctypes.c_float, _P, _P,
                              _P, _P, _P, _P], ctypes.c_int),
@@ -92,6 +92,7 @@ _SIGS = {
     "tg_adam_step": ([_P, ctypes.POINTER(AdamParams), _P, _P, ctypes.c_size_t, ctypes.c_int32, _P], ctypes.c_int),
     "tg_query": ([ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(Request), ctypes.c_int32, _P], ctypes.c_int),
     "tg_sync_storage": ([_P, _P], ctypes.c_int),
+    "tg_field_lattice": ([_P, ctypes.c_int32, _P, _P], ctypes.c_int),
     "tg_sdf_loss_noalloc": ([ctypes.c_int32, ctypes.c_int64, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P,
                              _P], ctypes.c_int),
     "tg_status_string": ([ctypes.c_int], ctypes.c_char_p),

@@ -640,6 +640,24 @@ tg_status tg_iou_counts(int64_t n, const float* f, const float* d, int64_t* coun
                          "tg_iou_counts");
 }
 
+tg_status tg_field_lattice(const tg_grid* grid, int32_t s, float* values, void* stream)
+{
+    if (!grid) return fail(TG_ERR_INVALID_ARG, "tg_field_lattice: grid is NULL");
+    if (grid->desc.dim != 3) return fail(TG_ERR_UNSUPPORTED, "tg_field_lattice: needs a 3D grid");
+    if (grid->kord != grid->desc.order)
+        return fail(TG_ERR_UNSUPPORTED, "tg_field_lattice: needs a single-channel grid in the symmetric layout");
+    if (s < 1 || s > 64) return fail(TG_ERR_INVALID_ARG, "tg_field_lattice: s = %d outside 1..64", s);
+    if (!grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_field_lattice: grid has no coeffs buffer");
+    if (!values) return fail(TG_ERR_INVALID_ARG, "tg_field_lattice: values is NULL");
+    int64_t npts = 1;
+    for (int a = 0; a < 3; ++a) npts *= (int64_t)s * (grid->desc.res[a] - 1) + 1;
+    if (npts >= ((int64_t)1 << 31))
+        return fail(TG_ERR_CAPACITY, "tg_field_lattice: %lld lattice points (at most 2^31 - 1)", (long long)npts);
+    (void)hipGetLastError();
+    return device_status(tg::launch_field_lattice(grid, s, values, static_cast<hipStream_t>(stream)),
+                         "tg_field_lattice");
+}
+
 static bool mesh_cells(const int32_t* n, int64_t* ncell)
 {
     if (!n) return false;
@@ -689,17 +707,18 @@ size_t tg_chamfer_workspace_bytes(int64_t na, int64_t nb)
     return tg::chamfer_workspace_bytes(na, nb);
 }
 
-tg_status tg_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, void* ws, size_t ws_bytes,
-                     void* stream)
+tg_status tg_chamfer(const float* a, int64_t na, const float* b, int64_t nb, int32_t norm, double* out, void* ws,
+                     size_t ws_bytes, void* stream)
 {
     if (na < 1 || nb < 1 || na > tg::kMaxQueries || nb > tg::kMaxQueries)
         return fail(TG_ERR_INVALID_ARG, "tg_chamfer: point counts must be in 1..%lld", (long long)tg::kMaxQueries);
+    if (norm != 1 && norm != 2) return fail(TG_ERR_INVALID_ARG, "tg_chamfer: norm must be 1 (L1) or 2 (Euclidean)");
     if (!a || !b || !out) return fail(TG_ERR_INVALID_ARG, "tg_chamfer: a, b and out must not be NULL");
     if (!ws || !aligned(ws, 256)) return fail(TG_ERR_INVALID_ARG, "tg_chamfer: workspace NULL or not 256-byte aligned");
     const size_t need = tg::chamfer_workspace_bytes(na, nb);
     if (ws_bytes < need) return fail(TG_ERR_CAPACITY, "tg_chamfer: workspace has %zu bytes, needs %zu", ws_bytes, need);
     (void)hipGetLastError();
-    return device_status(tg::launch_chamfer(a, na, b, nb, out, static_cast<char*>(ws),
+    return device_status(tg::launch_chamfer(a, na, b, nb, norm, out, static_cast<char*>(ws),
                                             static_cast<hipStream_t>(stream)),
                          "tg_chamfer");
 }

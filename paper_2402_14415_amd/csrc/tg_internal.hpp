@@ -134,7 +134,7 @@ size_t mesh_workspace_bytes(int64_t ncell);
 hipError_t launch_mesh(const int* n, const float* lo, const float* hi, const float* values, float* tri,
                        int64_t max_tris, int64_t* n_tris, char* ws, hipStream_t s);
 size_t chamfer_workspace_bytes(int64_t na, int64_t nb);
-hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, char* ws,
+hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb, int norm, double* out, char* ws,
                           hipStream_t s);
 hipError_t launch_sum_finish(const double* partials, int64_t nblocks, double* out, hipStream_t s);
 hipError_t launch_sum_finish_scaled(const double* partials, int64_t nblocks, double scale, double* out, hipStream_t s);
@@ -150,6 +150,9 @@ hipError_t launch_sdf_loss_noalloc(int dim, int64_t n, const float* f, const flo
                                    float eik_weight, float surf_k, float* g_f, float* g_grad, double* loss,
                                    hipStream_t s);
 size_t noalloc_scratch_bytes();
+// The field of a 3D single-channel symmetric-layout grid at the lattice s times finer than
+// the grid, values [nz][ny][nx] with n = s (res - 1) + 1 (fewer than 2^31 points).
+hipError_t launch_field_lattice(const tg_grid* g, int32_t s, float* values, hipStream_t st);
 hipError_t launch_query(const tg_grid* const* grids, int32_t n_grids, const tg_request* reqs, int32_t n_reqs,
                         hipStream_t s);
 

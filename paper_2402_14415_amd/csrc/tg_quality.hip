@@ -1,18 +1,24 @@
 // SDF quality measures (the paper evaluates reconstructions by IoU and Chamfer distance,
-// Sec. 4.1): IoU counts of the inside sets on sample points, a zero-level-set mesh of a
-// sampled field by marching tetrahedra, and the Chamfer distance between two point sets.
+// Sec. 4.1): IoU counts of the inside sets on sample points, the field of a grid sampled on a
+// lattice, a zero-level-set mesh of a sampled field by marching cubes, and the Chamfer
+// distance between two point sets.
 //
-// Mesh: the lattice cell with corner (i, j, k) is split into 6 tetrahedra around its main
-// diagonal (corner 0 to corner 7, corner index bx + 2 by + 4 bz), tetrahedron t being
-// (0, P_t.a, P_t.b, 7).  Corners with value < 0 are inside.  One corner apart from the other
-// three gives one triangle across the edges leaving it (edges in the order of the other
-// corners); two and two give the quadrilateral (i0 o0, i0 o1, i1 o1, i1 o0) split along its
-// first diagonal.  Each triangle is oriented so that its normal points from the inside
-// corners to the outside ones, decided on the triangle through the edge midpoints in integer
-// cell coordinates (exact; moving the points along their edges never flips it).  Triangles
-// are written cell by cell (x fastest), tetrahedron by tetrahedron: a first pass counts each
-// cell's triangles, an exclusive scan gives every cell its output offset, a second pass
-// writes them.
+// Mesh (marching cubes; Sec. 4.1 extracts its meshes with marching cubes and prints no
+// variant).  A lattice cell has corners c = bx + 2 by + 4 bz; a corner is inside when its
+// value is < 0.  The 12 edges are numbered axis by axis (x, y, z), each axis's four in
+// increasing order of their lower corner; a crossing edge (ends on different sides) carries
+// the vertex p_a + v_a / (v_a - v_b) (p_b - p_a), a its lower end.  The triangles of each of
+// the 256 inside/outside patterns come from a table built at compile time by one rule: walk
+// every face of the cube counterclockwise as seen from outside, join each crossing where the
+// walk enters the inside set to the next crossing where it leaves it (so a face with inside
+// corners on a diagonal separates them); the joins form closed loops; each loop, started at
+// its smallest edge and taken in increasing order of that edge, is cut into the fan
+// (e0, e_i, e_i+1).  The walk's direction puts every triangle's normal (p1 - p0) x (p2 - p0)
+// from the inside to the outside, and neighbouring cells put the same joins on a shared face,
+// so the mesh is closed wherever the inside set is.  Triangles are written cell by cell (x
+// fastest), then in table order: a first pass counts each cell's triangles, an exclusive
+// scan gives every cell its output offset, the cells that cross the level set are compacted,
+// and a last pass writes their triangles.
 #include "tg_internal.hpp"
 
 namespace tg {
@@ -20,7 +26,106 @@ namespace tg {
 constexpr int kMeshThreads = 256;
 constexpr int kMeshCellsPerThread = 8;
 constexpr int kMeshCellsPerBlock = kMeshThreads * kMeshCellsPerThread;
-constexpr int kTetPair[6][2] = {{1, 3}, {3, 2}, {2, 6}, {6, 4}, {4, 5}, {5, 1}};
+
+// ------------------------------------------------------------------ marching cubes table
+constexpr int kCubeEdge[12][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7},   // along x
+                                  {0, 2}, {1, 3}, {4, 6}, {5, 7},   // along y
+                                  {0, 4}, {1, 5}, {2, 6}, {3, 7}};  // along z
+constexpr int kMcMaxTris = 5;
+
+struct McCase {
+    uint8_t ntri;
+    uint8_t edge[3 * kMcMaxTris];
+};
+struct McTable {
+    McCase c[256];
+};
+
+constexpr int cube_edge_of(int a, int b)
+{
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    for (int k = 0; k < 12; ++k)
+        if (kCubeEdge[k][0] == lo && kCubeEdge[k][1] == hi) return k;
+    return -1;
+}
+
+// The triangles of every inside/outside pattern, by the face-walk rule described above.
+constexpr McTable make_mc_table()
+{
+    McTable T{};
+    for (int pat = 0; pat < 256; ++pat) {
+        int next[12] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+        for (int axis = 0; axis < 3; ++axis) {
+            const int u = (axis + 1) % 3, v = (axis + 2) % 3;
+            for (int side = 0; side < 2; ++side) {
+                // the face's corners, counterclockwise about the outward normal
+                const int sq[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+                int walk[4] = {0, 0, 0, 0};
+                for (int k = 0; k < 4; ++k) {
+                    const int kk = side == 1 ? k : (4 - k) % 4;  // the inner face runs the other way
+                    walk[k] = (side << axis) | (sq[kk][0] << u) | (sq[kk][1] << v);
+                }
+                int enter_at[2] = {0, 0}, enter_edge[2] = {0, 0}, leave_at[2] = {0, 0}, leave_edge[2] = {0, 0};
+                int ne = 0, nl = 0;
+                for (int k = 0; k < 4; ++k) {
+                    const int a = walk[k], b = walk[(k + 1) % 4];
+                    const int ia = (pat >> a) & 1, ib = (pat >> b) & 1;
+                    if (ia == ib) continue;
+                    if (ia) {
+                        leave_at[nl] = k;
+                        leave_edge[nl++] = cube_edge_of(a, b);
+                    } else {
+                        enter_at[ne] = k;
+                        enter_edge[ne++] = cube_edge_of(a, b);
+                    }
+                }
+                for (int j = 0; j < ne; ++j) {
+                    int best = 0, best_gap = 5;
+                    for (int l = 0; l < nl; ++l) {
+                        const int gap = (leave_at[l] - enter_at[j] + 4) % 4;
+                        if (gap < best_gap) {
+                            best_gap = gap;
+                            best = l;
+                        }
+                    }
+                    next[enter_edge[j]] = leave_edge[best];
+                }
+            }
+        }
+        bool seen[12] = {false, false, false, false, false, false, false, false, false, false, false, false};
+        int nt = 0;
+        for (int e0 = 0; e0 < 12; ++e0) {
+            if (next[e0] < 0 || seen[e0]) continue;
+            int loop[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            int len = 0;
+            for (int e = e0; !seen[e]; e = next[e]) {
+                seen[e] = true;
+                loop[len++] = e;
+            }
+            for (int i = 1; i + 1 < len; ++i) {
+                T.c[pat].edge[3 * nt + 0] = (uint8_t)loop[0];
+                T.c[pat].edge[3 * nt + 1] = (uint8_t)loop[i];
+                T.c[pat].edge[3 * nt + 2] = (uint8_t)loop[i + 1];
+                ++nt;
+            }
+        }
+        T.c[pat].ntri = (uint8_t)nt;
+    }
+    return T;
+}
+
+constexpr McTable kMcHostTable = make_mc_table();
+__constant__ McTable kMc = kMcHostTable;
+
+constexpr int mc_max_tris()
+{
+    int m = 0;
+    for (int p = 0; p < 256; ++p) m = kMcHostTable.c[p].ntri > m ? kMcHostTable.c[p].ntri : m;
+    return m;
+}
+static_assert(mc_max_tris() <= kMcMaxTris, "a cube yields at most five triangles");
+static_assert(kMcHostTable.c[1].ntri == 1 && kMcHostTable.c[0].ntri == 0 && kMcHostTable.c[255].ntri == 0,
+              "one inside corner: one triangle; uniform cubes: none");
 
 struct Lattice {
     int nx, ny, nz;
@@ -45,22 +150,18 @@ __device__ __forceinline__ void cell_values(const Lattice& L, const float* __res
         cv[c] = v[((int64_t)(k + ((c >> 2) & 1)) * L.ny + (j + ((c >> 1) & 1))) * L.nx + (i + (c & 1))];
 }
 
-// triangles of tetrahedron t of a cell with corner values cv
-__device__ __forceinline__ int tet_count(const float* cv, int t)
+// Inside/outside pattern of a cell's corners (bit c set when corner c is inside).
+__device__ __forceinline__ int cell_pattern(const float* cv)
 {
-    const int idx[4] = {0, kTetPair[t][0], kTetPair[t][1], 7};
-    int nin = 0;
+    int p = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) nin += cv[idx[q]] < 0.0f ? 1 : 0;
-    return nin == 2 ? 2 : (nin == 1 || nin == 3 ? 1 : 0);
+    for (int c = 0; c < 8; ++c) p |= (cv[c] < 0.0f ? 1 : 0) << c;
+    return p;
 }
 
 __device__ __forceinline__ int cell_count(const float* cv)
 {
-    int n = 0;
-#pragma unroll
-    for (int t = 0; t < 6; ++t) n += tet_count(cv, t);
-    return n;
+    return kMc.c[cell_pattern(cv)].ntri;
 }
 
 // Exclusive scan over the block of one value per thread (kMeshThreads threads); returns the
@@ -197,73 +298,20 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_emit(Lattice L, const flo
         cell_of(L, c, i, j, k);
         float cv[8];
         cell_values(L, v, i, j, k, cv);
-        if (cell_count(cv) == 0) continue;
-        int64_t out = (int64_t)offs[c] + bsum[c / kMeshCellsPerBlock];
-        for (int t = 0; t < 6; ++t) {
-            const int idx[4] = {0, kTetPair[t][0], kTetPair[t][1], 7};
-            int in[4], ou[4], nin = 0, nout = 0;
-            for (int q = 0; q < 4; ++q) {
-                if (cv[idx[q]] < 0.0f) in[nin++] = q;
-                else ou[nout++] = q;
-            }
-            if (nin == 0 || nout == 0) continue;
-            // corner offsets (0 / 1) in the cell of the tetrahedron's corners
-            int pc[4][3];
-            for (int q = 0; q < 4; ++q) {
-                pc[q][0] = idx[q] & 1;
-                pc[q][1] = (idx[q] >> 1) & 1;
-                pc[q][2] = (idx[q] >> 2) & 1;
-            }
-            // from the inside centroid to the outside one, scaled by nin * nout (integers)
-            int D[3];
-            for (int a = 0; a < 3; ++a) {
-                int si = 0, so = 0;
-                for (int q = 0; q < nin; ++q) si += pc[in[q]][a];
-                for (int q = 0; q < nout; ++q) so += pc[ou[q]][a];
-                D[a] = nin * so - nout * si;
-            }
-            int e[2][3][2];  // up to two triangles, three edges (tetrahedron-local corners)
-            int ntri;
-            if (nin == 2) {
-                const int q[4][2] = {{in[0], ou[0]}, {in[0], ou[1]}, {in[1], ou[1]}, {in[1], ou[0]}};
-                const int sel[2][3] = {{0, 1, 2}, {0, 2, 3}};
-                for (int s = 0; s < 2; ++s)
-                    for (int m = 0; m < 3; ++m) {
-                        e[s][m][0] = q[sel[s][m]][0];
-                        e[s][m][1] = q[sel[s][m]][1];
-                    }
-                ntri = 2;
-            } else {
-                const int lone = nin == 1 ? in[0] : ou[0];
-                int m = 0;
-                for (int q = 0; q < 4; ++q)
-                    if (q != lone) {
-                        e[0][m][0] = lone;
-                        e[0][m][1] = q;
-                        ++m;
-                    }
-                ntri = 1;
-            }
-            for (int s = 0; s < ntri; ++s, ++out) {
-                // orientation on the midpoint triangle, in doubled integer cell coordinates
-                int mp[3][3];
-                for (int m = 0; m < 3; ++m)
-                    for (int a = 0; a < 3; ++a) mp[m][a] = pc[e[s][m][0]][a] + pc[e[s][m][1]][a];
-                const int u[3] = {mp[1][0] - mp[0][0], mp[1][1] - mp[0][1], mp[1][2] - mp[0][2]};
-                const int w[3] = {mp[2][0] - mp[0][0], mp[2][1] - mp[0][1], mp[2][2] - mp[0][2]};
-                const int n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
-                const bool keep = n[0] * D[0] + n[1] * D[1] + n[2] * D[2] > 0;
-                if (out >= max_tris) continue;  // past the caller's capacity: counted, not written
-                for (int m = 0; m < 3; ++m) {
-                    const int mm = keep ? m : (m == 0 ? 0 : 3 - m);
-                    const int a = e[s][mm][0], b = e[s][mm][1];
-                    float pa[3], pb[3];
-                    corner_pos(L, i, j, k, idx[a], pa);
-                    corner_pos(L, i, j, k, idx[b], pb);
-                    const float va = cv[idx[a]], vb = cv[idx[b]];
-                    const float tt = va / (va - vb);
-                    for (int x = 0; x < 3; ++x) tri[(out * 3 + m) * 3 + x] = fmaf(tt, pb[x] - pa[x], pa[x]);
-                }
+        const McCase& mc = kMc.c[cell_pattern(cv)];
+        const int64_t out0 = (int64_t)offs[c] + bsum[c / kMeshCellsPerBlock];
+        for (int t = 0; t < mc.ntri; ++t) {
+            const int64_t out = out0 + t;
+            if (out >= max_tris) break;  // past the caller's capacity: counted, not written
+            for (int m = 0; m < 3; ++m) {
+                const int e = mc.edge[3 * t + m];
+                const int a = kCubeEdge[e][0], b = kCubeEdge[e][1];
+                float pa[3], pb[3];
+                corner_pos(L, i, j, k, a, pa);
+                corner_pos(L, i, j, k, b, pb);
+                const float va = cv[a], vb = cv[b];
+                const float tt = va / (va - vb);
+                for (int x = 0; x < 3; ++x) tri[(out * 3 + m) * 3 + x] = fmaf(tt, pb[x] - pa[x], pa[x]);
             }
         }
     }
@@ -402,6 +450,9 @@ constexpr int kNnTile = 2048;     // destination points per LDS tile (a multiple
 // its kNnPerThread source points held in registers.
 constexpr int kNnTargetBlocks = 2048;
 
+// NORM 1: the L1 distance |dx| + |dy| + |dz|; NORM 2: the squared Euclidean distance (the
+// square root is taken once per source, in k_nn_reduce).
+template <int NORM>
 __global__ __launch_bounds__(kNnThreads) void k_nn_min(const float* __restrict__ src, int64_t ns,
                                                       const float* __restrict__ dst, int64_t nd, int64_t chunks,
                                                       int64_t tiles_per_split, float* __restrict__ mins)
@@ -442,7 +493,8 @@ __global__ __launch_bounds__(kNnThreads) void k_nn_min(const float* __restrict__
 #pragma unroll
                 for (int r = 0; r < kNnPerThread; ++r) {
                     const float dx = xs[u] - px[r], dy = ys[u] - py[r], dz = zs[u] - pz[r];
-                    best[r] = fminf(best[r], fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+                    if constexpr (NORM == 1) best[r] = fminf(best[r], fabsf(dx) + fabsf(dy) + fabsf(dz));
+                    else best[r] = fminf(best[r], fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
                 }
         }
     }
@@ -454,7 +506,8 @@ __global__ __launch_bounds__(kNnThreads) void k_nn_min(const float* __restrict__
 }
 
 // partials[block] = sum over this block's sources of the distance to the nearest destination
-// (the smallest of the splits' squared distances, then its square root).
+// (the smallest of the splits' distances; for NORM 2, its square root).
+template <int NORM>
 __global__ __launch_bounds__(kThreads) void k_nn_reduce(const float* __restrict__ mins, int64_t ns, int64_t nsplit,
                                                        double* __restrict__ partials)
 {
@@ -462,7 +515,7 @@ __global__ __launch_bounds__(kThreads) void k_nn_reduce(const float* __restrict_
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < ns; i += (int64_t)gridDim.x * kThreads) {
         float m = mins[i];
         for (int64_t sp = 1; sp < nsplit; ++sp) m = fminf(m, mins[sp * ns + i]);
-        acc += (double)sqrtf(m);
+        acc += NORM == 1 ? (double)m : (double)sqrtf(m);
     }
     const double tot = block_sum_f64<kThreads>(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -499,7 +552,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_chamfer_finish(const double*
     }
 }
 
-hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb, double* out, char* ws,
+hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb, int norm, double* out, char* ws,
                           hipStream_t s)
 {
     double* partials = reinterpret_cast<double*>(ws);
@@ -511,13 +564,15 @@ hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb
     const int64_t ca = (na + CHUNK - 1) / CHUNK, cb = (nb + CHUNK - 1) / CHUNK;
     const int64_t ta = ((nb + kNnTile - 1) / kNnTile + sa - 1) / sa;  // destination tiles per split
     const int64_t tb = ((na + kNnTile - 1) / kNnTile + sb - 1) / sb;
-    hipLaunchKernelGGL(k_nn_min, dim3((unsigned)(ca * sa)), dim3(kNnThreads), 0, s, a, na, b, nb, ca, ta, mins_a);
-    hipLaunchKernelGGL(k_nn_min, dim3((unsigned)(cb * sb)), dim3(kNnThreads), 0, s, b, nb, a, na, cb, tb, mins_b);
+    auto nn_min = norm == 1 ? k_nn_min<1> : k_nn_min<2>;
+    auto nn_reduce = norm == 1 ? k_nn_reduce<1> : k_nn_reduce<2>;
+    hipLaunchKernelGGL(nn_min, dim3((unsigned)(ca * sa)), dim3(kNnThreads), 0, s, a, na, b, nb, ca, ta, mins_a);
+    hipLaunchKernelGGL(nn_min, dim3((unsigned)(cb * sb)), dim3(kNnThreads), 0, s, b, nb, a, na, cb, tb, mins_b);
     const int half = kMaxReduceBlocks / 2;
     const unsigned ga = (unsigned)std::min<int64_t>((na + kThreads - 1) / kThreads, half);
     const unsigned gb = (unsigned)std::min<int64_t>((nb + kThreads - 1) / kThreads, half);
-    hipLaunchKernelGGL(k_nn_reduce, dim3(ga), dim3(kThreads), 0, s, mins_a, na, sa, partials);
-    hipLaunchKernelGGL(k_nn_reduce, dim3(gb), dim3(kThreads), 0, s, mins_b, nb, sb, partials + half);
+    hipLaunchKernelGGL(nn_reduce, dim3(ga), dim3(kThreads), 0, s, mins_a, na, sa, partials);
+    hipLaunchKernelGGL(nn_reduce, dim3(gb), dim3(kThreads), 0, s, mins_b, nb, sb, partials + half);
     hipLaunchKernelGGL(k_chamfer_finish, dim3(1), dim3(kFinishThreads), 0, s, partials, (int)ga, na, partials + half,
                        (int)gb, nb, out);
     return hipGetLastError();

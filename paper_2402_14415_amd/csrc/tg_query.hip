@@ -180,4 +180,58 @@ hipError_t launch_query(const tg_grid* const* grids, int32_t n_grids, const tg_r
     return hipSuccess;
 }
 
+// ------------------------------------------------------------------ field on a lattice
+// The grid's field at the points of the lattice s times finer than the grid (for the
+// zero-level-set mesh of the field): point (i, j, k) at lo + (i, j, k) hl, hl = (hi - lo) /
+// (n - 1), n = s (res - 1) + 1; one thread per point, x fastest, the same evaluation as a
+// served query.  Neighbouring threads share the cell's corner blocks through the caches.
+template <int K, int ST>
+__global__ __launch_bounds__(kThreads) void k_field_lattice(QGrid G, int32_t nx, int32_t ny, int64_t npts, float hx,
+                                                            float hy, float hz, float* __restrict__ out)
+{
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= npts) return;
+    const uint32_t pp = (uint32_t)p, row = pp / (uint32_t)nx;  // npts < 2^31
+    const uint32_t i = pp - row * (uint32_t)nx, k = row / (uint32_t)ny, j = row - k * (uint32_t)ny;
+    const float q[3] = {fmaf((float)i, hx, G.lo[0]), fmaf((float)j, hy, G.lo[1]), fmaf((float)k, hz, G.lo[2])};
+    float f, gr[3];
+    serve_point<3, K, ST>(G, q, f, gr);
+    out[p] = f;
+}
+
+hipError_t launch_field_lattice(const tg_grid* g, int32_t s, float* values, hipStream_t st)
+{
+    QGrid G;
+    std::memset(static_cast<void*>(&G), 0, sizeof(G));
+    G.coeffs = g->bufs.coeffs;
+    G.dim = 3;
+    G.order = (int8_t)g->desc.order;
+    G.storage = (int8_t)g->desc.storage;
+    int32_t n[3];
+    float hl[3];
+    for (int a = 0; a < 3; ++a) {
+        G.res[a] = g->geom.res[a];
+        G.lo[a] = g->geom.lo[a];
+        G.hi[a] = g->geom.hi[a];
+        G.h[a] = g->geom.h[a];
+        G.inv_h[a] = g->geom.inv_h[a];
+        G.inv_h_lo[a] = g->geom.inv_h_lo[a];
+        n[a] = s * (g->geom.res[a] - 1) + 1;
+        hl[a] = (float)(((double)g->geom.hi[a] - (double)g->geom.lo[a]) / (double)(n[a] - 1));
+    }
+    const int64_t npts = (int64_t)n[0] * n[1] * n[2];
+    const dim3 grid((unsigned)((npts + kThreads - 1) / kThreads)), block(kThreads);
+#define TG_FL_CASE(KK, ST)                                                                                    \
+    if (G.order == KK && G.storage == ST) {                                                                 \
+        hipLaunchKernelGGL((k_field_lattice<KK, ST>), grid, block, 0, st, G, n[0], n[1], npts, hl[0], hl[1], hl[2], \
+                           values);                                                                          \
+        return hipGetLastError();                                                                            \
+    }
+#define TG_FL_ST(KK) TG_FL_CASE(KK, 0) TG_FL_CASE(KK, 1) TG_FL_CASE(KK, 2)
+    TG_FL_ST(2) TG_FL_ST(1) TG_FL_ST(0)
+#undef TG_FL_ST
+#undef TG_FL_CASE
+    return hipErrorInvalidValue;
+}
+
 }  // namespace tg

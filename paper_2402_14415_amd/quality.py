@@ -1,9 +1,10 @@
-"""SDF quality measures on the GPU (the paper reports IoU and Chamfer distance, Sec. 4.1):
-IoU of the inside sets on sample points, the zero-level-set mesh of a sampled field
-(marching tetrahedra), and the Chamfer distance between point sets.
+"""SDF quality measures on the GPU (the paper reports IoU and the Chamfer-L1 distance of the
+mesh that marching cubes extracts from the field, Sec. 4.1): IoU of the inside sets on sample
+points, a grid's field on a lattice finer than the grid, the zero-level-set mesh of a sampled
+field (marching cubes), and the Chamfer distance between point sets (L1 or Euclidean).
 
-Argument marshalling only: the counting, the meshing and the distances run in the library
-(``tg_iou_counts``, ``tg_mesh``, ``tg_chamfer``).
+Argument marshalling only: the counting, the sampling, the meshing and the distances run in
+the library (``tg_iou_counts``, ``tg_field_lattice``, ``tg_mesh``, ``tg_chamfer``).
 """
 from __future__ import annotations
 
@@ -37,6 +38,17 @@ def iou(f, d, ws=None):
     return (1.0 if union == 0 else inter / union), inter, union
 
 
+def field_lattice(grid, s, out=None):
+    """The grid's field on the lattice s times finer than the grid: values [nz, ny, nx] with
+    n = s (res - 1) + 1 per axis (point i at lo + i (hi - lo) / (n - 1))."""
+    n = [s * (r - 1) + 1 for r in grid.res]
+    shape = (n[2], n[1], n[0])
+    out = torch.empty(shape, dtype=torch.float32, device=grid.device) if out is None else out
+    _check_tensor("out", out, torch.float32, grid.device, n[0] * n[1] * n[2])
+    _lib.call("tg_field_lattice", grid.handle, int(s), _ptr(out), _stream(grid.device))
+    return out
+
+
 class MeshLattice:
     """The lattice arguments and workspace of tg_mesh for values [nz, ny, nx] over [lo, hi]^3."""
 
@@ -60,7 +72,7 @@ class MeshLattice:
 
 def mesh(values, lo, hi, max_tris=None):
     """Zero-level-set triangles [T, 3, 3] of values [nz, ny, nx] sampled on the lattice over
-    [lo, hi]^3 (marching tetrahedra, in the library's documented order), and the total count."""
+    [lo, hi]^3 (marching cubes, in the library's documented order), and the total count."""
     dev = values.device
     lat = MeshLattice(values.shape, lo, hi, dev)
     cap = 0 if max_tris is None else int(max_tris)
@@ -82,19 +94,20 @@ def chamfer_workspace(na, nb, device):
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def chamfer_into(a, b, out, ws):
+def chamfer_into(a, b, out, ws, norm=1):
     """Enqueue the Chamfer distance of a [Na, 3] and b [Nb, 3] into out (device float64 [3]);
-    ws: chamfer_workspace(Na, Nb)."""
+    norm 1: L1 point distances (the paper's CD-L1), 2: Euclidean; ws: chamfer_workspace(Na, Nb)."""
     dev = a.device
     _check_tensor("a", a, torch.float32, dev)
     _check_tensor("b", b, torch.float32, dev)
     _check_tensor("out", out, torch.float64, dev, 3)
-    _lib.call("tg_chamfer", _ptr(a), a.shape[0], _ptr(b), b.shape[0], _ptr(out), _ptr(ws), ws.numel(), _stream(dev))
+    _lib.call("tg_chamfer", _ptr(a), a.shape[0], _ptr(b), b.shape[0], int(norm), _ptr(out), _ptr(ws), ws.numel(),
+              _stream(dev))
     return out
 
 
-def chamfer(a, b, ws=None):
+def chamfer(a, b, ws=None, norm=1):
     """Chamfer distance of point sets a [Na, 3], b [Nb, 3]: (total, mean a->b, mean b->a)."""
     ws = chamfer_workspace(a.shape[0], b.shape[0], a.device) if ws is None else ws
     out = torch.empty(3, dtype=torch.float64, device=a.device)
-    return tuple(float(x) for x in chamfer_into(a, b, out, ws).cpu())
+    return tuple(float(x) for x in chamfer_into(a, b, out, ws, norm).cpu())

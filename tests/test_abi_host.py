@@ -292,12 +292,13 @@ def test_quality_validation():
     assert L().tg_mesh(n, lo, hi, fake, fake, -1, fake, fake, wsb, None) == 1
     assert L().tg_mesh(n, lo, hi, fake, fake, 10, None, fake, wsb, None) == 1
     assert L().tg_mesh(n, lo, hi, fake, fake, 10, fake, fake, wsb - 1, None) == 4
-    assert L().tg_chamfer(fake, 0, fake, 5, fake, fake, red, None) == 1
-    assert L().tg_chamfer(fake, 5, None, 5, fake, fake, red, None) == 1
+    assert L().tg_chamfer(fake, 0, fake, 5, 1, fake, fake, red, None) == 1
+    assert L().tg_chamfer(fake, 5, None, 5, 1, fake, fake, red, None) == 1
+    assert L().tg_chamfer(fake, 5, fake, 5, 3, fake, fake, 1 << 30, None) == 1  # norm 1 or 2 only
     chb = L().tg_chamfer_workspace_bytes(5, 5)
     assert chb >= red and L().tg_chamfer_workspace_bytes(0, 5) == 0
     assert L().tg_chamfer_workspace_bytes(1_000_000, 100_000) > L().tg_chamfer_workspace_bytes(1_000_000, 2048)
-    assert L().tg_chamfer(fake, 5, fake, 5, fake, fake, chb - 1, None) == 4
+    assert L().tg_chamfer(fake, 5, fake, 5, 2, fake, fake, chb - 1, None) == 4
 
 
 def test_full_hessian_layout_validation():
@@ -391,4 +392,25 @@ def test_sync_storage_validation():
     L().tg_destroy(h)
     st, h = _create(_desc(storage=0))
     assert L().tg_sync_storage(h, None) == 0  # FP32 storage: nothing to do, nothing enqueued
+    L().tg_destroy(h)
+
+
+def test_field_lattice_validation():
+    """tg_field_lattice: 3D single-channel symmetric grids, 1 <= s <= 64, fewer than 2^31
+    points; refused before anything is enqueued."""
+    b = _lib.GridBuffers()
+    b.coeffs = b.master = 0x1000
+    fake = ctypes.c_void_p(0x2000)
+    st, h = _create(_desc(), b)
+    assert st == 0
+    assert L().tg_field_lattice(None, 2, fake, None) == 1
+    assert L().tg_field_lattice(h, 0, fake, None) == 1
+    assert L().tg_field_lattice(h, 65, fake, None) == 1
+    assert L().tg_field_lattice(h, 2, None, None) == 1
+    L().tg_destroy(h)
+    st, h = _create(_desc(res=(2000, 2000, 2000)), b)
+    assert L().tg_field_lattice(h, 1, fake, None) == 4  # 8e9 points
+    L().tg_destroy(h)
+    st, h = _create(_desc(dim=2, res=(16, 16)), b)
+    assert L().tg_field_lattice(h, 2, fake, None) == 2
     L().tg_destroy(h)

@@ -1,15 +1,18 @@
 """SDF quality measures on the GPU against the FP64 oracle (oracle/quality.py): exact IoU
-counts, the marching-tetrahedra mesh triangle for triangle in the documented order (ragged
-lattices, exact zeros, a 128^3 scene lattice, a short output buffer, an empty level set),
-the Chamfer distance, and the measures of a fitted grid against the analytic scene."""
+counts, the marching-cubes mesh triangle for triangle in the documented order (ragged
+lattices, exact zeros, every corner sign pattern, a 128^3 scene lattice, a short output
+buffer, an empty level set), a grid's field on a lattice finer than the grid, the mesh of a
+grid's field, the Chamfer distance in both norms, and the measures of fitted grids of every
+order against the analytic scene."""
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from oracle import quality as qo
 from paper_2402_14415_amd import quality, synth
 from paper_2402_14415_amd.grid import TaylorGrid
-from parity_util import to_np
+from parity_util import TOL_VALUE, geometry, nerr, to_np
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -45,7 +48,7 @@ def _wavy(x, y, z):
 
 def _check_mesh(values, lo, hi, max_tris=None):
     tri, total = quality.mesh(_t(values), lo, hi, max_tris=max_tris)
-    ref = qo.marching_tetrahedra(values.astype(np.float64), lo, hi)
+    ref = qo.marching_cubes(values.astype(np.float64), lo, hi)
     torch.cuda.synchronize()
     assert total == len(ref)
     got = to_np(tri)
@@ -61,6 +64,23 @@ def test_mesh_matches_oracle_ragged_lattice():
     lo, hi = (-1.0, -0.9, -1.1), (1.0, 0.8, 1.2)
     V = _lattice(_wavy, (31, 37, 29), lo, hi)
     V[5, 6, :] = 0.0  # exact zeros (outside)
+    _check_mesh(V, lo, hi)
+
+
+def test_mesh_every_sign_pattern():
+    """Random values padded with outside ones: all 256 corner patterns occur (ambiguous faces
+    included); triangle for triangle against the oracle (whose meshes of such lattices are
+    pinned closed and consistently oriented)."""
+    rng = np.random.default_rng(8)
+    V = np.ones((26, 25, 24), dtype=np.float32)
+    V[1:-1, 1:-1, 1:-1] = (rng.normal(size=(24, 23, 22)) + 0.1).astype(np.float32)
+    ins = V < 0
+    pat = np.zeros((25, 24, 23), dtype=np.int64)
+    for c in range(8):
+        pat |= ins[(c >> 2) & 1: 25 + ((c >> 2) & 1), (c >> 1) & 1: 24 + ((c >> 1) & 1), c & 1: 23 + (c & 1)].astype(
+            np.int64) << c
+    assert len(np.unique(pat)) == 256
+    lo, hi = (0.0, 0.0, 0.0), (23.0, 24.0, 25.0)
     _check_mesh(V, lo, hi)
 
 
@@ -84,12 +104,73 @@ def test_mesh_short_buffer_and_empty_level_set():
     assert total == 0 and tri.shape[0] == 0
 
 
-def test_chamfer_matches_oracle():
+@pytest.mark.parametrize("order,storage,s", [(2, "f32", 2), (1, "bf16", 3), (0, "f32", 1), (2, "f16", 4)])
+def test_field_lattice_matches_oracle(order, storage, s):
+    """The grid's field on the lattice s times finer than a ragged grid, against the C
+    oracle's field at the same lattice (FP64 positions) on the storage-rounded coefficients."""
+    rng = np.random.default_rng(10 + order)
+    res = (13, 11, 9)
+    lo, hi = (-1.0, -0.5, 0.0), (1.0, 1.5, 0.75)
+    nc = [1, 4, 10][order]
+    C32 = rng.normal(0, 0.1, size=(9, 11, 13, nc)).astype(np.float32)
+    g = TaylorGrid(3, res, order, lo, hi, storage=storage, coeffs=torch.from_numpy(C32), device=DEV)
+    vals = quality.field_lattice(g, s)
+    torch.cuda.synchronize()
+    Cr = g.coeffs.float().cpu().double().numpy()  # the storage rounding (checked against NumPy elsewhere)
+    n, pts = qo.field_lattice(geometry(g), Cr, s)
+    assert vals.shape == (n[2], n[1], n[0])
+    ref = oracle.forward(geometry(g), Cr, pts, want_grad=False)
+    assert nerr(to_np(vals).reshape(-1), ref) <= TOL_VALUE
+    # every s-th point is a grid vertex: the stored value
+    np.testing.assert_allclose(to_np(vals)[::s, ::s, ::s], Cr[..., 0], rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_mesh_of_a_grid_field_matches_oracle(order):
+    """The mesh of a grid's field (tg_field_lattice then tg_mesh, s = 2) against the oracle's
+    (FP64 field on the same lattice, inside decided in FP32): triangle for triangle in every
+    cell whose corner signs both sides decide alike; the lattice points where they differ
+    (|f| at rounding level) are counted and must be rare."""
+    scene = synth.Scene(0)
+    res = 24
+    C32 = synth.scene_taylor_grid(scene, res, order).numpy()
+    g = TaylorGrid(3, (res,) * 3, order, (-1.0,) * 3, (1.0,) * 3, coeffs=torch.from_numpy(C32), device=DEV)
+    vals = quality.field_lattice(g, 2)
+    tri, total = quality.mesh(vals, (-1.0,) * 3, (1.0,) * 3)
+    torch.cuda.synchronize()
+    geom = geometry(g)
+    C = C32.astype(np.float64)
+    n, pts = qo.field_lattice(geom, C, 2)
+    f64 = oracle.forward(geom, C, pts, want_grad=False).reshape(n[2], n[1], n[0])
+    ref, cells = qo.mesh_field(geom, C, 2, with_cells=True)
+    gv = to_np(vals)
+    differ = (gv < 0) != (f64.astype(np.float32) < 0)
+    print(f"order {order}: {total} triangles, {int(differ.sum())} lattice points decided differently")
+    assert differ.sum() <= 10
+    # cells touching a differing point
+    bad = np.zeros((n[2] - 1, n[1] - 1, n[0] - 1), dtype=bool)
+    for z, y, x in np.argwhere(differ):
+        bad[max(z - 1, 0): z + 1, max(y - 1, 0): y + 1, max(x - 1, 0): x + 1] = True
+    bad_ids = np.nonzero(bad.reshape(-1))[0]
+    got = to_np(tri)
+    h = 2.0 / (n[0] - 1)
+    gcell = np.floor((got.mean(axis=1) + 1.0) / h).astype(np.int64).clip(0, n[0] - 2)
+    gid = gcell[:, 0] + (n[0] - 1) * (gcell[:, 1] + (n[1] - 1) * gcell[:, 2])
+    keep_g = ~np.isin(gid, bad_ids)
+    keep_r = ~np.isin(cells, bad_ids)
+    assert keep_g.sum() == keep_r.sum()
+    assert np.max(np.abs(got[keep_g] - ref[keep_r])) <= 1e-4 * h
+    if not differ.any():
+        assert total == len(ref)
+
+
+@pytest.mark.parametrize("norm", [1, 2])
+def test_chamfer_matches_oracle(norm):
     rng = np.random.default_rng(4)
     a = rng.normal(0, 0.3, size=(20_000, 3)).astype(np.float32)
     b = (rng.normal(0, 0.3, size=(15_000, 3)) + 0.02).astype(np.float32)
-    got = quality.chamfer(_t(a), _t(b))
-    ref = qo.chamfer(a.astype(np.float64), b.astype(np.float64))
+    got = quality.chamfer(_t(a), _t(b), norm=norm)
+    ref = qo.chamfer(a.astype(np.float64), b.astype(np.float64), norm)
     assert abs(got[0] - ref) <= 1e-5 * ref
     assert abs(got[1] + got[2] - got[0]) <= 1e-12 * got[0]
 
@@ -102,45 +183,47 @@ def test_chamfer_lopsided_sets(na, nb):
     a = rng.uniform(-1, 1, size=(na, 3)).astype(np.float32)
     b = rng.normal(0, 0.5, size=(nb, 3)).astype(np.float32)
     got = quality.chamfer(_t(a), _t(b))
-    ref_ab = qo.chamfer(a.astype(np.float64), b.astype(np.float64))
+    ref_ab = qo.chamfer(a.astype(np.float64), b.astype(np.float64), 1)
     assert abs(got[0] - ref_ab) <= 1e-5 * ref_ab
     swapped = quality.chamfer(_t(b), _t(a))
     assert abs(swapped[1] - got[2]) <= 1e-12 * got[2] and abs(swapped[2] - got[1]) <= 1e-12 * got[1]
 
 
-def test_quality_of_a_fitted_grid():
-    """Fit 64^3 K=2 to the scene for 150 steps; IoU on 100k uniform points and the Chamfer
-    distance between the mesh of the grid's vertex values and 50k analytic surface points.
-    The fitted grid is the GPU's own result, so these are checked as properties (the fit is
-    good: IoU > 0.9, Chamfer under 2 cells; the mesh lies in the box and every triangle within
-    one cell); the kernels' parity is the tests above, on independent inputs."""
+def test_quality_of_fitted_grids_by_order():
+    """Fit 48^3 grids of order 0, 1 and 2 to the scene for 150 steps each; IoU on 100k uniform
+    points, and the Chamfer-L1 distance between the vertices of the mesh of each grid's field
+    (s = 2) and 50k analytic surface points.  The fitted grids are the GPU's own results, so
+    these are checked as properties: good fits (IoU > 0.85, Chamfer under 2 cells), meshes in
+    the box with every triangle inside one lattice cell, and orders that differ."""
     scene = synth.Scene(0)
-    g = TaylorGrid(3, (64,) * 3, 2, (-1.0,) * 3, (1.0,) * 3, device=DEV)
-    n = 1 << 17
-    ws = g.workspace(n)
-    for s in range(150):
-        q, d = synth.scene_batch(scene, n, seed=5, step=s)
-        g.train_step(_t(q), _t(d), ws, eik_weight=0.1, lr=1e-2)
+    res = 48
+    h = 2.0 / (res - 1)
     rng = np.random.default_rng(6)
     pts = rng.uniform(-1, 1, size=(100_000, 3)).astype(np.float32)
-    wq = g.workspace(len(pts))
-    qt = _t(pts)
-    g.sort(qt, wq)
-    f, _ = g.forward(qt, wq, want_grad=False)
-    d = scene.sdf(pts.astype(np.float64)).astype(np.float32)
-    got = quality.iou(f, _t(d))
-    assert 0 < got[1] <= got[2] <= len(pts)
-    assert got[0] > 0.9, got
-    verts = g.master[..., 0].contiguous()
-    tri, total = quality.mesh(verts, (-1.0,) * 3, (1.0,) * 3)
-    mv = tri.reshape(-1, 3).contiguous()
-    surf = scene.surface_points(np.random.default_rng(7), 50_000).astype(np.float32)
-    ch = quality.chamfer(mv, _t(surf))
-    print(f"IoU {got[0]:.4f}, triangles {total}, Chamfer {ch[0]:.5f}")
-    assert ch[0] < 2 * 2.0 / 63 and abs(ch[1] + ch[2] - ch[0]) <= 1e-12 * ch[0]
-    # every vertex lies in the box, and every triangle has its three vertices within one
-    # cell's diagonal of each other
-    p = to_np(tri)
-    assert np.all(np.abs(p) <= 1.0 + 1e-6)
-    span = np.max(np.linalg.norm(p[:, [0, 1, 2]] - p[:, [1, 2, 0]], axis=2))
-    assert span <= np.sqrt(3) * 2.0 / 63 * (1 + 1e-5)
+    d = _t(scene.sdf(pts.astype(np.float64)).astype(np.float32))
+    surf = _t(scene.surface_points(np.random.default_rng(7), 50_000).astype(np.float32))
+    n = 1 << 17
+    out = []
+    for order in (0, 1, 2):
+        g = TaylorGrid(3, (res,) * 3, order, (-1.0,) * 3, (1.0,) * 3, device=DEV)
+        ws = g.workspace(n)
+        for st in range(150):
+            q, dd = synth.scene_batch(scene, n, seed=5, step=st)
+            g.train_step(_t(q), _t(dd), ws, eik_weight=0.1, lr=1e-2)
+        wq = g.workspace(len(pts))
+        qt = _t(pts)
+        g.sort(qt, wq)
+        f, _ = g.forward(qt, wq, want_grad=False)
+        iou = quality.iou(f, d)
+        assert 0 < iou[1] <= iou[2] <= len(pts)
+        vals = quality.field_lattice(g, 2)
+        tri, total = quality.mesh(vals, (-1.0,) * 3, (1.0,) * 3)
+        ch = quality.chamfer(tri.reshape(-1, 3).contiguous(), surf)
+        print(f"order {order}: IoU {iou[0]:.4f}, triangles {total}, CD-L1 {ch[0]:.5f}")
+        assert iou[0] > 0.85 and ch[0] < 2 * 3 * h and abs(ch[1] + ch[2] - ch[0]) <= 1e-12 * ch[0]
+        p = to_np(tri)
+        assert np.all(np.abs(p) <= 1.0 + 1e-6)
+        span = np.max(np.linalg.norm(p[:, [0, 1, 2]] - p[:, [1, 2, 0]], axis=2))
+        assert span <= np.sqrt(3) * h / 2 * (1 + 1e-5)
+        out.append((iou[0], ch[0]))
+    assert len({c for _, c in out}) == 3  # the three orders give three different meshes
