@@ -35,6 +35,13 @@ METRIC = "queries/s fwd+bwd at 128^3 K=2 (and % HBM peak); served query p50/p99 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3  # dense FP32 vector
 COPY_REF_BYTES = 256 << 20
+FLUSH_BYTES = 512 << 20  # written before a cold repetition: twice the 256 MB Infinity Cache
+# VALU issue peak: 1024 SIMDs each issuing one wave64 FP32 instruction every 4 cycles at 2.4 GHz
+VALU_WAVE_INSTR_PEAK = 1024 * 2.4e9 / 4
+# VALU wave instructions per wave of 64 served points of k_query (SQ_INSTS_VALU / SQ_WAVES =
+# 9.335e6 / 2.057e4 per dispatch), from the SQ counter pass of the serving section
+# (profiles/sq_counters_serving_kernel.md)
+QUERY_VALU_PER_WAVE = 453.8
 RES = 128
 ORDER = 2
 NQ = 1 << 20
@@ -70,6 +77,60 @@ def algorithmic_bytes(nq, U, C, nvert):
             "forward_loss": fwd_loss, "backward_adam": bwd_adam}
 
 
+def unique_vertices_dev(q, res, lo=-1.0, hi=1.0):
+    """Distinct vertices the queries q (a device tensor [n, 3]) touch, counted on the device
+    with a bitmap (input analysis for the algorithmic byte counts, not the method)."""
+    import torch
+
+    h = (hi - lo) / (res - 1)
+    c = torch.clamp(torch.floor((torch.clamp(q.double(), lo, hi) - lo) / h).long(), max=res - 2)
+    seen = torch.zeros(res ** 3, dtype=torch.bool, device=q.device)
+    for b in range(8):
+        v = c + torch.tensor([(b >> a) & 1 for a in range(3)], device=q.device)
+        seen[v[:, 0] + res * (v[:, 1] + res * v[:, 2])] = True
+    return int(seen.sum())
+
+
+def percentiles(xs):
+    xs = np.asarray(xs, dtype=np.float64)
+    return {"median": float(np.median(xs)), "p10": float(np.percentile(xs, 10)), "p90": float(np.percentile(xs, 90))}
+
+
+def fwd_bwd_bench(grid, q, gf, gg, ws, f, g, reps=200, warmup=20, flush=None):
+    """The metric's forward + backward: tg_forward (f, grad f in query order) then
+    tg_backward (dC from precomputed upstream gradients) on one stream, timed with HIP events
+    per repetition, and the bucketing sort that both reuse.  With `flush` (a 512 MiB device
+    buffer) the Infinity Cache (MALL) is flushed before the sort and again between the sort
+    and the forward, by rewriting the buffer outside the timed windows.  Returns per-repetition
+    medians and p10 / p90 in microseconds (sort_fwd_bwd adds the sort's window to fwd_bwd's)."""
+    import torch
+
+    s = torch.cuda.current_stream(q.device)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(reps)]
+    for e5 in evs:
+        for e in e5:
+            e.record(s)
+    torch.cuda.synchronize()
+    for i in range(warmup + reps):
+        e = evs[i - warmup] if i >= warmup else None
+        if flush is not None:
+            flush.add_(1.0)
+        e and e[0].record(s)
+        grid.sort(q, ws)
+        e and e[1].record(s)
+        if flush is not None:
+            flush.add_(1.0)
+        e and e[2].record(s)
+        grid.forward(q, ws, out=(f, g))
+        e and e[3].record(s)
+        grid.backward(q, ws, gf, gg)
+        e and e[4].record(s)
+    torch.cuda.synchronize()
+    us = lambda a, b: np.array([1e3 * e[a].elapsed_time(e[b]) for e in evs])
+    return {"fwd_bwd": percentiles(us(2, 4)), "sort_fwd_bwd": percentiles(us(0, 1) + us(2, 4)),
+            "sort": percentiles(us(0, 1)), "forward": percentiles(us(2, 3)), "backward": percentiles(us(3, 4))}
+
+
 def kernel_source_sha256():
     import glob
     import hashlib
@@ -102,30 +163,65 @@ def measured_traffic(call):
     return vals.get(call)
 
 
-def cpu_baseline(C64, batches, min_seconds=10.0, max_steps=64):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n):
+    """Set the OpenMP thread count of this process (the oracle's loops)."""
+    import ctypes
+
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def cpu_baseline(C64, batches, min_seconds=10.0, max_steps=64, single_queries=1 << 18):
     """The FP64 oracle on the same step (forward + loss + adjoint over a batch of 2^20
     queries, then Adam over every coefficient), on the host cores, repeated over the bench's
-    batches until at least min_seconds of work have run."""
+    batches until at least min_seconds of work have run; then on one thread, the same step
+    over the first single_queries queries of a batch."""
     import oracle
 
     geom = oracle.Geometry(3, (RES,) * 3, ORDER, (-1.0,) * 3, (1.0,) * 3)
     flat = C64.reshape(-1).copy()
     m = np.zeros_like(flat)
     v = np.zeros_like(flat)
+
+    def one_step(q, d, step):
+        nonlocal flat, m, v
+        f, g = oracle.forward(geom, flat.reshape(C64.shape), q)
+        _, gf, gg = oracle.sdf_loss(f, g, d, EIK)
+        dC, _ = oracle.backward(geom, flat.reshape(C64.shape), q, gf, gg)
+        flat, m, v, _ = oracle.adam(flat, m, v, dC.reshape(-1), LR, step=step)
+
+    threads = oracle.threads()
+    _omp_threads(threads)
     steps, nq = 0, 0
     t0 = time.perf_counter()
     while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < min_seconds):
         q, d = batches[steps % len(batches)]
-        f, g = oracle.forward(geom, flat.reshape(C64.shape), q)
-        _, gf, gg = oracle.sdf_loss(f, g, d, EIK)
-        dC, _ = oracle.backward(geom, flat.reshape(C64.shape), q, gf, gg)
-        flat, m, v, _ = oracle.adam(flat, m, v, dC.reshape(-1), LR, step=steps + 1)
+        one_step(q, d, steps + 1)
         steps += 1
         nq += len(q)
     dt = time.perf_counter() - t0
-    return {"value": nq / dt, "unit": "queries/s", "cores": oracle.threads(), "kind": "oracle",
+    q, d = batches[0]
+    _omp_threads(1)
+    t1 = time.perf_counter()
+    one_step(q[:single_queries], d[:single_queries], steps + 1)
+    dt1 = time.perf_counter() - t1
+    _omp_threads(threads)
+    return {"value": nq / dt, "unit": "queries/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{steps} full training steps of {len(batches[0][0])} scene queries each at {RES}^3 K={ORDER} "
-                      f"(forward + loss + adjoint + Adam over {flat.size} coefficients), FP64, {dt:.1f} s"}
+                      f"(forward + loss + adjoint + Adam over {flat.size} coefficients), FP64, {dt:.1f} s",
+            "single_thread": {"value": single_queries / dt1, "unit": "queries/s", "cores": 1,
+                              "sample": f"one training step of {single_queries} scene queries (forward + loss + "
+                                        f"adjoint, then Adam over every coefficient), FP64, {dt1:.1f} s"}}
 
 
 def serving_bench(dev, batches_dev, n_req=400, fit_steps=20):
@@ -171,6 +267,39 @@ def serving_bench(dev, batches_dev, n_req=400, fit_steps=20):
     nmax = 4_000_000
     pool = torch.rand((2 * nmax, 3), generator=gen, device=dev) * 2.0 - 1.0
 
+    # the serving kernel alone: one launch of 16 requests of 2^20 uniform points, one per grid
+    from paper_2402_14415_amd.grid import query
+
+    npk = 1 << 20
+    kreqs, alg_bytes = [], 0
+    for k in range(16):
+        qk = pool[k * npk:(k + 1) * npk]
+        kreqs.append((k, qk, torch.empty(npk, device=dev), torch.empty((npk, 3), device=dev)))
+        Ck = (desc[k]["order"] + 1) * (desc[k]["order"] + 2) * (desc[k]["order"] + 3) // 6
+        alg_bytes += npk * 28 + unique_vertices_dev(qk, desc[k]["res"]) * Ck * 2  # BF16 coefficients
+    kev = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
+    for e in kev:
+        e.record()
+    query(grids, kreqs)
+    torch.cuda.synchronize()
+    kev[0].record()
+    for r in range(10):
+        query(grids, kreqs)
+        kev[r + 1].record()
+    torch.cuda.synchronize()
+    k_us = float(np.median([kev[r].elapsed_time(kev[r + 1]) * 1e3 for r in range(10)]))
+    kpts = 16 * npk
+    kernel = {"points": kpts, "us": k_us, "points_per_s": kpts / (k_us * 1e-6),
+              "hbm": {"algorithmic_bytes": alg_bytes, "achieved_GBs": alg_bytes / (k_us * 1e-6) / 1e9,
+                      "peak": HBM_PEAK_GBS, "frac": alg_bytes / (k_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
+              "valu": None if QUERY_VALU_PER_WAVE is None else {
+                  "wave_instructions_per_wave": QUERY_VALU_PER_WAVE,
+                  "achieved_wave_instr_per_s": QUERY_VALU_PER_WAVE * kpts / 64 / (k_us * 1e-6),
+                  "peak_wave_instr_per_s": VALU_WAVE_INSTR_PEAK,
+                  "frac": QUERY_VALU_PER_WAVE * kpts / 64 / (k_us * 1e-6) / VALU_WAVE_INSTR_PEAK}}
+    log(f"bench: serving kernel: {kernel}")
+    del kreqs
+
     def make_requests(seed):
         r = np.random.default_rng(seed)
         out = []
@@ -180,7 +309,8 @@ def serving_bench(dev, batches_dev, n_req=400, fit_steps=20):
             out.append((int(r.integers(0, 16)), pool[off:off + n]))
         return out
 
-    res = {"grids": desc, "requests_per_phase": n_req, "budget_bytes": 1 << 30, "fit_steps": fit_steps}
+    res = {"grids": desc, "requests_per_phase": n_req, "budget_bytes": 1 << 30, "fit_steps": fit_steps,
+           "kernel": kernel}
     srv = Server(grids, budget_bytes=1 << 30, streams=2, depth=4, chunk_points=1 << 20)
     # warm-up pass (allocator, kernels)
     run_trace(srv, [(0.0, g, q) for g, q in make_requests(9)[:40]])
@@ -203,12 +333,15 @@ def serving_bench(dev, batches_dev, n_req=400, fit_steps=20):
 
 
 def precision_bench(dev, steps=10, warmup=3, n_batches=2):
-    """Precision form at 256^3, K=2, 2^22 queries per step: the same training step with FP32,
-    BF16 and FP16 coefficient storage (FP32 master and accumulation), timed per call, plus
-    the storage rounding's effect on the field: max / RMS of f(storage) - f(FP32 master) on
-    2^16 held-out scene points, both evaluated by the GPU kernels."""
+    """Precision form at 256^3, K=2, 2^22 queries per step: the training step with FP32, BF16
+    and FP16 coefficient storage (FP32 master and accumulation), every form starting from the
+    same coefficients; the separate calls and the fused tg_train_step are both timed.  Then
+    each trained grid's field on 2^16 held-out scene points (seed 1) against the FP64 oracle:
+    the arithmetic error (oracle on the storage-rounded coefficients the kernels read) and the
+    deployment error (oracle on the FP32 master), max and RMS of f_GPU - f_oracle."""
     import torch
 
+    import oracle
     from paper_2402_14415_amd.grid import TaylorGrid, sdf_loss
 
     res, nq = 256, 1 << 22
@@ -217,12 +350,13 @@ def precision_bench(dev, steps=10, warmup=3, n_batches=2):
     for b in range(n_batches):
         q, d = synth.scene_batch(scene, nq, seed=0, step=100 + b)
         batches.append((torch.tensor(q, dtype=torch.float32, device=dev), torch.tensor(d, dtype=torch.float32, device=dev)))
-    qh, _ = synth.scene_batch(scene, 1 << 16, seed=1, step=0)
-    qh = torch.tensor(qh, dtype=torch.float32, device=dev)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(0)
-    C0 = torch.randn((res, res, res, 10), generator=gen, device=dev) * 0.05
-    out = {"workload": "sdf_fit_256^3_K2", "queries_per_step": nq, "steps": steps, "forms": {}}
+    qh64, _ = synth.scene_batch(scene, 1 << 16, seed=1, step=0)
+    qh64 = qh64.astype(np.float32).astype(np.float64)
+    qh = torch.tensor(qh64, dtype=torch.float32, device=dev)
+    C0 = torch.from_numpy(synth.normal_coeffs((res, res, res, 10), std=0.05, seed=0)[0].astype(np.float32))
+    geom = oracle.Geometry(3, (res,) * 3, 2, (-1.0,) * 3, (1.0,) * 3)
+    out = {"workload": "sdf_fit_256^3_K2", "queries_per_step": nq, "steps": steps, "held_out_points": len(qh64),
+           "forms": {}}
     for storage in ("f32", "bf16", "f16"):
         grid = TaylorGrid(3, (res,) * 3, 2, (-1.0,) * 3, (1.0,) * 3, storage=storage, coeffs=C0, device=dev)
         ws = grid.workspace(nq)
@@ -250,33 +384,56 @@ def precision_bench(dev, steps=10, warmup=3, n_batches=2):
         names = ["sort", "forward", "loss", "backward", "adam"]
         us = {nm: 1e3 * float(np.mean([e[k].elapsed_time(e[k + 1]) for e in evs])) for k, nm in enumerate(names)}
         step_us = 1e3 * float(np.mean([e[0].elapsed_time(e[5]) for e in evs]))
-        # rounding effect on the field: storage form vs an FP32 grid on the same master
-        ref = TaylorGrid(3, (res,) * 3, 2, (-1.0,) * 3, (1.0,) * 3, storage="f32", coeffs=grid.master.clone(),
-                         device=dev, optimizer=False)
+        # the fused training step, continuing from the same state
+        fev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        for e4 in fev:
+            for e in e4:
+                e.record()
+        torch.cuda.synchronize()
+        for it in range(steps):
+            q, d = batches[it % len(batches)]
+            fev[it][0].record()
+            grid.train_step(q, d, ws, eik_weight=EIK, lr=LR, loss=loss, stage_events=fev[it][1:])
+        torch.cuda.synchronize()
+        fused_us = 1e3 * float(np.mean([e[0].elapsed_time(e[3]) for e in fev]))
+        fused_stage = {nm: 1e3 * float(np.mean([e[k].elapsed_time(e[k + 1]) for e in fev]))
+                       for k, nm in enumerate(["sort", "forward_loss", "backward_adam"])}
+        # the trained grid's field on the held-out points against the FP64 oracle
         wsh = grid.workspace(qh.shape[0])
         grid.sort(qh, wsh)
-        fh, _ = grid.forward(qh, wsh)
-        ref.sort(qh, wsh)
-        fr, _ = ref.forward(qh, wsh)
-        diff = (fh.double() - fr.double()).abs()
+        fh, _ = grid.forward(qh, wsh, want_grad=False)
+        torch.cuda.synchronize()
+        fh64 = fh.double().cpu().numpy()
+        master64 = grid.master.double().cpu().numpy()
+        stored64 = master64 if storage == "f32" else grid.coeffs.double().cpu().numpy()
+        errs = {}
+        for name, C in (("arithmetic", stored64), ("deployment", master64)):
+            e = fh64 - oracle.forward(geom, C, qh64, want_grad=False)
+            errs[name] = {"max": float(np.max(np.abs(e))), "rms": float(np.sqrt(np.mean(e * e)))}
+        del master64, stored64
         out["forms"][storage] = {
             "us_per_call": us, "step_us": step_us, "step_queries_per_s": nq / (step_us * 1e-6),
             "fwd_bwd_queries_per_s": nq / ((us["forward"] + us["backward"]) * 1e-6),
-            "sdf_diff_vs_fp32_master": {"max": float(diff.max()), "rms": float(diff.pow(2).mean().sqrt())},
-            "final_loss": float(loss[0])}
+            "fused_step_us": fused_us, "fused_step_queries_per_s": nq / (fused_us * 1e-6),
+            "fused_stage_us": fused_stage,
+            "sdf_error_vs_fp64_oracle": errs, "final_loss": float(loss[0])}
         log(f"bench: precision {storage}: {out['forms'][storage]}")
-        del grid, ref, ws, wsh
+        del grid, ws, wsh
         torch.cuda.empty_cache()
     return out
 
 
-def radiance_bench(dev, steps=10, warmup=3, n_batches=2, n_rays=4096, n_samples=256, res=160):
+def radiance_bench(dev, steps=10, warmup=3, train_steps=2000, n_pool=64, n_heldout=8, n_rays=4096, n_samples=256,
+                   res=160):
     """Radiance-field form: a 160^3 density grid (K=2, ReLU) and a three-channel K=1 colour grid,
     4096 rays x 256 stratified samples per step from cameras on a radius-4 sphere.  Targets
     are the ray colours of the seeded blob volume, rendered by the library's own compositing
     from the volume's density and colour at the samples.  One step evaluates the two grids
-    (one shared sort, a forward each), composites with the photometric loss and its adjoint, and applies
-    the fused adjoint + Adam to each grid."""
+    (one shared sort, a forward each), composites with the photometric loss and its adjoint,
+    and applies the fused adjoint + Adam to each grid.  The step is timed per stage, then the
+    fit runs to train_steps steps over a pool of n_pool batches, and the PSNR of the rendered
+    colours against the targets is measured on n_heldout batches of other rays (seed 1)
+    before and after, as the paper reports PSNR of its radiance fields (Sec. 4.2)."""
     import torch
 
     from paper_2402_14415_amd.radiance import RadianceField, composite
@@ -287,19 +444,31 @@ def radiance_bench(dev, steps=10, warmup=3, n_batches=2, n_rays=4096, n_samples=
         torch.from_numpy((0.5 + 0.05 * rng.standard_normal((res, res, res, 10))).astype(np.float32)),
         [torch.from_numpy((0.5 + 0.05 * rng.standard_normal((res, res, res, 4))).astype(np.float32))
          for _ in range(3)]), device=dev)
-    batches = []
-    for b in range(n_batches):
-        o, d = synth.camera_rays(n_rays, seed=0, step=b)
-        q64, delta64 = synth.stratified_samples(o, d, n_samples, seed=0, step=b)
-        dens, col = vol.density_and_colour(q64)
+
+    def make_batch(seed, b):
+        o, d = synth.camera_rays(n_rays, seed=seed, step=b)
+        q64, delta64 = synth.stratified_samples(o, d, n_samples, seed=seed, step=b)
         q = torch.tensor(q64, dtype=torch.float32, device=dev)
         delta = torch.tensor(delta64, dtype=torch.float32, device=dev)
-        rgb = composite(torch.tensor(dens, dtype=torch.float32, device=dev),
-                        torch.tensor(np.ascontiguousarray(col.T), dtype=torch.float32, device=dev),
-                        delta, n_samples, field.reduce_ws)[0]
-        batches.append((q, delta, rgb))
+        dens, col = vol.density_and_colour_torch(q)
+        rgb = composite(dens.float().contiguous(), col.t().float().contiguous(), delta, n_samples,
+                        field.reduce_ws)[0]
+        return q, delta, rgb
+
+    batches = [make_batch(0, b) for b in range(n_pool)]
+    heldout = [make_batch(1, b) for b in range(n_heldout)]
     n = n_rays * n_samples
     ws = field.workspace(n)
+
+    def psnr():
+        se, cnt = 0.0, 0
+        for q, delta, target in heldout:
+            rgb = field.render(q, delta, n_samples, ws)
+            se += float(((rgb.double() - target.double()) ** 2).sum())
+            cnt += target.numel()
+        return -10.0 * math.log10(se / cnt)  # colours in [0, 1]: peak 1
+
+    psnr0 = psnr()
     bufs = (torch.empty(n, device=dev), torch.empty((3, n), device=dev), torch.empty((n_rays, 3), device=dev),
             torch.empty(1, dtype=torch.float64, device=dev), torch.empty(n, device=dev),
             torch.empty((3, n), device=dev))
@@ -310,15 +479,23 @@ def radiance_bench(dev, steps=10, warmup=3, n_batches=2, n_rays=4096, n_samples=
     torch.cuda.synchronize()
     losses = []
     for i in range(steps + warmup):
-        q, delta, target = batches[i % n_batches]
+        q, delta, target = batches[i % n_pool]
         ev[i][0].record()
         loss = field.train_step(q, delta, n_samples, target, ws, lr=1e-2, bufs=bufs, stage_events=ev[i][1:])
-        if i == 0 or i == steps + warmup - 1:
+        if i == 0:
             losses.append(float(loss[0]))
     torch.cuda.synchronize()
     stage = lambda k: float(np.median([ev[i][k].elapsed_time(ev[i][k + 1]) * 1e3 for i in range(warmup, warmup + steps)]))
     step_us = float(np.median([ev[i][0].elapsed_time(ev[i][3]) * 1e3 for i in range(warmup, warmup + steps)]))
     comp_us = stage(1)
+    t0 = time.perf_counter()
+    for i in range(steps + warmup, train_steps):
+        q, delta, target = batches[i % n_pool]
+        loss = field.train_step(q, delta, n_samples, target, ws, lr=1e-2, bufs=bufs)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t0
+    losses.append(float(loss[0]))
+    psnr1 = psnr()
     comp_bytes = n * 36 + n_rays * 24  # f, 3 colours, delta in; g_f, 3 g_c out; target in, colour out
     return {"workload": f"radiance_{res}^3_density_K2_relu_colour_K1x3ch", "rays_per_step": n_rays,
             "composite_kernel": {"us": comp_us, "algorithmic_bytes": comp_bytes,
@@ -328,7 +505,9 @@ def radiance_bench(dev, steps=10, warmup=3, n_batches=2, n_rays=4096, n_samples=
             "samples_per_s": n / (step_us * 1e-6),
             "stage_us": {"sort_and_evaluate_2_grids": stage(0), "composite_loss_adjoint": stage(1),
                          "adjoint_adam_2_grids": stage(2)},
-            "loss_first_last": losses}
+            "train_steps": train_steps, "training_pool_rays": n_pool * n_rays,
+            "fit_seconds_after_timing": fit_s, "loss_first_last": losses,
+            "heldout_rays": n_heldout * n_rays, "psnr_db_before": psnr0, "psnr_db_after": psnr1}
 
 
 def objective_bench(dev, C32, dev_batches, U, steps=10, warmup=3):
@@ -535,6 +714,47 @@ def order_scaling_bench(dev, dev_batches, steps=10, warmup=3):
             "paper_table2_ratios": {"time": [1.0, 27.1 / 7.0, 95.0 / 7.0], "size": [1.0, 32.7 / 9.2, 106.0 / 9.2]}}
 
 
+def nq_sweep(grid, dev_batches, exps=(20, 21, 22, 23, 24), reps=20, warmup=5):
+    """Forward + backward (warm) at 2^20 .. 2^24 scene queries on the headline grid.  Batches
+    beyond the four distinct 2^20 ones repeat them with N(0, 1e-3) jitter (the spatial mix is
+    unchanged); upstream gradients are seeded normals scaled by 1/n."""
+    import torch
+
+    rows = {}
+    base = torch.cat([q for q, _ in dev_batches])
+    gen = torch.Generator(device=base.device)
+    gen.manual_seed(3)
+    for e in exps:
+        n = 1 << e
+        parts, have = [], 0
+        while have < n:
+            take = min(n - have, base.shape[0])
+            blk = base[:take]
+            if have >= base.shape[0]:
+                blk = torch.clamp(blk + 1e-3 * torch.randn(blk.shape, generator=gen, device=blk.device), -1.0, 1.0)
+            parts.append(blk)
+            have += take
+        q = torch.cat(parts).contiguous()
+        gf = torch.randn(n, generator=gen, device=q.device) / n
+        gg = torch.randn((n, 3), generator=gen, device=q.device) / n
+        f = torch.empty(n, device=q.device)
+        g = torch.empty((n, 3), device=q.device)
+        ws = grid.workspace(n)
+        U = unique_vertices_dev(q, RES)
+        r = fwd_bwd_bench(grid, q, gf, gg, ws, f, g, reps=reps, warmup=warmup)
+        b = algorithmic_bytes(n, U, 10, RES ** 3)
+        fb_bytes = b["forward"] + b["backward"]
+        t, ts = r["fwd_bwd"]["median"], r["sort_fwd_bwd"]["median"]
+        rows[f"2^{e}"] = {"queries": n, "unique_vertices": U, "fwd_bwd_us": t, "sort_fwd_bwd_us": ts,
+                          "queries_per_s": n / (t * 1e-6), "queries_per_s_with_sort": n / (ts * 1e-6),
+                          "frac": fb_bytes / (t * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                          "frac_with_sort": fb_bytes / (ts * 1e-6) / 1e9 / HBM_PEAK_GBS}
+        log(f"bench: sweep 2^{e}: " + json.dumps(rows[f"2^{e}"]))
+        del q, gf, gg, f, g, ws
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -549,6 +769,9 @@ def main():
     ap.add_argument("--no-objective", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--no-order-scaling", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--fwd-bwd-reps", type=int, default=200,
+                    help="repetitions of the warm and the cold fwd+bwd measurement (each after 20 warm-up)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="end with device-to-device copies of 256 MiB (the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
@@ -683,11 +906,29 @@ def main():
                            "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                            "algorithmic_bytes": alg[dom]}
-        fb_us = unfused_us["forward"] + unfused_us["backward"]
+        # the metric's forward + backward (query-order outputs, precomputed upstream gradients),
+        # warm and with the Infinity Cache flushed before each repetition
+        q0, d0 = dev_batches[0]
+        grid.sort(q0, ws)
+        grid.forward(q0, ws, out=(f, g))
+        sdf_loss(f, g, d0, EIK, ws, g_f=gf, g_grad=gg, loss=loss)
+        flush = torch.zeros(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
         fb_bytes = alg["forward"] + alg["backward"]
-        out["fwd_bwd"] = {"queries_per_s": NQ / (fb_us * 1e-6), "us": fb_us,
-                          "achieved_GBs": fb_bytes / (fb_us * 1e-6) / 1e9,
-                          "frac": fb_bytes / (fb_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+        fb = {"algorithmic_bytes": fb_bytes, "unique_vertices": U, "repetitions": args.fwd_bwd_reps,
+              "flush_bytes": FLUSH_BYTES}
+        for mode, fl in (("warm", None), ("cold", flush)):
+            r = fwd_bwd_bench(grid, q0, gf, gg, ws, f, g, reps=args.fwd_bwd_reps, flush=fl)
+            t, ts = r["fwd_bwd"]["median"], r["sort_fwd_bwd"]["median"]
+            r["queries_per_s"] = NQ / (t * 1e-6)
+            r["frac"] = fb_bytes / (t * 1e-6) / 1e9 / HBM_PEAK_GBS
+            r["queries_per_s_with_sort"] = NQ / (ts * 1e-6)
+            r["frac_with_sort"] = fb_bytes / (ts * 1e-6) / 1e9 / HBM_PEAK_GBS
+            fb[mode] = r
+            log(f"bench: fwd+bwd {mode}: {t:.1f} us ({r['frac']:.3f} of HBM peak), with the sort {ts:.1f} us")
+        del flush
+        out["fwd_bwd"] = fb
+        if not args.no_sweep:
+            out["nq_sweep"] = nq_sweep(grid, dev_batches)
         out["breakdown_us"] = per_call_us
         out["unfused_breakdown_us"] = unfused_us
         out["kernels"] = {nm: {"us": t, "algorithmic_bytes": alg[nm], "GBs": alg[nm] / (t * 1e-6) / 1e9}

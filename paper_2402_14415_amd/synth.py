@@ -300,3 +300,23 @@ class BlobVolume:
         dens = g.sum(axis=1)
         col = (g @ self.rgb) / np.maximum(dens, 1e-12)[:, None]
         return dens, col
+
+    def density_and_colour_torch(self, x):
+        """The same density [n] and colour [n, 3] for a torch tensor x [n, 3] on its device,
+        in FP64 (a faster generator of targets for long runs; the same values as the NumPy
+        form up to rounding)."""
+        import torch
+
+        dev = x.device
+        x = x.double()
+        m = torch.tensor(self.m, dtype=torch.float64, device=dev)
+        A = torch.tensor(self.A, dtype=torch.float64, device=dev)
+        a = torch.tensor(self.a, dtype=torch.float64, device=dev)
+        rgb = torch.tensor(self.rgb, dtype=torch.float64, device=dev)
+        g = torch.empty((x.shape[0], len(self.a)), dtype=torch.float64, device=dev)
+        for k in range(len(self.a)):
+            y = (x - m[k]) @ A[k].T
+            g[:, k] = a[k] * torch.exp(-0.5 * (y * y).sum(dim=1))
+        dens = g.sum(dim=1)
+        col = (g @ rgb) / dens.clamp_min(1e-12)[:, None]
+        return dens, col
