@@ -381,6 +381,17 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
  * with Adam and the
  * final FP64 reductions of the loss and the gradient norm (for timing). */
 
+/* tg_train_step without its sort: the workspace must already hold the sort of (q, n) for this
+ * handle (tg_sort_queries, or tg_share_sort), else TG_ERR_STATE.  Arguments, buffers and
+ * results are tg_train_step's; stage_events[0] is recorded when the step starts.  The
+ * bucketing of a batch depends only on its queries (Sec. 3.1's cell location), not on the
+ * coefficients a step updates, so a loop may sort a batch ahead of its step: into a second
+ * workspace through a second handle on the same buffers, on another stream ordered by events. */
+tg_status tg_train_step_sorted(tg_grid* grid, const float* q, const float* d, int64_t n,
+                               const tg_sdf_objective* obj, const tg_adam_params* params, double* loss,
+                               double* grad_norm_sq, void* ws, size_t ws_bytes, void* const* stage_events,
+                               void* stream);
+
 /* One Adam step over every coefficient.  The grid is optimised directly by gradient descent
  * with no network (Sec. 3.1); Sec. 4.1 trains it with a fixed learning rate and names no
  * optimizer.  This is Adam with bias correction, eps added to the corrected root, and weight

@@ -87,6 +87,8 @@ _SIGS = {
                           ctypes.c_int32, _P], ctypes.c_int),
     "tg_train_step": ([_P, _P, _P, ctypes.c_int64, ctypes.POINTER(SdfObjective), ctypes.POINTER(AdamParams), _P, _P,
                        _P, ctypes.c_size_t, ctypes.POINTER(_P), _P], ctypes.c_int),
+    "tg_train_step_sorted": ([_P, _P, _P, ctypes.c_int64, ctypes.POINTER(SdfObjective), ctypes.POINTER(AdamParams), _P,
+                              _P, _P, ctypes.c_size_t, ctypes.POINTER(_P), _P], ctypes.c_int),
     "tg_composite": ([ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
                      ctypes.c_int),
     "tg_adam_step": ([_P, ctypes.POINTER(AdamParams), _P, _P, ctypes.c_size_t, ctypes.c_int32, _P], ctypes.c_int),

@@ -476,38 +476,46 @@ tg_status tg_backward_adam(tg_grid* grid, const float* q, int64_t n, void* ws, s
                          "tg_backward_adam");
 }
 
-tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n, const tg_sdf_objective* obj,
-                        const tg_adam_params* params, double* loss, double* grad_norm_sq, void* ws, size_t ws_bytes,
-                        void* const* stage_events, void* stream)
+// The training step; with sort == false the workspace must hold the sort of (q, n) already.
+static tg_status train_step(const char* fn, bool sort, tg_grid* grid, const float* q, const float* d, int64_t n,
+                            const tg_sdf_objective* obj, const tg_adam_params* params, double* loss,
+                            double* grad_norm_sq, void* ws, size_t ws_bytes, void* const* stage_events, void* stream)
 {
     tg::WsLayout L;
-    tg_status st = check_queries("tg_train_step", grid, q, n, ws, ws_bytes, &L);
+    tg_status st = check_queries(fn, grid, q, n, ws, ws_bytes, &L);
     if (st != TG_OK) return st;
-    if (n > 0 && !d) return fail(TG_ERR_INVALID_ARG, "tg_train_step: d is NULL");
-    if (!loss) return fail(TG_ERR_INVALID_ARG, "tg_train_step: loss is NULL");
-    if (!obj) return fail(TG_ERR_INVALID_ARG, "tg_train_step: objective is NULL");
+    if (n > 0 && !d) return fail(TG_ERR_INVALID_ARG, "%s: d is NULL", fn);
+    if (!loss) return fail(TG_ERR_INVALID_ARG, "%s: loss is NULL", fn);
+    if (!obj) return fail(TG_ERR_INVALID_ARG, "%s: objective is NULL", fn);
     const float eik_weight = obj->eik_weight, surface_k = obj->surface_k, tv_weight = obj->tv_weight;
-    if (!std::isfinite(eik_weight)) return fail(TG_ERR_INVALID_ARG, "tg_train_step: eik_weight is not finite");
-    st = check_surface_k("tg_train_step", surface_k);
+    if (!std::isfinite(eik_weight)) return fail(TG_ERR_INVALID_ARG, "%s: eik_weight is not finite", fn);
+    st = check_surface_k(fn, surface_k);
     if (st != TG_OK) return st;
-    st = refuse_rgb("tg_train_step", grid);
+    st = refuse_rgb(fn, grid);
     if (st != TG_OK) return st;
-    if (!std::isfinite(tv_weight)) return fail(TG_ERR_INVALID_ARG, "tg_train_step: tv_weight is not finite");
+    if (!std::isfinite(tv_weight)) return fail(TG_ERR_INVALID_ARG, "%s: tv_weight is not finite", fn);
     const bool tv = tv_weight != 0.0f;
     if (tv && !grid->bufs.grad)
-        return fail(TG_ERR_INVALID_ARG, "tg_train_step: the TV term needs bufs.grad (it holds the TV gradient)");
-    if (!grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_train_step: grid has no coeffs buffer");
-    st = check_adam("tg_train_step", grid, params);
+        return fail(TG_ERR_INVALID_ARG, "%s: the TV term needs bufs.grad (it holds the TV gradient)", fn);
+    if (!grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "%s: grid has no coeffs buffer", fn);
+    st = check_adam(fn, grid, params);
     if (st != TG_OK) return st;
+    if (!sort) {
+        st = check_sorted(fn, grid, q, n, ws);
+        if (st != TG_OK) return st;
+    }
     (void)hipGetLastError();
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(ws);
-    grid->sort_valid = false;
-    const uint64_t gen = ws_new_generation(ws);
+    uint64_t gen = grid->sort_gen;
+    if (sort) {
+        grid->sort_valid = false;
+        gen = ws_new_generation(ws);
+    }
     auto mark = [&](int k) -> hipError_t {
         return stage_events ? hipEventRecord(static_cast<hipEvent_t>(stage_events[k]), s) : hipSuccess;
     };
-    hipError_t e = tg::launch_sort(grid, q, n, w, L, s);
+    hipError_t e = sort ? tg::launch_sort(grid, q, n, w, L, s) : hipSuccess;
     if (e == hipSuccess) e = mark(0);
     // the TV term reads the coefficients before the update: its gradient goes to bufs.grad,
     // its value to loss[3]
@@ -528,7 +536,7 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
                                    grad_norm_sq ? reinterpret_cast<const double*>(w + L.bpart_off) : nullptr,
                                    L.max_bitems + L.merge_blocks, grad_norm_sq, tv_weight, tv ? loss + 3 : nullptr);
     if (e == hipSuccess) e = mark(2);
-    st = device_status(e, "tg_train_step");
+    st = device_status(e, fn);
     if (st == TG_OK) {  // the workspace holds this sort: tg_forward / tg_backward may reuse it
         grid->sort_q = q;
         grid->sort_n = n;
@@ -537,6 +545,22 @@ tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n
         grid->sort_valid = true;
     }
     return st;
+}
+
+tg_status tg_train_step(tg_grid* grid, const float* q, const float* d, int64_t n, const tg_sdf_objective* obj,
+                        const tg_adam_params* params, double* loss, double* grad_norm_sq, void* ws, size_t ws_bytes,
+                        void* const* stage_events, void* stream)
+{
+    return train_step("tg_train_step", true, grid, q, d, n, obj, params, loss, grad_norm_sq, ws, ws_bytes, stage_events,
+                      stream);
+}
+
+tg_status tg_train_step_sorted(tg_grid* grid, const float* q, const float* d, int64_t n, const tg_sdf_objective* obj,
+                               const tg_adam_params* params, double* loss, double* grad_norm_sq, void* ws,
+                               size_t ws_bytes, void* const* stage_events, void* stream)
+{
+    return train_step("tg_train_step_sorted", false, grid, q, d, n, obj, params, loss, grad_norm_sq, ws, ws_bytes,
+                      stage_events, stream);
 }
 
 tg_status tg_sdf_loss(int32_t dim, int64_t n, const float* f, const float* grad_f, const float* d, float eik_weight,

@@ -285,13 +285,28 @@ class TaylorGrid:
                   _ptr(ws), ws.numel(), _stream(self.device))
         return loss
 
+    def twin(self):
+        """A second handle on the same tensors (coefficients, gradient, moments), with its own
+        record of a sort: a training loop can sort the next batch into a second workspace with
+        the twin while this grid steps on the current one (``train_step(presorted=True)``)."""
+        import copy
+
+        t = copy.copy(self)
+        handle = ctypes.c_void_p()
+        _lib.call("tg_create", ctypes.byref(self._desc), ctypes.byref(self._buffers()), ctypes.byref(handle))
+        t._h = handle
+        t._sorted = None
+        return t
+
     def train_step(self, q, d, ws, eik_weight=0.1, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0,
-                   loss=None, grad_norm_sq=None, step=None, stage_events=None, surface_k=0.0, tv_weight=0.0):
+                   loss=None, grad_norm_sq=None, step=None, stage_events=None, surface_k=0.0, tv_weight=0.0,
+                   presorted=False):
         """One SDF-fitting step (sort, forward + loss, adjoint + Adam) in one call; returns the
         loss (device float64 [3]: total, weighted L1 mean, eikonal mean; with a TV term [4],
         the TV value last).  ``surface_k`` is Eq. 7's k (0: unweighted), ``tv_weight`` the TV
         term's weight (0: none; else ``grad`` holds the TV gradient).  stage_events: optional
-        three recorded torch.cuda.Events, re-recorded after each stage (for timing)."""
+        three recorded torch.cuda.Events, re-recorded after each stage (for timing).  With
+        ``presorted`` the step reuses the sort of (q, ws) that ``sort`` wrote (tg_train_step_sorted)."""
         n = self._q(q)
         _check_tensor("d", d, torch.float32, self.device, n)
         nl = 4 if tv_weight != 0.0 else 3
@@ -306,9 +321,11 @@ class TaylorGrid:
                 raise ValueError("stage_events must hold three events")
             evs = (ctypes.c_void_p * 3)(*[e.cuda_event for e in stage_events])
         obj = _lib.SdfObjective(eik_weight, surface_k, tv_weight)
-        _lib.call("tg_train_step", self._h, _ptr(q), _ptr(d), n, ctypes.byref(obj), ctypes.byref(p), _ptr(loss),
-                  _ptr(grad_norm_sq), _ptr(ws), ws.numel(), evs, _stream(self.device))
-        self._sorted = _new_sort(q, ws)
+        _lib.call("tg_train_step_sorted" if presorted else "tg_train_step", self._h, _ptr(q), _ptr(d), n,
+                  ctypes.byref(obj), ctypes.byref(p), _ptr(loss), _ptr(grad_norm_sq), _ptr(ws), ws.numel(), evs,
+                  _stream(self.device))
+        if not presorted:
+            self._sorted = _new_sort(q, ws)
         return loss
 
     def adam_step(self, ws, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0, grad_norm_sq=None,

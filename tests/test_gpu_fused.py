@@ -207,7 +207,9 @@ def test_train_step_matches_separate_calls(dim, res, order, storage, eik):
             e = nerr(to_np(getattr(b, name)).reshape(-1), to_np(getattr(a, name)).reshape(-1))
             print(f"step {step} {name}: err {e:.2e}")
             assert e <= tol
-        np.testing.assert_allclose(nb.item(), na.item(), rtol=1e-6)
+        # sum(dC^2) of two FP32 adjoints whose records were summed in different orders (two
+        # sorts rank a bucket's records by LDS atomics): the value tolerance
+        np.testing.assert_allclose(nb.item(), na.item(), rtol=TOL_VALUE)
     # the workspace holds the last sort: the separate forward can reuse it
     f, _ = b.forward(q, ws_b)
     fa, _ = a.forward(q, ws_a)

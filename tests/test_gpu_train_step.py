@@ -93,3 +93,63 @@ def test_train_step_split_bricks_against_oracle(order):
     g.adam_v.copy_(torch.from_numpy(v0))
     d = _away_from_residual_zero(geometry(g), C, q, rng.normal(0, 0.1, size=n).astype(np.float32).astype(np.float64))
     _step_against_oracle(g, C, m0.astype(np.float64), v0.astype(np.float64), q, d, step=3)
+
+
+def test_presorted_step_and_pipelined_loop_match_the_plain_step():
+    """tg_train_step_sorted on a sort written beforehand gives tg_train_step's result, and a
+    loop that sorts the next batch on a second stream (a twin handle, a second workspace)
+    while the current step runs ends where the plain loop ends.  Without a sort of the batch
+    in the workspace the presorted step refuses (TG_ERR_STATE)."""
+    from paper_2402_14415_amd._lib import TaylorGridError
+
+    rng = np.random.default_rng(57)
+    res = (40, 36, 33)
+    C32 = rng.normal(0, 0.05, size=(33, 36, 40, 10)).astype(np.float32)
+    scene = synth.Scene(0)
+    batches = []
+    for b in range(5):
+        q, d = synth.scene_batch(scene, 1 << 16, seed=7, step=b)
+        batches.append((torch.tensor(q, dtype=torch.float32, device=DEV), torch.tensor(d, dtype=torch.float32, device=DEV)))
+    a = TaylorGrid(3, res, 2, (-1.0,) * 3, (1.0,) * 3, coeffs=torch.from_numpy(C32), device=DEV)
+    b = TaylorGrid(3, res, 2, (-1.0,) * 3, (1.0,) * 3, coeffs=torch.from_numpy(C32), device=DEV)
+    # established moments: from zero moments Adam's first steps move every coefficient by about
+    # lr whatever the size of its gradient, which turns rounding-level differences of tiny
+    # gradients into visible ones
+    m0 = torch.from_numpy(rng.normal(0, 1e-5, size=C32.shape).astype(np.float32))
+    v0 = torch.from_numpy(rng.uniform(1e-9, 1e-8, size=C32.shape).astype(np.float32))
+    for g_ in (a, b):
+        g_.adam_m.copy_(m0)
+        g_.adam_v.copy_(v0)
+    wa = a.workspace(1 << 16)
+    with pytest.raises(TaylorGridError) as e:
+        a.train_step(*batches[0], wa, step=10, presorted=True)
+    assert e.value.status == 5
+    for k, (q, d) in enumerate(batches):
+        a.train_step(q, d, wa, step=k + 10)
+    # the pipelined loop on b
+    twin = b.twin()
+    hs, wss = (b, twin), (b.workspace(1 << 16), b.workspace(1 << 16))
+    side = torch.cuda.Stream(DEV)
+    main = torch.cuda.current_stream(DEV)
+    sorted_ev = [torch.cuda.Event(), torch.cuda.Event()]
+    done_ev = [torch.cuda.Event(), torch.cuda.Event()]
+    hs[0].sort(batches[0][0], wss[0])
+    sorted_ev[0].record(main)
+    for k in range(len(batches)):
+        h, h1 = k % 2, (k + 1) % 2
+        if k + 1 < len(batches):
+            with torch.cuda.stream(side):
+                if k > 0:
+                    side.wait_event(done_ev[h1])
+                hs[h1].sort(batches[k + 1][0], wss[h1])
+                sorted_ev[h1].record(side)
+        main.wait_event(sorted_ev[h])
+        hs[h].train_step(*batches[k], wss[h], step=k + 10, presorted=True)
+        done_ev[h].record(main)
+    torch.cuda.synchronize()
+    # the same arithmetic; two sorts of one batch may order a bucket's records differently,
+    # so the FP32 sums agree to rounding: the tolerances of the comparisons with the oracle
+    for name, tol in (("master", TOL_VALUE), ("adam_m", TOL_GRAD), ("adam_v", 2 * TOL_GRAD)):
+        e = nerr(to_np(getattr(b, name)).reshape(-1), to_np(getattr(a, name)).reshape(-1))
+        print(name, f"{e:.2e}")
+        assert e <= tol
