@@ -278,16 +278,24 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
     for (int k = 0; k < C; ++k) acc[k] = 0.0f;
     int vid = threadIdx.x;  // this thread's vertex (x + B (y + B z) within the brick)
 
+    // The record table's space holds the accumulators between passes ([vertex][C]).
+    float* vals = reinterpret_cast<float*>(ent);
+
     // One pass per kBwdItem records: stage them in LDS sorted by cell, then every thread
-    // adds the pairs of its vertex.  The lane assignment is chosen in the first pass and kept,
-    // so that a vertex's sums stay in one thread's registers.
+    // adds the pairs of its vertex.  Lanes are assigned to vertices anew in every pass, by
+    // that pass's pair counts (the records of a crowded brick's passes differ: its secondary
+    // records touch only the vertices of its lower faces); a vertex's sums move to its new
+    // lane through LDS.
     for (int32_t cbeg = beg; cbeg < end; cbeg += kBwdItem) {
         const int m = min(kBwdItem, end - cbeg);
         const bool first_pass = cbeg == beg;
-        if (!first_pass) __syncthreads();  // the previous pass is done with the LDS tables
+        if (!first_pass) {
+            __syncthreads();  // the previous pass is done with the record table
+#pragma unroll
+            for (int k = 0; k < C; ++k) vals[vid * C + k] = acc[k];
+        }
         for (int e = threadIdx.x; e < NCELL; e += NOWN) ccount[e] = 0u;
-        if (first_pass)
-            for (int e = threadIdx.x; e < NBIN; e += NOWN) bins[e] = 0u;
+        for (int e = threadIdx.x; e < NBIN; e += NOWN) bins[e] = 0u;
         __syncthreads();
 
         // Stage: decode this thread's records and rank each within its cell.
@@ -377,26 +385,14 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
             if (threadIdx.x == NOWN - 1) cstart[NCELL] = run;
         }
         __syncthreads();
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            if (my_cell[u] < 0) continue;
-            const uint32_t pos = cstart[my_cell[u]] + my_rank[u];
-            const float4 t = my_t[u], sg = my_g[u];
-            const float ta[3] = {t.x, t.y, t.z};
-            ent[kEntStride * pos] = make_float4(t.w, sg.x, sg.y, sg.z);
-#pragma unroll
-            for (int a = 0; a < DIM; ++a)
-                ent[kEntStride * pos + 1 + a] =
-                    make_float4(1.0f - ta[a], ta[a] * g.h[a], ta[a], (ta[a] - 1.0f) * g.h[a]);
-        }
 
+        // Lane assignment: threads take vertices in decreasing order of their record count in
+        // this pass, so the lanes of a wave have similar trip counts (the gather loop runs as
+        // long as its longest lane).
         int v[3];
         bool owned;
         uint32_t off[NRUN], mid[NRUN], pre[NRUN + 1];
-        if (first_pass) {
-            // Lane assignment: threads take vertices in decreasing order of their record
-            // count, so the lanes of a wave have similar trip counts (the gather loop runs as
-            // long as its longest lane).
+        {
             vertex_runs(threadIdx.x, v, owned, off, mid, pre);
             const uint32_t key = NBIN - 1 - min(pre[NRUN], (uint32_t)(NBIN - 1));
             const uint32_t brank = atomicAdd(&bins[key], 1u);
@@ -426,9 +422,26 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
             perm[bins[key] + brank] = (uint16_t)threadIdx.x;
             __syncthreads();
             vid = perm[threadIdx.x];
-        } else {
-            __syncthreads();  // records placed
         }
+        if (!first_pass) {
+#pragma unroll
+            for (int k = 0; k < C; ++k) acc[k] = vals[vid * C + k];
+            __syncthreads();  // every sum is read before the records overwrite the table
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            if (my_cell[u] < 0) continue;
+            const uint32_t pos = cstart[my_cell[u]] + my_rank[u];
+            const float4 t = my_t[u], sg = my_g[u];
+            const float ta[3] = {t.x, t.y, t.z};
+            ent[kEntStride * pos] = make_float4(t.w, sg.x, sg.y, sg.z);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+                ent[kEntStride * pos + 1 + a] =
+                    make_float4(1.0f - ta[a], ta[a] * g.h[a], ta[a], (ta[a] - 1.0f) * g.h[a]);
+        }
+
+        __syncthreads();  // records placed
         vertex_runs(vid, v, owned, off, mid, pre);
 
         const uint32_t total = pre[NRUN];
@@ -496,7 +509,6 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
     // Hand the sums over through LDS in [vertex][C] order (the record table is free now),
     // then write them row by row.
     __syncthreads();
-    float* vals = reinterpret_cast<float*>(ent);
 #pragma unroll
     for (int k = 0; k < C; ++k) vals[vid * C + k] = acc[k];
     __syncthreads();
