@@ -927,6 +927,10 @@ def main():
             log(f"bench: fwd+bwd {mode}: {t:.1f} us ({r['frac']:.3f} of HBM peak), with the sort {ts:.1f} us")
         del flush
         out["fwd_bwd"] = fb
+        # the metric's forward + backward beside the dominant kernel: fractions of HBM peak,
+        # warm and cold, without and with the sort both calls reuse
+        out["roofline"]["fwd_bwd_frac"] = {m: {"frac": fb[m]["frac"], "frac_with_sort": fb[m]["frac_with_sort"]}
+                                           for m in ("warm", "cold")}
         if not args.no_sweep:
             out["nq_sweep"] = nq_sweep(grid, dev_batches)
         out["breakdown_us"] = per_call_us
