@@ -240,3 +240,31 @@ def test_adam_step(storage):
         th64 = to_np(grid.master)
         m64 = to_np(grid.adam_m)
         v64 = to_np(grid.adam_v)
+
+
+def test_adam_step_full_size():
+    """tg_adam_step at the training workload's size (128^3 vertices x 10 coefficients, FP32)
+    against the oracle's Adam, every element, with established moments."""
+    rng = np.random.default_rng(6)
+    shape = (128, 128, 128, 10)
+    th = rng.normal(0, 0.05, size=shape).astype(np.float32)
+    grid = TaylorGrid(3, (128,) * 3, 2, (-1,) * 3, (1,) * 3, coeffs=torch.from_numpy(th), device=DEV)
+    m = rng.normal(0, 1e-3, size=shape).astype(np.float32)
+    v = rng.uniform(0, 1e-6, size=shape).astype(np.float32)
+    g = (rng.normal(size=shape) * 1e-3).astype(np.float32)
+    grid.adam_m.copy_(torch.from_numpy(m))
+    grid.adam_v.copy_(torch.from_numpy(v))
+    grid.grad.copy_(torch.from_numpy(g))
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device=DEV)
+    gns = torch.zeros(1, dtype=torch.float64, device=DEV)
+    grid.adam_step(ws, lr=1e-2, grad_norm_sq=gns, zero_grad=True, step=7)
+    torch.cuda.synchronize()
+    th64, m64, v64, ss = oracle.adam(th.astype(np.float64).reshape(-1), m.astype(np.float64).reshape(-1),
+                                     v.astype(np.float64).reshape(-1), g.astype(np.float64).reshape(-1), 1e-2,
+                                     0.9, 0.999, 1e-8, 0.0, 7)
+    assert nerr(to_np(grid.master).reshape(-1), th64) <= TOL_VALUE
+    assert nerr(to_np(grid.adam_m).reshape(-1), m64) <= TOL_VALUE
+    assert nerr(to_np(grid.adam_v).reshape(-1), v64) <= TOL_VALUE
+    # FP64 sums of the same 21M exact squares in two orders: n * 2^-53 bounds the difference
+    assert abs(float(gns[0]) - ss) <= 21e6 * 2.0 ** -53 * ss
+    assert torch.count_nonzero(grid.grad) == 0
