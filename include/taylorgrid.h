@@ -59,7 +59,7 @@ extern "C" {
 typedef enum {
     TG_OK = 0,
     TG_ERR_INVALID_ARG = 1, /* a NULL, out-of-range or inconsistent argument */
-    TG_ERR_UNSUPPORTED = 2, /* valid request this build does not implement */
+    TG_ERR_UNSUPPORTED = 2, /* valid request this library does not implement */
     TG_ERR_DEVICE = 3,      /* HIP reported an error on launch */
     TG_ERR_CAPACITY = 4,    /* workspace too small or size beyond the supported maximum */
     TG_ERR_STATE = 5        /* workspace does not hold the sort this call needs */
