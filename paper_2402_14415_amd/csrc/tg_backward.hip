@@ -5,8 +5,10 @@
 //   m_alpha(d_b) s_b + sum_a u_a dm_alpha/dd_a(d_b),   s_b = g_f w_b + g_grad . grad w_b,
 //   u = w_b g_grad,  m_alpha(d) = d^alpha / alpha!  (the Taylor monomials of Sec. 3.1, Eq. 1).
 //
-// Gather formulation: a workgroup owns a brick of B^dim vertices and one thread owns one
-// vertex, accumulating its C coefficients in registers.  The brick's records (the queries
+// Gather formulation: a workgroup owns a brick of B^dim vertices and, in each pass over the
+// brick's records, one thread owns one vertex, accumulating its C coefficients in registers
+// (vertices go to lanes by their pair count in the pass; the sums move with them through
+// LDS between passes).  The brick's records (the queries
 // whose cells touch its vertices: the primary and secondary buckets of the vertex brick,
 // see tg_sort.hip) are staged in LDS in chunks, counting-sorted by cell (LDS integer
 // atomics); each thread then walks the records of the 2^dim cells around its vertex, as

@@ -24,3 +24,14 @@ def test_algorithmic_bytes_of_the_training_step():
     # the adjoint with Adam: 12 B query + 16 B upstream per query, master/m/v read and written
     assert alg["backward_adam"] == n * 28 + nvert * C * 24
     assert alg["forward_loss"] == n * 32 + U * C * 4
+
+
+def test_kernel_hash_ignores_comments_only():
+    import bench
+
+    a = 'int f(int x) { return x + 1; } // one\n/* two */ const char* s = "a // b /* c */";\n'
+    b = '/* other words */ int f(int x)\n{\n    return x + 1;  // changed\n}\nconst char* s = "a // b /* c */";\n'
+    c = 'int f(int x) { return x + 2; }\nconst char* s = "a // b /* c */";\n'
+    assert bench.strip_comments(a) == bench.strip_comments(b)
+    assert bench.strip_comments(a) != bench.strip_comments(c)
+    assert '"a // b /* c */"' in bench.strip_comments(a)
