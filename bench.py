@@ -959,6 +959,21 @@ def main():
         # warm and cold, without and with the sort both calls reuse
         out["roofline"]["fwd_bwd_frac"] = {m: {"frac": fb[m]["frac"], "frac_with_sort": fb[m]["frac_with_sort"]}
                                            for m in ("warm", "cold")}
+        # The same batch handed over in brick order (its points and upstream gradients permuted
+        # together; the results are the same values, permuted): what the query-order scatter
+        # of f, grad f and the gather of g_f, g_grad cost in the calls above.
+        cell = torch.clamp(((q0 + 1.0) * ((RES - 1) / 2.0)).floor().long(), 0, RES - 2)
+        bk = cell // 8
+        nb = (RES + 7) // 8
+        loc = cell % 8
+        key = ((bk[:, 2] * nb + bk[:, 1]) * nb + bk[:, 0]) * 512 + loc[:, 0] + 8 * loc[:, 1] + 64 * loc[:, 2]
+        order = torch.argsort(key)
+        qc, gfc, ggc = q0[order].contiguous(), gf[order].contiguous(), gg[order].contiguous()
+        rc = fwd_bwd_bench(grid, qc, gfc, ggc, ws, f, g, reps=args.fwd_bwd_reps)
+        tc = rc["fwd_bwd"]["median"]
+        fb["brick_ordered_batch"] = {"fwd_bwd": rc["fwd_bwd"], "forward": rc["forward"], "backward": rc["backward"],
+                                     "queries_per_s": NQ / (tc * 1e-6), "frac": fb_bytes / (tc * 1e-6) / 1e9 / HBM_PEAK_GBS}
+        log(f"bench: fwd+bwd warm, the batch in brick order: {tc:.1f} us ({fb['brick_ordered_batch']['frac']:.3f} of HBM peak)")
         if not args.no_sweep:
             out["nq_sweep"] = nq_sweep(grid, dev_batches)
         out["breakdown_us"] = per_call_us
