@@ -96,10 +96,11 @@ def percentiles(xs):
     return {"median": float(np.median(xs)), "p10": float(np.percentile(xs, 10)), "p90": float(np.percentile(xs, 90))}
 
 
-def fwd_bwd_bench(grid, q, gf, gg, ws, f, g, reps=200, warmup=20, flush=None):
+def fwd_bwd_bench(grid, q, gf, gg, ws, f, g, reps=200, warmup=20, flush=None, packed=False):
     """The metric's forward + backward: tg_forward (f, grad f in query order) then
     tg_backward (dC from precomputed upstream gradients) on one stream, timed with HIP events
-    per repetition, and the bucketing sort that both reuse.  With `flush` (a 512 MiB device
+    per repetition, and the bucketing sort that both reuse.  With `packed`, f is the [n, 4]
+    output of tg_forward_packed and gf the [n, 4] packed upstream (g, gg unused).  With `flush` (a 512 MiB device
     buffer) the Infinity Cache (MALL) is flushed before the sort and again between the sort
     and the forward, by rewriting the buffer outside the timed windows.  Returns per-repetition
     medians and p10 / p90 in microseconds (sort_fwd_bwd adds the sort's window to fwd_bwd's)."""
@@ -121,9 +122,15 @@ def fwd_bwd_bench(grid, q, gf, gg, ws, f, g, reps=200, warmup=20, flush=None):
         if flush is not None:
             flush.add_(1.0)
         e and e[2].record(s)
-        grid.forward(q, ws, out=(f, g))
+        if packed:
+            grid.forward_packed(q, ws, out=f)
+        else:
+            grid.forward(q, ws, out=(f, g))
         e and e[3].record(s)
-        grid.backward(q, ws, gf, gg)
+        if packed:
+            grid.backward(q, ws, packed=gf)
+        else:
+            grid.backward(q, ws, gf, gg)
         e and e[4].record(s)
     torch.cuda.synchronize()
     us = lambda a, b: np.array([1e3 * e[a].elapsed_time(e[b]) for e in evs])
@@ -944,21 +951,35 @@ def main():
         fb_bytes = alg["forward"] + alg["backward"]
         fb = {"algorithmic_bytes": fb_bytes, "unique_vertices": U, "repetitions": args.fwd_bwd_reps,
               "flush_bytes": FLUSH_BYTES}
-        for mode, fl in (("warm", None), ("cold", flush)):
-            r = fwd_bwd_bench(grid, q0, gf, gg, ws, f, g, reps=args.fwd_bwd_reps, flush=fl)
-            t, ts = r["fwd_bwd"]["median"], r["sort_fwd_bwd"]["median"]
-            r["queries_per_s"] = NQ / (t * 1e-6)
-            r["frac"] = fb_bytes / (t * 1e-6) / 1e9 / HBM_PEAK_GBS
-            r["queries_per_s_with_sort"] = NQ / (ts * 1e-6)
-            r["frac_with_sort"] = fb_bytes / (ts * 1e-6) / 1e9 / HBM_PEAK_GBS
-            fb[mode] = r
-            log(f"bench: fwd+bwd {mode}: {t:.1f} us ({r['frac']:.3f} of HBM peak), with the sort {ts:.1f} us")
-        del flush
+        # the same calls with (f, grad f) and (g_f, g_grad) packed in one 16-byte row per query
+        fg4 = torch.empty((NQ, 4), device=dev)
+        up4 = torch.cat([gf[:, None], gg], dim=1).contiguous()
+        fb["packed"] = {"layout": "tg_forward_packed + tg_backward(TG_BWD_PACKED): [n][4] rows (f, grad f) "
+                                  "and (g_f, g_grad)"}
+        for lay, dst in (("separate", fb), ("packed", fb["packed"])):
+            for mode, fl in (("warm", None), ("cold", flush)):
+                if lay == "packed":
+                    r = fwd_bwd_bench(grid, q0, up4, None, ws, fg4, None, reps=args.fwd_bwd_reps, flush=fl,
+                                      packed=True)
+                else:
+                    r = fwd_bwd_bench(grid, q0, gf, gg, ws, f, g, reps=args.fwd_bwd_reps, flush=fl)
+                t, ts = r["fwd_bwd"]["median"], r["sort_fwd_bwd"]["median"]
+                r["queries_per_s"] = NQ / (t * 1e-6)
+                r["frac"] = fb_bytes / (t * 1e-6) / 1e9 / HBM_PEAK_GBS
+                r["queries_per_s_with_sort"] = NQ / (ts * 1e-6)
+                r["frac_with_sort"] = fb_bytes / (ts * 1e-6) / 1e9 / HBM_PEAK_GBS
+                dst[mode] = r
+                log(f"bench: fwd+bwd {mode} ({lay}): {t:.1f} us ({r['frac']:.3f} of HBM peak), "
+                    f"with the sort {ts:.1f} us")
+        del flush, fg4, up4
         out["fwd_bwd"] = fb
         # the metric's forward + backward beside the dominant kernel: fractions of HBM peak,
-        # warm and cold, without and with the sort both calls reuse
+        # warm and cold, without and with the sort both calls reuse, for both output layouts
         out["roofline"]["fwd_bwd_frac"] = {m: {"frac": fb[m]["frac"], "frac_with_sort": fb[m]["frac_with_sort"]}
                                            for m in ("warm", "cold")}
+        out["roofline"]["fwd_bwd_frac"]["packed"] = {
+            m: {"frac": fb["packed"][m]["frac"], "frac_with_sort": fb["packed"][m]["frac_with_sort"]}
+            for m in ("warm", "cold")}
         # The same batch handed over in brick order (its points and upstream gradients permuted
         # together; the results are the same values, permuted): what the query-order scatter
         # of f, grad f and the gather of g_f, g_grad cost in the calls above.

@@ -134,6 +134,9 @@ typedef struct {
 #define TG_ADAM_ZERO_GRAD 1  /* tg_adam_step: zero grad after reading it */
 #define TG_BWD_ADD_GRAD 1    /* tg_backward_adam: add bufs.grad (e.g. tg_tv_loss's gradient) to the
                                 adjoint before the update */
+#define TG_BWD_PACKED 2      /* tg_backward, tg_backward_adam: g_f is [n][4], each query's
+                                (g_f, g_grad) in one 16-byte row (in 2D the last word is ignored),
+                                the layout tg_forward_packed writes; g_grad must be NULL */
 
 /* binom(dim + order, order), or -1 when dim is not 2/3 or order is not 0..2. */
 int32_t tg_coeffs_per_vertex(int32_t dim, int32_t order);
@@ -187,6 +190,17 @@ tg_status tg_share_sort(tg_grid* grid, const tg_grid* sorted, const float* q, in
  * Requires the sort of (q, n) in ws (TG_ERR_STATE otherwise).  grad_f may be NULL. */
 tg_status tg_forward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes,
                      float* f, float* grad_f, void* stream);
+
+/* tg_forward (Sec. 3.1, Eq. 2-4) with each query's value and gradient packed in one 16-byte
+ * row: fg[i] = (f[i], grad_f[i][0], grad_f[i][1], grad_f[i][2]), fg [n][4] (in 2D the last
+ * word is written 0), the same values as tg_forward's.  The queries are evaluated in bucket
+ * order, so their outputs land at scattered rows: one aligned 16-byte store per query costs
+ * about half of tg_forward's two.  tg_backward with TG_BWD_PACKED takes the upstream
+ * gradients in the same layout.  fg: device, 16-byte aligned, written only.  Single-channel
+ * grids only (TG_ERR_UNSUPPORTED for a three-channel grid); TG_ERR_INVALID_ARG for a NULL or
+ * misaligned fg with n > 0; requires the sort of (q, n) in ws (TG_ERR_STATE otherwise). */
+tg_status tg_forward_packed(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes,
+                            float* fg, void* stream);
 
 /* SDF objective (Sec. 3.2, Eq. 6 with the adaptive weight of Eq. 7, plus the eikonal term
  * of Eq. 8):
@@ -327,6 +341,8 @@ tg_status tg_composite(int64_t n_rays, int32_t n_samples, const float* f, const 
  * touches are written 0 (or left unchanged when accumulating).  If dq != NULL it also
  * writes dq[i][a] = g_f df/dx_a + sum_c g_grad_c d2f/dx_a dx_c (0 on a clamped axis).
  * Requires the sort of (q, n) in ws; needs bufs.grad (and bufs.coeffs when dq != NULL).
+ * With TG_BWD_PACKED in flags, g_f is [n][4] ((g_f, g_grad) of a query in one 16-byte row,
+ * 16-byte aligned, required for n > 0) and g_grad must be NULL; a single-channel grid only.
  * The result does not depend on the order of the queries up to FP32 rounding of the sums. */
 tg_status tg_backward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes,
                       const float* g_f, const float* g_grad, float* dq, int32_t flags,
@@ -355,7 +371,8 @@ tg_status tg_backward_adam(tg_grid* grid, const float* q, int64_t n, void* ws, s
                            double* grad_norm_sq, int32_t flags, void* stream);
 /* flags: 0, or TG_BWD_ADD_GRAD, which adds bufs.grad (required then; read, not written) to
  * every coefficient's adjoint before its update, and counts it in grad_norm_sq: a gradient
- * computed beforehand, such as the TV term's from tg_tv_loss. */
+ * computed beforehand, such as the TV term's from tg_tv_loss; TG_BWD_PACKED as for
+ * tg_backward. */
 
 /* One SDF-fitting step (Sec. 3.2: the grid is optimised directly against the objective of
  * Eq. 8) in one call: tg_sort_queries, then tg_forward_sdf_loss, then

@@ -20,6 +20,7 @@ TG_F32, TG_BF16, TG_F16 = 0, 1, 2
 TG_BWD_ACCUMULATE = 1
 TG_ADAM_ZERO_GRAD = 1
 TG_BWD_ADD_GRAD = 1
+TG_BWD_PACKED = 2
 TG_HESSIAN_SYMMETRIC, TG_HESSIAN_FULL = 0, 1
 TG_QUERY_MAX_REQS = 32
 TG_QUERY_MAX_GRIDS = 16
@@ -70,6 +71,7 @@ _SIGS = {
     "tg_sort_queries": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "tg_share_sort": ([_P, _P, _P, ctypes.c_int64, _P, ctypes.c_size_t], ctypes.c_int),
     "tg_forward": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
+    "tg_forward_packed": ([_P, _P, ctypes.c_int64, _P, ctypes.c_size_t, _P, _P], ctypes.c_int),
     "tg_sdf_loss": ([ctypes.c_int32, ctypes.c_int64, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P,
                      ctypes.c_size_t, _P], ctypes.c_int),
     "tg_tv_loss": ([_P, ctypes.c_float, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P], ctypes.c_int),

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -368,6 +369,39 @@ tg_status tg_forward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t 
                          "tg_forward");
 }
 
+tg_status tg_forward_packed(tg_grid* grid, const float* q, int64_t n, void* ws, size_t ws_bytes, float* fg,
+                            void* stream)
+{
+    tg::WsLayout L;
+    tg_status st = check_queries("tg_forward_packed", grid, q, n, ws, ws_bytes, &L);
+    if (st != TG_OK) return st;
+    if (grid->kord == tg::kOrderRGB1)
+        return fail(TG_ERR_UNSUPPORTED, "tg_forward_packed: a three-channel grid has no packed layout");
+    if (n > 0 && (!fg || reinterpret_cast<uintptr_t>(fg) % 16 != 0))
+        return fail(TG_ERR_INVALID_ARG, "tg_forward_packed: fg must be a 16-byte aligned device pointer");
+    if (!grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_forward_packed: grid has no coeffs buffer");
+    st = check_sorted("tg_forward_packed", grid, q, n, ws);
+    if (st != TG_OK) return st;
+    if (n == 0) return ok();
+    (void)hipGetLastError();
+    return device_status(tg::launch_forward(grid, n, static_cast<const char*>(ws), L, fg, nullptr,
+                                            static_cast<hipStream_t>(stream), true),
+                         "tg_forward_packed");
+}
+
+// TG_BWD_PACKED: g_f is the [n][4] upstream (16-byte aligned, required for n > 0), g_grad NULL,
+// single-channel grids only.
+static tg_status check_packed_upstream(const char* fn, const tg_grid* grid, int64_t n, const float* g_f,
+                                       const float* g_grad)
+{
+    if (grid->kord == tg::kOrderRGB1)
+        return fail(TG_ERR_UNSUPPORTED, "%s: a three-channel grid has no packed layout", fn);
+    if (g_grad) return fail(TG_ERR_INVALID_ARG, "%s: TG_BWD_PACKED takes g_grad = NULL", fn);
+    if (n > 0 && (!g_f || reinterpret_cast<uintptr_t>(g_f) % 16 != 0))
+        return fail(TG_ERR_INVALID_ARG, "%s: TG_BWD_PACKED needs a 16-byte aligned g_f [n][4]", fn);
+    return ok();
+}
+
 // A three-channel grid's adjoint takes g_f [3][n] and nothing else.
 static tg_status check_rgb_upstream(const char* fn, const tg_grid* grid, int64_t n, const float* g_f,
                                     const float* g_grad, const float* dq)
@@ -391,10 +425,13 @@ tg_status tg_backward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t
     tg::WsLayout L;
     tg_status st = check_queries("tg_backward", grid, q, n, ws, ws_bytes, &L);
     if (st != TG_OK) return st;
-    if (flags & ~TG_BWD_ACCUMULATE) return fail(TG_ERR_INVALID_ARG, "tg_backward: unknown flags 0x%x", flags);
+    if (flags & ~(TG_BWD_ACCUMULATE | TG_BWD_PACKED))
+        return fail(TG_ERR_INVALID_ARG, "tg_backward: unknown flags 0x%x", flags);
     if (!grid->bufs.grad) return fail(TG_ERR_INVALID_ARG, "tg_backward: grid has no grad buffer");
     if (dq && !grid->bufs.coeffs) return fail(TG_ERR_INVALID_ARG, "tg_backward: dq needs the coeffs buffer");
-    st = check_rgb_upstream("tg_backward", grid, n, g_f, g_grad, dq);
+    const bool packed = (flags & TG_BWD_PACKED) != 0;
+    st = packed ? check_packed_upstream("tg_backward", grid, n, g_f, g_grad)
+                : check_rgb_upstream("tg_backward", grid, n, g_f, g_grad, dq);
     if (st != TG_OK) return st;
     st = check_sorted("tg_backward", grid, q, n, ws);
     if (st != TG_OK) return st;
@@ -403,8 +440,8 @@ tg_status tg_backward(tg_grid* grid, const float* q, int64_t n, void* ws, size_t
     (void)hipGetLastError();
     hipStream_t s = static_cast<hipStream_t>(stream);
     const char* w = static_cast<const char*>(ws);
-    hipError_t e = tg::launch_backward(grid, n, w, L, g_f, g_grad, acc, s);
-    if (e == hipSuccess && dq && n > 0) e = tg::launch_dq(grid, n, w, L, g_f, g_grad, dq, s);
+    hipError_t e = tg::launch_backward(grid, n, w, L, g_f, g_grad, acc, s, packed);
+    if (e == hipSuccess && dq && n > 0) e = tg::launch_dq(grid, n, w, L, g_f, g_grad, dq, s, packed);
     return device_status(e, "tg_backward");
 }
 
@@ -462,8 +499,11 @@ tg_status tg_backward_adam(tg_grid* grid, const float* q, int64_t n, void* ws, s
     if (st != TG_OK) return st;
     st = check_adam("tg_backward_adam", grid, params);
     if (st != TG_OK) return st;
-    if (flags & ~TG_BWD_ADD_GRAD) return fail(TG_ERR_INVALID_ARG, "tg_backward_adam: unknown flags 0x%x", flags);
-    st = check_rgb_upstream("tg_backward_adam", grid, n, g_f, g_grad, nullptr);
+    if (flags & ~(TG_BWD_ADD_GRAD | TG_BWD_PACKED))
+        return fail(TG_ERR_INVALID_ARG, "tg_backward_adam: unknown flags 0x%x", flags);
+    const bool packed = (flags & TG_BWD_PACKED) != 0;
+    st = packed ? check_packed_upstream("tg_backward_adam", grid, n, g_f, g_grad)
+                : check_rgb_upstream("tg_backward_adam", grid, n, g_f, g_grad, nullptr);
     if (st != TG_OK) return st;
     const bool add = (flags & TG_BWD_ADD_GRAD) != 0;
     if (add && !grid->bufs.grad) return fail(TG_ERR_INVALID_ARG, "tg_backward_adam: TG_BWD_ADD_GRAD needs bufs.grad");
@@ -472,7 +512,7 @@ tg_status tg_backward_adam(tg_grid* grid, const float* q, int64_t n, void* ws, s
     (void)hipGetLastError();
     return device_status(tg::launch_backward_adam(grid, n, static_cast<const char*>(ws), L, g_f, g_grad, *params,
                                                   grad_norm_sq, static_cast<hipStream_t>(stream), false,
-                                                  add ? grid->bufs.grad : nullptr),
+                                                  add ? grid->bufs.grad : nullptr, packed),
                          "tg_backward_adam");
 }
 

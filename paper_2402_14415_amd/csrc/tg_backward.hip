@@ -201,7 +201,7 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
                                                                  const float* __restrict__ gg,
                                                                  const float4* __restrict__ urec,
                                                                  float* __restrict__ grad, int accumulate, AdamBuf AB,
-                                                                 int64_t nq)
+                                                                 int64_t nq, int packed)
 {
     using S = BwdShape<DIM>;
     constexpr int B = S::B, NOWN = S::NOWN, NCELL = S::NCELL, NRUN = S::NRUN, PER = S::PER, NBIN = S::NBIN;
@@ -313,7 +313,8 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
                 const float q[3] = {r.x, r.y, r.z};
                 const int32_t tag = __float_as_int(r.w);
                 // upstream gradients of the record's query: in record order (found through the
-                // primary copy), or in query order (the query index is the primary's tag)
+                // primary copy), or in query order (the query index is the primary's tag), as
+                // separate arrays or packed (g_f, g_grad) in one 16-byte row of gf
                 float ugf = 0.0f, ugg[3] = {0.0f, 0.0f, 0.0f};
                 const int32_t prim = (tag & kRecSecondary) ? (tag & ~kRecSecondary) : cbeg + i;
                 if (urec) {
@@ -324,10 +325,18 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
                     ugg[2] = uv.w;
                 } else {
                     const int32_t idx = (tag & kRecSecondary) ? __float_as_int(rec[prim].w) : tag;
-                    if (gf) ugf = gf[idx];
-                    if (gg) {
+                    if (packed) {
+                        const float4 uv = reinterpret_cast<const float4*>(gf)[idx];
+                        ugf = uv.x;
+                        ugg[0] = uv.y;
+                        ugg[1] = uv.z;
+                        ugg[2] = uv.w;
+                    } else {
+                        if (gf) ugf = gf[idx];
+                        if (gg) {
 #pragma unroll
-                        for (int a = 0; a < DIM; ++a) ugg[a] = gg[(int64_t)idx * DIM + a];
+                            for (int a = 0; a < DIM; ++a) ugg[a] = gg[(int64_t)idx * DIM + a];
+                        }
                     }
                 }
                 AxisLoc L[DIM];
@@ -581,7 +590,7 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward_merge(Geom g, 
 template <int AD>
 static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const WsLayout& L, const float* g_f,
                                        const float* g_grad, const float4* urec, bool accumulate, const AdamBuf& AB,
-                                       hipStream_t s, int64_t nq)
+                                       hipStream_t s, int64_t nq, bool packed)
 {
     const float4* rec = reinterpret_cast<const float4*>(ws + L.rec_off);
     const int4* items = reinterpret_cast<const int4*>(ws + L.bitems_off);
@@ -596,7 +605,7 @@ static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const W
     if (dim == D && K == KK) {                                                                               \
         const dim3 block(BwdShape<D>::NOWN);                                                                 \
         hipLaunchKernelGGL((k_backward<D, KK, AD>), grid, block, 0, s, g->geom, items, meta, L.max_bitems, parts, \
-                           rec, g_f, g_grad, urec, gr, acc, AB, nq);                                         \
+                           rec, g_f, packed ? nullptr : g_grad, urec, gr, acc, AB, nq, packed ? 1 : 0);      \
         hipLaunchKernelGGL((k_backward_merge<D, KK, AD>), dim3((unsigned)L.merge_blocks), block, 0, s, g->geom, \
                            items, split_first, meta, parts, gr, acc, L.max_bitems, AB);                      \
         return hipGetLastError();                                                                            \
@@ -608,14 +617,14 @@ static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const W
 }
 
 hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
-                           const float* g_grad, bool accumulate, hipStream_t s)
+                           const float* g_grad, bool accumulate, hipStream_t s, bool packed)
 {
-    return launch_backward_impl<-1>(g, ws, L, g_f, g_grad, nullptr, accumulate, AdamBuf{}, s, n);
+    return launch_backward_impl<-1>(g, ws, L, g_f, g_grad, nullptr, accumulate, AdamBuf{}, s, n, packed);
 }
 
 hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
                                 const float* g_grad, const tg_adam_params& p, double* grad_norm_sq, hipStream_t s,
-                                bool record_order, const float* extra_grad)
+                                bool record_order, const float* extra_grad, bool packed)
 {
     const float4* urec = record_order ? reinterpret_cast<const float4*>(ws + L.urec_off) : nullptr;
     AdamBuf AB;
@@ -628,9 +637,9 @@ hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, con
     AB.extra = extra_grad;
     hipError_t e;
     switch (g->desc.storage) {
-    case ST_F32: e = launch_backward_impl<ST_F32>(g, ws, L, g_f, g_grad, urec, false, AB, s, n); break;
-    case ST_BF16: e = launch_backward_impl<ST_BF16>(g, ws, L, g_f, g_grad, urec, false, AB, s, n); break;
-    default: e = launch_backward_impl<ST_F16>(g, ws, L, g_f, g_grad, urec, false, AB, s, n); break;
+    case ST_F32: e = launch_backward_impl<ST_F32>(g, ws, L, g_f, g_grad, urec, false, AB, s, n, packed); break;
+    case ST_BF16: e = launch_backward_impl<ST_BF16>(g, ws, L, g_f, g_grad, urec, false, AB, s, n, packed); break;
+    default: e = launch_backward_impl<ST_F16>(g, ws, L, g_f, g_grad, urec, false, AB, s, n, packed); break;
     }
     if (e != hipSuccess || !grad_norm_sq) return e;
     return launch_sum_finish(AB.partials, L.max_bitems + L.merge_blocks, grad_norm_sq, s);

@@ -5,8 +5,11 @@
 // the way), with coalesced row loads, then evaluates every query bucketed to the brick
 // (its primary records) reading corners from LDS:
 //   f = sum_b w_b T_b(d_b),  grad f = sum_b (grad w_b T_b + w_b grad T_b)      (Sec. 3.1, Eq. 2-4)
-// Results are written in the caller's query order.  The dq mode evaluates the field's
-// Hessian as well and writes dq = g_f grad f + Hess f . g_grad.
+// Results are written in the caller's query order: f and grad f as separate arrays, or
+// packed as one 16-byte row (f, grad f) per query, which takes one store (the queries are
+// evaluated in bucket order, so these stores land at scattered rows).  The dq mode evaluates
+// the field's Hessian as well and writes dq = g_f grad f + Hess f . g_grad, reading the
+// upstream gradients from separate arrays or from one packed row per query.
 #include "tg_internal.hpp"
 
 namespace tg {
@@ -30,7 +33,15 @@ struct LossArgs {
     float inv_n;
     int eik;            // eikonal term on (record mode; query mode tests gg)
     int64_t nq;         // queries: the channel stride of a three-channel field's output
+    int packed;         // MODE_FWD: f_out is [n][4] (f, grad f); MODE_DQ: gf is [n][4] (g_f, g_grad)
 };
+
+// (v, x, y, z) of one query as a 16-byte row; in 2D the last word is 0.
+template <int DIM>
+__device__ __forceinline__ float4 pack_row(float v, const float* x)
+{
+    return make_float4(v, x[0], x[1], DIM == 3 ? x[DIM - 1] : 0.0f);
+}
 
 template <int DIM> __device__ __forceinline__ void brick_coords(const Geom& g, int32_t brick, int32_t* bc)
 {
@@ -295,7 +306,9 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
         for (int a = 0; a < DIM; ++a)
             if (L[a].clamped) gr[a] = 0.0f;
 
-        if constexpr (MODE == MODE_FWD || MODE == MODE_LOSS) {
+        if (MODE == MODE_FWD && LA.packed) {
+            reinterpret_cast<float4*>(f_out)[idx] = pack_row<DIM>(f, gr);
+        } else if constexpr (MODE == MODE_FWD || MODE == MODE_LOSS) {
             if (f_out) f_out[idx] = f;
             if (grad_out) {
 #pragma unroll
@@ -333,10 +346,18 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
             }
         }
         if constexpr (MODE == MODE_DQ) {
-            const float sf = gf ? gf[idx] : 0.0f;
-            float sg[DIM];
+            float sf, sg[DIM];
+            if (LA.packed) {
+                const float4 u = reinterpret_cast<const float4*>(gf)[idx];
+                const float uu[3] = {u.y, u.z, u.w};
+                sf = u.x;
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) sg[a] = (gg && !L[a].clamped) ? gg[(int64_t)idx * DIM + a] : 0.0f;
+                for (int a = 0; a < DIM; ++a) sg[a] = L[a].clamped ? 0.0f : uu[a];
+            } else {
+                sf = gf ? gf[idx] : 0.0f;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) sg[a] = (gg && !L[a].clamped) ? gg[(int64_t)idx * DIM + a] : 0.0f;
+            }
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
                 float v = sf * gr[a];
@@ -384,11 +405,12 @@ static hipError_t dispatch(const tg_grid* g, const char* ws, const WsLayout& L, 
 }
 
 hipError_t launch_forward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, float* f,
-                          float* grad_f, hipStream_t s)
+                          float* grad_f, hipStream_t s, bool packed)
 {
     LossArgs LA{};
     LA.nq = n;
-    return dispatch<MODE_FWD>(g, ws, L, f, grad_f, nullptr, nullptr, nullptr, s, LA);
+    LA.packed = packed ? 1 : 0;
+    return dispatch<MODE_FWD>(g, ws, L, f, packed ? nullptr : grad_f, nullptr, nullptr, nullptr, s, LA);
 }
 
 hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* d,
@@ -416,10 +438,12 @@ hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, cons
 }
 
 hipError_t launch_dq(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
-                     const float* g_grad, float* dq, hipStream_t s)
+                     const float* g_grad, float* dq, hipStream_t s, bool packed)
 {
-    (void)n;
-    return dispatch<MODE_DQ>(g, ws, L, nullptr, nullptr, g_f, g_grad, dq, s);
+    LossArgs LA{};
+    LA.nq = n;
+    LA.packed = packed ? 1 : 0;
+    return dispatch<MODE_DQ>(g, ws, L, nullptr, nullptr, g_f, packed ? nullptr : g_grad, dq, s, LA);
 }
 
 }  // namespace tg

@@ -93,12 +93,15 @@ WsLayout ws_layout(const tg_grid* g, int64_t n);
 // Kernel launchers (return the launch status).
 hipError_t launch_sort(const tg_grid* g, const float* q, int64_t n, char* ws, const WsLayout& L,
                        hipStream_t s);
+// packed: f (forward) or g_f (adjoint, dq) is [n][4], one row (value, gradient) per query, and
+// grad_f / g_grad are unused.
 hipError_t launch_forward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, float* f,
-                          float* grad_f, hipStream_t s);
+                          float* grad_f, hipStream_t s, bool packed = false);
 hipError_t launch_dq(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
-                     const float* g_grad, float* dq, hipStream_t s);
+                     const float* g_grad, float* dq, hipStream_t s, bool packed = false);
 hipError_t launch_backward(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L,
-                           const float* g_f, const float* g_grad, bool accumulate, hipStream_t s);
+                           const float* g_f, const float* g_grad, bool accumulate, hipStream_t s,
+                           bool packed = false);
 hipError_t launch_sdf_loss(int dim, int64_t n, const float* f, const float* grad_f, const float* d,
                            float eik_weight, float surf_k, float* g_f, float* g_grad, double* loss,
                            double* partials, hipStream_t s);
@@ -113,7 +116,7 @@ hipError_t launch_forward_loss(const tg_grid* g, int64_t n, const char* ws, cons
 // the update (the TV term's, written beforehand).
 hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, const WsLayout& L, const float* g_f,
                                 const float* g_grad, const tg_adam_params& p, double* grad_norm_sq, hipStream_t s,
-                                bool record_order = false, const float* extra_grad = nullptr);
+                                bool record_order = false, const float* extra_grad = nullptr, bool packed = false);
 // Also sums ng sum(dC^2) partials into *gnorm when gpart is given, and adds tv_weight * *tv
 // to the total when tv is given.
 hipError_t launch_loss_finish(const double* partials, int64_t nblocks, int64_t n, float eik_weight, double* loss,

@@ -199,17 +199,39 @@ class TaylorGrid:
         _lib.call("tg_forward", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _ptr(f), _ptr(g), _stream(self.device))
         return f, g
 
-    def backward(self, q, ws, g_f=None, g_grad=None, want_dq=False, accumulate=False, grad_out=None, dq_out=None):
-        """Writes (or accumulates) dL/dC into ``grad`` (or ``grad_out``); returns dq or None."""
+    def forward_packed(self, q, ws, out=None):
+        """f and grad f of each query in one 16-byte row: a [n, 4] tensor (f, grad f; in 2D
+        the last column is 0).  ``out[:, 0]`` and ``out[:, 1:1 + dim]`` are views of f and
+        grad f; ``backward(..., packed=...)`` takes upstream gradients in the same layout."""
         n = self._q(q)
+        fg = torch.empty((n, 4), dtype=torch.float32, device=self.device) if out is None else out
+        _check_tensor("out", fg, torch.float32, self.device, 4 * n)
+        _lib.call("tg_forward_packed", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _ptr(fg), _stream(self.device))
+        return fg
+
+    def _upstream(self, n, g_f, g_grad, packed):
+        """Checks the upstream gradients; returns (g_f pointer tensor, g_grad, flag bits)."""
+        if packed is not None:
+            if g_f is not None or g_grad is not None:
+                raise ValueError("pass either packed or g_f / g_grad")
+            _check_tensor("packed", packed, torch.float32, self.device, 4 * n)
+            return packed, None, _lib.TG_BWD_PACKED
         if g_f is not None:
             _check_tensor("g_f", g_f, torch.float32, self.device, self.channels * n)
         if g_grad is not None:
             _check_tensor("g_grad", g_grad, torch.float32, self.device, n * self.dim)
+        return g_f, g_grad, 0
+
+    def backward(self, q, ws, g_f=None, g_grad=None, want_dq=False, accumulate=False, grad_out=None, dq_out=None,
+                 packed=None):
+        """Writes (or accumulates) dL/dC into ``grad`` (or ``grad_out``); returns dq or None.
+        ``packed`` ([n, 4], the layout of ``forward_packed``) replaces g_f and g_grad."""
+        n = self._q(q)
+        g_f, g_grad, pflag = self._upstream(n, g_f, g_grad, packed)
         dq = None
         if want_dq:
             dq = dq_out if dq_out is not None else torch.empty((n, self.dim), dtype=torch.float32, device=self.device)
-        flags = _lib.TG_BWD_ACCUMULATE if accumulate else 0
+        flags = (_lib.TG_BWD_ACCUMULATE if accumulate else 0) | pflag
         if grad_out is not None:
             _check_tensor("grad_out", grad_out, torch.float32, self.device, self.master.numel())
             self.rebind(grad=grad_out)
@@ -254,20 +276,19 @@ class TaylorGrid:
         return _lib.AdamParams(lr, betas[0], betas[1], eps, weight_decay, self.step_count)
 
     def backward_adam(self, q, ws, g_f=None, g_grad=None, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0,
-                      grad_norm_sq=None, step=None, add_grad=False):
+                      grad_norm_sq=None, step=None, add_grad=False, packed=None):
         """Adjoint and Adam step in one pass (``grad`` is not written); grad_norm_sq
         (device float64 [1]) receives sum(dC^2).  ``add_grad`` adds the gradient already in
-        ``grad`` (e.g. the TV term's) to the adjoint before the update."""
+        ``grad`` (e.g. the TV term's) to the adjoint before the update.  ``packed`` ([n, 4],
+        the layout of ``forward_packed``) replaces g_f and g_grad."""
         n = self._q(q)
-        if g_f is not None:
-            _check_tensor("g_f", g_f, torch.float32, self.device, self.channels * n)
-        if g_grad is not None:
-            _check_tensor("g_grad", g_grad, torch.float32, self.device, n * self.dim)
+        g_f, g_grad, pflag = self._upstream(n, g_f, g_grad, packed)
         if grad_norm_sq is not None:
             _check_tensor("grad_norm_sq", grad_norm_sq, torch.float64, self.device)
         p = self._adam_params(lr, betas, eps, weight_decay, step)
         _lib.call("tg_backward_adam", self._h, _ptr(q), n, _ptr(ws), ws.numel(), _ptr(g_f), _ptr(g_grad),
-                  ctypes.byref(p), _ptr(grad_norm_sq), _lib.TG_BWD_ADD_GRAD if add_grad else 0, _stream(self.device))
+                  ctypes.byref(p), _ptr(grad_norm_sq), (_lib.TG_BWD_ADD_GRAD if add_grad else 0) | pflag,
+                  _stream(self.device))
 
     def upsample_from(self, coarse):
         """Start this grid (same box) from the field of ``coarse``: value, gradient and Hessian

@@ -214,7 +214,7 @@ def test_objective_validation():
         p = _lib.AdamParams(1e-2, 0.9, 0.999, 1e-8, 0.0, 1)
         # tg_backward_adam: TG_BWD_ADD_GRAD needs bufs.grad; unknown flags
         assert L().tg_backward_adam(h, fake, n, fake, ws, fake, None, ctypes.byref(p), None, 1, None) == 1
-        assert L().tg_backward_adam(hg, fake, n, fake, ws, fake, None, ctypes.byref(p), None, 2, None) == 1
+        assert L().tg_backward_adam(hg, fake, n, fake, ws, fake, None, ctypes.byref(p), None, 4, None) == 1
         # tg_train_step: objective required and finite, k >= 0, TV needs bufs.grad
         ok = _lib.SdfObjective(0.1, 0.0, 0.0)
         for obj, handle in ((None, hg), (_lib.SdfObjective(float("nan"), 0.0, 0.0), hg),
@@ -367,6 +367,47 @@ def test_channels_validation():
     finally:
         assert L().tg_destroy(h) == 0
         assert L().tg_destroy(h1) == 0
+
+
+def test_packed_layout_validation():
+    """tg_forward_packed and TG_BWD_PACKED: a 16-byte aligned [n][4] array, g_grad NULL,
+    single-channel grids only.  A call that passes validation stops at the missing sort
+    (TG_ERR_STATE); nothing is enqueued."""
+    fake = ctypes.c_void_p(0x100000)
+    odd = ctypes.c_void_p(0x100004)  # 4-byte but not 16-byte aligned
+    b = _lib.GridBuffers()
+    b.coeffs = b.master = b.grad = b.adam_m = b.adam_v = 0x1000
+    st, h = _create(_desc(order=2), b)
+    assert st == 0
+    d3 = _desc(order=1)
+    d3.channels = 3
+    st, hc = _create(d3, b)
+    assert st == 0
+    try:
+        n = 1000
+        ws, wsc = L().tg_workspace_bytes(h, n), L().tg_workspace_bytes(hc, n)
+        P = _lib.TG_BWD_PACKED
+        assert L().tg_forward_packed(h, fake, n, fake, ws, fake, None) == 5
+        assert L().tg_forward_packed(h, fake, n, fake, ws, odd, None) == 1
+        assert L().tg_forward_packed(h, fake, n, fake, ws, None, None) == 1
+        assert L().tg_forward_packed(hc, fake, n, fake, wsc, fake, None) == 2
+        assert L().tg_forward_packed(None, fake, n, fake, ws, fake, None) == 1
+        for flags in (P, P | _lib.TG_BWD_ACCUMULATE):
+            assert L().tg_backward(h, fake, n, fake, ws, fake, None, None, flags, None) == 5
+            assert L().tg_backward(h, fake, n, fake, ws, fake, None, fake, flags, None) == 5  # with dq
+            assert L().tg_backward(h, fake, n, fake, ws, fake, fake, None, flags, None) == 1  # g_grad given
+            assert L().tg_backward(h, fake, n, fake, ws, odd, None, None, flags, None) == 1
+            assert L().tg_backward(h, fake, n, fake, ws, None, None, None, flags, None) == 1
+            assert L().tg_backward(hc, fake, n, fake, wsc, fake, None, None, flags, None) == 2
+        assert L().tg_backward(h, fake, n, fake, ws, fake, None, None, 4, None) == 1  # unknown flag
+        p = _lib.AdamParams(1e-2, 0.9, 0.999, 1e-8, 0.0, 1)
+        for flags in (P, P | _lib.TG_BWD_ADD_GRAD):
+            assert L().tg_backward_adam(h, fake, n, fake, ws, fake, None, ctypes.byref(p), None, flags, None) == 5
+            assert L().tg_backward_adam(h, fake, n, fake, ws, fake, fake, ctypes.byref(p), None, flags, None) == 1
+            assert L().tg_backward_adam(h, fake, n, fake, ws, odd, None, ctypes.byref(p), None, flags, None) == 1
+    finally:
+        assert L().tg_destroy(h) == 0
+        assert L().tg_destroy(hc) == 0
 
 
 @pytest.mark.parametrize("dim", [2, 3])
