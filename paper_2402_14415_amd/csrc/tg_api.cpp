@@ -149,10 +149,12 @@ WsLayout ws_layout(const tg_grid* g, int64_t n)
     off = align_up(off + (size_t)L.max_bitems * 16, 256);
     L.splitb_off = off;
     off = align_up(off + (size_t)g->nbricks * 4, 256);
+    L.split_off = off;
+    off = align_up(off + (size_t)g->nbricks * 8, 256);
     L.fpart_off = off;
     off = align_up(off + (size_t)L.fwd_blocks * 2 * sizeof(double), 256);
     L.bpart_off = off;
-    off = align_up(off + (size_t)(L.max_bitems + L.merge_blocks) * sizeof(double), 256);
+    off = align_up(off + (size_t)L.max_bitems * sizeof(double), 256);
     L.rec_off = off;
     off = align_up(off + (size_t)n * ((size_t)1 << dim) * 16, 256);
     L.urec_off = off;
@@ -574,7 +576,7 @@ static tg_status train_step(const char* fn, bool sort, tg_grid* grid, const floa
         e = tg::launch_loss_finish(reinterpret_cast<const double*>(w + L.fpart_off), n > 0 ? L.fwd_blocks : 0, n,
                                    eik_weight, loss, s,
                                    grad_norm_sq ? reinterpret_cast<const double*>(w + L.bpart_off) : nullptr,
-                                   L.max_bitems + L.merge_blocks, grad_norm_sq, tv_weight, tv ? loss + 3 : nullptr);
+                                   L.max_bitems, grad_norm_sq, tv_weight, tv ? loss + 3 : nullptr);
     if (e == hipSuccess) e = mark(2);
     st = device_status(e, fn);
     if (st == TG_OK) {  // the workspace holds this sort: tg_forward / tg_backward may reuse it

@@ -15,6 +15,10 @@
 // one flattened loop over (corner, record) so that a lane's trip count is its total record
 // count.  No floating-point atomics, no races, and every vertex is written exactly once.
 // Crowded bricks are split into several work items whose partial sums a merge kernel adds.
+// With Adam in the epilogue there is no merge launch: the first item of a split brick stages
+// all of the brick's records (in more passes) when they number at most kBwdWholeMax, and the
+// items of a larger brick store their partial sums, the one that finishes last (found with a
+// device-scope count per brick) adding them in item order.
 #include "tg_internal.hpp"
 
 namespace tg {
@@ -196,6 +200,7 @@ template <int DIM, int K, int AD>
 __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_per_eu(DIM == 3 ? 6 : 4))) void k_backward(Geom g, const int4* __restrict__ items,
                                                                  const int32_t* __restrict__ meta, int64_t max_items,
                                                                  float* __restrict__ parts,
+                                                                 int2* __restrict__ split,
                                                                  const float4* __restrict__ rec,
                                                                  const float* __restrict__ gf,
                                                                  const float* __restrict__ gg,
@@ -238,8 +243,25 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
         return;
     }
     const int4 wi = items[item];
-    const int32_t brick = wi.x, beg = wi.y, end = wi.z, nchunk = wi.w;
+    const int32_t brick = wi.x, beg = wi.y;
+    int32_t end = wi.z, nchunk = wi.w;
     if (accumulate && nchunk == 1 && end <= beg) return;
+    int32_t first_item = item;
+    if constexpr (AD >= 0) {
+        if (nchunk > 1) {
+            // a split brick: its items are consecutive from first_item
+            first_item = split[brick].y;
+            const int32_t brick_end = items[first_item + nchunk - 1].z;
+            if (brick_end - items[first_item].y <= kBwdWholeMax) {
+                if (item != first_item) {  // the first item takes the whole brick
+                    if (threadIdx.x == 0) AB.partials[bid] = 0.0;
+                    return;
+                }
+                end = brick_end;
+                nchunk = 1;
+            }
+        }
+    }
 
     int32_t bc[3];
     vbrick_coords<DIM>(g, brick, bc);
@@ -531,10 +553,32 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
         float* slot = parts + (int64_t)item * (NOWN * C);
 #pragma unroll
         for (int k = 0; k < C; ++k) slot[epi_elem<DIM, C>(k)] = vk[k];
-        if constexpr (AD >= 0) {
-            if (threadIdx.x == 0) AB.partials[bid] = 0.0;  // counted by the merge
+        if constexpr (AD < 0) {
+            return;  // the merge launch adds the slots
+        } else {
+            // The item that finishes last adds the brick's slots in item order (the same sums
+            // whichever item it is).  The release fence makes this slot visible to every XCD
+            // before the count moves; the acquire fence drops this XCD's stale copies of the
+            // other slots.  Only bricks above kBwdWholeMax records come here.
+            __shared__ int32_t last_item;
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0) last_item = atomicAdd(&split[brick].x, 1) == nchunk - 1;
+            __syncthreads();
+            if (!last_item) {
+                if (threadIdx.x == 0) AB.partials[bid] = 0.0;  // the last item counts the brick
+                return;
+            }
+            __threadfence();
+            if (threadIdx.x == 0) split[brick].x = 0;  // ready for the next call on this sort
+#pragma unroll
+            for (int k = 0; k < C; ++k) vk[k] = 0.0f;
+            for (int32_t j = 0; j < nchunk; ++j) {
+                const float* sl = parts + (int64_t)(first_item + j) * (NOWN * C);
+#pragma unroll
+                for (int k = 0; k < C; ++k) vk[k] += sl[epi_elem<DIM, C>(k)];
+            }
         }
-        return;
     }
     if constexpr (AD >= 0) {
         const double tot = block_sum_f64<NOWN>(brick_epilogue<DIM, C, AD>(g, base, nown, vk, grad, 0, AB));
@@ -544,22 +588,20 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) __attribute__((amdgpu_waves_pe
     }
 }
 
-// Adds the partial sums of every split brick, in slot order, and writes the brick (or, with
-// AD >= 0, applies Adam to it).  Block b takes split bricks b, b + G, ... (G blocks); its
-// sum(dC^2) goes to partials[max_items + b].
-template <int DIM, int K, int AD>
+// The adjoint without Adam: adds the partial sums of every split brick, in slot order, and
+// writes (or accumulates) the brick's gradient.  Block b takes split bricks b, b + G, ... (G
+// blocks).
+template <int DIM, int K>
 __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward_merge(Geom g, const int4* __restrict__ items,
                                                                        const int32_t* __restrict__ split_first,
                                                                        const int32_t* __restrict__ meta,
                                                                        const float* __restrict__ parts,
-                                                                       float* __restrict__ grad, int accumulate,
-                                                                       int64_t max_items, AdamBuf AB)
+                                                                       float* __restrict__ grad, int accumulate)
 {
     using S = BwdShape<DIM>;
     constexpr int B = S::B, NOWN = S::NOWN;
     constexpr int C = NumCoeffs<DIM, K>::value;
     const int32_t nsplit = meta[META_NSPLITB];
-    double ss = 0.0;
     for (int32_t sb = blockIdx.x; sb < nsplit; sb += gridDim.x) {
         const int32_t first = split_first[sb];
         const int4 wi = items[first];
@@ -579,11 +621,7 @@ __global__ __launch_bounds__(BwdShape<DIM>::NOWN) void k_backward_merge(Geom g, 
 #pragma unroll
             for (int k = 0; k < C; ++k) vk[k] += slot[epi_elem<DIM, C>(k)];
         }
-        ss += brick_epilogue<DIM, C, AD>(g, base, nown, vk, grad, accumulate, AB);
-    }
-    if constexpr (AD >= 0) {
-        const double tot = block_sum_f64<NOWN>(ss);
-        if (threadIdx.x == 0) AB.partials[max_items + blockIdx.x] = tot;
+        brick_epilogue<DIM, C, -1>(g, base, nown, vk, grad, accumulate, AdamBuf{});
     }
 }
 
@@ -597,6 +635,7 @@ static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const W
     const int32_t* meta = reinterpret_cast<const int32_t*>(ws + L.meta_off);
     float* parts = reinterpret_cast<float*>(const_cast<char*>(ws) + L.parts_off);
     const int32_t* split_first = reinterpret_cast<const int32_t*>(ws + L.splitb_off);
+    int2* split = reinterpret_cast<int2*>(const_cast<char*>(ws) + L.split_off);
     const dim3 grid((unsigned)L.max_bitems);
     const int dim = g->desc.dim, K = g->kord;
     float* gr = g->bufs.grad;
@@ -605,9 +644,10 @@ static hipError_t launch_backward_impl(const tg_grid* g, const char* ws, const W
     if (dim == D && K == KK) {                                                                               \
         const dim3 block(BwdShape<D>::NOWN);                                                                 \
         hipLaunchKernelGGL((k_backward<D, KK, AD>), grid, block, 0, s, g->geom, items, meta, L.max_bitems, parts, \
-                           rec, g_f, packed ? nullptr : g_grad, urec, gr, acc, AB, nq, packed ? 1 : 0);      \
-        hipLaunchKernelGGL((k_backward_merge<D, KK, AD>), dim3((unsigned)L.merge_blocks), block, 0, s, g->geom, \
-                           items, split_first, meta, parts, gr, acc, L.max_bitems, AB);                      \
+                           split, rec, g_f, packed ? nullptr : g_grad, urec, gr, acc, AB, nq, packed ? 1 : 0); \
+        if (AD < 0)                                                                                           \
+            hipLaunchKernelGGL((k_backward_merge<D, KK>), dim3((unsigned)L.merge_blocks), block, 0, s, g->geom, \
+                               items, split_first, meta, parts, gr, acc);                                   \
         return hipGetLastError();                                                                            \
     }
     TG_BWD_CASE(3, 2) TG_BWD_CASE(3, 1) TG_BWD_CASE(3, 0) TG_BWD_CASE(2, 2) TG_BWD_CASE(2, 1) TG_BWD_CASE(2, 0)
@@ -642,7 +682,7 @@ hipError_t launch_backward_adam(const tg_grid* g, int64_t n, const char* ws, con
     default: e = launch_backward_impl<ST_F16>(g, ws, L, g_f, g_grad, urec, false, AB, s, n, packed); break;
     }
     if (e != hipSuccess || !grad_norm_sq) return e;
-    return launch_sum_finish(AB.partials, L.max_bitems + L.merge_blocks, grad_norm_sq, s);
+    return launch_sum_finish(AB.partials, L.max_bitems, grad_norm_sq, s);
 }
 
 }  // namespace tg

@@ -40,6 +40,9 @@ constexpr int kFwdChunk = 1024;          // primary records per forward work ite
 constexpr int32_t kRecSecondary = (int32_t)0x80000000;  // record tag bit: secondary bucket copy
 constexpr int kBwdItem = 512;            // records staged per pass of a backward work item
 constexpr int kBwdItemMax = 2048;        // records per backward work item (4 passes)
+// The adjoint with Adam stages every record of a split brick in the brick's first item (no
+// partial sums) up to this many records; larger bricks keep their items.
+constexpr int kBwdWholeMax = 8192;
 constexpr int64_t kMaxMeshCells = (int64_t)1 << 28;  // 12 triangles per cell stay below 2^32
 constexpr int kMaxReduceBlocks = 2048;  // FP64 partials: 4 per block
 constexpr size_t kReduceBytes = (size_t)kMaxReduceBlocks * 4 * sizeof(double);
@@ -63,9 +66,11 @@ struct WsLayout {
     size_t bitems_off;   // int4 [max_bitems]: backward items (brick, first record, end, items of
                          // the brick): split bricks' items from the front, whole bricks from the back
     size_t splitb_off;   // int32 [nbricks]: first backward item of each split brick
+    size_t split_off;    // int2 [nbricks]: per split brick, (items finished, first item); the
+                         // sort writes (0, first), the adjoint with Adam counts and resets
     size_t parts_off;    // float [max_slots x brick accumulator]: partial sums of split bricks
     size_t fpart_off;    // double [2 x fwd_blocks]: per-workgroup loss sums of the fused forward
-    size_t bpart_off;    // double [max_bitems + merge_blocks]: per-workgroup sum(dC^2) of the fused adjoint
+    size_t bpart_off;    // double [max_bitems]: per-workgroup sum(dC^2) of the fused adjoint
     size_t rec_off;      // float4 [n * 2^dim]: sorted query records (x, y, z, tag)
     size_t urec_off;     // float4 [n * 2^dim]: upstream gradients (g_f, g_grad) in record order
     size_t total;
@@ -77,7 +82,7 @@ struct WsLayout {
     int64_t fwd_blocks;  // workgroups of a forward launch
     int64_t max_bitems;  // bound on backward work items
     int64_t max_slots;   // bound on partial-sum slots of split backward bricks
-    int64_t merge_blocks;  // workgroups of the merge launch (each takes split bricks in turn)
+    int64_t merge_blocks;  // workgroups of the merge launch (the adjoint without Adam)
     int64_t acc_floats;  // floats in one brick accumulator (B^dim * C)
 };
 

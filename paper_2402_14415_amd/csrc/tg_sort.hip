@@ -85,12 +85,14 @@ __device__ __forceinline__ void load_query(const float* __restrict__ q, int64_t 
 // items of bricks with more than kBwdItem records are listed first (the longest work starts
 // first), every other brick is one item listed from the end of the array backwards,
 // including bricks no query touches (the item writes their zero gradient).  A split brick's
-// item index doubles as its partial-sum slot; a merge kernel adds the slots of a brick in
-// order.
+// items are consecutive and an item's index doubles as its partial-sum slot: the adjoint's
+// merge launch adds the slots of a brick in order (the adjoint with Adam takes a split brick
+// whole in its first item, or merges in the item that finishes last).
 struct WorkPtrs {
     int4* fitems;  // (brick, first record, end record, 0)
     int4* bitems;  // (brick, first record, end record, items of the brick)
     int32_t* split_first;  // first item of each split brick, in order
+    int2* split;           // per split brick: (0, its first item), the adjoint's arrival count
     int32_t* meta;
     int64_t max_bitems;
 };
@@ -176,7 +178,10 @@ __device__ __forceinline__ void brick_items(int64_t b, int32_t tp, int32_t ts, i
             for (int32_t j = 0; j < nb; ++j)
                 W.bitems[pos[2] + j] =
                     make_int4((int32_t)b, r0 + j * kBwdItemMax, min(r1, r0 + (j + 1) * kBwdItemMax), nb);
-            if (nb > 1) W.split_first[pos[4]] = pos[2];
+            if (nb > 1) {
+                W.split_first[pos[4]] = pos[2];
+                W.split[b] = make_int2(0, pos[2]);
+            }
         } else {
             W.bitems[W.max_bitems - 1 - pos[3]] = make_int4((int32_t)b, r0, r1, 1);
         }
@@ -516,6 +521,7 @@ hipError_t launch_sort(const tg_grid* g, const float* q, int64_t n, char* ws, co
     W.bitems = reinterpret_cast<int4*>(ws + L.bitems_off);
     W.max_bitems = L.max_bitems;
     W.split_first = reinterpret_cast<int32_t*>(ws + L.splitb_off);
+    W.split = reinterpret_cast<int2*>(ws + L.split_off);
     W.meta = reinterpret_cast<int32_t*>(ws + L.meta_off);
     if (L.sort_mode != SORT_ATOMIC) {
         int32_t* mat = reinterpret_cast<int32_t*>(ws + L.scratch_off);

@@ -130,6 +130,34 @@ def test_backward_adam_matches_unfused(dim, res, order, storage):
         np.testing.assert_allclose(nb.item(), na.item(), rtol=1e-6)  # FP32 gradients equal up to rounding
 
 
+def test_backward_adam_twice_on_one_sort():
+    """Two fused steps on one sort of a batch with a brick far above the size one workgroup
+    stages whole (its items merge through a per-brick arrival count, which the last item
+    resets): both steps match the separate calls."""
+    a, b, rng = _twin_grids(3, (30, 26, 28), 2, "f32", seed=23)
+    n = 60_000
+    q64 = rng.uniform(-1, 1, size=(n, 3))
+    q64[: n // 2] = 0.11 + rng.uniform(0, 0.02, size=(n // 2, 3))  # one brick, ~30,000 records
+    q = torch.tensor(q64.astype(np.float32), device=DEV)
+    ws_a, ws_b = a.workspace(n), b.workspace(n)
+    a.sort(q, ws_a)
+    b.sort(q, ws_b)
+    for step in range(2):
+        gf = torch.tensor(rng.normal(size=n) / n, dtype=torch.float32, device=DEV)
+        gg = torch.tensor(rng.normal(size=(n, 3)) / n, dtype=torch.float32, device=DEV)
+        na = torch.zeros(1, dtype=torch.float64, device=DEV)
+        nb = torch.zeros(1, dtype=torch.float64, device=DEV)
+        a.backward(q, ws_a, gf, gg)
+        a.adam_step(ws_a, lr=1e-2, grad_norm_sq=na, step=10 + step)
+        b.backward_adam(q, ws_b, gf, gg, lr=1e-2, grad_norm_sq=nb, step=10 + step)
+        torch.cuda.synchronize()
+        for name, tol in (("master", 1e-6), ("adam_m", TOL_VALUE), ("adam_v", TOL_VALUE)):
+            e = nerr(to_np(getattr(b, name)).reshape(-1), to_np(getattr(a, name)).reshape(-1))
+            print(f"step {step} {name}: err {e:.2e}")
+            assert e <= tol
+        np.testing.assert_allclose(nb.item(), na.item(), rtol=1e-6)
+
+
 def test_backward_adam_no_queries():
     """No queries: every coefficient takes the Adam step of a zero gradient."""
     a, b, _ = _twin_grids(3, (12, 12, 12), 2, "f32", seed=5)

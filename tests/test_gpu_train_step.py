@@ -71,19 +71,21 @@ def test_train_step_full_size_against_oracle():
     _step_against_oracle(g, C, m0.astype(np.float64), v0.astype(np.float64), q, d, step=5)
 
 
-@pytest.mark.parametrize("order", [1, 2])
-def test_train_step_split_bricks_against_oracle(order):
-    """Most queries packed into a few cells of one brick: its records exceed one adjoint work
-    item several times over, so its partial sums go through the merge launch and its Adam
-    update is applied there."""
-    rng = np.random.default_rng(56 + order)
+@pytest.mark.parametrize("order,crowd", [(1, 48_000), (2, 48_000), (2, 5_000)])
+def test_train_step_split_bricks_against_oracle(order, crowd):
+    """`crowd` queries packed into a few cells of one brick: its records exceed one adjoint
+    work item several times over.  With 48,000 the brick is above the size the adjoint with
+    Adam stages in one workgroup, so its items store partial sums and the one that finishes
+    last adds them and applies Adam; with 5,000 the brick's first item stages all of its
+    records."""
+    rng = np.random.default_rng(56 + order + crowd)
     res = (24, 20, 22)
     nc = [1, 4, 10][order]
     C32 = rng.normal(0, 0.05, size=(22, 20, 24, nc)).astype(np.float32)
     C = C32.astype(np.float64)
     n = 80_000
     q = rng.uniform(-1, 1, size=(n, 3))
-    k = int(0.6 * n)
+    k = crowd
     q[:k] = -0.3 + rng.uniform(0, 0.15, size=(k, 3))  # about 2 cells per axis of one brick
     q = q.astype(np.float32).astype(np.float64)
     m0 = rng.normal(0, 1e-4, size=C.shape).astype(np.float32)
