@@ -1,5 +1,5 @@
 """The production training step (tg_train_step: sort, forward with the loss in its epilogue,
-adjoint with Adam in the same pass, split bricks merged) against the FP64 oracle's forward,
+adjoint with Adam in the same pass, crowded bricks taken whole or merged) against the FP64 oracle's forward,
 loss, adjoint and Adam, at the full SDF-fitting size and on crowded bricks."""
 import numpy as np
 import pytest
@@ -54,8 +54,8 @@ def _away_from_residual_zero(geom, C, q, d, gap=1e-4):
 
 
 def test_train_step_full_size_against_oracle():
-    """128^3 vertices, K=2, 2^20 scene queries (half on the surfaces: crowded bricks split
-    over several work items and merged), L1 + 0.1 eikonal, Adam with established moments at
+    """128^3 vertices, K=2, 2^20 scene queries (half on the surfaces: crowded bricks above one
+    adjoint work item, staged whole by their first item), L1 + 0.1 eikonal, Adam with established moments at
     step 5, every one of the 21 M coefficients compared."""
     C64, q, d, _ = synth.scene3d_inputs(res=128, order=2, n=1 << 20, seed=0)
     C32 = C64.astype(np.float32)
