@@ -97,6 +97,27 @@ def test_train_step_split_bricks_against_oracle(order, crowd):
     _step_against_oracle(g, C, m0.astype(np.float64), v0.astype(np.float64), q, d, step=3)
 
 
+@pytest.mark.parametrize("crowd", [5_000, 30_000])
+def test_train_step_split_bricks_2d_against_oracle(crowd):
+    """The same in 2D (bricks of 16 x 16 cells): a brick of about `crowd` records is staged whole
+    by its first item (5,000) or merged by its last item (30,000)."""
+    rng = np.random.default_rng(60 + crowd)
+    res = (50, 40)
+    C32 = rng.normal(0, 0.05, size=(40, 50, 6)).astype(np.float32)
+    C = C32.astype(np.float64)
+    n = 60_000
+    q = rng.uniform(-1, 1, size=(n, 2))
+    q[:crowd] = 0.2 + rng.uniform(0, 0.05, size=(crowd, 2))
+    q = q.astype(np.float32).astype(np.float64)
+    m0 = rng.normal(0, 1e-4, size=C.shape).astype(np.float32)
+    v0 = rng.uniform(1e-9, 1e-8, size=C.shape).astype(np.float32)
+    g = TaylorGrid(2, res, 2, (-1.0,) * 2, (1.0,) * 2, coeffs=torch.from_numpy(C32), device=DEV)
+    g.adam_m.copy_(torch.from_numpy(m0))
+    g.adam_v.copy_(torch.from_numpy(v0))
+    d = _away_from_residual_zero(geometry(g), C, q, rng.normal(0, 0.1, size=n).astype(np.float32).astype(np.float64))
+    _step_against_oracle(g, C, m0.astype(np.float64), v0.astype(np.float64), q, d, step=4)
+
+
 def test_presorted_step_and_pipelined_loop_match_the_plain_step():
     """tg_train_step_sorted on a sort written beforehand gives tg_train_step's result, and a
     loop that sorts the next batch on a second stream (a twin handle, a second workspace)
