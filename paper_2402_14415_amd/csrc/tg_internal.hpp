@@ -90,7 +90,9 @@ struct WsLayout {
 // Backward items: "front" items belong to bricks with more than one pass of records (listed
 // from the front of the array, heaviest work first), "back" items to the other bricks
 // (listed from the end); a brick with more than kBwdItemMax records is split into several
-// items whose partial sums a merge kernel adds ("split" bricks).
+// items ("split" bricks), whose partial sums the merge launch adds (the adjoint with Adam
+// takes the brick whole in its first item up to kBwdWholeMax records, else merges in the
+// item that finishes last).
 enum { META_FITEMS = 0, META_BFRONT = 1, META_BBACK = 2, META_NSPLITB = 3 };
 
 WsLayout ws_layout(const tg_grid* g, int64_t n);
