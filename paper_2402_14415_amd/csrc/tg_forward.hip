@@ -224,6 +224,12 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
         const float4 r = rec[j];
         const float q[3] = {r.x, r.y, r.z};
         const int32_t idx = __float_as_int(r.w);
+        // the loss's target, loaded before the corner loop so that its latency hides behind it
+        float dt = 0.0f;
+        if constexpr (MODE == MODE_LOSS) {
+            dt = LA.d[idx];
+            __builtin_amdgcn_sched_barrier(0);  // keep the load here; it is waited for at its use
+        }
         AxisLoc L[DIM];
         locate<DIM>(g, q, L);
         int lc[DIM];
@@ -317,7 +323,6 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
         }
         if constexpr (MODE == MODE_LOSS) {
             const bool rec_mode = LA.urec != nullptr;
-            const float dt = LA.d[idx];
             const float res = f - dt;
             const float w = surface_weight(LA.surf_k, f, dt);  // held fixed in the gradient
             sum_r += (double)w * (double)fabsf(res);
