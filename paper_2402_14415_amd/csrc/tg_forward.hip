@@ -220,8 +220,13 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
     __syncthreads();
 
     double sum_r = 0.0, sum_e = 0.0;  // loss sums (MODE_LOSS)
-    for (int32_t j = beg + threadIdx.x; j < end; j += kThreads) {
-        const float4 r = rec[j];
+    // A thread's records are kThreads apart; the next one is loaded while this one is evaluated.
+    int32_t j = beg + threadIdx.x;
+    float4 rnext = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (j < end) rnext = rec[j];
+    for (; j < end; j += kThreads) {
+        const float4 r = rnext;
+        if (j + kThreads < end) rnext = rec[j + kThreads];
         const float q[3] = {r.x, r.y, r.z};
         const int32_t idx = __float_as_int(r.w);
         // the loss's target, loaded before the corner loop so that its latency hides behind it
