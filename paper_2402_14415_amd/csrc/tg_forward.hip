@@ -138,6 +138,11 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
         }
         return;
     }
+    // A thread's records are kThreads apart; each is loaded before the previous one is
+    // evaluated, the first before the brick's coefficients are staged.
+    int32_t j = beg + threadIdx.x;
+    float4 rnext = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (j < end) rnext = rec[j];
 
     int32_t bc[3];
     brick_coords<DIM>(g, brick, bc);
@@ -220,10 +225,6 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const int4* __rest
     __syncthreads();
 
     double sum_r = 0.0, sum_e = 0.0;  // loss sums (MODE_LOSS)
-    // A thread's records are kThreads apart; the next one is loaded while this one is evaluated.
-    int32_t j = beg + threadIdx.x;
-    float4 rnext = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (j < end) rnext = rec[j];
     for (; j < end; j += kThreads) {
         const float4 r = rnext;
         if (j + kThreads < end) rnext = rec[j + kThreads];
