@@ -127,7 +127,9 @@ def test_backward_adam_matches_unfused(dim, res, order, storage):
             diff = (b.coeffs.float() - a.coeffs.float()).abs().max().item()
             scale = a.coeffs.float().abs().max().item()
             assert diff <= 2 ** -7 * scale  # at most one storage ulp where the masters differ by rounding
-        np.testing.assert_allclose(nb.item(), na.item(), rtol=1e-6)  # FP32 gradients equal up to rounding
+        # sum(dC^2) in FP64 of FP32 gradients equal up to rounding: a crowded vertex sums thousands of
+        # terms in an order set by LDS atomics, which two launches may permute
+        np.testing.assert_allclose(nb.item(), na.item(), rtol=TOL_VALUE)
 
 
 def test_backward_adam_twice_on_one_sort():
@@ -151,11 +153,12 @@ def test_backward_adam_twice_on_one_sort():
         a.adam_step(ws_a, lr=1e-2, grad_norm_sq=na, step=10 + step)
         b.backward_adam(q, ws_b, gf, gg, lr=1e-2, grad_norm_sq=nb, step=10 + step)
         torch.cuda.synchronize()
-        for name, tol in (("master", 1e-6), ("adam_m", TOL_VALUE), ("adam_v", TOL_VALUE)):
+        # v carries twice the relative rounding of the crowded vertices' gradients
+        for name, tol in (("master", 1e-6), ("adam_m", TOL_VALUE), ("adam_v", 2 * TOL_VALUE)):
             e = nerr(to_np(getattr(b, name)).reshape(-1), to_np(getattr(a, name)).reshape(-1))
             print(f"step {step} {name}: err {e:.2e}")
             assert e <= tol
-        np.testing.assert_allclose(nb.item(), na.item(), rtol=1e-6)
+        np.testing.assert_allclose(nb.item(), na.item(), rtol=TOL_VALUE)  # FP32 gradients equal up to rounding
 
 
 def test_backward_adam_no_queries():

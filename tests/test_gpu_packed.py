@@ -152,7 +152,7 @@ def test_packed_backward_adam_equals_separate():
         b.sort(q, ws)
         b.backward_adam(q, ws, packed=_pack(gf32, gg32, 3), grad_norm_sq=nb, step=10 + step)
         torch.cuda.synchronize()
-        np.testing.assert_allclose(nb.item(), na.item(), rtol=1e-6)
+        np.testing.assert_allclose(nb.item(), na.item(), rtol=TOL_VALUE)  # FP32 gradients equal up to rounding
     for name, tol in (("master", 1e-6), ("adam_m", TOL_VALUE), ("adam_v", TOL_VALUE)):
         e = nerr(to_np(getattr(b, name)), to_np(getattr(a, name)))
         print(f"{name}: {e:.2e}")
