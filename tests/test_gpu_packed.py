@@ -106,6 +106,25 @@ def test_packed_2d_ignores_the_fourth_word(order):
     _check(grid, C32.astype(np.float64), q64, gf32, gg32, r)
 
 
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_packed_16bit_storage(storage):
+    """BF16 / FP16 storage (coefficients widened when staged): the packed rows equal the
+    separate-array outputs bit for bit, and the adjoint from packed upstream gradients equals
+    the separate one to rounding."""
+    rng = np.random.default_rng(725)
+    res, lo, hi = (29, 22, 17), (-1.0,) * 3, (1.0,) * 3
+    C32 = rng.normal(0, 0.05, size=(res[2], res[1], res[0], 10)).astype(np.float32)
+    grid = TaylorGrid(3, res, 2, lo, hi, storage=storage, coeffs=torch.from_numpy(C32), device=DEV)
+    n = 30_000
+    q64 = _queries(3, lo, hi, n, rng)
+    gf32 = (rng.normal(size=n) / n).astype(np.float32)
+    gg32 = (rng.normal(size=(n, 3)) / n).astype(np.float32)
+    r = _both(grid, q64, gf32, gg32)
+    assert torch.equal(r["fg"][:, 0], r["f"]) and torch.equal(r["fg"][:, 1:], r["g"])
+    assert torch.equal(r["dq_p"], r["dq"])
+    assert nerr(to_np(r["dC_p"]), to_np(r["dC"])) <= TOL_VALUE
+
+
 def test_packed_full_hessian_layout():
     """The 13-coefficient layout through the packed calls equals its separate-array calls."""
     rng = np.random.default_rng(720)
