@@ -161,6 +161,34 @@ def test_backward_adam_twice_on_one_sort():
         np.testing.assert_allclose(nb.item(), na.item(), rtol=TOL_VALUE)  # FP32 gradients equal up to rounding
 
 
+@pytest.mark.parametrize("n", [8192, 8193])
+def test_backward_adam_whole_brick_boundary(n):
+    """n queries inside one cell in the interior of a brick (no secondary records), so the
+    brick holds exactly n records: 8192 is the most the adjoint with Adam stages whole in the
+    brick's first item, 8193 goes through the per-brick arrival count.  Both match the
+    separate calls."""
+    a, b, rng = _twin_grids(3, (20, 20, 20), 1, "f32", seed=29)
+    h = 2.0 / 19
+    q64 = -1.0 + h * (2.0 + rng.uniform(0.1, 0.9, size=(n, 3)))  # cell (2, 2, 2) of brick 0
+    q = torch.tensor(q64.astype(np.float32), device=DEV)
+    ws_a, ws_b = a.workspace(n), b.workspace(n)
+    a.sort(q, ws_a)
+    b.sort(q, ws_b)
+    gf = torch.tensor(rng.normal(size=n) / n, dtype=torch.float32, device=DEV)
+    gg = torch.tensor(rng.normal(size=(n, 3)) / n, dtype=torch.float32, device=DEV)
+    na = torch.zeros(1, dtype=torch.float64, device=DEV)
+    nb = torch.zeros(1, dtype=torch.float64, device=DEV)
+    a.backward(q, ws_a, gf, gg)
+    a.adam_step(ws_a, lr=1e-2, grad_norm_sq=na, step=10)
+    b.backward_adam(q, ws_b, gf, gg, lr=1e-2, grad_norm_sq=nb, step=10)
+    torch.cuda.synchronize()
+    for name, tol in (("master", 1e-6), ("adam_m", TOL_VALUE), ("adam_v", 2 * TOL_VALUE)):
+        e = nerr(to_np(getattr(b, name)).reshape(-1), to_np(getattr(a, name)).reshape(-1))
+        print(f"n {n} {name}: err {e:.2e}")
+        assert e <= tol
+    np.testing.assert_allclose(nb.item(), na.item(), rtol=TOL_VALUE)
+
+
 def test_backward_adam_no_queries():
     """No queries: every coefficient takes the Adam step of a zero gradient."""
     a, b, _ = _twin_grids(3, (12, 12, 12), 2, "f32", seed=5)
