@@ -13,7 +13,46 @@ namespace tg {
 
 constexpr int kCompositeThreads = 256;  // 4 rays per workgroup
 
+// SPL consecutive floats at p (16-byte aligned when SPL is a multiple of 4, 8-byte when 2).
 template <int SPL>
+__device__ __forceinline__ void load_run(const float* __restrict__ p, float* v)
+{
+    if constexpr (SPL % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < SPL; k += 4) {
+            const float4 t = *reinterpret_cast<const float4*>(p + k);
+            v[k] = t.x;
+            v[k + 1] = t.y;
+            v[k + 2] = t.z;
+            v[k + 3] = t.w;
+        }
+    } else if constexpr (SPL == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+        v[0] = p[0];
+    }
+}
+
+template <int SPL>
+__device__ __forceinline__ void store_run(float* __restrict__ p, const float* v)
+{
+    if constexpr (SPL % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < SPL; k += 4)
+            *reinterpret_cast<float4*>(p + k) = make_float4(v[k], v[k + 1], v[k + 2], v[k + 3]);
+    } else if constexpr (SPL == 2) {
+        *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+    } else {
+        p[0] = v[0];
+    }
+}
+
+// VEC: every lane's SPL samples lie wholly inside the ray or wholly past its end (ns is a
+// multiple of SPL) and the arrays are aligned for SPL-wide accesses, so a lane moves its
+// samples of each array in 8- or 16-byte accesses.
+template <int SPL, bool VEC>
 __global__ __launch_bounds__(kCompositeThreads) void k_composite(int64_t n_rays, int32_t ns,
                                                                const float* __restrict__ f,
                                                                const float* __restrict__ col,
@@ -33,16 +72,42 @@ __global__ __launch_bounds__(kCompositeThreads) void k_composite(int64_t n_rays,
         const int64_t base = r * ns;
         float fk[SPL], dk[SPL], ak[SPL], ck[SPL][3];
         float lane_a = 0.0f;
+        const bool lane_in = lane * SPL < ns;  // (VEC) all of this lane's samples are in the ray
+        if constexpr (VEC) {
+            float cv[3][SPL];
+            if (lane_in) {
+                const int64_t o = base + lane * SPL;
+                load_run<SPL>(f + o, fk);
+                load_run<SPL>(delta + o, dk);
 #pragma unroll
-        for (int k = 0; k < SPL; ++k) {
-            const int i = lane * SPL + k;
-            const bool ok = i < ns;
-            fk[k] = ok ? f[base + i] : 0.0f;
-            dk[k] = ok ? delta[base + i] : 0.0f;
+                for (int ch = 0; ch < 3; ++ch) load_run<SPL>(col + ch * n + o, cv[ch]);
+            } else {
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) ck[k][ch] = ok ? col[ch * n + base + i] : 0.0f;
-            ak[k] = fmaxf(fk[k], 0.0f) * dk[k];  // sigma delta, sigma = relu(f)
-            lane_a += ak[k];
+                for (int k = 0; k < SPL; ++k) {
+                    fk[k] = dk[k] = 0.0f;
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) cv[ch][k] = 0.0f;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < SPL; ++k) {
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) ck[k][ch] = cv[ch][k];
+                ak[k] = fmaxf(fk[k], 0.0f) * dk[k];  // sigma delta, sigma = relu(f)
+                lane_a += ak[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < SPL; ++k) {
+                const int i = lane * SPL + k;
+                const bool ok = i < ns;
+                fk[k] = ok ? f[base + i] : 0.0f;
+                dk[k] = ok ? delta[base + i] : 0.0f;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) ck[k][ch] = ok ? col[ch * n + base + i] : 0.0f;
+                ak[k] = fmaxf(fk[k], 0.0f) * dk[k];  // sigma delta, sigma = relu(f)
+                lane_a += ak[k];
+            }
         }
         // exclusive prefix of the lanes' sums of sigma delta
         float incl = lane_a;
@@ -97,21 +162,37 @@ __global__ __launch_bounds__(kCompositeThreads) void k_composite(int64_t n_rays,
             }
             after[ch] = inc - lane_c[ch];
         }
+        float gfk[SPL], gck[3][SPL];
 #pragma unroll
         for (int k = SPL - 1; k >= 0; --k) {
-            const int i = lane * SPL + k;
             // dL/dsigma = delta sum_ch g_ch (T_{i+1} c_i - sum_{j>i} T_j alpha_j c_j)
             float gs = 0.0f;
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) gs = fmaf(g_rgb[ch], fmaf(Tn[k], ck[k][ch], -after[ch]), gs);
             gs *= dk[k];
-            if (i < ns) {
-                g_f[base + i] = fk[k] > 0.0f ? gs : 0.0f;
+            gfk[k] = fk[k] > 0.0f ? gs : 0.0f;
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) g_c[ch * n + base + i] = g_rgb[ch] * wk[k];
-            }
+            for (int ch = 0; ch < 3; ++ch) gck[ch][k] = g_rgb[ch] * wk[k];
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) after[ch] = fmaf(wk[k], ck[k][ch], after[ch]);
+        }
+        if constexpr (VEC) {
+            if (lane_in) {
+                const int64_t o = base + lane * SPL;
+                store_run<SPL>(g_f + o, gfk);
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) store_run<SPL>(g_c + ch * n + o, gck[ch]);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < SPL; ++k) {
+                const int i = lane * SPL + k;
+                if (i < ns) {
+                    g_f[base + i] = gfk[k];
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) g_c[ch * n + base + i] = gck[ch][k];
+                }
+            }
         }
     }
     if (partials) {
@@ -129,10 +210,23 @@ hipError_t launch_composite(int64_t n_rays, int32_t ns, const float* f, const fl
     const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, kMaxReduceBlocks));
     double* part = loss ? partials : nullptr;
     const int spl = (ns + 63) / 64;
+    // the wide-access variant: ns a multiple of the samples per lane, every array aligned
+    // (a NULL gradient output, as when only rendering, adds nothing to the alignment test)
+    auto aligned = [&](int S) {
+        const uintptr_t bytes = (uintptr_t)(S % 4 == 0 ? 16 : S * 4);
+        const uintptr_t a = reinterpret_cast<uintptr_t>(f) | reinterpret_cast<uintptr_t>(col) |
+                            reinterpret_cast<uintptr_t>(delta) | reinterpret_cast<uintptr_t>(g_f) |
+                            reinterpret_cast<uintptr_t>(g_c);
+        return S > 1 && ns % S == 0 && a % bytes == 0;
+    };
 #define TG_COMPOSITE(S)                                                                                     \
     if (spl <= S) {                                                                                         \
-        hipLaunchKernelGGL(k_composite<S>, dim3(nb), dim3(kCompositeThreads), 0, s, n_rays, ns, f, col, delta, \
-                           target, rgb, g_f, g_c, part);                                                   \
+        if (aligned(S))                                                                                     \
+            hipLaunchKernelGGL((k_composite<S, true>), dim3(nb), dim3(kCompositeThreads), 0, s, n_rays, ns, f, \
+                               col, delta, target, rgb, g_f, g_c, part);                                   \
+        else                                                                                                \
+            hipLaunchKernelGGL((k_composite<S, false>), dim3(nb), dim3(kCompositeThreads), 0, s, n_rays, ns, f, \
+                               col, delta, target, rgb, g_f, g_c, part);                                   \
     } else
     TG_COMPOSITE(1) TG_COMPOSITE(2) TG_COMPOSITE(4) TG_COMPOSITE(8) TG_COMPOSITE(16) { return hipErrorInvalidValue; }
 #undef TG_COMPOSITE
