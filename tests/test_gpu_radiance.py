@@ -21,7 +21,8 @@ def _f32(x):
     return np.asarray(x, dtype=np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("n_rays,ns", [(1000, 256), (777, 37), (300, 100), (64, 1), (40, 1024), (0, 16)])
+@pytest.mark.parametrize("n_rays,ns", [(1000, 256), (777, 37), (300, 100), (64, 1), (40, 1024), (0, 16),
+                                         (200, 480), (50, 300)])
 def test_composite_matches_oracle(n_rays, ns):
     rng = np.random.default_rng(ns)
     f = _f32(rng.normal(0.5, 2.0, size=(n_rays, ns)))  # a fifth or so non-positive: ReLU zeroes them
