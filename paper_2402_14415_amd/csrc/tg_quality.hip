@@ -187,12 +187,13 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* w
     return before + incl - x;
 }
 
-// Per thread: the triangle counts of kMeshCellsPerThread consecutive cells and their
-// exclusive prefix within the block (offs), the block's total (bsum); and the block's cells
-// that cross the level set (count > 0), listed in cell order from blist[block *
-// kMeshCellsPerBlock], with their number in scnt.
+// Per thread: the triangle counts of kMeshCellsPerThread consecutive cells; per block, the
+// cells that cross the level set (count > 0), listed in cell order from blist[block *
+// kMeshCellsPerBlock] with the exclusive prefix of the block's triangle counts at each of
+// them in boff (so that nothing is written for the many cells that do not cross), their
+// number in scnt and the block's triangle total in bsum.
 __global__ __launch_bounds__(kMeshThreads) void k_mesh_count(Lattice L, const float* __restrict__ v, int64_t ncell,
-                                                            uint32_t* __restrict__ offs, uint32_t* __restrict__ bsum,
+                                                            uint32_t* __restrict__ boff, uint32_t* __restrict__ bsum,
                                                             uint32_t* __restrict__ blist, uint32_t* __restrict__ scnt)
 {
     __shared__ uint32_t wsum[kMeshThreads / 64];
@@ -218,12 +219,15 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_count(Lattice L, const fl
     uint32_t run = block_exclusive_scan(tot, wsum, &btot);
     uint32_t srun = block_exclusive_scan(nstr, wsum, &bstr);
     uint32_t* mine = blist + (int64_t)blockIdx.x * kMeshCellsPerBlock;
+    uint32_t* mine_off = boff + (int64_t)blockIdx.x * kMeshCellsPerBlock;
 #pragma unroll
     for (int q = 0; q < kMeshCellsPerThread; ++q) {
-        const int64_t c = c0 + q;
-        if (c < ncell) offs[c] = run;
+        if (cnt[q] > 0) {
+            mine[srun] = (uint32_t)(c0 + q);
+            mine_off[srun] = run;
+            ++srun;
+        }
         run += cnt[q];
-        if (cnt[q] > 0) mine[srun++] = (uint32_t)c;
     }
     if (threadIdx.x == 0) {
         bsum[blockIdx.x] = btot;
@@ -231,16 +235,22 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_count(Lattice L, const fl
     }
 }
 
-// Gathers every block's list of crossing cells into one list at the block's scanned offset.
+// Gathers every block's list of crossing cells into one list at the block's scanned offset,
+// with each cell's first triangle (the block's scanned triangle offset bsum added).
 __global__ __launch_bounds__(kMeshThreads) void k_mesh_list(const uint32_t* __restrict__ blist,
+                                                           const uint32_t* __restrict__ boff,
                                                            const uint32_t* __restrict__ scnt,
                                                            const uint32_t* __restrict__ soff,
-                                                           uint32_t* __restrict__ list, int64_t nb)
+                                                           const uint32_t* __restrict__ bsum,
+                                                           uint32_t* __restrict__ list, uint32_t* __restrict__ lofs,
+                                                           int64_t nb)
 {
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        const uint32_t m = scnt[b], base = soff[b];
-        for (uint32_t r = threadIdx.x; r < m; r += kMeshThreads)
+        const uint32_t m = scnt[b], base = soff[b], tb = bsum[b];
+        for (uint32_t r = threadIdx.x; r < m; r += kMeshThreads) {
             list[base + r] = blist[b * kMeshCellsPerBlock + r];
+            lofs[base + r] = tb + boff[b * kMeshCellsPerBlock + r];
+        }
     }
 }
 
@@ -286,8 +296,7 @@ __device__ __forceinline__ void corner_pos(const Lattice& L, int i, int j, int k
 __global__ __launch_bounds__(kMeshThreads) void k_mesh_emit(Lattice L, const float* __restrict__ v,
                                                            const uint32_t* __restrict__ list,
                                                            const int64_t* __restrict__ nlist,
-                                                           const uint32_t* __restrict__ offs,
-                                                           const uint32_t* __restrict__ bsum, float* __restrict__ tri,
+                                                           const uint32_t* __restrict__ lofs, float* __restrict__ tri,
                                                            int64_t max_tris)
 {
     const int64_t nl = *nlist;
@@ -299,7 +308,7 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_emit(Lattice L, const flo
         float cv[8];
         cell_values(L, v, i, j, k, cv);
         const McCase& mc = kMc.c[cell_pattern(cv)];
-        const int64_t out0 = (int64_t)offs[c] + bsum[c / kMeshCellsPerBlock];
+        const int64_t out0 = lofs[li];
         for (int t = 0; t < mc.ntri; ++t) {
             const int64_t out = out0 + t;
             if (out >= max_tris) break;  // past the caller's capacity: counted, not written
@@ -317,11 +326,12 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_emit(Lattice L, const flo
     }
 }
 
-// Workspace sections: triangle offsets [ncell], per-block crossing-cell lists [nb * cells per
-// block], the compacted list [ncell], per-block triangle totals / offsets, crossing-cell
-// counts and offsets [nb each], the number of crossing cells and of triangles (int64).
+// Workspace sections: per-block crossing-cell lists and their triangle offsets [nb * cells
+// per block each], the compacted list and its triangle offsets [ncell each], per-block
+// triangle totals / offsets, crossing-cell counts and offsets [nb each], the number of
+// crossing cells and of triangles (int64).
 struct MeshWs {
-    size_t offs, blist, list, bsum, scnt, soff, nlist, total;
+    size_t boff, blist, list, lofs, bsum, scnt, soff, nlist, total;
 };
 
 static MeshWs mesh_ws(int64_t ncell)
@@ -330,11 +340,13 @@ static MeshWs mesh_ws(int64_t ncell)
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     MeshWs W;
     size_t off = 0;
-    W.offs = off;
-    off = up(off + (size_t)ncell * 4);
+    W.boff = off;
+    off = up(off + (size_t)nb * kMeshCellsPerBlock * 4);
     W.blist = off;
     off = up(off + (size_t)nb * kMeshCellsPerBlock * 4);
     W.list = off;
+    off = up(off + (size_t)ncell * 4);
+    W.lofs = off;
     off = up(off + (size_t)ncell * 4);
     W.bsum = off;
     off = up(off + (size_t)nb * 4);
@@ -367,24 +379,26 @@ hipError_t launch_mesh(const int* n, const float* lo, const float* hi, const flo
     const int64_t ncell = (int64_t)(n[0] - 1) * (n[1] - 1) * (n[2] - 1);
     const int64_t nb = (ncell + kMeshCellsPerBlock - 1) / kMeshCellsPerBlock;
     const MeshWs W = mesh_ws(ncell);
-    uint32_t* offs = reinterpret_cast<uint32_t*>(ws + W.offs);
+    uint32_t* boff = reinterpret_cast<uint32_t*>(ws + W.boff);
     uint32_t* blist = reinterpret_cast<uint32_t*>(ws + W.blist);
     uint32_t* list = reinterpret_cast<uint32_t*>(ws + W.list);
+    uint32_t* lofs = reinterpret_cast<uint32_t*>(ws + W.lofs);
     uint32_t* bsum = reinterpret_cast<uint32_t*>(ws + W.bsum);
     uint32_t* scnt = reinterpret_cast<uint32_t*>(ws + W.scnt);
     uint32_t* soff = reinterpret_cast<uint32_t*>(ws + W.soff);
     int64_t* nlist = reinterpret_cast<int64_t*>(ws + W.nlist);
     if (nb > 0)
-        hipLaunchKernelGGL(k_mesh_count, dim3((unsigned)nb), dim3(kMeshThreads), 0, s, L, values, ncell, offs, bsum,
+        hipLaunchKernelGGL(k_mesh_count, dim3((unsigned)nb), dim3(kMeshThreads), 0, s, L, values, ncell, boff, bsum,
                            blist, scnt);
     hipLaunchKernelGGL(k_mesh_scan_blocks, dim3(1), dim3(1024), 0, s, bsum, bsum, nb, n_tris);
     hipLaunchKernelGGL(k_mesh_scan_blocks, dim3(1), dim3(1024), 0, s, scnt, soff, nb, nlist);
     if (nb > 0) {
         const unsigned nlb = (unsigned)std::min<int64_t>(nb, 4096);
-        hipLaunchKernelGGL(k_mesh_list, dim3(nlb), dim3(kMeshThreads), 0, s, blist, scnt, soff, list, nb);
+        hipLaunchKernelGGL(k_mesh_list, dim3(nlb), dim3(kMeshThreads), 0, s, blist, boff, scnt, soff, bsum, list,
+                           lofs, nb);
         // at most every cell crosses; the kernel reads the actual count on the device
         const unsigned ne = (unsigned)std::min<int64_t>((ncell + kMeshThreads - 1) / kMeshThreads, 4096);
-        hipLaunchKernelGGL(k_mesh_emit, dim3(ne), dim3(kMeshThreads), 0, s, L, values, list, nlist, offs, bsum, tri,
+        hipLaunchKernelGGL(k_mesh_emit, dim3(ne), dim3(kMeshThreads), 0, s, L, values, list, nlist, lofs, tri,
                            max_tris);
     }
     return hipGetLastError();
