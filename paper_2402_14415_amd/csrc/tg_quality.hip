@@ -16,9 +16,10 @@
 // (e0, e_i, e_i+1).  The walk's direction puts every triangle's normal (p1 - p0) x (p2 - p0)
 // from the inside to the outside, and neighbouring cells put the same joins on a shared face,
 // so the mesh is closed wherever the inside set is.  Triangles are written cell by cell (x
-// fastest), then in table order: a first pass counts each cell's triangles, an exclusive
-// scan gives every cell its output offset, the cells that cross the level set are compacted,
-// and a last pass writes their triangles.
+// fastest), then in table order: a first pass counts each cell's triangles and lists the
+// cells that cross the level set with their offsets within the block, a scan of the block
+// totals places the lists, which are compacted into one, and a last pass writes their
+// triangles.
 #include "tg_internal.hpp"
 
 namespace tg {
@@ -164,74 +165,70 @@ __device__ __forceinline__ int cell_count(const float* cv)
     return kMc.c[cell_pattern(cv)].ntri;
 }
 
-// Exclusive scan over the block of one value per thread (kMeshThreads threads); returns the
-// thread's prefix and leaves the block total in *total.
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* wsum, uint32_t* total)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t incl = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += o;
-    }
-    __syncthreads();  // wsum may still be read by an earlier scan
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0, all = 0;
-    for (int w = 0; w < kMeshThreads / 64; ++w) {
-        if (w < wave) before += wsum[w];
-        all += wsum[w];
-    }
-    *total = all;
-    return before + incl - x;
-}
-
-// Per thread: the triangle counts of kMeshCellsPerThread consecutive cells; per block, the
-// cells that cross the level set (count > 0), listed in cell order from blist[block *
-// kMeshCellsPerBlock] with the exclusive prefix of the block's triangle counts at each of
-// them in boff (so that nothing is written for the many cells that do not cross), their
+// Per block: kMeshCellsPerBlock consecutive cells, thread t taking cells q kMeshThreads + t
+// (q < kMeshCellsPerThread), so that the 64 lanes of a wave read neighbouring lattice values.
+// The block's cells that cross the level set (count > 0) are listed in cell order from
+// blist[block * kMeshCellsPerBlock] with the exclusive prefix of the block's triangle counts
+// at each of them in boff (nothing is written for the many cells that do not cross), their
 // number in scnt and the block's triangle total in bsum.
 __global__ __launch_bounds__(kMeshThreads) void k_mesh_count(Lattice L, const float* __restrict__ v, int64_t ncell,
                                                             uint32_t* __restrict__ boff, uint32_t* __restrict__ bsum,
                                                             uint32_t* __restrict__ blist, uint32_t* __restrict__ scnt)
 {
-    __shared__ uint32_t wsum[kMeshThreads / 64];
-    const int64_t c0 = (int64_t)blockIdx.x * kMeshCellsPerBlock + (int64_t)threadIdx.x * kMeshCellsPerThread;
-    uint32_t cnt[kMeshCellsPerThread], tot = 0;
+    constexpr int kWaves = kMeshThreads / 64;
+    // per (q, wave): the wave's sums, in cell order
+    __shared__ uint32_t wtot[kMeshCellsPerThread * kWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t cb = (int64_t)blockIdx.x * kMeshCellsPerBlock + threadIdx.x;
+    // per cell: its triangle count in the high half-word and 1 if it crosses in the low one
+    // (the block's sums stay below 2^16: at most 5 triangles per cell)
+    uint32_t x[kMeshCellsPerThread], incl[kMeshCellsPerThread];
 #pragma unroll
     for (int q = 0; q < kMeshCellsPerThread; ++q) {
-        cnt[q] = 0;
-        const int64_t c = c0 + q;
+        const int64_t c = cb + (int64_t)q * kMeshThreads;
+        uint32_t n = 0;
         if (c < ncell) {
             int i, j, k;
             cell_of(L, c, i, j, k);
             float cv[8];
             cell_values(L, v, i, j, k, cv);
-            cnt[q] = (uint32_t)cell_count(cv);
+            n = (uint32_t)cell_count(cv);
         }
-        tot += cnt[q];
+        x[q] = (n << 16) | (n > 0 ? 1u : 0u);
     }
-    uint32_t nstr = 0;
-#pragma unroll
-    for (int q = 0; q < kMeshCellsPerThread; ++q) nstr += cnt[q] > 0 ? 1u : 0u;
-    uint32_t btot, bstr;
-    uint32_t run = block_exclusive_scan(tot, wsum, &btot);
-    uint32_t srun = block_exclusive_scan(nstr, wsum, &bstr);
-    uint32_t* mine = blist + (int64_t)blockIdx.x * kMeshCellsPerBlock;
-    uint32_t* mine_off = boff + (int64_t)blockIdx.x * kMeshCellsPerBlock;
 #pragma unroll
     for (int q = 0; q < kMeshCellsPerThread; ++q) {
-        if (cnt[q] > 0) {
-            mine[srun] = (uint32_t)(c0 + q);
-            mine_off[srun] = run;
-            ++srun;
+        uint32_t sc = x[q];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(sc, d, 64);
+            if (lane >= d) sc += o;
         }
-        run += cnt[q];
+        incl[q] = sc;
+        if (lane == 63) wtot[q * kWaves + wave] = sc;
+    }
+    __syncthreads();
+    uint32_t* mine = blist + (int64_t)blockIdx.x * kMeshCellsPerBlock;
+    uint32_t* mine_off = boff + (int64_t)blockIdx.x * kMeshCellsPerBlock;
+    uint32_t all = 0;  // sums of the entries of earlier q
+#pragma unroll
+    for (int q = 0; q < kMeshCellsPerThread; ++q) {
+        uint32_t before = all;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t t = wtot[q * kWaves + w];
+            if (w < wave) before += t;
+            all += t;
+        }
+        if (x[q] & 0xffffu) {
+            const uint32_t ex = before + incl[q] - x[q];
+            mine[ex & 0xffffu] = (uint32_t)(cb + (int64_t)q * kMeshThreads);
+            mine_off[ex & 0xffffu] = ex >> 16;
+        }
     }
     if (threadIdx.x == 0) {
-        bsum[blockIdx.x] = btot;
-        scnt[blockIdx.x] = bstr;
+        bsum[blockIdx.x] = all >> 16;
+        scnt[blockIdx.x] = all & 0xffffu;
     }
 }
 
@@ -254,35 +251,51 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_list(const uint32_t* __re
     }
 }
 
-// One block: exclusive scan of the block totals in place; *total = their sum.  Called once
-// for the triangle counts and once for the crossing-cell counts.
-__global__ __launch_bounds__(1024) void k_mesh_scan_blocks(const uint32_t* __restrict__ in, uint32_t* __restrict__ bsum,
-                                                          int64_t nb, int64_t* __restrict__ total)
+// One block: exclusive scans of the blocks' triangle totals (tri, in place) and crossing-cell
+// counts (scnt into soff); *ntri and *nlist = their sums.
+__global__ __launch_bounds__(1024) void k_mesh_scan_blocks(uint32_t* __restrict__ tri, const uint32_t* __restrict__ scnt,
+                                                          uint32_t* __restrict__ soff, int64_t nb,
+                                                          int64_t* __restrict__ ntri, int64_t* __restrict__ nlist)
 {
-    __shared__ uint32_t wsum[16];
-    __shared__ uint32_t carry;
-    if (threadIdx.x == 0) carry = 0;
+    __shared__ uint32_t wsum[2][16];
+    __shared__ uint32_t carry[2];
+    if (threadIdx.x == 0) carry[0] = carry[1] = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
         const int64_t b = b0 + threadIdx.x;
-        const uint32_t x = b < nb ? in[b] : 0u;
-        uint32_t incl = x;
+        uint32_t x[2] = {b < nb ? tri[b] : 0u, b < nb ? scnt[b] : 0u}, incl[2];
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t o = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += o;
+        for (int u = 0; u < 2; ++u) {
+            incl[u] = x[u];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t o = __shfl_up(incl[u], d, 64);
+                if (lane >= d) incl[u] += o;
+            }
+            if (lane == 63) wsum[u][wave] = incl[u];
         }
-        if (lane == 63) wsum[wave] = incl;
         __syncthreads();
-        uint32_t before = carry;
-        for (int w = 0; w < wave; ++w) before += wsum[w];
-        if (b < nb) bsum[b] = before + incl - x;
+        uint32_t before[2] = {carry[0], carry[1]};
+        for (int w = 0; w < wave; ++w) {
+            before[0] += wsum[0][w];
+            before[1] += wsum[1][w];
+        }
+        if (b < nb) {
+            tri[b] = before[0] + incl[0] - x[0];
+            soff[b] = before[1] + incl[1] - x[1];
+        }
         __syncthreads();
-        if (threadIdx.x == 1023) carry = before + incl;
+        if (threadIdx.x == 1023) {
+            carry[0] = before[0] + incl[0];
+            carry[1] = before[1] + incl[1];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *total = (int64_t)carry;
+    if (threadIdx.x == 0) {
+        *ntri = (int64_t)carry[0];
+        *nlist = (int64_t)carry[1];
+    }
 }
 
 __device__ __forceinline__ void corner_pos(const Lattice& L, int i, int j, int k, int c, float* p)
@@ -390,8 +403,7 @@ hipError_t launch_mesh(const int* n, const float* lo, const float* hi, const flo
     if (nb > 0)
         hipLaunchKernelGGL(k_mesh_count, dim3((unsigned)nb), dim3(kMeshThreads), 0, s, L, values, ncell, boff, bsum,
                            blist, scnt);
-    hipLaunchKernelGGL(k_mesh_scan_blocks, dim3(1), dim3(1024), 0, s, bsum, bsum, nb, n_tris);
-    hipLaunchKernelGGL(k_mesh_scan_blocks, dim3(1), dim3(1024), 0, s, scnt, soff, nb, nlist);
+    hipLaunchKernelGGL(k_mesh_scan_blocks, dim3(1), dim3(1024), 0, s, bsum, scnt, soff, nb, n_tris, nlist);
     if (nb > 0) {
         const unsigned nlb = (unsigned)std::min<int64_t>(nb, 4096);
         hipLaunchKernelGGL(k_mesh_list, dim3(nlb), dim3(kMeshThreads), 0, s, blist, boff, scnt, soff, bsum, list,

@@ -1,7 +1,7 @@
 """SDF quality measures on the GPU against the FP64 oracle (oracle/quality.py): exact IoU
 counts, the marching-cubes mesh triangle for triangle in the documented order (ragged
-lattices, exact zeros, every corner sign pattern, a 128^3 scene lattice, a short output
-buffer, an empty level set), a grid's field on a lattice finer than the grid, the mesh of a
+lattices, exact zeros, every corner sign pattern, every cell crossing, a 128^3 scene
+lattice, a short output buffer, an empty level set), a grid's field on a lattice finer than the grid, the mesh of a
 grid's field, the Chamfer distance in both norms, and the measures of fitted grids of every
 order against the analytic scene."""
 import numpy as np
@@ -82,6 +82,18 @@ def test_mesh_every_sign_pattern():
     assert len(np.unique(pat)) == 256
     lo, hi = (0.0, 0.0, 0.0), (23.0, 24.0, 25.0)
     _check_mesh(V, lo, hi)
+
+
+def test_mesh_every_cell_crossing():
+    """A sign checkerboard: every cell crosses the level set, so each block's list of crossing
+    cells is full (and the last block's ragged); four triangles in every cell."""
+    n = (45, 38, 41)
+    k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    V = np.where((i + j + k) % 2 == 0, 1.0, -1.0).astype(np.float32)
+    V *= (1.0 + 0.25 * np.sin(0.7 * i + 0.3 * j - 0.5 * k)).astype(np.float32)
+    lo, hi = (-1.0, -0.5, 0.0), (1.0, 1.5, 1.0)
+    got = _check_mesh(V, lo, hi)
+    assert len(got) == 4 * (n[0] - 1) * (n[1] - 1) * (n[2] - 1)
 
 
 def test_mesh_full_size_scene_lattice():
