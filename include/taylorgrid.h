@@ -266,9 +266,11 @@ tg_status tg_iou_counts(int64_t n, const float* f, const float* d, int64_t* coun
 
 /* The field of a grid on the lattice s times finer than the grid, for the zero-level-set mesh
  * of the learned field (Sec. 4.1 meshes its fields with marching cubes): values [nz][ny][nx]
- * (device FP32, x fastest), n[a] = s (res[a] - 1) + 1, point (i, j, k) at lo + (i, j, k) hl
- * with hl = (hi - lo) / (n - 1) (in FP32); every s-th point is a grid vertex.  Each value is
- * the field of Sec. 3.1, Eq. 2-4, evaluated as tg_query does.  3D grids of one channel in the
+ * (device FP32, x fastest), n[a] = s (res[a] - 1) + 1, point (i, j, k) at lo + (i, j, k) h / s
+ * (h the cell size); every s-th point is a grid vertex.  Each value is the field of Sec. 3.1,
+ * Eq. 2-4 (in FP32), at its point located exactly: on axis a point i lies in cell
+ * c = min(floor(i / s), res[a] - 2) at local coordinate (i - s c) / s, so a point on a cell
+ * face takes the cell above (the top face: the last cell).  3D grids of one channel in the
  * symmetric layout (TG_ERR_UNSUPPORTED otherwise), 1 <= s <= 64, fewer than 2^31 points
  * (TG_ERR_CAPACITY).  No workspace. */
 tg_status tg_field_lattice(const tg_grid* grid, int32_t s, float* values, void* stream);

@@ -182,21 +182,64 @@ hipError_t launch_query(const tg_grid* const* grids, int32_t n_grids, const tg_r
 
 // ------------------------------------------------------------------ field on a lattice
 // The grid's field at the points of the lattice s times finer than the grid (for the
-// zero-level-set mesh of the field): point (i, j, k) at lo + (i, j, k) hl, hl = (hi - lo) /
-// (n - 1), n = s (res - 1) + 1; one thread per point, x fastest, the same evaluation as a
-// served query.  Neighbouring threads share the cell's corner blocks through the caches.
+// zero-level-set mesh of the field), n = s (res - 1) + 1 points per axis.  Point i on an axis
+// lies at i / s in cell units, located exactly: cell c = min(floor(i / s), res - 2), local
+// coordinate (i - s c) / s, so a point on a face takes the cell above and the top face the
+// last cell.  One thread per (cell along x, cell along y, lattice layer k): it gathers the
+// cell's 8 corner blocks once into registers and writes the cell's s x s points of layer k
+// (s + 1 along an axis for the last cell), with the per-point arithmetic of the forward.
 template <int K, int ST>
-__global__ __launch_bounds__(kThreads) void k_field_lattice(QGrid G, int32_t nx, int32_t ny, int64_t npts, float hx,
-                                                            float hy, float hz, float* __restrict__ out)
+__global__ __launch_bounds__(kThreads) void k_field_lattice(QGrid G, int32_t s, int32_t nx, int32_t ny, int32_t nz,
+                                                            float* __restrict__ out)
 {
-    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (p >= npts) return;
-    const uint32_t pp = (uint32_t)p, row = pp / (uint32_t)nx;  // npts < 2^31
-    const uint32_t i = pp - row * (uint32_t)nx, k = row / (uint32_t)ny, j = row - k * (uint32_t)ny;
-    const float q[3] = {fmaf((float)i, hx, G.lo[0]), fmaf((float)j, hy, G.lo[1]), fmaf((float)k, hz, G.lo[2])};
-    float f, gr[3];
-    serve_point<3, K, ST>(G, q, f, gr);
-    out[p] = f;
+    constexpr int C = NumCoeffs<3, K>::value;
+    const int32_t cxn = G.res[0] - 1, cyn = G.res[1] - 1;
+    const int64_t tid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (tid >= (int64_t)cxn * cyn * nz) return;
+    const int32_t cx = (int32_t)(tid % cxn);
+    const int64_t rest = tid / cxn;
+    const int32_t cy = (int32_t)(rest % cyn), k = (int32_t)(rest / cyn);
+    const int32_t cz = min(k / s, G.res[2] - 2);
+    Geom g;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g.h[a] = G.h[a];
+        g.inv_h[a] = G.inv_h[a];
+    }
+    const float fs = (float)s;
+    AxisLoc L[3];
+    L[0].cell = cx;
+    L[1].cell = cy;
+    L[2].cell = cz;
+    L[2].t = (float)(k - cz * s) / fs;
+    L[0].clamped = L[1].clamped = L[2].clamped = false;
+    float c[8][C];
+    const int64_t sy = G.res[0], sz = (int64_t)G.res[0] * G.res[1];
+    const int64_t base = cx + cy * sy + cz * sz;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        load_vertex<ST, C>(G.coeffs, base + (b & 1) + ((b >> 1) & 1) * sy + ((b >> 2) & 1) * sz, c[b]);
+    const int32_t mx = s + (cx == cxn - 1 ? 1 : 0), my = s + (cy == cyn - 1 ? 1 : 0);
+    for (int32_t ry = 0; ry < my; ++ry) {
+        L[1].t = (float)ry / fs;
+        float* row = out + ((int64_t)k * ny + (int64_t)cy * s + ry) * nx + (int64_t)cx * s;
+        for (int32_t rx = 0; rx < mx; ++rx) {
+            L[0].t = (float)rx / fs;
+            const AxisFactors<3> F = axis_factors<3>(g, L);
+            float f = 0.0f;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                float d[3];
+                corner_offset<3>(F, b, d);
+                float T, dT[3];
+                taylor_eval<3, K>(c[b], d, T, dT);
+                float w, dw[3];
+                corner_weight<3>(F, b, w, dw);
+                f = fmaf(w, T, f);
+            }
+            row[rx] = f;
+        }
+    }
 }
 
 hipError_t launch_field_lattice(const tg_grid* g, int32_t s, float* values, hipStream_t st)
@@ -208,7 +251,6 @@ hipError_t launch_field_lattice(const tg_grid* g, int32_t s, float* values, hipS
     G.order = (int8_t)g->desc.order;
     G.storage = (int8_t)g->desc.storage;
     int32_t n[3];
-    float hl[3];
     for (int a = 0; a < 3; ++a) {
         G.res[a] = g->geom.res[a];
         G.lo[a] = g->geom.lo[a];
@@ -217,14 +259,12 @@ hipError_t launch_field_lattice(const tg_grid* g, int32_t s, float* values, hipS
         G.inv_h[a] = g->geom.inv_h[a];
         G.inv_h_lo[a] = g->geom.inv_h_lo[a];
         n[a] = s * (g->geom.res[a] - 1) + 1;
-        hl[a] = (float)(((double)g->geom.hi[a] - (double)g->geom.lo[a]) / (double)(n[a] - 1));
     }
-    const int64_t npts = (int64_t)n[0] * n[1] * n[2];
-    const dim3 grid((unsigned)((npts + kThreads - 1) / kThreads)), block(kThreads);
+    const int64_t nthreads = (int64_t)(G.res[0] - 1) * (G.res[1] - 1) * n[2];
+    const dim3 grid((unsigned)((nthreads + kThreads - 1) / kThreads)), block(kThreads);
 #define TG_FL_CASE(KK, ST)                                                                                    \
     if (G.order == KK && G.storage == ST) {                                                                 \
-        hipLaunchKernelGGL((k_field_lattice<KK, ST>), grid, block, 0, st, G, n[0], n[1], npts, hl[0], hl[1], hl[2], \
-                           values);                                                                          \
+        hipLaunchKernelGGL((k_field_lattice<KK, ST>), grid, block, 0, st, G, s, n[0], n[1], n[2], values);      \
         return hipGetLastError();                                                                            \
     }
 #define TG_FL_ST(KK) TG_FL_CASE(KK, 0) TG_FL_CASE(KK, 1) TG_FL_CASE(KK, 2)

@@ -40,7 +40,8 @@ def iou(f, d, ws=None):
 
 def field_lattice(grid, s, out=None):
     """The grid's field on the lattice s times finer than the grid: values [nz, ny, nx] with
-    n = s (res - 1) + 1 per axis (point i at lo + i (hi - lo) / (n - 1))."""
+    n = s (res - 1) + 1 per axis (point i at lo + i h / s, located exactly: a point on a cell
+    face takes the cell above)."""
     n = [s * (r - 1) + 1 for r in grid.res]
     shape = (n[2], n[1], n[0])
     out = torch.empty(shape, dtype=torch.float32, device=grid.device) if out is None else out
