@@ -185,21 +185,27 @@ hipError_t launch_query(const tg_grid* const* grids, int32_t n_grids, const tg_r
 // zero-level-set mesh of the field), n = s (res - 1) + 1 points per axis.  Point i on an axis
 // lies at i / s in cell units, located exactly: cell c = min(floor(i / s), res - 2), local
 // coordinate (i - s c) / s, so a point on a face takes the cell above and the top face the
-// last cell.  One thread per (cell along x, cell along y, lattice layer k): it gathers the
-// cell's 8 corner blocks once into registers and writes the cell's s x s points of layer k
-// (s + 1 along an axis for the last cell), with the per-point arithmetic of the forward.
+// last cell.  One thread per cell (s <= kLatCellMax) or per (cell along x, cell along y,
+// lattice layer): it gathers the cell's 8 corner blocks once into registers and writes the
+// cell's points (s + 1 along an axis for the last cell), or those of its layer, with the
+// per-point arithmetic of the forward.
+constexpr int32_t kLatCellMax = 4;
 template <int K, int ST>
 __global__ __launch_bounds__(kThreads) void k_field_lattice(QGrid G, int32_t s, int32_t nx, int32_t ny, int32_t nz,
                                                             float* __restrict__ out)
 {
     constexpr int C = NumCoeffs<3, K>::value;
-    const int32_t cxn = G.res[0] - 1, cyn = G.res[1] - 1;
+    const int32_t cxn = G.res[0] - 1, cyn = G.res[1] - 1, czn = G.res[2] - 1;
+    const bool per_cell = s <= kLatCellMax;
     const int64_t tid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (tid >= (int64_t)cxn * cyn * nz) return;
+    if (tid >= (int64_t)cxn * cyn * (per_cell ? czn : nz)) return;
     const int32_t cx = (int32_t)(tid % cxn);
     const int64_t rest = tid / cxn;
-    const int32_t cy = (int32_t)(rest % cyn), k = (int32_t)(rest / cyn);
-    const int32_t cz = min(k / s, G.res[2] - 2);
+    const int32_t cy = (int32_t)(rest % cyn), u = (int32_t)(rest / cyn);
+    // the cell along z and the thread's lattice layers [k0, k1)
+    const int32_t cz = per_cell ? u : min(u / s, czn - 1);
+    const int32_t k0 = per_cell ? u * s : u;
+    const int32_t k1 = per_cell ? k0 + s + (cz == czn - 1 ? 1 : 0) : u + 1;
     Geom g;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -211,7 +217,6 @@ __global__ __launch_bounds__(kThreads) void k_field_lattice(QGrid G, int32_t s, 
     L[0].cell = cx;
     L[1].cell = cy;
     L[2].cell = cz;
-    L[2].t = (float)(k - cz * s) / fs;
     L[0].clamped = L[1].clamped = L[2].clamped = false;
     float c[8][C];
     const int64_t sy = G.res[0], sz = (int64_t)G.res[0] * G.res[1];
@@ -220,24 +225,27 @@ __global__ __launch_bounds__(kThreads) void k_field_lattice(QGrid G, int32_t s, 
     for (int b = 0; b < 8; ++b)
         load_vertex<ST, C>(G.coeffs, base + (b & 1) + ((b >> 1) & 1) * sy + ((b >> 2) & 1) * sz, c[b]);
     const int32_t mx = s + (cx == cxn - 1 ? 1 : 0), my = s + (cy == cyn - 1 ? 1 : 0);
-    for (int32_t ry = 0; ry < my; ++ry) {
-        L[1].t = (float)ry / fs;
-        float* row = out + ((int64_t)k * ny + (int64_t)cy * s + ry) * nx + (int64_t)cx * s;
-        for (int32_t rx = 0; rx < mx; ++rx) {
-            L[0].t = (float)rx / fs;
-            const AxisFactors<3> F = axis_factors<3>(g, L);
-            float f = 0.0f;
+    for (int32_t k = k0; k < k1; ++k) {
+        L[2].t = (float)(k - cz * s) / fs;
+        for (int32_t ry = 0; ry < my; ++ry) {
+            L[1].t = (float)ry / fs;
+            float* row = out + ((int64_t)k * ny + (int64_t)cy * s + ry) * nx + (int64_t)cx * s;
+            for (int32_t rx = 0; rx < mx; ++rx) {
+                L[0].t = (float)rx / fs;
+                const AxisFactors<3> F = axis_factors<3>(g, L);
+                float f = 0.0f;
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                float d[3];
-                corner_offset<3>(F, b, d);
-                float T, dT[3];
-                taylor_eval<3, K>(c[b], d, T, dT);
-                float w, dw[3];
-                corner_weight<3>(F, b, w, dw);
-                f = fmaf(w, T, f);
+                for (int b = 0; b < 8; ++b) {
+                    float d[3];
+                    corner_offset<3>(F, b, d);
+                    float T, dT[3];
+                    taylor_eval<3, K>(c[b], d, T, dT);
+                    float w, dw[3];
+                    corner_weight<3>(F, b, w, dw);
+                    f = fmaf(w, T, f);
+                }
+                row[rx] = f;
             }
-            row[rx] = f;
         }
     }
 }
@@ -260,7 +268,7 @@ hipError_t launch_field_lattice(const tg_grid* g, int32_t s, float* values, hipS
         G.inv_h_lo[a] = g->geom.inv_h_lo[a];
         n[a] = s * (g->geom.res[a] - 1) + 1;
     }
-    const int64_t nthreads = (int64_t)(G.res[0] - 1) * (G.res[1] - 1) * n[2];
+    const int64_t nthreads = (int64_t)(G.res[0] - 1) * (G.res[1] - 1) * (s <= kLatCellMax ? G.res[2] - 1 : n[2]);
     const dim3 grid((unsigned)((nthreads + kThreads - 1) / kThreads)), block(kThreads);
 #define TG_FL_CASE(KK, ST)                                                                                    \
     if (G.order == KK && G.storage == ST) {                                                                 \

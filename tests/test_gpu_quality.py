@@ -116,10 +116,12 @@ def test_mesh_short_buffer_and_empty_level_set():
     assert total == 0 and tri.shape[0] == 0
 
 
-@pytest.mark.parametrize("order,storage,s", [(2, "f32", 2), (1, "bf16", 3), (0, "f32", 1), (2, "f16", 4)])
+@pytest.mark.parametrize("order,storage,s", [(2, "f32", 2), (1, "bf16", 3), (0, "f32", 1), (2, "f16", 4),
+                                             (2, "f32", 6)])
 def test_field_lattice_matches_oracle(order, storage, s):
     """The grid's field on the lattice s times finer than a ragged grid, against the C
-    oracle's field at the same lattice (FP64 positions) on the storage-rounded coefficients."""
+    oracle's field at the same lattice (FP64 positions) on the storage-rounded coefficients
+    (s <= 4: a thread per cell; s = 6: a thread per cell row pair and lattice layer)."""
     rng = np.random.default_rng(10 + order)
     res = (13, 11, 9)
     lo, hi = (-1.0, -0.5, 0.0), (1.0, 1.5, 0.75)
