@@ -300,15 +300,18 @@ tg_status tg_mesh(const int32_t* n, const float* lo, const float* hi, const floa
                   float* tri, int64_t max_tris, int64_t* n_tris, void* ws, size_t ws_bytes,
                   void* stream);
 
-/* Bytes of device workspace tg_chamfer needs for na and nb points (per-source minima for each
- * split of the destination set, and the reduction partials); 0 if a count is out of range. */
+/* Bytes of device workspace tg_chamfer needs for na and nb points (a bucket grid and a
+ * bucketed copy of each set, and the reduction partials); 0 if a count is out of range. */
 size_t tg_chamfer_workspace_bytes(int64_t na, int64_t nb);
 
 /* Chamfer distance between point sets a [na][3] and b [nb][3] (device; na, nb >= 1), the CD
  * of Sec. 4.1 (the paper's "Chamfer-L1", computed there with PyTorch3D's code): out (device
  * double [3]) = {mean_a min_b |a - b| + mean_b min_a |a - b|, the first mean, the second
  * mean}, with |.| the L1 norm |dx| + |dy| + |dz| (norm = 1) or the Euclidean norm (norm = 2).
- * Brute force (every pair), distances in FP32, means in FP64.  ws must hold
+ * Exact nearest points: each set is bucketed on a grid of cubic cells over its bounding box,
+ * and a point of the other set searches the rings of cells around its own until no unvisited
+ * cell can hold a nearer point, which finds the minimum over every pair; distances in FP32,
+ * means in FP64 (a direction's mean is the same whichever argument the set is).  ws must hold
  * tg_chamfer_workspace_bytes(na, nb); TG_ERR_CAPACITY if smaller. */
 tg_status tg_chamfer(const float* a, int64_t na, const float* b, int64_t nb, int32_t norm, double* out,
                      void* ws, size_t ws_bytes, void* stream);

@@ -464,102 +464,549 @@ hipError_t launch_iou(int64_t n, const float* f, const float* d, int64_t* counts
 }
 
 // ------------------------------------------------------------------ Chamfer
-constexpr int kNnThreads = 256;
-constexpr int kNnPerThread = 4;   // source points per thread (each staged point is read once for all)
-constexpr int kNnTile = 2048;     // destination points per LDS tile (a multiple of 4)
+// Exact nearest points on a bucket grid of the destination set.  The grid covers the bounding
+// box of the destination's finite points with cubic cells (at most one cell per two points,
+// at most kNnDimMax along an axis); a point's cell is floor((x - org) / cs) per axis, clamped
+// to the grid (non-finite coordinates included), so it is monotone in x.  The points are
+// counting-sorted by cell (x fastest).  A source point visits the rings of cells around its
+// own cell (ring r: the cells whose largest index difference is r), nearest first.  Every
+// point of a cell in ring r + 1 differs from the source by at least r cells along one axis,
+// so by at least r cs in the L1 and Euclidean norms (less a rounding allowance): the search
+// stops once its best distance is below that bound, or when the rings leave the grid.  A point
+// whose bound is not met within kNnNearRings rings (far from the other set, where the rings
+// would grow large and serialise its thread) is listed instead, and a brute-force pass over
+// the destination points (split over many workgroups) finishes the listed points.  The
+// minimum is the one a comparison with every point finds (the same FP32 distances).
+struct NnGrid {
+    float org[3];
+    float cs, inv_cs;
+    float slack;  // rounding allowance of the ring bound
+    int32_t dims[3];
+    int32_t pad_;
+};
+constexpr int kNnDimMax = 1024;
+constexpr int64_t kNnMaxCells = (int64_t)1 << 24;
+constexpr int kNnBoxBlocks = 1024;
+constexpr int kNnScanThreads = 1024;
+constexpr int kNnScanPer = 4;  // cells per thread of the start scan
+constexpr int kNnScanCells = kNnScanThreads * kNnScanPer;
+constexpr int kNnNearRings = 2;   // rings a point searches before it is left to the brute-force pass
+constexpr int kNnFarChunks = 16;  // workgroups along the list of far points (kThreads points each)
+constexpr int kNnFarSplits = 64;  // workgroups along the destination points
+constexpr int kNnFarTile = 1024;  // destination points per LDS tile of the brute-force pass
 
-// The destination set of one direction is split over S groups of workgroups (enough
-// workgroups to fill the GPU when the source set is small): mins[split * ns + i] = the
-// smallest squared distance from source i to split `split` of the destinations.  Brute
-// force: destination tiles are staged in LDS as x, y, z arrays (padded to a multiple of 4
-// with points at infinity), read 4 points at a time, and every thread compares each with
-// its kNnPerThread source points held in registers.
-constexpr int kNnTargetBlocks = 2048;
-
-// NORM 1: the L1 distance |dx| + |dy| + |dz|; NORM 2: the squared Euclidean distance (the
-// square root is taken once per source, in k_nn_reduce).
-template <int NORM>
-__global__ __launch_bounds__(kNnThreads) void k_nn_min(const float* __restrict__ src, int64_t ns,
-                                                      const float* __restrict__ dst, int64_t nd, int64_t chunks,
-                                                      int64_t tiles_per_split, float* __restrict__ mins)
+static int64_t nn_max_cells(int64_t nd)
 {
-    __shared__ __align__(16) float tx[kNnTile], ty[kNnTile], tz[kNnTile];
-    constexpr int CHUNK = kNnThreads * kNnPerThread;
-    const int64_t chunk = blockIdx.x % chunks, split = blockIdx.x / chunks;
-    const int64_t s0 = chunk * CHUNK;
-    const int64_t dbeg = split * tiles_per_split * kNnTile, dend = min(nd, dbeg + tiles_per_split * kNnTile);
-    float px[kNnPerThread], py[kNnPerThread], pz[kNnPerThread], best[kNnPerThread];
+    return std::min<int64_t>(kNnMaxCells, std::max<int64_t>(1, nd / 2));
+}
+
+__device__ __forceinline__ int32_t nn_axis_cell(float x, float org, float inv_cs, int32_t dim)
+{
+    float f = floorf((x - org) * inv_cs);
+    if (!(f >= 0.0f)) f = 0.0f;  // NaN too
+    if (f > (float)(dim - 1)) f = (float)(dim - 1);
+    return (int32_t)f;
+}
+
+// Per block: min and max of the finite coordinates on every axis (part[6 block ..]).
+__global__ __launch_bounds__(kThreads) void k_nn_box(const float* __restrict__ p, int64_t n, float* __restrict__ part)
+{
+    __shared__ float red[6][kThreads / 64];
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
 #pragma unroll
-    for (int r = 0; r < kNnPerThread; ++r) {
-        const int64_t si = s0 + threadIdx.x + (int64_t)r * kNnThreads;
-        const bool ok = si < ns;
-        px[r] = ok ? src[3 * si] : 0.0f;
-        py[r] = ok ? src[3 * si + 1] : 0.0f;
-        pz[r] = ok ? src[3 * si + 2] : 0.0f;
-        best[r] = INFINITY;
-    }
-    for (int64_t d0 = dbeg; d0 < dend; d0 += kNnTile) {
-        const int cnt = (int)min((int64_t)kNnTile, dend - d0);
-        const int cnt4 = (cnt + 3) & ~3;
-        __syncthreads();
-        for (int q = threadIdx.x; q < cnt4; q += kNnThreads) {
-            const bool ok = q < cnt;
-            tx[q] = ok ? dst[3 * (d0 + q)] : INFINITY;
-            ty[q] = ok ? dst[3 * (d0 + q) + 1] : INFINITY;
-            tz[q] = ok ? dst[3 * (d0 + q) + 2] : INFINITY;
-        }
-        __syncthreads();
-        for (int q = 0; q < cnt4; q += 4) {
-            const float4 X = *reinterpret_cast<const float4*>(tx + q);
-            const float4 Y = *reinterpret_cast<const float4*>(ty + q);
-            const float4 Z = *reinterpret_cast<const float4*>(tz + q);
-            const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w}, zs[4] = {Z.x, Z.y, Z.z, Z.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int r = 0; r < kNnPerThread; ++r) {
-                    const float dx = xs[u] - px[r], dy = ys[u] - py[r], dz = zs[u] - pz[r];
-                    if constexpr (NORM == 1) best[r] = fminf(best[r], fabsf(dx) + fabsf(dy) + fabsf(dz));
-                    else best[r] = fminf(best[r], fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-                }
+        for (int a = 0; a < 3; ++a) {
+            const float x = p[3 * i + a];
+            if (isfinite(x)) {
+                v[a] = fminf(v[a], x);
+                v[3 + a] = fmaxf(v[3 + a], x);
+            }
         }
     }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int r = 0; r < kNnPerThread; ++r) {
-        const int64_t si = s0 + threadIdx.x + (int64_t)r * kNnThreads;
-        if (si < ns) mins[split * ns + si] = best[r];
+    for (int k = 0; k < 6; ++k) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const float o = __shfl_xor(v[k], d, 64);
+            v[k] = k < 3 ? fminf(v[k], o) : fmaxf(v[k], o);
+        }
+        if (lane == 0) red[k][wave] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        float r = red[k][0];
+        for (int w = 1; w < kThreads / 64; ++w) r = k < 3 ? fminf(r, red[k][w]) : fmaxf(r, red[k][w]);
+        part[6 * blockIdx.x + k] = r;
     }
 }
 
-// partials[block] = sum over this block's sources of the distance to the nearest destination
-// (the smallest of the splits' distances; for NORM 2, its square root).
-template <int NORM>
-__global__ __launch_bounds__(kThreads) void k_nn_reduce(const float* __restrict__ mins, int64_t ns, int64_t nsplit,
-                                                       double* __restrict__ partials)
+// One block: the box from the block partials; then thread 0 picks the cell size, the
+// smallest of 2 emax 2^(-k/8) whose grid has at most max_cells cells (emax the largest
+// extent).
+__global__ __launch_bounds__(kThreads) void k_nn_setup(const float* __restrict__ part, int nblk, int64_t max_cells,
+                                                      NnGrid* __restrict__ G, int32_t* __restrict__ nfar)
 {
+    __shared__ float red[6][kThreads / 64];
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nblk; b += kThreads)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] = k < 3 ? fminf(v[k], part[6 * b + k]) : fmaxf(v[k], part[6 * b + k]);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const float o = __shfl_xor(v[k], d, 64);
+            v[k] = k < 3 ? fminf(v[k], o) : fmaxf(v[k], o);
+        }
+        if (lane == 0) red[k][wave] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    *nfar = 0;
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = red[a][0];
+        hi[a] = red[3 + a][0];
+        for (int w = 1; w < kThreads / 64; ++w) {
+            lo[a] = fminf(lo[a], red[a][w]);
+            hi[a] = fmaxf(hi[a], red[3 + a][w]);
+        }
+    }
+    double ext[3], emax = 0.0, amax = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (!(lo[a] <= hi[a])) lo[a] = hi[a] = 0.0f;  // no finite coordinate
+        ext[a] = (double)hi[a] - (double)lo[a];
+        emax = fmax(emax, ext[a]);
+        amax = fmax(amax, fmax(fabs((double)lo[a]), fabs((double)hi[a])));
+    }
+    double cs = emax > 0.0 ? 2.0 * emax : 1.0;
+    int64_t dims[3] = {1, 1, 1};
+    if (emax > 0.0) {
+        for (int k = 1; k <= 8 * 40; ++k) {
+            const double c = 2.0 * emax * exp2(-(double)k / 8.0);
+            int64_t d[3], prod = 1;
+            for (int a = 0; a < 3; ++a) {
+                d[a] = std::min<int64_t>(kNnDimMax, (int64_t)floor(ext[a] / c) + 1);
+                prod *= d[a];
+            }
+            if (prod > max_cells) break;
+            cs = c;
+            for (int a = 0; a < 3; ++a) dims[a] = d[a];
+        }
+    }
+    NnGrid g;
+    for (int a = 0; a < 3; ++a) {
+        g.org[a] = lo[a];
+        g.dims[a] = (int32_t)dims[a];
+    }
+    g.cs = (float)cs;
+    g.inv_cs = (float)(1.0 / cs);
+    // cell faces and FP32 differences are off by a few units in the last place of the
+    // coordinates' magnitude; a generous allowance keeps the bound below every such error
+    g.slack = (float)(1e-5 * (amax + cs));
+    g.pad_ = 0;
+    *G = g;
+}
+
+__global__ __launch_bounds__(kThreads) void k_nn_zero(int32_t* __restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) p[i] = 0;
+}
+
+__device__ __forceinline__ int32_t nn_cell(const NnGrid& g, float x, float y, float z)
+{
+    const int32_t cx = nn_axis_cell(x, g.org[0], g.inv_cs, g.dims[0]);
+    const int32_t cy = nn_axis_cell(y, g.org[1], g.inv_cs, g.dims[1]);
+    const int32_t cz = nn_axis_cell(z, g.org[2], g.inv_cs, g.dims[2]);
+    return cx + g.dims[0] * (cy + g.dims[1] * cz);
+}
+
+// Runs of neighbouring lanes of a wave with the same cell (c < 0: the lane has no point).  The
+// run's first lane (head) stands for it in one atomic, which keeps the many repeated points of
+// a triangle mesh (listed cell by cell) from queueing on one counter.
+struct WaveRun {
+    int head;  // lane of the run's first lane (-1 for a lane without a point)
+    int off;   // position in the run
+    int len;   // lanes in the run
+};
+__device__ __forceinline__ WaveRun wave_run(int32_t c)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t cp = __shfl_up(c, 1, 64);
+    const bool valid = c >= 0;
+    const uint64_t heads = __ballot(valid && (lane == 0 || cp != c));
+    const uint64_t stops = heads | __ballot(!valid);
+    const uint64_t upto = heads & ((2ull << lane) - 1);  // heads at or below this lane
+    WaveRun r;
+    r.head = upto ? 63 - __builtin_clzll(upto) : -1;
+    r.off = lane - r.head;
+    const uint64_t after = r.head >= 0 ? stops & ~((2ull << r.head) - 1) : 0ull;
+    r.len = (after ? __builtin_ctzll(after) : 64) - r.head;
+    return r;
+}
+
+// Grid-stride loops over whole waves (the run detection needs every lane of the wave).
+__global__ __launch_bounds__(kThreads) void k_nn_count(const float* __restrict__ p, int64_t n,
+                                                      const NnGrid* __restrict__ G, int32_t* __restrict__ cnt)
+{
+    const NnGrid g = *G;
+    const int lane = threadIdx.x & 63;
+    for (int64_t i0 = (int64_t)blockIdx.x * kThreads + (threadIdx.x & ~63); i0 < n;
+         i0 += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = i0 + lane;
+        const int32_t c = i < n ? nn_cell(g, p[3 * i], p[3 * i + 1], p[3 * i + 2]) : -1;
+        const WaveRun r = wave_run(c);
+        if (c >= 0 && r.off == 0) atomicAdd(&cnt[c], r.len);
+    }
+}
+
+// Exclusive scan of the kNnScanPer cells of each thread across the block; *total = the
+// block's sum.
+__device__ __forceinline__ void nn_block_scan(const int32_t* v, int32_t* ex, int32_t* wsum, int32_t* total)
+{
+    int32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kNnScanPer; ++k) t += v[k];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t incl = t;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int32_t before = 0, all = 0;
+    for (int w = 0; w < kNnScanThreads / 64; ++w) {
+        if (w < wave) before += wsum[w];
+        all += wsum[w];
+    }
+    int32_t run = before + incl - t;
+#pragma unroll
+    for (int k = 0; k < kNnScanPer; ++k) {
+        ex[k] = run;
+        run += v[k];
+    }
+    *total = all;
+}
+
+__global__ __launch_bounds__(kNnScanThreads) void k_nn_scan_blocks(const int32_t* __restrict__ cnt, int64_t ncell,
+                                                                  int32_t* __restrict__ bsum)
+{
+    __shared__ int32_t wsum[kNnScanThreads / 64];
+    const int64_t c0 = (int64_t)blockIdx.x * kNnScanCells + (int64_t)threadIdx.x * kNnScanPer;
+    int32_t v[kNnScanPer], ex[kNnScanPer], total;
+#pragma unroll
+    for (int k = 0; k < kNnScanPer; ++k) v[k] = c0 + k < ncell ? cnt[c0 + k] : 0;
+    nn_block_scan(v, ex, wsum, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// One block: exclusive scan of the block sums in place.
+__global__ __launch_bounds__(kNnScanThreads) void k_nn_scan_top(int32_t* __restrict__ bsum, int64_t nb)
+{
+    __shared__ int32_t wsum[kNnScanThreads / 64];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t b0 = 0; b0 < nb; b0 += kNnScanThreads) {
+        const int64_t b = b0 + threadIdx.x;
+        const int32_t x = b < nb ? bsum[b] : 0;
+        int32_t incl = x;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        int32_t before = carry;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (b < nb) bsum[b] = before + incl - x;
+        __syncthreads();
+        if (threadIdx.x == kNnScanThreads - 1) carry = before + incl;
+        __syncthreads();
+    }
+}
+
+// start[c] = first sorted position of cell c (start[ncell] = the total), cursor[c] = start[c].
+__global__ __launch_bounds__(kNnScanThreads) void k_nn_scan_apply(const int32_t* __restrict__ cnt, int64_t ncell,
+                                                                 const int32_t* __restrict__ boff,
+                                                                 int32_t* __restrict__ start,
+                                                                 int32_t* __restrict__ cursor)
+{
+    __shared__ int32_t wsum[kNnScanThreads / 64];
+    const int64_t c0 = (int64_t)blockIdx.x * kNnScanCells + (int64_t)threadIdx.x * kNnScanPer;
+    int32_t v[kNnScanPer], ex[kNnScanPer], total;
+#pragma unroll
+    for (int k = 0; k < kNnScanPer; ++k) v[k] = c0 + k < ncell ? cnt[c0 + k] : 0;
+    nn_block_scan(v, ex, wsum, &total);
+    const int32_t base = boff[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kNnScanPer; ++k) {
+        const int64_t c = c0 + k;
+        if (c < ncell) {
+            start[c] = base + ex[k];
+            cursor[c] = base + ex[k];
+            if (c == ncell - 1) start[ncell] = base + ex[k] + v[k];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_nn_scatter(const float* __restrict__ p, int64_t n,
+                                                        const NnGrid* __restrict__ G, int32_t* __restrict__ cursor,
+                                                        float4* __restrict__ pts)
+{
+    const NnGrid g = *G;
+    const int lane = threadIdx.x & 63;
+    for (int64_t i0 = (int64_t)blockIdx.x * kThreads + (threadIdx.x & ~63); i0 < n;
+         i0 += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = i0 + lane;
+        float x = 0.0f, y = 0.0f, z = 0.0f;
+        int32_t c = -1;
+        if (i < n) {
+            x = p[3 * i];
+            y = p[3 * i + 1];
+            z = p[3 * i + 2];
+            c = nn_cell(g, x, y, z);
+        }
+        const WaveRun r = wave_run(c);
+        int32_t base = 0;
+        if (c >= 0 && r.off == 0) base = atomicAdd(&cursor[c], r.len);
+        base = __shfl(base, r.head >= 0 ? r.head : lane, 64);
+        if (c >= 0) pts[base + r.off] = make_float4(x, y, z, 0.0f);
+    }
+}
+
+// NORM 1: the L1 distance; NORM 2: the squared Euclidean distance (its square root is taken
+// once per source).
+template <int NORM>
+__device__ __forceinline__ float nn_scan_range(const float4* __restrict__ pts, int32_t b, int32_t e, float x, float y,
+                                               float z, float best)
+{
+#pragma unroll 4
+    for (int32_t j = b; j < e; ++j) {
+        const float4 q = pts[j];
+        const float dx = q.x - x, dy = q.y - y, dz = q.z - z;
+        if constexpr (NORM == 1) best = fminf(best, fabsf(dx) + fabsf(dy) + fabsf(dz));
+        else best = fminf(best, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+    }
+    return best;
+}
+
+// partials[block] = sum over the block's sources of the distance to the nearest destination,
+// for the sources whose search completes within kNnNearRings rings; the others are appended
+// to far_idx (their best distance so far, as float bits, to far_min).
+template <int NORM>
+__global__ __launch_bounds__(kThreads) void k_nn_search(const float* __restrict__ src, int64_t ns,
+                                                       const NnGrid* __restrict__ G, const int32_t* __restrict__ start,
+                                                       const float4* __restrict__ pts, double* __restrict__ partials,
+                                                       int32_t* __restrict__ nfar, int32_t* __restrict__ far_idx,
+                                                       uint32_t* __restrict__ far_min)
+{
+    const NnGrid g = *G;
+    const int32_t rmax = max(g.dims[0], max(g.dims[1], g.dims[2]));
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < ns; i += (int64_t)gridDim.x * kThreads) {
-        float m = mins[i];
-        for (int64_t sp = 1; sp < nsplit; ++sp) m = fminf(m, mins[sp * ns + i]);
-        acc += NORM == 1 ? (double)m : (double)sqrtf(m);
+        const float x = src[3 * i], y = src[3 * i + 1], z = src[3 * i + 2];
+        const int32_t cx = nn_axis_cell(x, g.org[0], g.inv_cs, g.dims[0]);
+        const int32_t cy = nn_axis_cell(y, g.org[1], g.inv_cs, g.dims[1]);
+        const int32_t cz = nn_axis_cell(z, g.org[2], g.inv_cs, g.dims[2]);
+        float best = INFINITY;
+        // every cell of ring r is at least (r - 1) cs away
+        auto bound_met = [&](int32_t r) {
+            const float lb = (float)(r - 1) * g.cs - g.slack;
+            return r >= 1 && lb > 0.0f && best <= (NORM == 1 ? lb : lb * lb);
+        };
+        // rings 0 and 1 together: the 3 x 3 rows of the cube around the cell, each a contiguous
+        // run of up to 3 cells, all bounds loaded up front
+        {
+            const int32_t x0 = max(cx - 1, 0), x1 = min(cx + 1, g.dims[0] - 1);
+            int32_t rb[9], re[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int32_t yy = cy - 1 + q % 3, zz = cz - 1 + q / 3;
+                const bool in = yy >= 0 && yy < g.dims[1] && zz >= 0 && zz < g.dims[2];
+                // the row of the clamped indices, so that no address leaves the grid
+                const int32_t row = g.dims[0] * (min(max(yy, 0), g.dims[1] - 1) +
+                                                 g.dims[1] * min(max(zz, 0), g.dims[2] - 1));
+                rb[q] = in ? start[row + x0] : 0;
+                re[q] = in ? start[row + x1 + 1] : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < 9; ++q) best = nn_scan_range<NORM>(pts, rb[q], re[q], x, y, z, best);
+        }
+        int32_t r = 2;
+        for (; r <= min(rmax, kNnNearRings); ++r) {
+            if (bound_met(r)) break;
+            const int32_t z0 = max(cz - r, 0), z1 = min(cz + r, g.dims[2] - 1);
+            const int32_t y0 = max(cy - r, 0), y1 = min(cy + r, g.dims[1] - 1);
+            const int32_t x0 = max(cx - r, 0), x1 = min(cx + r, g.dims[0] - 1);
+            for (int32_t zz = z0; zz <= z1; ++zz) {
+                for (int32_t yy = y0; yy <= y1; ++yy) {
+                    const int32_t row = g.dims[0] * (yy + g.dims[1] * zz);
+                    if (zz == cz - r || zz == cz + r || yy == cy - r || yy == cy + r) {
+                        // a row on the ring's faces: every cell of the row in range, contiguous
+                        best = nn_scan_range<NORM>(pts, start[row + x0], start[row + x1 + 1], x, y, z, best);
+                    } else {
+                        if (cx - r >= 0)
+                            best = nn_scan_range<NORM>(pts, start[row + cx - r], start[row + cx - r + 1], x, y, z, best);
+                        if (cx + r < g.dims[0])
+                            best = nn_scan_range<NORM>(pts, start[row + cx + r], start[row + cx + r + 1], x, y, z, best);
+                    }
+                }
+            }
+        }
+        // complete when every ring was visited or the next ring's bound is met
+        if (r > rmax || bound_met(r)) {
+            acc += NORM == 1 ? (double)best : (double)sqrtf(best);
+        } else {
+            const int32_t k = atomicAdd(nfar, 1);
+            far_idx[k] = (int32_t)i;
+            far_min[k] = __float_as_uint(best);
+        }
     }
     const double tot = block_sum_f64<kThreads>(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-// Splits of the destination set for sources ns: enough workgroups to fill the GPU, at least
-// one tile of destinations per split.
-static int64_t nn_splits(int64_t ns, int64_t nd)
+// The listed far sources against every destination point: kNnFarChunks x kNnFarSplits
+// workgroups, destination tiles staged in LDS; each workgroup's minimum over its split enters
+// far_min with an integer atomic min (the bits of non-negative floats order as the floats).
+template <int NORM>
+__global__ __launch_bounds__(kThreads) void k_nn_far(const float* __restrict__ src, const int32_t* __restrict__ nfar_p,
+                                                    const int32_t* __restrict__ far_idx, const float4* __restrict__ pts,
+                                                    int64_t nd, uint32_t* __restrict__ far_min)
 {
-    constexpr int CHUNK = kNnThreads * kNnPerThread;
-    const int64_t chunks = (ns + CHUNK - 1) / CHUNK, tiles = (nd + kNnTile - 1) / kNnTile;
-    return std::max<int64_t>(1, std::min<int64_t>({(kNnTargetBlocks + chunks - 1) / chunks, tiles, 64}));
+    __shared__ float4 tile[kNnFarTile];
+    const int32_t nfar = *nfar_p;
+    const int32_t chunk = blockIdx.x % kNnFarChunks, split = blockIdx.x / kNnFarChunks;
+    const int64_t per = (nd + kNnFarSplits - 1) / kNnFarSplits;
+    const int64_t d0 = (int64_t)split * per, d1 = min(nd, d0 + per);
+    for (int32_t k0 = chunk * kThreads; k0 < nfar; k0 += kNnFarChunks * kThreads) {
+        const int32_t k = k0 + threadIdx.x;
+        float x = 0.0f, y = 0.0f, z = 0.0f;
+        if (k < nfar) {
+            const int64_t i = far_idx[k];
+            x = src[3 * i];
+            y = src[3 * i + 1];
+            z = src[3 * i + 2];
+        }
+        float best = INFINITY;
+        for (int64_t t0 = d0; t0 < d1; t0 += kNnFarTile) {
+            const int cnt = (int)min((int64_t)kNnFarTile, d1 - t0);
+            __syncthreads();
+            for (int q = threadIdx.x; q < cnt; q += kThreads) tile[q] = pts[t0 + q];
+            __syncthreads();
+            for (int q = 0; q < cnt; ++q) {
+                const float4 p = tile[q];
+                const float dx = p.x - x, dy = p.y - y, dz = p.z - z;
+                if constexpr (NORM == 1) best = fminf(best, fabsf(dx) + fabsf(dy) + fabsf(dz));
+                else best = fminf(best, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+            }
+        }
+        if (k < nfar) atomicMin(&far_min[k], __float_as_uint(best));
+    }
+}
+
+// *part = sum over the far sources of their distance to the nearest destination.
+template <int NORM>
+__global__ __launch_bounds__(kThreads) void k_nn_far_sum(const int32_t* __restrict__ nfar_p,
+                                                        const uint32_t* __restrict__ far_min, double* __restrict__ part)
+{
+    const int32_t nfar = *nfar_p;
+    double acc = 0.0;
+    for (int32_t k = threadIdx.x; k < nfar; k += kThreads) {
+        const float m = __uint_as_float(far_min[k]);
+        acc += NORM == 1 ? (double)m : (double)sqrtf(m);
+    }
+    const double tot = block_sum_f64<kThreads>(acc);
+    if (threadIdx.x == 0) *part = tot;
+}
+
+// Workspace of one direction's grid (offsets from the section's base, 256-byte aligned).
+struct NnWs {
+    size_t grid, box, cnt, bsum, start, cursor, pts, nfar, far_idx, far_min, total;
+};
+
+// nd destination points (bucketed), ns source points (the far list).
+static NnWs nn_ws(int64_t nd, int64_t ns)
+{
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const int64_t mc = nn_max_cells(nd);
+    NnWs W;
+    size_t off = 0;
+    W.grid = off;
+    off = up(off + sizeof(NnGrid));
+    W.box = off;
+    off = up(off + (size_t)kNnBoxBlocks * 6 * 4);
+    W.cnt = off;
+    off = up(off + (size_t)mc * 4);
+    W.bsum = off;
+    off = up(off + (size_t)((mc + kNnScanCells - 1) / kNnScanCells) * 4);
+    W.start = off;
+    off = up(off + (size_t)(mc + 1) * 4);
+    W.cursor = off;
+    off = up(off + (size_t)mc * 4);
+    W.pts = off;
+    off = up(off + (size_t)nd * 16);
+    W.nfar = off;
+    off = up(off + 4);
+    W.far_idx = off;
+    off = up(off + (size_t)ns * 4);
+    W.far_min = off;
+    off = up(off + (size_t)ns * 4);
+    W.total = off;
+    return W;
 }
 
 size_t chamfer_workspace_bytes(int64_t na, int64_t nb)
 {
-    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
-    return kReduceBytes + up((size_t)na * nn_splits(na, nb) * 4) + up((size_t)nb * nn_splits(nb, na) * 4);
+    return kReduceBytes + nn_ws(nb, na).total + nn_ws(na, nb).total;
+}
+
+// Builds the bucket grid of dst in the section at base and sums the nearest distances of
+// src's points into partials (nblk + 1 of them: one per search block, then the far sources').
+static void nn_direction(const float* src, int64_t ns, const float* dst, int64_t nd, int norm, char* base,
+                         double* partials, unsigned nblk, hipStream_t s)
+{
+    const NnWs W = nn_ws(nd, ns);
+    int32_t* nfar = reinterpret_cast<int32_t*>(base + W.nfar);
+    int32_t* far_idx = reinterpret_cast<int32_t*>(base + W.far_idx);
+    uint32_t* far_min = reinterpret_cast<uint32_t*>(base + W.far_min);
+    NnGrid* G = reinterpret_cast<NnGrid*>(base + W.grid);
+    float* box = reinterpret_cast<float*>(base + W.box);
+    int32_t* cnt = reinterpret_cast<int32_t*>(base + W.cnt);
+    int32_t* bsum = reinterpret_cast<int32_t*>(base + W.bsum);
+    int32_t* start = reinterpret_cast<int32_t*>(base + W.start);
+    int32_t* cursor = reinterpret_cast<int32_t*>(base + W.cursor);
+    float4* pts = reinterpret_cast<float4*>(base + W.pts);
+    const int64_t mc = nn_max_cells(nd);
+    const int64_t nsb = (mc + kNnScanCells - 1) / kNnScanCells;
+    const unsigned gbox = (unsigned)std::min<int64_t>((nd + kThreads - 1) / kThreads, kNnBoxBlocks);
+    const unsigned gpts = (unsigned)std::min<int64_t>((nd + kThreads - 1) / kThreads, 8192);
+    const unsigned gz = (unsigned)std::min<int64_t>((mc + kThreads - 1) / kThreads, 8192);
+    hipLaunchKernelGGL(k_nn_box, dim3(gbox), dim3(kThreads), 0, s, dst, nd, box);
+    hipLaunchKernelGGL(k_nn_setup, dim3(1), dim3(kThreads), 0, s, box, (int)gbox, mc, G, nfar);
+    hipLaunchKernelGGL(k_nn_zero, dim3(gz), dim3(kThreads), 0, s, cnt, mc);
+    hipLaunchKernelGGL(k_nn_count, dim3(gpts), dim3(kThreads), 0, s, dst, nd, G, cnt);
+    hipLaunchKernelGGL(k_nn_scan_blocks, dim3((unsigned)nsb), dim3(kNnScanThreads), 0, s, cnt, mc, bsum);
+    hipLaunchKernelGGL(k_nn_scan_top, dim3(1), dim3(kNnScanThreads), 0, s, bsum, nsb);
+    hipLaunchKernelGGL(k_nn_scan_apply, dim3((unsigned)nsb), dim3(kNnScanThreads), 0, s, cnt, mc, bsum, start,
+                       cursor);
+    hipLaunchKernelGGL(k_nn_scatter, dim3(gpts), dim3(kThreads), 0, s, dst, nd, G, cursor, pts);
+    auto search = norm == 1 ? k_nn_search<1> : k_nn_search<2>;
+    auto far = norm == 1 ? k_nn_far<1> : k_nn_far<2>;
+    auto far_sum = norm == 1 ? k_nn_far_sum<1> : k_nn_far_sum<2>;
+    hipLaunchKernelGGL(search, dim3(nblk), dim3(kThreads), 0, s, src, ns, G, start, pts, partials, nfar, far_idx,
+                       far_min);
+    hipLaunchKernelGGL(far, dim3(kNnFarChunks * kNnFarSplits), dim3(kThreads), 0, s, src, nfar, far_idx, pts, nd,
+                       far_min);
+    hipLaunchKernelGGL(far_sum, dim3(1), dim3(kThreads), 0, s, nfar, far_min, partials + nblk);
 }
 
 __global__ __launch_bounds__(kFinishThreads) void k_chamfer_finish(const double* __restrict__ pa, int na_b,
@@ -582,25 +1029,16 @@ hipError_t launch_chamfer(const float* a, int64_t na, const float* b, int64_t nb
                           hipStream_t s)
 {
     double* partials = reinterpret_cast<double*>(ws);
-    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
-    const int64_t sa = nn_splits(na, nb), sb = nn_splits(nb, na);
-    float* mins_a = reinterpret_cast<float*>(ws + kReduceBytes);
-    float* mins_b = reinterpret_cast<float*>(ws + kReduceBytes + up((size_t)na * sa * 4));
-    constexpr int CHUNK = kNnThreads * kNnPerThread;
-    const int64_t ca = (na + CHUNK - 1) / CHUNK, cb = (nb + CHUNK - 1) / CHUNK;
-    const int64_t ta = ((nb + kNnTile - 1) / kNnTile + sa - 1) / sa;  // destination tiles per split
-    const int64_t tb = ((na + kNnTile - 1) / kNnTile + sb - 1) / sb;
-    auto nn_min = norm == 1 ? k_nn_min<1> : k_nn_min<2>;
-    auto nn_reduce = norm == 1 ? k_nn_reduce<1> : k_nn_reduce<2>;
-    hipLaunchKernelGGL(nn_min, dim3((unsigned)(ca * sa)), dim3(kNnThreads), 0, s, a, na, b, nb, ca, ta, mins_a);
-    hipLaunchKernelGGL(nn_min, dim3((unsigned)(cb * sb)), dim3(kNnThreads), 0, s, b, nb, a, na, cb, tb, mins_b);
-    const int half = kMaxReduceBlocks / 2;
-    const unsigned ga = (unsigned)std::min<int64_t>((na + kThreads - 1) / kThreads, half);
-    const unsigned gb = (unsigned)std::min<int64_t>((nb + kThreads - 1) / kThreads, half);
-    hipLaunchKernelGGL(nn_reduce, dim3(ga), dim3(kThreads), 0, s, mins_a, na, sa, partials);
-    hipLaunchKernelGGL(nn_reduce, dim3(gb), dim3(kThreads), 0, s, mins_b, nb, sb, partials + half);
-    hipLaunchKernelGGL(k_chamfer_finish, dim3(1), dim3(kFinishThreads), 0, s, partials, (int)ga, na, partials + half,
-                       (int)gb, nb, out);
+    const int half = kMaxReduceBlocks * 2;  // the reduction area holds 4 kMaxReduceBlocks doubles
+    // search blocks of each direction, one partial left for its far sources
+    const unsigned ga = (unsigned)std::min<int64_t>((na + kThreads - 1) / kThreads, half - 1);
+    const unsigned gb = (unsigned)std::min<int64_t>((nb + kThreads - 1) / kThreads, half - 1);
+    char* sec_b = ws + kReduceBytes;  // the grid of b (searched by a's points)
+    char* sec_a = sec_b + nn_ws(nb, na).total;
+    nn_direction(a, na, b, nb, norm, sec_b, partials, ga, s);
+    nn_direction(b, nb, a, na, norm, sec_a, partials + half, gb, s);
+    hipLaunchKernelGGL(k_chamfer_finish, dim3(1), dim3(kFinishThreads), 0, s, partials, (int)ga + 1, na,
+                       partials + half, (int)gb + 1, nb, out);
     return hipGetLastError();
 }
 

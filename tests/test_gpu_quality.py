@@ -191,8 +191,8 @@ def test_chamfer_matches_oracle(norm):
 
 @pytest.mark.parametrize("na,nb", [(3001, 200_003), (1, 70_000), (5, 1)])
 def test_chamfer_lopsided_sets(na, nb):
-    """A small source set against a large destination set (the destinations split over many
-    workgroups), single points, and ragged tiles."""
+    """A small source set against a large destination set, single points (a one-cell grid),
+    and the arguments swapped."""
     rng = np.random.default_rng(na)
     a = rng.uniform(-1, 1, size=(na, 3)).astype(np.float32)
     b = rng.normal(0, 0.5, size=(nb, 3)).astype(np.float32)
@@ -201,6 +201,26 @@ def test_chamfer_lopsided_sets(na, nb):
     assert abs(got[0] - ref_ab) <= 1e-5 * ref_ab
     swapped = quality.chamfer(_t(b), _t(a))
     assert abs(swapped[1] - got[2]) <= 1e-12 * got[2] and abs(swapped[2] - got[1]) <= 1e-12 * got[1]
+
+
+@pytest.mark.parametrize("layout", ["far", "flat", "duplicates"])
+def test_chamfer_bucket_grid_layouts(layout):
+    """Layouts that test the bucket search's stopping bound: sets far apart (every search runs
+    out of the other set's grid), a destination set of zero extent along z, and many copies of
+    a few points (one crowded cell per copy), in both norms."""
+    rng = np.random.default_rng(12)
+    a = rng.normal(0, 0.4, size=(4000, 3))
+    if layout == "far":
+        b = rng.normal(0, 0.3, size=(6000, 3)) + np.array([6.0, -2.0, 1.0])
+    elif layout == "flat":
+        b = np.c_[rng.uniform(-1, 1, size=(6000, 2)), np.full(6000, 0.25)]
+    else:
+        b = np.repeat(rng.normal(0, 0.5, size=(3, 3)), 2000, axis=0)
+    a, b = a.astype(np.float32), b.astype(np.float32)
+    for norm in (1, 2):
+        got = quality.chamfer(_t(a), _t(b), norm=norm)
+        ref = qo.chamfer(a.astype(np.float64), b.astype(np.float64), norm)
+        assert abs(got[0] - ref) <= 1e-5 * ref, (norm, got, ref)
 
 
 def test_quality_of_fitted_grids_by_order():
