@@ -160,11 +160,6 @@ __device__ __forceinline__ int cell_pattern(const float* cv)
     return p;
 }
 
-__device__ __forceinline__ int cell_count(const float* cv)
-{
-    return kMc.c[cell_pattern(cv)].ntri;
-}
-
 // Per block: kMeshCellsPerBlock consecutive cells, thread t taking cells q kMeshThreads + t
 // (q < kMeshCellsPerThread), so that the 64 lanes of a wave read neighbouring lattice values.
 // The block's cells that cross the level set (count > 0) are listed in cell order from
@@ -176,8 +171,13 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_count(Lattice L, const fl
                                                             uint32_t* __restrict__ blist, uint32_t* __restrict__ scnt)
 {
     constexpr int kWaves = kMeshThreads / 64;
+    static_assert(kMeshThreads == 256, "one thread per sign pattern stages the triangle counts");
     // per (q, wave): the wave's sums, in cell order
     __shared__ uint32_t wtot[kMeshCellsPerThread * kWaves];
+    // triangles of every sign pattern (an LDS read instead of a per-lane gather from the table)
+    __shared__ uint8_t ntri[256];
+    ntri[threadIdx.x] = kMc.c[threadIdx.x].ntri;
+    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t cb = (int64_t)blockIdx.x * kMeshCellsPerBlock + threadIdx.x;
     // per cell: its triangle count in the high half-word and 1 if it crosses in the low one
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_count(Lattice L, const fl
             cell_of(L, c, i, j, k);
             float cv[8];
             cell_values(L, v, i, j, k, cv);
-            n = (uint32_t)cell_count(cv);
+            n = ntri[cell_pattern(cv)];
         }
         x[q] = (n << 16) | (n > 0 ? 1u : 0u);
     }
