@@ -252,22 +252,31 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_list(const uint32_t* __re
 }
 
 // One block: exclusive scans of the blocks' triangle totals (tri, in place) and crossing-cell
-// counts (scnt into soff); *ntri and *nlist = their sums.
+// counts (scnt into soff); *ntri and *nlist = their sums.  Each thread takes 4 consecutive
+// entries of a pass.
 __global__ __launch_bounds__(1024) void k_mesh_scan_blocks(uint32_t* __restrict__ tri, const uint32_t* __restrict__ scnt,
                                                           uint32_t* __restrict__ soff, int64_t nb,
                                                           int64_t* __restrict__ ntri, int64_t* __restrict__ nlist)
 {
+    constexpr int kPer = 4, kPass = 1024 * kPer;
     __shared__ uint32_t wsum[2][16];
     __shared__ uint32_t carry[2];
     if (threadIdx.x == 0) carry[0] = carry[1] = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
-        const int64_t b = b0 + threadIdx.x;
-        uint32_t x[2] = {b < nb ? tri[b] : 0u, b < nb ? scnt[b] : 0u}, incl[2];
+    for (int64_t b0 = 0; b0 < nb; b0 += kPass) {
+        const int64_t b = b0 + (int64_t)threadIdx.x * kPer;
+        uint32_t x[2][kPer], t[2] = {0u, 0u}, incl[2];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            x[0][k] = b + k < nb ? tri[b + k] : 0u;
+            x[1][k] = b + k < nb ? scnt[b + k] : 0u;
+            t[0] += x[0][k];
+            t[1] += x[1][k];
+        }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            incl[u] = x[u];
+            incl[u] = t[u];
 #pragma unroll
             for (int d = 1; d < 64; d <<= 1) {
                 const uint32_t o = __shfl_up(incl[u], d, 64);
@@ -276,19 +285,27 @@ __global__ __launch_bounds__(1024) void k_mesh_scan_blocks(uint32_t* __restrict_
             if (lane == 63) wsum[u][wave] = incl[u];
         }
         __syncthreads();
-        uint32_t before[2] = {carry[0], carry[1]};
+        uint32_t run[2] = {carry[0], carry[1]};
         for (int w = 0; w < wave; ++w) {
-            before[0] += wsum[0][w];
-            before[1] += wsum[1][w];
+            run[0] += wsum[0][w];
+            run[1] += wsum[1][w];
         }
-        if (b < nb) {
-            tri[b] = before[0] + incl[0] - x[0];
-            soff[b] = before[1] + incl[1] - x[1];
+        const uint32_t end0 = run[0] + incl[0], end1 = run[1] + incl[1];
+        run[0] += incl[0] - t[0];
+        run[1] += incl[1] - t[1];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (b + k < nb) {
+                tri[b + k] = run[0];
+                soff[b + k] = run[1];
+            }
+            run[0] += x[0][k];
+            run[1] += x[1][k];
         }
         __syncthreads();
         if (threadIdx.x == 1023) {
-            carry[0] = before[0] + incl[0];
-            carry[1] = before[1] + incl[1];
+            carry[0] = end0;
+            carry[1] = end1;
         }
         __syncthreads();
     }
