@@ -482,7 +482,7 @@ hipError_t launch_iou(int64_t n, const float* f, const float* d, int64_t* counts
 
 // ------------------------------------------------------------------ Chamfer
 // Exact nearest points on a bucket grid of the destination set.  The grid covers the bounding
-// box of the destination's finite points with cubic cells (at most one cell per two points,
+// box of the destination's finite points with cubic cells (at most one cell per point,
 // at most kNnDimMax along an axis); a point's cell is floor((x - org) / cs) per axis, clamped
 // to the grid (non-finite coordinates included), so it is monotone in x.  The points are
 // counting-sorted by cell (x fastest).  A source point visits the rings of cells around its
@@ -509,12 +509,12 @@ constexpr int kNnScanPer = 4;  // cells per thread of the start scan
 constexpr int kNnScanCells = kNnScanThreads * kNnScanPer;
 constexpr int kNnNearRings = 2;   // rings a point searches before it is left to the brute-force pass
 constexpr int kNnFarChunks = 16;  // workgroups along the list of far points (kThreads points each)
-constexpr int kNnFarSplits = 64;  // workgroups along the destination points
+constexpr int kNnFarSplits = 256;  // workgroups along the destination points
 constexpr int kNnFarTile = 1024;  // destination points per LDS tile of the brute-force pass
 
 static int64_t nn_max_cells(int64_t nd)
 {
-    return std::min<int64_t>(kNnMaxCells, std::max<int64_t>(1, nd / 2));
+    return std::min<int64_t>(kNnMaxCells, std::max<int64_t>(1, nd));
 }
 
 __device__ __forceinline__ int32_t nn_axis_cell(float x, float org, float inv_cs, int32_t dim)
@@ -919,6 +919,7 @@ __global__ __launch_bounds__(kThreads) void k_nn_far(const float* __restrict__ s
             __syncthreads();
             for (int q = threadIdx.x; q < cnt; q += kThreads) tile[q] = pts[t0 + q];
             __syncthreads();
+#pragma unroll 4
             for (int q = 0; q < cnt; ++q) {
                 const float4 p = tile[q];
                 const float dx = p.x - x, dy = p.y - y, dz = p.z - z;
