@@ -510,7 +510,6 @@ constexpr int kNnScanCells = kNnScanThreads * kNnScanPer;
 constexpr int kNnNearRings = 2;   // rings a point searches before it is left to the brute-force pass
 constexpr int kNnFarChunks = 16;  // workgroups along the list of far points (kThreads points each)
 constexpr int kNnFarSplits = 256;  // workgroups along the destination points
-constexpr int kNnFarTile = 1024;  // destination points per LDS tile of the brute-force pass
 
 static int64_t nn_max_cells(int64_t nd)
 {
@@ -892,14 +891,14 @@ __global__ __launch_bounds__(kThreads) void k_nn_search(const float* __restrict_
 }
 
 // The listed far sources against every destination point: kNnFarChunks x kNnFarSplits
-// workgroups, destination tiles staged in LDS; each workgroup's minimum over its split enters
-// far_min with an integer atomic min (the bits of non-negative floats order as the floats).
+// workgroups, every lane of a wave reading the same destination point; each workgroup's
+// minimum over its split enters far_min with an integer atomic min (the bits of non-negative
+// floats order as the floats).
 template <int NORM>
 __global__ __launch_bounds__(kThreads) void k_nn_far(const float* __restrict__ src, const int32_t* __restrict__ nfar_p,
                                                     const int32_t* __restrict__ far_idx, const float4* __restrict__ pts,
                                                     int64_t nd, uint32_t* __restrict__ far_min)
 {
-    __shared__ float4 tile[kNnFarTile];
     const int32_t nfar = *nfar_p;
     const int32_t chunk = blockIdx.x % kNnFarChunks, split = blockIdx.x / kNnFarChunks;
     const int64_t per = (nd + kNnFarSplits - 1) / kNnFarSplits;
@@ -914,18 +913,13 @@ __global__ __launch_bounds__(kThreads) void k_nn_far(const float* __restrict__ s
             z = src[3 * i + 2];
         }
         float best = INFINITY;
-        for (int64_t t0 = d0; t0 < d1; t0 += kNnFarTile) {
-            const int cnt = (int)min((int64_t)kNnFarTile, d1 - t0);
-            __syncthreads();
-            for (int q = threadIdx.x; q < cnt; q += kThreads) tile[q] = pts[t0 + q];
-            __syncthreads();
-#pragma unroll 4
-            for (int q = 0; q < cnt; ++q) {
-                const float4 p = tile[q];
-                const float dx = p.x - x, dy = p.y - y, dz = p.z - z;
-                if constexpr (NORM == 1) best = fminf(best, fabsf(dx) + fabsf(dy) + fabsf(dz));
-                else best = fminf(best, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-            }
+        // the destination index is the same in every lane: wave-uniform loads, no LDS
+#pragma unroll 8
+        for (int64_t j = d0; j < d1; ++j) {
+            const float4 p = pts[j];
+            const float dx = p.x - x, dy = p.y - y, dz = p.z - z;
+            if constexpr (NORM == 1) best = fminf(best, fabsf(dx) + fabsf(dy) + fabsf(dz));
+            else best = fminf(best, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
         }
         if (k < nfar) atomicMin(&far_min[k], __float_as_uint(best));
     }
