@@ -853,8 +853,20 @@ __global__ __launch_bounds__(kThreads) void k_nn_search(const float* __restrict_
                 rb[q] = in ? start[row + x0] : 0;
                 re[q] = in ? start[row + x1 + 1] : 0;
             }
+            // the cell's own row first; a row below or above along y or z is skipped when the
+            // point's distance to those cell faces (less the rounding allowance) is no smaller
+            // than the best distance found
+            const float ly = y - fmaf((float)cy, g.cs, g.org[1]), lz = z - fmaf((float)cz, g.cs, g.org[2]);
+            const float gy[3] = {fmaxf(ly - g.slack, 0.0f), 0.0f, fmaxf(g.cs - ly - g.slack, 0.0f)};
+            const float gz[3] = {fmaxf(lz - g.slack, 0.0f), 0.0f, fmaxf(g.cs - lz - g.slack, 0.0f)};
+            best = nn_scan_range<NORM>(pts, rb[4], re[4], x, y, z, best);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) best = nn_scan_range<NORM>(pts, rb[q], re[q], x, y, z, best);
+            for (int q = 0; q < 9; ++q) {
+                if (q == 4) continue;
+                const float by = gy[q % 3], bz = gz[q / 3];
+                const float lb = NORM == 1 ? by + bz : fmaf(by, by, bz * bz);
+                if (lb < best) best = nn_scan_range<NORM>(pts, rb[q], re[q], x, y, z, best);
+            }
         }
         int32_t r = 2;
         for (; r <= min(rmax, kNnNearRings); ++r) {
