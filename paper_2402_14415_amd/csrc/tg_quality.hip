@@ -839,10 +839,10 @@ __global__ __launch_bounds__(kThreads) void k_nn_search(const float* __restrict_
             return r >= 1 && lb > 0.0f && best <= (NORM == 1 ? lb : lb * lb);
         };
         // rings 0 and 1 together: the 3 x 3 rows of the cube around the cell, each a contiguous
-        // run of up to 3 cells, all bounds loaded up front
+        // run of up to 3 cells whose 4 cell starts are loaded up front
         {
-            const int32_t x0 = max(cx - 1, 0), x1 = min(cx + 1, g.dims[0] - 1);
-            int32_t rb[9], re[9];
+            const int32_t xl = max(cx - 1, 0), xr = min(cx + 1, g.dims[0] - 1);
+            int32_t sa[9], sm0[9], sm1[9], se[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const int32_t yy = cy - 1 + q % 3, zz = cz - 1 + q / 3;
@@ -850,22 +850,35 @@ __global__ __launch_bounds__(kThreads) void k_nn_search(const float* __restrict_
                 // the row of the clamped indices, so that no address leaves the grid
                 const int32_t row = g.dims[0] * (min(max(yy, 0), g.dims[1] - 1) +
                                                  g.dims[1] * min(max(zz, 0), g.dims[2] - 1));
-                rb[q] = in ? start[row + x0] : 0;
-                re[q] = in ? start[row + x1 + 1] : 0;
+                sa[q] = in ? start[row + xl] : 0;
+                sm0[q] = in ? start[row + cx] : 0;
+                sm1[q] = in ? start[row + cx + 1] : 0;
+                se[q] = in ? start[row + xr + 1] : 0;
             }
-            // the cell's own row first; a row below or above along y or z is skipped when the
-            // point's distance to those cell faces (less the rounding allowance) is no smaller
-            // than the best distance found
+            // lower bounds of the distance to the neighbouring cells along each axis: the
+            // point's distance to the shared cell face, less the rounding allowance
+            const float lx = x - fmaf((float)cx, g.cs, g.org[0]);
             const float ly = y - fmaf((float)cy, g.cs, g.org[1]), lz = z - fmaf((float)cz, g.cs, g.org[2]);
+            const float gx[3] = {fmaxf(lx - g.slack, 0.0f), 0.0f, fmaxf(g.cs - lx - g.slack, 0.0f)};
             const float gy[3] = {fmaxf(ly - g.slack, 0.0f), 0.0f, fmaxf(g.cs - ly - g.slack, 0.0f)};
             const float gz[3] = {fmaxf(lz - g.slack, 0.0f), 0.0f, fmaxf(g.cs - lz - g.slack, 0.0f)};
-            best = nn_scan_range<NORM>(pts, rb[4], re[4], x, y, z, best);
+            auto lower = [&](float bx, float by, float bz) {
+                return NORM == 1 ? bx + by + bz : fmaf(bx, bx, fmaf(by, by, bz * bz));
+            };
+            // the cell itself first, then its row's other cells, then the other rows, each
+            // trimmed to the cells whose bound is below the best distance found
+            best = nn_scan_range<NORM>(pts, sm0[4], sm1[4], x, y, z, best);
+            if (lower(gx[0], 0.0f, 0.0f) < best) best = nn_scan_range<NORM>(pts, sa[4], sm0[4], x, y, z, best);
+            if (lower(gx[2], 0.0f, 0.0f) < best) best = nn_scan_range<NORM>(pts, sm1[4], se[4], x, y, z, best);
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 if (q == 4) continue;
                 const float by = gy[q % 3], bz = gz[q / 3];
-                const float lb = NORM == 1 ? by + bz : fmaf(by, by, bz * bz);
-                if (lb < best) best = nn_scan_range<NORM>(pts, rb[q], re[q], x, y, z, best);
+                if (lower(0.0f, by, bz) < best) {
+                    const int32_t b = lower(gx[0], by, bz) < best ? sa[q] : sm0[q];
+                    const int32_t e = lower(gx[2], by, bz) < best ? se[q] : sm1[q];
+                    best = nn_scan_range<NORM>(pts, b, e, x, y, z, best);
+                }
             }
         }
         int32_t r = 2;
